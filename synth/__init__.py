@@ -1,0 +1,395 @@
+"""Seeded synthetic visibility graphs: the inputs shared by the oracle and the HIP path.
+
+The paper's inputs (OpenStreetMap footprints of Valdivia, sparkSieve2 edge sets,
+Sec. 3.1 and Sec. 4.1) are not available, so seeded obstacle rasters stand in for
+them.  This module draws the rasters (numpy PCG64 streams, unrelated to the
+method's SplitMix64 hash), keeps the main connected component, numbers its cells
+in raster order and builds the sorted adjacency lists with an exact integer
+visibility rule (``synth.c``; a GPU twin in ``synth_gpu.hip`` serves the largest
+rasters).  It holds none of the method's arithmetic: no hashing, no registers, no
+estimator and no LEB128 coding.  A graph leaves this module as plain arrays:
+``adj_offsets`` (u64, n+1) and ``adj_ids`` (u32, sorted ascending per row).
+
+Workload recipes (sizes are those of the paper's T2/T3 rows this build measures):
+
+* ``tiny(seed)``: 32x32 grid of 1 m cells, axis-aligned rectangles with sides 3-8
+  cells at uniform positions until >= 30 % of cells are covered.
+* ``urban(seed)``: 230x230 cells of 3 m, perturbed street grid (streets 8-20 m
+  wide, 40-90 m blocks with ragged edges) with rectangular buildings of 10-40 m
+  sides filling 20 % of each block; about 42,700 nodes and 1.4e8 directed edges
+  (the paper's T2 row: 42,705 cells, 161M edges).
+* ``city(seed)``: the same seeded layout drawn CITY_SCALE = 2.35 times finer on a
+  541x541 raster: about 236,000 nodes and 4.7e9 directed edges (the paper's
+  largest T2 row: 235,983 cells, 4.8e9 edges).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+_GPU_LIB = None
+
+# Street/building generator parameters in metres, calibrated once on the urban
+# configuration (nodes and directed edges of the paper's 42,705-cell T2 row) and
+# then frozen.  The city configuration draws the same seeded layout at a spacing
+# CITY_SCALE times finer, as the paper's T2 rows at 7 m and 3 m spacing cover one
+# study area.
+URBAN = dict(
+    street_m=(8, 20),
+    block_m=(40, 90),
+    bldg_m=(10, 40),
+    block_fill=0.20,
+    jitter_m=2,
+)
+URBAN_EXTENT = (230, 230)
+URBAN_CELL_M = 3.0
+CITY_SCALE = 2.35
+CITY_EXTENT = (541, 541)
+
+
+C_FLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC", "-std=c11"]
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libsynth.so")
+
+
+def build(verbose: bool = False) -> None:
+    """Compile synth.c (gcc) and synth_gpu.hip (hipcc, gfx950) in place."""
+    import subprocess
+    out = lib_path()
+    cmd = ["gcc", *C_FLAGS, "-o", out + ".tmp", os.path.join(_HERE, "synth.c")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    gout = gpu_lib_path()
+    hip_src = os.path.join(_HERE, "synth_gpu.hip")
+    if os.path.exists(hip_src):
+        cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+               "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-o", gout + ".tmp", hip_src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc failed for synth_gpu.hip:\n" + res.stderr)
+        os.replace(gout + ".tmp", gout)
+
+
+def gpu_lib_path() -> str:
+    return os.path.join(_HERE, "libsynth_gpu.so")
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        c_u8p = ctypes.POINTER(ctypes.c_uint8)
+        c_i32p = ctypes.POINTER(ctypes.c_int32)
+        c_i64p = ctypes.POINTER(ctypes.c_int64)
+        c_u64p = ctypes.POINTER(ctypes.c_uint64)
+        c_u32p = ctypes.POINTER(ctypes.c_uint32)
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        L.syn_visible.argtypes = [c_u8p, i32, i32, i32, i32, i32, i32]
+        L.syn_visible.restype = ctypes.c_int
+        L.syn_main_component.argtypes = [c_u8p, i32, i32, c_i32p]
+        L.syn_main_component.restype = i64
+        L.syn_degrees.argtypes = [c_u8p, i32, i32, c_i32p, i64, c_u64p]
+        L.syn_degrees.restype = None
+        L.syn_fill.argtypes = [c_u8p, i32, i32, c_i32p, i64, c_u64p, c_u32p]
+        L.syn_fill.restype = None
+        L.syn_degrees_sample.argtypes = [c_u8p, i32, i32, c_i32p, i64, c_i64p, i64, c_u64p]
+        L.syn_degrees_sample.restype = None
+        L.syn_visible_pairs.argtypes = [c_u8p, i32, i32, c_i32p, c_i64p, c_i64p, i64, c_u8p]
+        L.syn_visible_pairs.restype = None
+        L.syn_num_threads.argtypes = []
+        L.syn_num_threads.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+@dataclass
+class Graph:
+    """A visibility graph over the main component of an obstacle raster."""
+
+    n: int
+    adj_offsets: np.ndarray  # u64[n+1]
+    adj_ids: np.ndarray  # u32[adj_offsets[n]], ascending per row
+    obst: np.ndarray  # u8[H, W], 1 = obstacle
+    xy: np.ndarray  # i32[n, 2], (x, y) cell of each node
+    name: str = ""
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.adj_offsets[-1])
+
+    @property
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.adj_offsets).astype(np.uint32)
+
+    def row(self, v: int) -> np.ndarray:
+        return self.adj_ids[self.adj_offsets[v]: self.adj_offsets[v + 1]]
+
+
+# ---------------------------------------------------------------- rasters
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(stream)]))
+
+
+def tiny_raster(seed: int, W: int = 32, H: int = 32, cover: float = 0.30,
+                side=(3, 8)) -> np.ndarray:
+    """Rectangles with integer sides in [side] at uniform positions until cover is reached."""
+    rng = _rng(seed, 1)
+    obst = np.zeros((H, W), np.uint8)
+    while obst.mean() < cover:
+        w = int(rng.integers(side[0], side[1] + 1))
+        h = int(rng.integers(side[0], side[1] + 1))
+        x = int(rng.integers(0, W - w + 1))
+        y = int(rng.integers(0, H - h + 1))
+        obst[y:y + h, x:x + w] = 1
+    return obst
+
+
+def _cuts(rng, length: int, street, block, cell_m: float):
+    """Alternating street / block spans along one axis, in cells: list of (b0, b1) blocks."""
+    blocks = []
+    pos = -int(rng.integers(0, max(1, round(block[1] / cell_m))))
+    while pos < length:
+        ws = max(1, round(rng.integers(street[0], street[1] + 1) / cell_m))
+        wb = max(1, round(rng.integers(block[0], block[1] + 1) / cell_m))
+        b0, b1 = pos + ws, pos + ws + wb
+        if b1 > 0 and b0 < length:
+            blocks.append((max(0, b0), min(length, b1)))
+        pos = b1
+    return blocks
+
+
+def urban_raster(seed: int, W: int, H: int, cell_m: float = 1.0, street_m=(8, 20),
+                 block_m=(40, 90), bldg_m=(10, 40), block_fill=0.20, jitter_m=2) -> np.ndarray:
+    """Perturbed street grid with rectangular buildings inside the blocks.
+
+    Streets run the full extent along both axes with widths drawn from street_m;
+    each block edge is jittered by up to jitter_m so street walls are ragged; inside
+    every block, rectangles with sides drawn from bldg_m are dropped at uniform
+    positions until the block's built fraction reaches block_fill.
+    """
+    rng = _rng(seed, 2)
+    obst = np.zeros((H, W), np.uint8)
+    xs = _cuts(rng, W, street_m, block_m, cell_m)
+    ys = _cuts(rng, H, street_m, block_m, cell_m)
+    jit = max(0, round(jitter_m / cell_m))
+    lo_b, hi_b = max(1, round(bldg_m[0] / cell_m)), max(1, round(bldg_m[1] / cell_m))
+    for (y0, y1) in ys:
+        for (x0, x1) in xs:
+            if jit:
+                bx0 = x0 + int(rng.integers(-jit, jit + 1))
+                bx1 = x1 + int(rng.integers(-jit, jit + 1))
+                by0 = y0 + int(rng.integers(-jit, jit + 1))
+                by1 = y1 + int(rng.integers(-jit, jit + 1))
+            else:
+                bx0, bx1, by0, by1 = x0, x1, y0, y1
+            bx0, by0 = max(0, bx0), max(0, by0)
+            bx1, by1 = min(W, bx1), min(H, by1)
+            bw, bh = bx1 - bx0, by1 - by0
+            if bw < 2 or bh < 2:
+                continue
+            blk = np.zeros((bh, bw), np.uint8)
+            tries = 0
+            while blk.mean() < block_fill and tries < 200:
+                tries += 1
+                w = min(bw, int(rng.integers(lo_b, hi_b + 1)))
+                h = min(bh, int(rng.integers(lo_b, hi_b + 1)))
+                x = int(rng.integers(0, bw - w + 1))
+                y = int(rng.integers(0, bh - h + 1))
+                blk[y:y + h, x:x + w] = 1
+            obst[by0:by1, bx0:bx1] |= blk
+    return obst
+
+
+# ---------------------------------------------------------------- graphs
+def component(obst: np.ndarray):
+    """Main 4-connected open component: (node_of_cell[H, W] int32 with -1 elsewhere, xy)."""
+    obst = np.ascontiguousarray(obst, dtype=np.uint8)
+    H, W = obst.shape
+    node_of_cell = np.empty((H, W), np.int32)
+    n = _lib().syn_main_component(_p(obst, ctypes.c_uint8), W, H, _p(node_of_cell, ctypes.c_int32))
+    if n < 0:
+        raise MemoryError("syn_main_component failed")
+    ys, xs = np.nonzero(node_of_cell >= 0)  # row-major order == raster order
+    xy = np.ascontiguousarray(np.stack([xs, ys], axis=1).astype(np.int32))
+    assert xy.shape[0] == n
+    return node_of_cell, xy
+
+
+def graph_from_raster(obst: np.ndarray, name: str = "", params: dict | None = None,
+                      device: str = "cpu") -> Graph:
+    """Visibility graph of the raster's main component (CPU or GPU generator)."""
+    obst = np.ascontiguousarray(obst, dtype=np.uint8)
+    H, W = obst.shape
+    _, xy = component(obst)
+    n = xy.shape[0]
+    if device == "gpu":
+        off, ids = _gpu_adjacency(obst, xy)
+    else:
+        L = _lib()
+        deg = np.empty(n, np.uint64)
+        L.syn_degrees(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
+                      _p(deg, ctypes.c_uint64))
+        off = np.zeros(n + 1, np.uint64)
+        np.cumsum(deg, out=off[1:])
+        ids = np.empty(int(off[-1]), np.uint32)
+        L.syn_fill(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
+                   _p(off, ctypes.c_uint64), _p(ids, ctypes.c_uint32))
+    return Graph(n=n, adj_offsets=off, adj_ids=ids, obst=obst, xy=xy, name=name,
+                 params=dict(params or {}))
+
+
+def visible_pairs(g: Graph, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """CPU visibility rule on explicit node pairs (u8 0/1)."""
+    a = np.ascontiguousarray(a, np.int64)
+    b = np.ascontiguousarray(b, np.int64)
+    out = np.empty(a.shape[0], np.uint8)
+    H, W = g.obst.shape
+    _lib().syn_visible_pairs(_p(g.obst, ctypes.c_uint8), W, H, _p(g.xy, ctypes.c_int32),
+                             _p(a, ctypes.c_int64), _p(b, ctypes.c_int64), a.shape[0],
+                             _p(out, ctypes.c_uint8))
+    return out
+
+
+def sample_degrees(obst: np.ndarray, n_src: int, seed: int = 0):
+    """(n, sampled degrees) of n_src seeded source nodes; for estimating E on big rasters."""
+    obst = np.ascontiguousarray(obst, dtype=np.uint8)
+    H, W = obst.shape
+    _, xy = component(obst)
+    n = xy.shape[0]
+    src = np.sort(_rng(seed, 9).choice(n, size=min(n, n_src), replace=False)).astype(np.int64)
+    deg = np.empty(src.shape[0], np.uint64)
+    _lib().syn_degrees_sample(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
+                              _p(src, ctypes.c_int64), src.shape[0], _p(deg, ctypes.c_uint64))
+    return n, deg
+
+
+# ---------------------------------------------------------------- named workloads
+def tiny(seed: int = 0) -> Graph:
+    """32x32 tiny VGA graph (1 m cells, 3-8 m rectangles, >= 30 % cover)."""
+    return graph_from_raster(tiny_raster(seed), name=f"tiny32-s{seed}",
+                             params=dict(kind="tiny", seed=seed, W=32, H=32))
+
+
+def grid_graph(seed: int, W: int, H: int, cover: float = 0.30, side=(3, 8)) -> Graph:
+    """Tiny-style rectangles on a W x H raster (parity cases between tiny and urban)."""
+    return graph_from_raster(tiny_raster(seed, W, H, cover, side), name=f"rect{W}x{H}-s{seed}",
+                             params=dict(kind="rect", seed=seed, W=W, H=H, cover=cover))
+
+
+def urban(seed: int = 0, device: str = "cpu") -> Graph:
+    """230x230 urban block graph (~42,700 nodes, ~1.4e8 directed edges)."""
+    W, H = URBAN_EXTENT
+    obst = urban_raster(seed, W, H, cell_m=URBAN_CELL_M, **URBAN)
+    return graph_from_raster(obst, name=f"urban230-s{seed}", device=device,
+                             params=dict(kind="urban", seed=seed, W=W, H=H, cell_m=URBAN_CELL_M,
+                                         **URBAN))
+
+
+def city_raster(seed: int = 0) -> np.ndarray:
+    W, H = CITY_EXTENT
+    return urban_raster(seed, W, H, cell_m=URBAN_CELL_M / CITY_SCALE, **URBAN)
+
+
+def city(seed: int = 0, device: str = "gpu") -> Graph:
+    """541x541 city-scale graph (~236,000 nodes, ~4.7e9 directed edges)."""
+    W, H = CITY_EXTENT
+    return graph_from_raster(city_raster(seed), name=f"city541-s{seed}", device=device,
+                             params=dict(kind="city", seed=seed, W=W, H=H, scale=CITY_SCALE,
+                                         **URBAN))
+
+
+# ---------------------------------------------------------------- special graphs
+def from_edges(n: int, edges, name: str = "") -> Graph:
+    """Undirected graph from an edge list (for closed-form cases: paths, stars, cliques)."""
+    nbrs = [set() for _ in range(n)]
+    for a, b in edges:
+        if a != b:
+            nbrs[a].add(b)
+            nbrs[b].add(a)
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum([len(s) for s in nbrs])
+    ids = np.array([v for s in nbrs for v in sorted(s)], np.uint32)
+    return Graph(n=n, adj_offsets=off, adj_ids=ids, obst=np.zeros((1, 1), np.uint8),
+                 xy=np.zeros((n, 2), np.int32), name=name, params=dict(kind="edges"))
+
+
+def path_graph(n: int) -> Graph:
+    return from_edges(n, [(i, i + 1) for i in range(n - 1)], name=f"path{n}")
+
+
+def cycle_graph(n: int) -> Graph:
+    return from_edges(n, [(i, (i + 1) % n) for i in range(n)], name=f"cycle{n}")
+
+
+def star_graph(n: int) -> Graph:
+    return from_edges(n, [(0, i) for i in range(1, n)], name=f"star{n}")
+
+
+def complete_graph(n: int) -> Graph:
+    return from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)], name=f"K{n}")
+
+
+def random_graph(n: int, p_edge: float, seed: int) -> Graph:
+    """Seeded G(n, p) graph (may be disconnected, may have isolated nodes)."""
+    rng = _rng(seed, 3)
+    iu = np.triu_indices(n, 1)
+    keep = rng.random(iu[0].shape[0]) < p_edge
+    return from_edges(n, list(zip(iu[0][keep].tolist(), iu[1][keep].tolist())),
+                      name=f"gnp{n}-{p_edge}-s{seed}")
+
+
+# ---------------------------------------------------------------- GPU generator
+def _gpu_lib():
+    global _GPU_LIB
+    if _GPU_LIB is None:
+        path = gpu_lib_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        L.syng_adjacency.argtypes = [
+            ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
+            ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+            ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_uint64]
+        L.syng_adjacency.restype = ctypes.c_int
+        L.syng_last_error.argtypes = []
+        L.syng_last_error.restype = ctypes.c_char_p
+        _GPU_LIB = L
+    return _GPU_LIB
+
+
+def _gpu_adjacency(obst: np.ndarray, xy: np.ndarray):
+    L = _gpu_lib()
+    H, W = obst.shape
+    n = xy.shape[0]
+    off = np.zeros(n + 1, np.uint64)
+    # pass 1: degrees only (ids == NULL)
+    rc = L.syng_adjacency(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
+                          _p(off, ctypes.c_uint64), None, 0)
+    if rc != 0:
+        raise RuntimeError("GPU visibility generator: " + L.syng_last_error().decode())
+    ids = np.empty(int(off[-1]), np.uint32)
+    rc = L.syng_adjacency(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
+                          _p(off, ctypes.c_uint64), ids.ctypes.data, ids.shape[0])
+    if rc != 0:
+        raise RuntimeError("GPU visibility generator: " + L.syng_last_error().decode())
+    return off, ids

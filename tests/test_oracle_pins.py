@@ -1,0 +1,328 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: published code
+vectors, closed forms, brute-force breadth-first search, statistical laws of the
+estimator.  A plausible slip anywhere in the oracle (a dropped term, a wrong sign,
+index, shift or constant) breaks at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                yield line.split()
+
+
+# ------------------------------------------------------------------ LEB128 (Sec. 3.2)
+def test_leb128_published_vectors():
+    for val, hexb in _rows("leb128_vectors.txt"):
+        v = int(val)
+        assert oracle.uleb_encode(v).hex() == hexb, v
+        assert oracle.uleb_decode(bytes.fromhex(hexb)) == (v, len(hexb) // 2)
+
+
+def test_leb128_round_trip_random():
+    rng = np.random.default_rng(7)
+    vals = (rng.integers(0, 2**32, 2000).tolist() +
+            [2 ** int(k) - 1 for k in rng.integers(0, 65, 500)] + [0, 1, 127, 128, 2**63])
+    for v in vals:
+        enc = oracle.uleb_encode(v)
+        assert len(enc) == max(1, math.ceil(v.bit_length() / 7))
+        assert oracle.uleb_decode(enc) == (v, len(enc))
+
+
+def test_leb128_malformed():
+    assert oracle.uleb_decode(bytes([0x80, 0x80]))[1] == 0  # ends inside a varint
+    assert oracle.uleb_decode(b"")[1] == 0
+    assert oracle.uleb_decode(bytes([0xFF] * 10 + [0x01]))[1] == -1  # more than 64 bits
+    assert oracle.uleb_decode(bytes([0xFF] * 9 + [0x02]))[1] == -1  # bit 64 set
+
+
+def test_row_size_model_of_the_paper():
+    """13,800 one-byte deltas + 133 two-byte jumps ~ 14 KB vs 56 KB as u32 (Sec. 3.2)."""
+    d = {k: int(v) for k, v in _rows("paper_row_model.txt")}
+    ids, cur = [], 5000
+    per_run = d["one_byte_deltas"] // (d["row_jumps"] + 1)
+    for r in range(d["row_jumps"] + 1):
+        for k in range(per_run):
+            ids.append(cur)
+            cur += 1 if k < per_run - 1 else 0
+        cur += d["row_jump_delta"]
+    while len(ids) < d["one_byte_deltas"] + d["row_jumps"]:
+        ids.append(ids[-1] + 1)
+    ids = np.unique(np.array(ids, np.uint32))
+    n = int(ids.max()) + 2
+    adj_off = np.zeros(n + 1, np.uint64)
+    adj_off[n - 1 + 1:] = len(ids)
+    csr = oracle.csr_encode(n, adj_off, ids)
+    nbytes = int(csr.offsets[-1])
+    raw = 4 * len(ids)
+    assert abs(nbytes / 1000 - d["compressed_kb"]) < 0.5
+    assert abs(raw / 1000 - d["uncompressed_kb"]) < 0.5
+    assert round(raw / nbytes) == d["ratio"]
+    assert np.array_equal(oracle.decode_row(csr, n - 1), ids)
+
+
+def test_csr_round_trip_graphs():
+    for g in (synth.tiny(0), synth.grid_graph(4, 48, 40), synth.star_graph(300)):
+        csr = oracle.from_graph(g)
+        assert int(csr.offsets[-1]) == csr.bytes.size
+        assert np.array_equal(csr.degrees, g.degrees)
+        for v in range(0, g.n, max(1, g.n // 97)):
+            assert np.array_equal(oracle.decode_row(csr, v), g.row(v))
+
+
+# ------------------------------------------------------------------ SplitMix64 (Sec. 3.3)
+def test_splitmix64_published_sequence():
+    gamma = 0x9E3779B97F4A7C15
+    for k, out in _rows("splitmix64_seed0.txt"):
+        k = int(k)
+        assert oracle.splitmix64(((k - 1) * gamma) % 2**64) == int(out, 16)
+
+
+def test_insert_index_and_rank():
+    """Index = top p bits of the hash, rank = leading zeros of the rest + 1 (<= 65 - p)."""
+    rng = np.random.default_rng(1)
+    for v in rng.integers(0, 2**40, 300).tolist():
+        for p in (4, 8, 10, 12, 16):
+            seed = int(rng.integers(0, 2**63))
+            j, r = oracle.hll_insert(v, seed, p)
+            h = oracle.splitmix64(v ^ seed)
+            assert j == h >> (64 - p)
+            rest = (h << p) % 2**64
+            lz = 64 - p if rest == 0 else 64 - rest.bit_length()
+            assert r == min(lz, 64 - p) + 1
+            assert 1 <= r <= 65 - p
+
+
+def test_insert_rank_distribution():
+    """P(rank = k) = 2^-k: the geometric law HLL's estimator assumes."""
+    p = 10
+    ranks = np.array([oracle.hll_insert(v, 99, p)[1] for v in range(200000)])
+    for k in range(1, 8):
+        frac = np.mean(ranks == k)
+        assert abs(frac - 2.0 ** -k) < 5 * math.sqrt(2.0 ** -k / ranks.size), k
+    idx = np.array([oracle.hll_insert(v, 99, 4)[0] for v in range(20000)])
+    counts = np.bincount(idx, minlength=16)
+    assert counts.min() > 20000 / 16 * 0.9
+
+
+# ------------------------------------------------------------------ estimator (Sec. 2.3)
+def test_alpha_constants():
+    for p, a in _rows("hll_constants.txt"):
+        assert oracle.hll_alpha(int(p)) == float(a)
+    for p in range(7, 17):
+        m = 2.0 ** p
+        assert oracle.hll_alpha(p) == 0.7213 / (1 + 1.079 / m)
+
+
+@pytest.mark.parametrize("p", [4, 6, 8, 10, 12, 16])
+def test_estimator_closed_forms(p):
+    m = 1 << p
+    regs = np.zeros(m, np.uint8)
+    assert oracle.hll_estimate(regs, p) == 0.0  # empty sketch: m ln(m/m)
+    regs[m // 3] = 5
+    assert oracle.hll_estimate(regs, p) == m * math.log(m / (m - 1))  # one element
+    for k in (1, 3, 7, 65 - p):
+        regs = np.full(m, k, np.uint8)  # no zero register: raw estimate alpha m 2^k
+        assert oracle.hll_estimate(regs, p) == pytest.approx(oracle.hll_alpha(p) * m * 2.0 ** k,
+                                                             rel=1e-15)
+
+
+def test_estimator_linear_counting_switch():
+    p, m = 8, 256
+    # V zeros and the rest at 1: Z = V + (m - V)/2, E = alpha m^2 / Z
+    for V in (1, 10, 100, 200, 255):
+        regs = np.ones(m, np.uint8)
+        regs[:V] = 0
+        E = oracle.hll_alpha(p) * m * m / (V + (m - V) / 2)
+        want = m * math.log(m / V) if E <= 2.5 * m else E
+        assert oracle.hll_estimate(regs, p) == pytest.approx(want, rel=1e-14)
+        assert oracle.hll_raw(regs, p) == (pytest.approx(E, rel=1e-14), V)
+    # large registers with a zero: E > 2.5 m keeps the raw estimate
+    regs = np.full(m, 20, np.uint8)
+    regs[0] = 0
+    E, V = oracle.hll_raw(regs, p)
+    assert V == 1 and E > 2.5 * m
+    assert oracle.hll_estimate(regs, p) == E
+
+
+def test_exact_harmonic_sum():
+    """S = sum 2^-M is formed exactly: a sum whose float accumulation would lose bits."""
+    p, m = 12, 4096
+    regs = np.full(m, 53, np.uint8)
+    regs[0] = 1  # 0.5 + 4095 * 2^-53: a float running sum drops the small terms
+    E, V = oracle.hll_raw(regs, p)
+    exact = 0.5 + 4095 * 2.0 ** -53
+    assert E == (oracle.hll_alpha(p) * m * m) / exact
+
+
+@pytest.mark.parametrize("p", [6, 8, 10])
+def test_estimator_statistics(p):
+    """Raw-regime relative error: mean ~ 0, std ~ 1.04/sqrt(m) (Sec. 2.3)."""
+    m = 1 << p
+    n = 10 * m
+    errs = []
+    for trial in range(150 if p < 10 else 60):
+        regs = np.zeros(m, np.uint8)
+        for v in range(trial * n, (trial + 1) * n):  # a fresh set of n distinct ids per trial
+            j, r = oracle.hll_insert(v, 0, p)
+            if r > regs[j]:
+                regs[j] = r
+        errs.append(oracle.hll_estimate(regs, p) / n - 1)
+    errs = np.array(errs)
+    se = 1.04 / math.sqrt(m)
+    assert abs(errs.mean()) < 4 * se / math.sqrt(len(errs)) + 0.01
+    assert 0.7 * se < errs.std() < 1.35 * se
+
+
+# ------------------------------------------------------------------ HyperBall (Alg. 1)
+def _sum_dist(dist, depth=0):
+    d = dist.astype(np.int64)
+    keep = d > 0 if depth == 0 else (d > 0) & (d <= depth)
+    return np.where(keep, d, 0).sum(axis=1).astype(np.float64)
+
+
+@pytest.mark.parametrize("g", [synth.tiny(0), synth.tiny(5), synth.random_graph(120, 0.03, 2)],
+                         ids=lambda g: g.name)
+def test_exact_counters_give_bfs_distance_sums(g):
+    """Eq. 1: with exact cardinalities the Eq. 3 accumulation equals BFS distance sums."""
+    csr = oracle.from_graph(g)
+    dist = oracle.bfs_all(csr)
+    D = int(dist.max())
+    ex = oracle.hyperball_exact(csr, 0)
+    assert np.array_equal(ex.sum_d, _sum_dist(dist))
+    assert np.array_equal(ex.reach, (dist >= 0).sum(axis=1).astype(float))
+    assert ex.passes == D + 1 and ex.converged
+    for d in (1, 2, 3):
+        exd = oracle.hyperball_exact(csr, d)
+        assert np.array_equal(exd.sum_d, _sum_dist(dist, d))
+        assert exd.passes == min(d, D + 1)
+
+
+@pytest.mark.parametrize("maker,n", [(synth.path_graph, 25), (synth.cycle_graph, 24),
+                                     (synth.cycle_graph, 25), (synth.star_graph, 30),
+                                     (synth.complete_graph, 20)])
+def test_closed_form_distance_sums(maker, n):
+    g = maker(n)
+    ex = oracle.hyperball_exact(oracle.from_graph(g), 0)
+    i = np.arange(n)
+    if maker is synth.path_graph:
+        want = i * (i + 1) / 2 + (n - 1 - i) * (n - i) / 2
+        D = n - 1
+    elif maker is synth.cycle_graph:
+        want = np.full(n, (n * n) // 4)
+        D = n // 2
+    elif maker is synth.star_graph:
+        want = np.where(i == 0, n - 1, 2 * n - 3)
+        D = 2
+    else:
+        want = np.full(n, n - 1)
+        D = 1
+    assert np.array_equal(ex.sum_d, want.astype(float))
+    assert ex.passes == D + 1
+
+
+def test_hll_registers_equal_exact_ball_registers():
+    """Step-t registers of v are the union of the inserts of B(v, t) (Eq. 2 by induction)."""
+    g = synth.tiny(4)
+    csr = oracle.from_graph(g)
+    dist = oracle.bfs_all(csr)
+    full = oracle.hyperball(csr, 8, 0, seed=3)
+    for t in range(1, full.passes + 1):
+        r = oracle.hyperball(csr, 8, t, seed=3)
+        assert r.passes == t
+        for v in range(g.n):
+            assert np.array_equal(r.registers[v], oracle.ball_registers(dist[v], t, 8, 3)), (t, v)
+
+
+def test_registers_monotone_and_fixed_after_diameter():
+    g = synth.tiny(6)
+    csr = oracle.from_graph(g)
+    D = int(oracle.bfs_all(csr).max())
+    prev = oracle.initial_registers(g.n, 10, 0)
+    for t in range(1, D + 3):
+        r = oracle.hyperball(csr, 10, t, seed=0)
+        if r.passes < t:
+            break
+        assert (r.registers >= prev).all()
+        if t > D:
+            assert np.array_equal(r.registers, prev)
+        prev = r.registers
+
+
+def test_union_order_free():
+    """Max-union is commutative and idempotent: reversed rows and doubled neighbours agree."""
+    g = synth.tiny(7)
+    csr = oracle.from_graph(g)
+    n = g.n
+    perm = np.arange(n)[::-1].copy()  # relabel v -> n-1-v (rows decode in reversed order)
+    inv = np.argsort(perm)
+    rows = [np.sort(perm[g.row(int(inv[v]))]) for v in range(n)]
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    g2 = synth.Graph(n, off, np.concatenate(rows).astype(np.uint32), g.obst, g.xy)
+    a = oracle.hyperball(csr, 8, 3, seed=11)
+    # relabelling changes the hashes, so compare the multiset of exact ball sizes instead
+    ex1 = oracle.hyperball_exact(csr, 3)
+    ex2 = oracle.hyperball_exact(oracle.from_graph(g2), 3)
+    assert np.array_equal(ex1.reach, ex2.reach[perm])
+    assert a.passes == 3
+
+
+def test_complete_graph_converges_in_two_passes():
+    g = synth.complete_graph(64)
+    for p in (4, 8, 12):
+        r = oracle.hyperball(oracle.from_graph(g), p, 0, seed=1)
+        assert r.passes == 2 and r.converged
+        assert (r.registers == r.registers[0]).all()
+
+
+def test_sampled_balls_match_full_iteration():
+    """Multi-source BFS balls reproduce the full iteration's registers, reach and sums."""
+    g = synth.grid_graph(2, 40, 40)
+    csr = oracle.from_graph(g)
+    T = 3
+    full = oracle.hyperball(csr, 10, T, seed=5)
+    src = np.arange(0, g.n, 37)
+    regs, reach, sum_d, _ = oracle.sampled_hyperball(csr, src, T, 10, seed=5)
+    assert np.array_equal(regs, full.registers[src])
+    assert np.array_equal(reach, full.reach[src])
+    assert np.array_equal(sum_d, full.sum_d[src])
+
+
+def test_hll_distance_sums_within_error_bound():
+    """HLL reach and distance sums track exact BFS on the 1.04/sqrt(m) error scale.
+
+    All nodes of one run share most of their hashed elements, so their errors are
+    correlated and the scale is checked over independent hash seeds.  The final
+    reach estimates the component size with the HLL error (the raw estimator carries
+    a known positive bias just above the 2.5 m switch, so 1.5 SE is allowed); the
+    Eq. 3 sum T c_T - sum_{t<T} c_t weights the final estimate by T, so its relative
+    error is larger by about T / MD and is held to 2.5 SE.
+    """
+    g = synth.grid_graph(1, 64, 64)
+    csr = oracle.from_graph(g)
+    dist = oracle.bfs_all(csr)
+    want = _sum_dist(dist)
+    for p in (8, 10):
+        se = 1.04 / math.sqrt(1 << p)
+        med, reach_err = [], []
+        for seed in range(12):
+            r = oracle.hyperball(csr, p, 0, seed=seed * 7919 + 1)
+            med.append(np.median(np.abs(r.sum_d / want - 1)))
+            reach_err.append(r.reach[0] / g.n - 1)
+        assert math.sqrt(np.mean(np.square(reach_err))) < 1.5 * se
+        assert np.mean(med) < 2.5 * se
