@@ -1,0 +1,153 @@
+/*
+ * hb.h -- HyperBall over a LEB128 delta-compressed CSR on one AMD Instinct GPU
+ * (gfx950).  Plain C ABI: host pointers and sizes in, host arrays out; no
+ * exceptions or aborts cross it.  Every call returns an hb_status; negative
+ * values leave a message for hb_last_error().
+ *
+ * The method is HyperBall (Boldi & Vigna) as the paper "City-Scale Visibility
+ * Graph Analysis via GPU-Accelerated HyperBall" applies it to visibility
+ * graphs: one HyperLogLog counter of 2^p registers per node, the register-wise
+ * max-union of each node's counter with its neighbours' counters per step
+ * (Eq. 2), the HLL estimate of every counter after each step, and the
+ * distance sum accumulated from the growth of the estimates (Eq. 3), stopped
+ * by a depth limit or when no estimate grows by more than 0.5 (Alg. 1).
+ *
+ * Register format: one uint8 register per byte (values 0..65-p), node-major
+ * rows of 2^p bytes.  Hash: SplitMix64 of (node id XOR hash_seed); register
+ * index = top p bits; value = leading zeros of the remaining bits + 1.
+ * Estimator: HLL raw estimate with the alpha_m constants of Flajolet et al.
+ * (2007), linear counting when the raw estimate is <= 2.5 m and a register is
+ * zero, computed in FP64 from an exactly summed harmonic mean.
+ *
+ * Threading: calls are serialised by the library; results of one call are
+ * complete when it returns.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hb_status;
+#define HB_OK 0
+#define HB_PENDING 1     /* not an error: the request is still running */
+#define HB_EINVAL (-1)   /* bad argument (p outside [4,16], n = 0, NULL) */
+#define HB_ECORRUPT (-2) /* the compressed CSR failed validation */
+#define HB_ENOMEM (-3)   /* host or device allocation failed */
+#define HB_EDEVICE (-4)  /* a HIP runtime call failed, or no GPU */
+#define HB_ENOTFOUND (-5)
+#define HB_EBUSY (-6)
+
+#define HB_P_MIN 4
+#define HB_P_MAX 16
+
+/* Opaque device-resident graph. */
+typedef struct hb_graph hb_graph;
+
+/*
+ * Compressed CSR (Sec. 3.2 of the paper): for node v the bytes
+ * bytes[offsets[v] .. offsets[v+1]) hold degrees[v] unsigned LEB128 varints
+ * (7-bit groups, least significant first, high bit = more bytes follow): the
+ * first is the smallest neighbour id, each later one the positive difference
+ * from the previous id, so the row lists the neighbours in increasing order.
+ * All pointers are host memory, owned by the caller, read only during the
+ * call.
+ */
+typedef struct {
+    uint32_t n;                /* nodes, >= 1 */
+    uint64_t n_edges;          /* directed edges = sum of degrees */
+    const uint64_t *offsets;   /* n + 1 byte offsets, offsets[0] = 0 */
+    const uint32_t *degrees;   /* n neighbour counts */
+    const uint8_t *bytes;      /* offsets[n] bytes (may be NULL if offsets[n] = 0) */
+    const uint32_t *comp_size; /* n exact component sizes N_v, or NULL = all n */
+} hb_csr;
+
+/*
+ * Results of one run.  Array pointers are caller-owned host buffers of n
+ * doubles (n * 2^p bytes for registers), or NULL to skip that output.
+ * reach[v] is the final estimate of |B(v, T)|, sum_d[v] the Eq. 3 sum and
+ * mean_depth[v] = sum_d[v] / (N_v - 1) (NaN when N_v < 2), as Sec. 3.3
+ * defines Visual Mean Depth with the exact component size.
+ */
+typedef struct {
+    double *reach;
+    double *sum_d;
+    double *mean_depth;
+    uint8_t *registers;
+    uint32_t passes;       /* union steps run (T) */
+    uint32_t converged;    /* 1 if step T changed no estimate by more than 0.5 */
+    double c0;             /* estimate of a one-element counter */
+    uint64_t edge_unions;  /* passes * n_edges */
+    double init_ms;        /* device time of the initialisation kernel */
+    double iter_ms;        /* device time summed over the passes union kernels */
+    double run_ms;         /* device time from init start to the last union end */
+    uint64_t t_start_ns;   /* host CLOCK_MONOTONIC at call entry */
+    uint64_t t_end_ns;     /* host CLOCK_MONOTONIC when results were written */
+} hb_result;
+
+/* Library version string. */
+const char *hb_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hb_last_error(void);
+
+/*
+ * Number of visible GPUs (0 if none).  Host-only callers may skip it; every
+ * device call returns HB_EDEVICE when no GPU is present.
+ */
+hb_status hb_device_count(int32_t *count);
+
+/*
+ * Encode a sorted adjacency list into the compressed CSR of Sec. 3.2.
+ * adj_offsets: n+1 entries indexing adj_ids; each row strictly increasing,
+ * ids < n, no self loops (HB_EINVAL otherwise).  Two-phase: call with
+ * bytes == NULL to get *bytes_len (and fill offsets/degrees), then again with
+ * a buffer of at least *bytes_len bytes in bytes_cap.  Host-only.
+ */
+hb_status hb_csr_encode(uint32_t n, const uint64_t *adj_offsets, const uint32_t *adj_ids,
+                        uint64_t *offsets, uint32_t *degrees, uint8_t *bytes, uint64_t bytes_cap,
+                        uint64_t *bytes_len);
+
+/*
+ * Check a compressed CSR without touching the GPU.  HB_ECORRUPT when: offsets
+ * are not monotone or offsets[0] != 0; a row ends inside a varint; a varint
+ * is longer than 5 bytes or exceeds 32 bits; a decoded id is >= n, repeats,
+ * decreases or equals the row's own node; a row's varint count differs from
+ * degrees[v]; or the degree sum differs from n_edges.  *bad_node (optional)
+ * receives the first failing node (or n for a global mismatch).  Host-only.
+ */
+hb_status hb_csr_validate(const hb_csr *csr, uint32_t *bad_node);
+
+/*
+ * Validate csr (as hb_csr_validate) and copy it into device memory.  The
+ * caller may free its arrays when this returns.  *out is library-owned until
+ * hb_graph_free.
+ */
+hb_status hb_graph_load(const hb_csr *csr, hb_graph **out);
+
+/* Release a graph and its device memory. */
+hb_status hb_graph_free(hb_graph *g);
+
+/* Nodes, directed edges and compressed bytes of a loaded graph. */
+hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint64_t *n_bytes);
+
+/*
+ * Run HyperBall (Alg. 1) on a loaded graph: insert every node v into its own
+ * counter, then for t = 1, 2, ...: union (Eq. 2), estimate, accumulate (Eq. 3),
+ * stop after step t when no estimate grew by more than 0.5 or t ==
+ * depth_limit (0 = no limit).  Blocking.  p in [4, 16].  Device memory for
+ * two counter buffers (2 n 2^p bytes) and 16 n bytes of FP64 state is held by
+ * the graph between runs and released by hb_graph_free.  The registers of a
+ * run with depth_limit t equal the step-t registers of any longer run.
+ */
+hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                 hb_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

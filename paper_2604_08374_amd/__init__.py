@@ -1,0 +1,240 @@
+"""Python binding for libhb.so: HyperBall over a LEB128 delta-compressed CSR on gfx950.
+
+Argument marshalling only (ctypes): every step of the computation runs in the
+library's HIP kernels and C++ host runtime.  The names mirror ``include/hb.h``.
+There is no fallback: if ``libhb.so`` is not built, importing works but every
+call raises ``HBError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "HBError", "Result", "Graph", "lib_path", "version", "device_count", "csr_encode",
+    "csr_validate", "graph_load", "run", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
+    "HB_ENOMEM", "HB_EDEVICE", "HB_ENOTFOUND", "HB_EBUSY",
+]
+
+HB_OK, HB_PENDING = 0, 1
+HB_EINVAL, HB_ECORRUPT, HB_ENOMEM, HB_EDEVICE, HB_ENOTFOUND, HB_EBUSY = -1, -2, -3, -4, -5, -6
+P_MIN, P_MAX = 4, 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+u8p = ctypes.POINTER(ctypes.c_uint8)
+u32p = ctypes.POINTER(ctypes.c_uint32)
+u64p = ctypes.POINTER(ctypes.c_uint64)
+dblp = ctypes.POINTER(ctypes.c_double)
+
+
+class HBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("offsets", u64p),
+                ("degrees", u32p), ("bytes", u8p), ("comp_size", u32p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("reach", dblp), ("sum_d", dblp), ("mean_depth", dblp), ("registers", u8p),
+                ("passes", ctypes.c_uint32), ("converged", ctypes.c_uint32),
+                ("c0", ctypes.c_double), ("edge_unions", ctypes.c_uint64),
+                ("init_ms", ctypes.c_double), ("iter_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("t_start_ns", ctypes.c_uint64),
+                ("t_end_ns", ctypes.c_uint64)]
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libhb.so")
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise HBError(HB_EDEVICE, f"{path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        st = ctypes.c_int32
+        L.hb_version.argtypes = []
+        L.hb_version.restype = ctypes.c_char_p
+        L.hb_last_error.argtypes = []
+        L.hb_last_error.restype = ctypes.c_char_p
+        L.hb_device_count.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        L.hb_device_count.restype = st
+        L.hb_csr_encode.argtypes = [ctypes.c_uint32, u64p, u32p, u64p, u32p, u8p, ctypes.c_uint64,
+                                    u64p]
+        L.hb_csr_encode.restype = st
+        L.hb_csr_validate.argtypes = [ctypes.POINTER(_CSR), u32p]
+        L.hb_csr_validate.restype = st
+        L.hb_graph_load.argtypes = [ctypes.POINTER(_CSR), ctypes.POINTER(ctypes.c_void_p)]
+        L.hb_graph_load.restype = st
+        L.hb_graph_free.argtypes = [ctypes.c_void_p]
+        L.hb_graph_free.restype = st
+        L.hb_graph_info.argtypes = [ctypes.c_void_p, u32p, u64p, u64p]
+        L.hb_graph_info.restype = st
+        L.hb_run.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                             ctypes.POINTER(_Result)]
+        L.hb_run.restype = st
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise HBError(status, _lib().hb_last_error().decode(errors="replace"))
+    return status
+
+
+def _ptr(a: np.ndarray | None, ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def version() -> str:
+    return _lib().hb_version().decode()
+
+
+def device_count() -> int:
+    c = ctypes.c_int32(0)
+    _check(_lib().hb_device_count(ctypes.byref(c)))
+    return int(c.value)
+
+
+def csr_encode(adj_offsets: np.ndarray, adj_ids: np.ndarray):
+    """Sorted adjacency -> (offsets u64[n+1], degrees u32[n], bytes u8[]) via hb_csr_encode."""
+    adj_offsets = np.ascontiguousarray(adj_offsets, np.uint64)
+    adj_ids = np.ascontiguousarray(adj_ids, np.uint32)
+    n = adj_offsets.shape[0] - 1
+    offsets = np.zeros(n + 1, np.uint64)
+    degrees = np.zeros(max(n, 1), np.uint32)[:n]
+    blen = ctypes.c_uint64(0)
+    L = _lib()
+    ids_p = _ptr(adj_ids, ctypes.c_uint32) if adj_ids.size else None
+    _check(L.hb_csr_encode(n, _ptr(adj_offsets, ctypes.c_uint64), ids_p,
+                           _ptr(offsets, ctypes.c_uint64), _ptr(degrees, ctypes.c_uint32), None, 0,
+                           ctypes.byref(blen)))
+    data = np.zeros(max(1, int(blen.value)), np.uint8)
+    _check(L.hb_csr_encode(n, _ptr(adj_offsets, ctypes.c_uint64), ids_p,
+                           _ptr(offsets, ctypes.c_uint64), _ptr(degrees, ctypes.c_uint32),
+                           _ptr(data, ctypes.c_uint8), data.shape[0], ctypes.byref(blen)))
+    return offsets, degrees, data[:int(blen.value)]
+
+
+def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None):
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    degrees = np.ascontiguousarray(degrees, np.uint32)
+    data = np.ascontiguousarray(data, np.uint8)
+    n = degrees.shape[0]
+    if offsets.shape[0] != n + 1:
+        raise HBError(HB_EINVAL, "offsets must have n + 1 entries")
+    keep = [offsets, degrees, data]
+    c = _CSR()
+    c.n = n
+    c.n_edges = int(degrees.sum(dtype=np.uint64)) if n_edges is None else int(n_edges)
+    c.offsets = _ptr(offsets, ctypes.c_uint64)
+    c.degrees = _ptr(degrees, ctypes.c_uint32)
+    c.bytes = _ptr(data, ctypes.c_uint8) if data.size else None
+    if comp_size is not None:
+        comp_size = np.ascontiguousarray(comp_size, np.uint32)
+        keep.append(comp_size)
+        c.comp_size = _ptr(comp_size, ctypes.c_uint32)
+    else:
+        c.comp_size = None
+    return c, keep
+
+
+def csr_validate(offsets, degrees, data, n_edges=None):
+    """(status, bad_node) from hb_csr_validate (no exception on HB_ECORRUPT)."""
+    c, keep = _make_csr(offsets, degrees, data, n_edges=n_edges)
+    bad = ctypes.c_uint32(0)
+    st = _lib().hb_csr_validate(ctypes.byref(c), ctypes.byref(bad))
+    del keep
+    if st not in (HB_OK, HB_ECORRUPT):
+        _check(st)
+    return int(st), int(bad.value)
+
+
+@dataclass
+class Result:
+    reach: np.ndarray | None
+    sum_d: np.ndarray | None
+    mean_depth: np.ndarray | None
+    registers: np.ndarray | None
+    passes: int
+    converged: bool
+    c0: float
+    edge_unions: int
+    init_ms: float
+    iter_ms: float
+    run_ms: float
+    t_start_ns: int
+    t_end_ns: int
+
+
+class Graph:
+    """A compressed CSR resident in device memory (hb_graph)."""
+
+    def __init__(self, offsets, degrees, data, comp_size=None, n_edges=None):
+        c, keep = _make_csr(offsets, degrees, data, comp_size, n_edges)
+        h = ctypes.c_void_p()
+        _check(_lib().hb_graph_load(ctypes.byref(c), ctypes.byref(h)))
+        del keep
+        self._h = h
+        n, e, b = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib().hb_graph_info(h, ctypes.byref(n), ctypes.byref(e), ctypes.byref(b)))
+        self.n, self.n_edges, self.n_bytes = int(n.value), int(e.value), int(b.value)
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_lib().hb_graph_free(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
+            outputs: bool = True) -> Result:
+        """hb_run: HyperBall with precision p; depth_limit 0 = until convergence."""
+        if self._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        n = self.n
+        reach = np.empty(n, np.float64) if outputs else None
+        sum_d = np.empty(n, np.float64) if outputs else None
+        md = np.empty(n, np.float64) if outputs else None
+        regs = np.empty((n, 1 << p), np.uint8) if (registers and P_MIN <= p <= P_MAX) else None
+        r = _Result()
+        r.reach = _ptr(reach, ctypes.c_double)
+        r.sum_d = _ptr(sum_d, ctypes.c_double)
+        r.mean_depth = _ptr(md, ctypes.c_double)
+        r.registers = _ptr(regs, ctypes.c_uint8)
+        _check(_lib().hb_run(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(r)))
+        return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
+                      int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.run_ms),
+                      int(r.t_start_ns), int(r.t_end_ns))
+
+
+def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:
+    return Graph(offsets, degrees, data, comp_size, n_edges)
+
+
+def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False) -> Result:
+    return g.run(p, depth_limit, seed, registers)

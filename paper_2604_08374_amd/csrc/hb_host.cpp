@@ -1,0 +1,436 @@
+// Host runtime behind include/hb.h: CSR encoding and validation (host only),
+// device-resident graphs, and the HyperBall run driver (Alg. 1's loop: init,
+// one fused union/estimate/accumulate launch per step, a 4-byte flag read
+// back after each step to decide whether to stop).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hb.h"
+#include "hb_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_dev_mu;  // serialises every call that touches the GPU
+
+hb_status fail(hb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hb_status hip_fail(hipError_t e, const char *what) {
+    return fail(HB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HB_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+uint64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+unsigned host_threads() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 1;
+    return std::min(h, 16u);
+}
+
+// Run f(lo, hi) over [0, n) split into contiguous ranges, one per thread.
+template <class F>
+void parallel_ranges(uint64_t n, F f) {
+    const unsigned nt = (unsigned)std::min<uint64_t>(host_threads(), std::max<uint64_t>(n / 1024, 1));
+    if (nt <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < nt; ++i) {
+        const uint64_t lo = n * i / nt, hi = n * (i + 1) / nt;
+        th.emplace_back([=] { f(lo, hi); });
+    }
+    for (auto &t : th) t.join();
+}
+
+int uleb_size(uint32_t v) {
+    int k = 1;
+    while (v >= 0x80u) {
+        v >>= 7;
+        ++k;
+    }
+    return k;
+}
+
+uint8_t *uleb_put(uint32_t v, uint8_t *out) {
+    while (v >= 0x80u) {
+        *out++ = (uint8_t)(v | 0x80u);
+        v >>= 7;
+    }
+    *out++ = (uint8_t)v;
+    return out;
+}
+
+// Check one compressed row; returns true if valid.
+bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32_t degree) {
+    uint64_t prev = 0;
+    uint32_t count = 0;
+    while (p < end) {
+        uint32_t val = 0;
+        int k = 0;
+        for (;;) {
+            if (p >= end || k == 5) return false;  // truncated, or longer than 5 bytes
+            const uint8_t b = *p++;
+            if (k == 4 && (b & 0xF0u)) return false;  // beyond 32 bits
+            val |= (uint32_t)(b & 0x7Fu) << (7 * k);
+            ++k;
+            if (!(b & 0x80u)) break;
+        }
+        uint64_t id;
+        if (count == 0) {
+            id = val;
+        } else {
+            if (val == 0) return false;  // repeated id
+            id = prev + val;
+        }
+        if (id >= n || id == v) return false;
+        prev = id;
+        if (++count > degree) return false;
+    }
+    return count == degree;
+}
+
+}  // namespace
+
+struct hb_graph {
+    uint32_t n = 0;
+    uint64_t n_edges = 0, n_bytes = 0;
+    int device = 0;
+    std::vector<uint32_t> comp_size;  // empty: one component of n
+    uint8_t *d_bytes = nullptr;
+    uint64_t *d_offsets = nullptr;
+    // run state, kept between runs
+    uint8_t *d_cnt[2] = {nullptr, nullptr};
+    uint64_t cnt_bytes = 0;
+    double *d_cprev = nullptr, *d_sumd = nullptr;
+    uint32_t *d_flags = nullptr;
+    uint64_t n_flags = 0;
+    uint32_t *h_flag = nullptr;  // pinned
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+void graph_release(hb_graph *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    (void)hipFree(g->d_bytes);
+    (void)hipFree(g->d_offsets);
+    (void)hipFree(g->d_cnt[0]);
+    (void)hipFree(g->d_cnt[1]);
+    (void)hipFree(g->d_cprev);
+    (void)hipFree(g->d_sumd);
+    (void)hipFree(g->d_flags);
+    if (g->h_flag) (void)hipHostFree(g->h_flag);
+    for (auto &e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+hb_status have_device() {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(HB_EDEVICE, "no GPU available");
+    return HB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hb_version(void) { return "hb 0.1.0 (gfx950)"; }
+
+const char *hb_last_error(void) { return g_err.c_str(); }
+
+hb_status hb_device_count(int32_t *count) {
+    if (!count) return fail(HB_EINVAL, "count is NULL");
+    int c = 0;
+    if (hipGetDeviceCount(&c) != hipSuccess) c = 0;
+    *count = c;
+    return HB_OK;
+}
+
+hb_status hb_csr_encode(uint32_t n, const uint64_t *adj_offsets, const uint32_t *adj_ids,
+                        uint64_t *offsets, uint32_t *degrees, uint8_t *bytes, uint64_t bytes_cap,
+                        uint64_t *bytes_len) {
+    if (n == 0) return fail(HB_EINVAL, "n must be >= 1");
+    if (!adj_offsets || !offsets || !degrees || !bytes_len)
+        return fail(HB_EINVAL, "NULL argument");
+    if (adj_offsets[n] > 0 && !adj_ids) return fail(HB_EINVAL, "adj_ids is NULL");
+    if (adj_offsets[0] != 0) return fail(HB_EINVAL, "adj_offsets[0] != 0");
+    std::vector<uint64_t> rowb(n);
+    std::atomic<uint32_t> bad{UINT32_MAX};
+    parallel_ranges(n, [&](uint64_t lo, uint64_t hi) {
+        for (uint64_t v = lo; v < hi; ++v) {
+            const uint64_t a = adj_offsets[v], b = adj_offsets[v + 1];
+            if (b < a) {
+                bad = std::min<uint32_t>(bad, (uint32_t)v);
+                return;
+            }
+            uint64_t nb = 0;
+            uint32_t prev = 0;
+            for (uint64_t k = a; k < b; ++k) {
+                const uint32_t id = adj_ids[k];
+                if (id >= n || id == v || (k > a && id <= prev)) {
+                    bad = std::min<uint32_t>(bad, (uint32_t)v);
+                    return;
+                }
+                nb += (uint64_t)uleb_size(k == a ? id : id - prev);
+                prev = id;
+            }
+            rowb[v] = nb;
+            degrees[v] = (uint32_t)(b - a);
+        }
+    });
+    if (bad != UINT32_MAX)
+        return fail(HB_EINVAL, "adjacency row %u is not strictly increasing within [0, n) "
+                               "without a self loop", (unsigned)bad.load());
+    offsets[0] = 0;
+    for (uint32_t v = 0; v < n; ++v) offsets[v + 1] = offsets[v] + rowb[v];
+    *bytes_len = offsets[n];
+    if (!bytes) return HB_OK;
+    if (bytes_cap < offsets[n])
+        return fail(HB_EINVAL, "bytes_cap %llu < %llu", (unsigned long long)bytes_cap,
+                    (unsigned long long)offsets[n]);
+    parallel_ranges(n, [&](uint64_t lo, uint64_t hi) {
+        for (uint64_t v = lo; v < hi; ++v) {
+            uint8_t *out = bytes + offsets[v];
+            uint32_t prev = 0;
+            for (uint64_t k = adj_offsets[v]; k < adj_offsets[v + 1]; ++k) {
+                const uint32_t id = adj_ids[k];
+                out = uleb_put(k == adj_offsets[v] ? id : id - prev, out);
+                prev = id;
+            }
+        }
+    });
+    return HB_OK;
+}
+
+hb_status hb_csr_validate(const hb_csr *csr, uint32_t *bad_node) {
+    if (bad_node) *bad_node = 0;
+    if (!csr) return fail(HB_EINVAL, "csr is NULL");
+    const uint32_t n = csr->n;
+    if (n == 0) return fail(HB_EINVAL, "n must be >= 1");
+    if (!csr->offsets || !csr->degrees) return fail(HB_EINVAL, "offsets/degrees NULL");
+    if (csr->offsets[0] != 0) {
+        if (bad_node) *bad_node = 0;
+        return fail(HB_ECORRUPT, "offsets[0] != 0");
+    }
+    if (csr->offsets[n] > 0 && !csr->bytes) return fail(HB_EINVAL, "bytes is NULL");
+    std::atomic<uint32_t> bad{UINT32_MAX};
+    std::atomic<uint64_t> deg_sum{0};
+    parallel_ranges(n, [&](uint64_t lo, uint64_t hi) {
+        uint64_t s = 0;
+        for (uint64_t v = lo; v < hi; ++v) {
+            const uint64_t a = csr->offsets[v], b = csr->offsets[v + 1];
+            s += csr->degrees[v];
+            if (b < a || !row_ok(csr->bytes + a, csr->bytes + b, (uint32_t)v, n, csr->degrees[v])) {
+                uint32_t cur = bad.load();
+                while ((uint32_t)v < cur && !bad.compare_exchange_weak(cur, (uint32_t)v)) {
+                }
+                return;
+            }
+        }
+        deg_sum += s;
+    });
+    if (bad != UINT32_MAX) {
+        if (bad_node) *bad_node = bad;
+        return fail(HB_ECORRUPT, "row %u of the compressed CSR is malformed", (unsigned)bad.load());
+    }
+    if (deg_sum != csr->n_edges) {
+        if (bad_node) *bad_node = n;
+        return fail(HB_ECORRUPT, "degree sum %llu != n_edges %llu",
+                    (unsigned long long)deg_sum.load(), (unsigned long long)csr->n_edges);
+    }
+    return HB_OK;
+}
+
+hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
+    if (!out) return fail(HB_EINVAL, "out is NULL");
+    *out = nullptr;
+    hb_status st = hb_csr_validate(csr, nullptr);
+    if (st != HB_OK) return st;
+    if (csr->comp_size)
+        for (uint32_t v = 0; v < csr->n; ++v)
+            if (csr->comp_size[v] == 0 || csr->comp_size[v] > csr->n)
+                return fail(HB_EINVAL, "comp_size[%u] outside [1, n]", v);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((st = have_device()) != HB_OK) return st;
+    hb_graph *g = new (std::nothrow) hb_graph;
+    if (!g) return fail(HB_ENOMEM, "host allocation failed");
+    g->n = csr->n;
+    g->n_edges = csr->n_edges;
+    g->n_bytes = csr->offsets[csr->n];
+    (void)hipGetDevice(&g->device);
+    if (csr->comp_size) g->comp_size.assign(csr->comp_size, csr->comp_size + csr->n);
+    auto bail = [&](hipError_t e, const char *what) {
+        graph_release(g);
+        if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "%s: out of device memory", what);
+        return hip_fail(e, what);
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(e, "hipStreamCreate");
+    for (auto &ev : g->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return bail(e, "hipEventCreate");
+    if ((e = hipHostMalloc((void **)&g->h_flag, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipMalloc(&g->d_bytes, std::max<uint64_t>(g->n_bytes, 16))) != hipSuccess)
+        return bail(e, "hipMalloc(bytes)");
+    if ((e = hipMalloc(&g->d_offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1))) != hipSuccess)
+        return bail(e, "hipMalloc(offsets)");
+    if ((e = hipMalloc(&g->d_cprev, sizeof(double) * g->n)) != hipSuccess)
+        return bail(e, "hipMalloc(c_prev)");
+    if ((e = hipMalloc(&g->d_sumd, sizeof(double) * g->n)) != hipSuccess)
+        return bail(e, "hipMalloc(sum_d)");
+    g->n_flags = (uint64_t)g->n + 2;
+    if ((e = hipMalloc(&g->d_flags, sizeof(uint32_t) * g->n_flags)) != hipSuccess)
+        return bail(e, "hipMalloc(flags)");
+    if (g->n_bytes &&
+        (e = hipMemcpy(g->d_bytes, csr->bytes, g->n_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(bytes)");
+    if ((e = hipMemcpy(g->d_offsets, csr->offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(offsets)");
+    *out = g;
+    return HB_OK;
+}
+
+hb_status hb_graph_free(hb_graph *g) {
+    if (!g) return fail(HB_EINVAL, "graph is NULL");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    graph_release(g);
+    return HB_OK;
+}
+
+hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint64_t *n_bytes) {
+    if (!g) return fail(HB_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (n_edges) *n_edges = g->n_edges;
+    if (n_bytes) *n_bytes = g->n_bytes;
+    return HB_OK;
+}
+
+hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                 hb_result *out) {
+    const uint64_t t_start = now_ns();
+    if (!g || !out) return fail(HB_EINVAL, "NULL argument");
+    if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    HB_HIP(hipSetDevice(g->device));
+    const uint32_t n = g->n;
+    const uint64_t m = 1ull << p;
+    const uint64_t need = (uint64_t)n * m;
+    if (g->cnt_bytes < need) {
+        (void)hipFree(g->d_cnt[0]);
+        (void)hipFree(g->d_cnt[1]);
+        g->d_cnt[0] = g->d_cnt[1] = nullptr;
+        g->cnt_bytes = 0;
+        hipError_t e = hipMalloc(&g->d_cnt[0], need);
+        if (e == hipSuccess) e = hipMalloc(&g->d_cnt[1], need);
+        if (e != hipSuccess) {
+            (void)hipFree(g->d_cnt[0]);
+            g->d_cnt[0] = nullptr;
+            if (e == hipErrorOutOfMemory)
+                return fail(HB_ENOMEM, "counters need 2 x %llu bytes", (unsigned long long)need);
+            return hip_fail(e, "hipMalloc(counters)");
+        }
+        g->cnt_bytes = need;
+    }
+    hipStream_t s = g->stream;
+    uint8_t *cur = g->d_cnt[0], *next = g->d_cnt[1];
+
+    HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
+    HB_HIP(hipEventRecord(g->ev[0], s));
+    HB_HIP(hbk::launch_init((int)p, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
+    HB_HIP(hipEventRecord(g->ev[1], s));
+
+    double iter_ms = 0.0;
+    uint32_t t = 0, converged = 0;
+    for (;;) {
+        ++t;
+        HB_HIP(hipEventRecord(g->ev[2], s));
+        HB_HIP(hbk::launch_union((int)p, g->d_bytes, g->d_offsets, cur, next, g->d_cprev,
+                                 g->d_sumd, g->d_flags + t, n, t, s));
+        HB_HIP(hipEventRecord(g->ev[3], s));
+        HB_HIP(hipMemcpyAsync(g->h_flag, g->d_flags + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HB_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HB_HIP(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
+        iter_ms += ms;
+        if (*g->h_flag == 0u) {
+            converged = 1;
+            break;
+        }
+        if (depth_limit != 0 && t == depth_limit) break;
+        if ((uint64_t)t + 1 >= g->n_flags) break;  // registers are fixed after D <= n - 1 steps
+        std::swap(cur, next);
+    }
+    float init_ms = 0.f, run_ms = 0.f;
+    HB_HIP(hipEventElapsedTime(&init_ms, g->ev[0], g->ev[1]));
+    HB_HIP(hipEventElapsedTime(&run_ms, g->ev[0], g->ev[3]));
+
+    if (out->reach)
+        HB_HIP(hipMemcpy(out->reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (out->sum_d || out->mean_depth) {
+        std::vector<double> tmp;
+        double *sd = out->sum_d;
+        if (!sd) {
+            tmp.resize(n);
+            sd = tmp.data();
+        }
+        HB_HIP(hipMemcpy(sd, g->d_sumd, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (out->mean_depth)
+            for (uint32_t v = 0; v < n; ++v) {
+                const double nv = g->comp_size.empty() ? (double)n : (double)g->comp_size[v];
+                out->mean_depth[v] = nv >= 2.0 ? sd[v] / (nv - 1.0) : NAN;
+            }
+    }
+    if (out->registers)
+        HB_HIP(hipMemcpy(out->registers, next, need, hipMemcpyDeviceToHost));
+    const double md = (double)m;
+    out->passes = t;
+    out->converged = converged;
+    out->c0 = md * std::log(md / (md - 1.0));
+    out->edge_unions = (uint64_t)t * g->n_edges;
+    out->init_ms = init_ms;
+    out->iter_ms = iter_ms;
+    out->run_ms = run_ms;
+    out->t_start_ns = t_start;
+    out->t_end_ns = now_ns();
+    return HB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Internal interface between the host runtime (hb_host.cpp) and the gfx950
+// kernels (hb_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hbk {
+
+// Counter layout and launch shape chosen for precision p (m = 2^p bytes per
+// counter, node-major rows).
+struct LaunchShape {
+    uint32_t waves_per_node;  // waves sharing one counter (p >= 13)
+    uint32_t nodes_per_block; // nodes handled by one workgroup
+    uint32_t threads;         // workgroup size
+};
+LaunchShape shape_for(int p);
+
+// Zero every counter, insert node v into its own counter (SplitMix64 of
+// v ^ seed), write the one-element estimate to c_prev[v] and zero sum_d[v].
+hipError_t launch_init(int p, uint8_t *cur, double *c_prev, double *sum_d, uint32_t n,
+                       uint64_t seed, hipStream_t stream);
+
+// One HyperBall step t: for every node v, decode its LEB128 row, take the
+// byte-wise max of cur[v] and cur[w] over its neighbours w into next[v],
+// estimate next[v], accumulate sum_d[v] += t (est - c_prev[v]), store est in
+// c_prev[v], and set *flag_t = 1 when est - c_prev[v] > 0.5.
+hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
+                        uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
+                        uint32_t n, uint32_t t, hipStream_t stream);
+
+// Fill count u32 words with value (used instead of hipMemsetAsync so the
+// sequence stays capturable).
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream);
+
+}  // namespace hbk

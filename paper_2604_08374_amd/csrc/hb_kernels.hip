@@ -1,0 +1,525 @@
+// HyperBall kernels for gfx950 (CDNA4, wave64).
+//
+// The hot loop is the paper's fused decode-union step (Sec. 3.4, "CUDA
+// kernels": LEB128 decode of a node's row, then the register-wise max of
+// Eq. 2 against every neighbour's counter), here with the estimator and the
+// Eq. 3 accumulation fused into its epilogue, so one launch is one whole
+// HyperBall step.  Design on gfx950:
+//
+//  * One wavefront per node (p <= 12).  A counter of m = 2^p uint8 registers
+//    is spread over the wave in 16-byte lane slices, so every neighbour
+//    gather is one coalesced 16 B/lane load: at p = 10 a single 1 KB wave
+//    load.  For p < 10 the wave splits into groups that gather different
+//    neighbours at once and are max-reduced at the end; for p >= 13 several
+//    waves of a workgroup share a node, each owning a 4 KB slice.
+//  * The row is decoded cooperatively 64 bytes at a time: a ballot of the
+//    continuation bits marks varint ends, a segmented OR joins the 7-bit
+//    groups (at most five per varint), a wave prefix sum turns the first id
+//    and the deltas into absolute ids, and a lane permute packs them into
+//    lanes 0..k-1.  Varints that straddle 64-byte chunks carry over.
+//  * Neighbour ids are read out with readlane into scalar registers, so each
+//    gather uses a scalar base address; eight gathers are kept in flight per
+//    wave.  Tail slots repeat an id already gathered (max is idempotent).
+//  * Byte-wise max without unpacking: v_pk_max_u16 on the raw dword keeps
+//    the max of bytes 1 and 3 in the high byte of each half, and on the
+//    dword shifted left by 8 the max of bytes 0 and 2; 3 VALU ops per 4
+//    registers.
+//  * The estimator sums 2^(65-p-M) over the registers as an exact 128-bit
+//    integer (wave butterfly with carries) and converts it to double with a
+//    single rounding, so the estimate is independent of the reduction order.
+//  * Workgroups are remapped so that each of the 8 XCDs (which take
+//    workgroups round-robin) works on one contiguous node range: adjacent
+//    nodes share most neighbours, so their gathers hit the same L2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "hb_internal.h"
+
+namespace hbk {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+template <int P>
+struct Cfg {
+    static constexpr int M = 1 << P;
+    static constexpr int SLICE = M < 4096 ? M : 4096;           // bytes per wave
+    static constexpr int WAVES = M > 4096 ? M / 4096 : 1;        // waves per node
+    static constexpr int LPC = SLICE >= 1024 ? 64 : SLICE / 16;  // lanes per counter
+    static constexpr int G = kWave / LPC;                        // neighbour groups
+    static constexpr int RPL = SLICE >= 1024 ? SLICE / 1024 : 1; // uint4 per lane
+    static constexpr int U = RPL >= 8 ? 1 : 8 / RPL;             // gathers in flight
+    static constexpr int NODES = WAVES == 1 ? 4 : 1;             // nodes per workgroup
+    static constexpr int THREADS = WAVES == 1 ? 256 : WAVES * kWave;
+    static constexpr int TOP = 65 - P;                           // largest register value
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t ballot(bool pred) {
+    return __builtin_amdgcn_ballot_w64(pred);
+}
+
+__device__ __forceinline__ uint32_t shfl_up(uint32_t x, uint32_t d) {
+    const int src = (int)lane_id() - (int)d;
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((src < 0 ? 0 : src) << 2, (int)x);
+}
+
+__device__ __forceinline__ uint32_t shfl_idx(uint32_t x, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
+
+__device__ __forceinline__ uint32_t shfl_xor(uint32_t x, uint32_t mask) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((lane_id() ^ mask) << 2), (int)x);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t x, uint32_t lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)lane);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+
+// Byte-wise max accumulator for one dword of 4 registers.  hi tracks bytes
+// 1 and 3 (the high byte of each 16-bit half); lo tracks bytes 0 and 2 after
+// a left shift by 8 moves them into the high bytes.  The low bytes of both
+// words are don't-care.
+struct Max4 {
+    uint32_t lo, hi;
+    __device__ __forceinline__ void init(uint32_t w) { lo = w << 8; hi = w; }
+    __device__ __forceinline__ void add(uint32_t w) {
+        hi = pk_max_u16(hi, w);
+        lo = pk_max_u16(lo, w << 8);
+    }
+    __device__ __forceinline__ uint32_t value() const {
+        return ((lo >> 8) & 0x00FF00FFu) | (hi & 0xFF00FF00u);
+    }
+};
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Exact partial of sum_j 2^(TOP - M[j]) (128-bit: lo, hi) and zero count.
+struct EstPart {
+    uint64_t lo, hi;
+    uint32_t zeros;
+    __device__ __forceinline__ void clear() { lo = 0; hi = 0; zeros = 0; }
+    __device__ __forceinline__ void add_term(uint64_t term) {
+        lo += term;
+        hi += (lo < term) ? 1u : 0u;
+    }
+    __device__ __forceinline__ void add_dword(uint32_t w, int top) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t M = (w >> (8 * b)) & 0xFFu;
+            add_term(1ull << (top - (int)M));
+            zeros += (M == 0u) ? 1u : 0u;
+        }
+    }
+    __device__ __forceinline__ void add(const EstPart &o) {
+        const uint64_t l = lo + o.lo;
+        hi = hi + o.hi + ((l < lo) ? 1u : 0u);
+        lo = l;
+        zeros += o.zeros;
+    }
+    // butterfly over the whole wave: every lane ends with the wave total
+    __device__ __forceinline__ void wave_reduce() {
+#pragma unroll
+        for (uint32_t mask = 1; mask < kWave; mask <<= 1) {
+            EstPart o;
+            o.lo = ((uint64_t)shfl_xor((uint32_t)(lo >> 32), mask) << 32) |
+                   shfl_xor((uint32_t)lo, mask);
+            o.hi = ((uint64_t)shfl_xor((uint32_t)(hi >> 32), mask) << 32) |
+                   shfl_xor((uint32_t)hi, mask);
+            o.zeros = shfl_xor(zeros, mask);
+            add(o);
+        }
+    }
+};
+
+// HLL estimate from the exact sum S = hi 2^64 + lo (units of 2^-top) and the
+// zero count: raw estimate alpha_m m^2 / Z, or linear counting m ln(m / V)
+// when the raw estimate is at most 2.5 m and V > 0.
+template <int P>
+__device__ double estimate(const EstPart &e) {
+    constexpr int top = Cfg<P>::TOP;
+    const double md = (double)(1u << P);
+    // S < 2^66: split into two exactly representable doubles, one rounding.
+    const uint64_t upper = (e.hi << 32) | (e.lo >> 32);  // < 2^34
+    const double s = (double)upper * 4294967296.0 + (double)(uint32_t)e.lo;
+    const double Z = ldexp(s, -top);
+    double alpha;
+    if (P == 4) alpha = 0.673;
+    else if (P == 5) alpha = 0.697;
+    else if (P == 6) alpha = 0.709;
+    else alpha = 0.7213 / (1.0 + 1.079 / md);
+    const double E = ((alpha * md) * md) / Z;
+    if (E <= 2.5 * md && e.zeros > 0u) return md * log(md / (double)e.zeros);
+    return E;
+}
+
+// Workgroup index -> logical block so that XCD x (taking workgroups i with
+// i % 8 == x) processes one contiguous range of logical blocks.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t i, uint32_t nblocks) {
+    const uint32_t q = nblocks / kXcds, r = nblocks % kXcds;
+    const uint32_t x = i % kXcds, k = i / kXcds;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Byte offset, within a counter, of lane-slot s (s < RPL) of this lane.
+template <int P>
+__device__ __forceinline__ uint32_t slot_offset(uint32_t slice, uint32_t lane, int s) {
+    using C = Cfg<P>;
+    if (C::SLICE >= 1024) return slice * C::SLICE + (uint32_t)s * 1024u + lane * 16u;
+    return (lane % C::LPC) * 16u;
+}
+
+// Combine the estimator partials of the waves sharing a node (p >= 13) and
+// return the node total in every lane of wave 0 (others: unspecified).
+template <int P>
+__device__ EstPart node_total(EstPart e, uint32_t slice) {
+    using C = Cfg<P>;
+    if (C::WAVES == 1) return e;
+    __shared__ uint64_t s_lo[C::WAVES > 1 ? C::WAVES : 1];
+    __shared__ uint64_t s_hi[C::WAVES > 1 ? C::WAVES : 1];
+    __shared__ uint32_t s_z[C::WAVES > 1 ? C::WAVES : 1];
+    if (lane_id() == 0) {
+        s_lo[slice] = e.lo;
+        s_hi[slice] = e.hi;
+        s_z[slice] = e.zeros;
+    }
+    __syncthreads();
+    EstPart tot;
+    tot.clear();
+    if (slice == 0) {
+        for (int w = 0; w < C::WAVES; ++w) {
+            EstPart o;
+            o.lo = s_lo[w];
+            o.hi = s_hi[w];
+            o.zeros = s_z[w];
+            tot.add(o);
+        }
+    }
+    return tot;
+}
+
+// ---------------------------------------------------------------- init
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restrict__ cur,
+                                                               double *__restrict__ c_prev,
+                                                               double *__restrict__ sum_d,
+                                                               uint32_t n, uint64_t seed) {
+    using C = Cfg<P>;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+
+    const uint64_t h = splitmix64((uint64_t)v ^ seed);
+    const uint32_t j = (uint32_t)(h >> (64 - P));
+    const uint64_t rest = h << P;
+    const uint32_t r = rest ? (uint32_t)__builtin_clzll(rest) + 1u : (uint32_t)(65 - P);
+
+    const bool owner = (lane / C::LPC) == 0;  // group 0 holds the counter
+    EstPart e;
+    e.clear();
+    uint8_t *row = cur + (uint64_t)v * C::M;
+#pragma unroll
+    for (int s = 0; s < C::RPL; ++s) {
+        const uint32_t off = slot_offset<P>(slice, lane, s);
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (j >= off && j < off + 16u) w[(j - off) >> 2] = r << (8 * ((j - off) & 3u));
+        if (owner) {
+            *reinterpret_cast<uint4 *>(row + off) = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e.add_dword(w[k], C::TOP);
+        }
+    }
+    e.wave_reduce();
+    const EstPart tot = node_total<P>(e, slice);
+    if (slice == 0 && lane == 0) {
+        c_prev[v] = estimate<P>(tot);
+        sum_d[v] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- union step
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
+    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
+    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
+    using C = Cfg<P>;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+
+    const uint32_t grp = lane / C::LPC;
+
+    // own counter seeds the accumulator (Alg. 1: next[v] <- cur[v])
+    Max4 acc[C::RPL][4];
+    {
+        const uint8_t *own = cur + (uint64_t)v * C::M;
+#pragma unroll
+        for (int s = 0; s < C::RPL; ++s) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(own + slot_offset<P>(slice, lane, s));
+            acc[s][0].init(x.x);
+            acc[s][1].init(x.y);
+            acc[s][2].init(x.z);
+            acc[s][3].init(x.w);
+        }
+    }
+
+    const uint64_t row_beg = offsets[v], row_end = offsets[v + 1];
+    uint32_t run = 0;        // last absolute id decoded (prefix sum of values)
+    uint32_t carry_val = 0;  // bits of a varint continued from the previous chunk
+    uint32_t carry_sh = 0;   // bit position where the carried varint continues
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+
+    for (uint64_t base = row_beg; base < row_end; base += kWave) {
+        // ---- cooperative decode of 64 bytes
+        const bool valid = base + lane < row_end;
+        const uint32_t b = valid ? (uint32_t)bytes[base + lane] : 0u;
+        const uint64_t term = ballot(valid && !(b & 0x80u));
+        const uint64_t cont = ballot(valid && (b & 0x80u));
+        const uint64_t below = term & lt_mask;
+        const uint32_t start = below ? 64u - (uint32_t)__builtin_clzll(below) : 0u;
+        const uint32_t pos = lane - start;
+        const uint32_t sh = (below ? 0u : carry_sh) + 7u * pos;
+        const uint32_t contrib = (sh < 32u) ? ((b & 0x7Fu) << sh) : 0u;
+        uint32_t val = contrib;
+#pragma unroll
+        for (uint32_t k = 1; k <= 4; ++k) {
+            const uint32_t x = shfl_up(contrib, k);
+            if (pos >= k) val |= x;
+        }
+        if (!below) val |= carry_val;
+        const bool is_term = (term >> lane) & 1ull;
+        // inclusive prefix sum of the terminated values: first id, then deltas
+        uint32_t sum = is_term ? val : 0u;
+#pragma unroll
+        for (uint32_t d = 1; d < kWave; d <<= 1) {
+            const uint32_t x = shfl_up(sum, d);
+            if (lane >= d) sum += x;
+        }
+        const uint32_t id = run + sum;
+        run = readlane(id, kWave - 1);
+        if ((cont >> (kWave - 1)) & 1ull) {
+            carry_val = readlane(val, kWave - 1);
+            carry_sh = readlane(sh, kWave - 1) + 7u;
+        } else {
+            carry_val = 0u;
+            carry_sh = 0u;
+        }
+        // pack the ids into lanes 0..cnt-1 (non-terminators park on lane 63,
+        // which is free whenever some lane is not a terminator)
+        const uint32_t cnt = (uint32_t)__builtin_popcountll(term);
+        const uint32_t rank = (uint32_t)__builtin_popcountll(below);
+        const uint32_t ids = (uint32_t)__builtin_amdgcn_ds_permute(
+            (int)((is_term ? rank : (uint32_t)(kWave - 1)) << 2), (int)id);
+
+        // ---- gather-max over the cnt neighbours of this chunk
+        if (C::G == 1) {
+            for (uint32_t k = 0; k < cnt; k += C::U) {
+                const uint8_t *src[C::U];
+#pragma unroll
+                for (int u = 0; u < C::U; ++u) {
+                    const uint32_t l = (k + u < cnt) ? k + u : k;
+                    const uint32_t w = readlane(ids, l);
+                    src[u] = cur + (uint64_t)w * C::M;
+                }
+                uint4 x[C::U][C::RPL];
+#pragma unroll
+                for (int u = 0; u < C::U; ++u)
+#pragma unroll
+                    for (int s = 0; s < C::RPL; ++s)
+                        x[u][s] = *reinterpret_cast<const uint4 *>(src[u] +
+                                                                   slot_offset<P>(slice, lane, s));
+#pragma unroll
+                for (int u = 0; u < C::U; ++u)
+#pragma unroll
+                    for (int s = 0; s < C::RPL; ++s) {
+                        acc[s][0].add(x[u][s].x);
+                        acc[s][1].add(x[u][s].y);
+                        acc[s][2].add(x[u][s].z);
+                        acc[s][3].add(x[u][s].w);
+                    }
+            }
+        } else {
+            // G groups gather G different neighbours per load
+            for (uint32_t k = 0; k < cnt; k += C::U * C::G) {
+                uint4 x[C::U];
+#pragma unroll
+                for (int u = 0; u < C::U; ++u) {
+                    const uint32_t idx = k + (uint32_t)u * C::G + grp;
+                    const uint32_t l = idx < cnt ? idx : k;
+                    const uint32_t w = shfl_idx(ids, l);
+                    x[u] = *reinterpret_cast<const uint4 *>(cur + (uint64_t)w * C::M +
+                                                             slot_offset<P>(0, lane, 0));
+                }
+#pragma unroll
+                for (int u = 0; u < C::U; ++u) {
+                    acc[0][0].add(x[u].x);
+                    acc[0][1].add(x[u].y);
+                    acc[0][2].add(x[u].z);
+                    acc[0][3].add(x[u].w);
+                }
+            }
+        }
+    }
+
+    // ---- final registers of this lane
+    uint32_t reg[C::RPL][4];
+#pragma unroll
+    for (int s = 0; s < C::RPL; ++s)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) reg[s][k] = acc[s][k].value();
+    if (C::G > 1) {
+        // max across the groups that gathered different neighbours
+#pragma unroll
+        for (uint32_t mask = C::LPC; mask < kWave; mask <<= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Max4 m;
+                m.init(reg[0][k]);
+                m.add(shfl_xor(reg[0][k], mask));
+                reg[0][k] = m.value();
+            }
+    }
+
+    // ---- store next[v] and estimate it
+    EstPart e;
+    e.clear();
+    if (grp == 0) {
+        uint8_t *row = next + (uint64_t)v * C::M;
+#pragma unroll
+        for (int s = 0; s < C::RPL; ++s) {
+            *reinterpret_cast<uint4 *>(row + slot_offset<P>(slice, lane, s)) =
+                make_uint4(reg[s][0], reg[s][1], reg[s][2], reg[s][3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e.add_dword(reg[s][k], C::TOP);
+        }
+    }
+    e.wave_reduce();
+    const EstPart tot = node_total<P>(e, slice);
+
+    // ---- Eq. 3 accumulation and the 0.5 stopping test
+    if (slice == 0 && lane == 0) {
+        const double est = estimate<P>(tot);
+        const double delta = est - c_prev[v];
+        sum_d[v] = sum_d[v] + (double)t * delta;
+        c_prev[v] = est;
+        if (delta > 0.5 && __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+            __hip_atomic_store(flag_t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = value;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <int P>
+hipError_t launch_init_p(uint8_t *cur, double *c_prev, double *sum_d, uint32_t n, uint64_t seed,
+                         hipStream_t stream) {
+    using C = Cfg<P>;
+    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
+    hipLaunchKernelGGL((init_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, cur, c_prev,
+                       sum_d, n, seed);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_union_p(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
+                          uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
+                          uint32_t n, uint32_t t, hipStream_t stream) {
+    using C = Cfg<P>;
+    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
+    hipLaunchKernelGGL((union_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, bytes,
+                       offsets, cur, next, c_prev, sum_d, flag_t, n, t);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+LaunchShape shape_for(int p) {
+    LaunchShape s;
+    const uint32_t m = 1u << p;
+    s.waves_per_node = m > 4096 ? m / 4096 : 1;
+    s.nodes_per_block = s.waves_per_node == 1 ? 4 : 1;
+    s.threads = s.waves_per_node == 1 ? 256 : s.waves_per_node * kWave;
+    return s;
+}
+
+hipError_t launch_init(int p, uint8_t *cur, double *c_prev, double *sum_d, uint32_t n,
+                       uint64_t seed, hipStream_t stream) {
+#define HB_CALL_INIT(P) launch_init_p<P>(cur, c_prev, sum_d, n, seed, stream)
+    switch (p) {
+        case 4: return HB_CALL_INIT(4);
+        case 5: return HB_CALL_INIT(5);
+        case 6: return HB_CALL_INIT(6);
+        case 7: return HB_CALL_INIT(7);
+        case 8: return HB_CALL_INIT(8);
+        case 9: return HB_CALL_INIT(9);
+        case 10: return HB_CALL_INIT(10);
+        case 11: return HB_CALL_INIT(11);
+        case 12: return HB_CALL_INIT(12);
+        case 13: return HB_CALL_INIT(13);
+        case 14: return HB_CALL_INIT(14);
+        case 15: return HB_CALL_INIT(15);
+        case 16: return HB_CALL_INIT(16);
+        default: return hipErrorInvalidValue;
+    }
+#undef HB_CALL_INIT
+}
+
+hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
+                        uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
+                        uint32_t n, uint32_t t, hipStream_t stream) {
+#define HB_CALL_UNION(P) \
+    launch_union_p<P>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, t, stream)
+    switch (p) {
+        case 4: return HB_CALL_UNION(4);
+        case 5: return HB_CALL_UNION(5);
+        case 6: return HB_CALL_UNION(6);
+        case 7: return HB_CALL_UNION(7);
+        case 8: return HB_CALL_UNION(8);
+        case 9: return HB_CALL_UNION(9);
+        case 10: return HB_CALL_UNION(10);
+        case 11: return HB_CALL_UNION(11);
+        case 12: return HB_CALL_UNION(12);
+        case 13: return HB_CALL_UNION(13);
+        case 14: return HB_CALL_UNION(14);
+        case 15: return HB_CALL_UNION(15);
+        case 16: return HB_CALL_UNION(16);
+        default: return hipErrorInvalidValue;
+    }
+#undef HB_CALL_UNION
+}
+
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t threads = 256;
+    const uint64_t blocks = (count + threads - 1) / threads;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(threads), 0, stream, dst,
+                       value, count);
+    return hipGetLastError();
+}
+
+}  // namespace hbk

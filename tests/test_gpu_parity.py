@@ -1,0 +1,95 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Registers must match byte for byte, pass counts and the convergence flag exactly;
+reach and the Eq. 3 sums within 1e-9 relative (the only floating-point step is the
+estimator, whose log may differ by an ulp between host libm and the device).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+def _load(hb, g):
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    return hb.graph_load(off, deg, data)
+
+
+def _compare(res, ref, what):
+    assert res.passes == ref.passes, (what, res.passes, ref.passes)
+    assert res.converged == ref.converged, (what, res.converged, ref.converged)
+    if ref.registers is not None:
+        bad = np.nonzero((res.registers != ref.registers).any(axis=1))[0]
+        assert bad.size == 0, f"{what}: registers differ at nodes {bad[:10]}"
+    np.testing.assert_allclose(res.reach, ref.reach, rtol=RTOL, atol=0, err_msg=what)
+    np.testing.assert_allclose(res.sum_d, ref.sum_d, rtol=RTOL, atol=1e-9, err_msg=what)
+
+
+def _check(hb, g, p, depth, seed=0):
+    print(f"[parity] {g.name} n={g.n} E={g.n_edges} p={p} depth={depth} seed={seed}", flush=True)
+    ref = oracle.hyperball(oracle.from_graph(g), p, depth, seed)
+    with _load(hb, g) as G:
+        res = G.run(p, depth, seed, registers=True)
+    _compare(res, ref, f"{g.name} p={p} d={depth} seed={seed}")
+    return res, ref
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("depth", [0, 1, 2, 3])
+def test_tiny_p10(hb, seed, depth):
+    _check(hb, synth.tiny(seed), 10, depth, seed=0)
+
+
+@pytest.mark.parametrize("p", range(4, 17))
+@pytest.mark.parametrize("depth", [0, 2])
+def test_tiny_all_p(hb, p, depth):
+    _check(hb, synth.tiny(1), p, depth, seed=12345)
+
+
+@pytest.mark.parametrize("hash_seed", [0, 1, 0xDEADBEEFCAFEF00D])
+def test_hash_seeds(hb, hash_seed):
+    _check(hb, synth.tiny(2), 8, 0, seed=hash_seed)
+
+
+@pytest.mark.parametrize("maker,n", [(synth.path_graph, 40), (synth.cycle_graph, 33),
+                                     (synth.star_graph, 50), (synth.complete_graph, 30)])
+@pytest.mark.parametrize("p", [4, 10])
+def test_closed_form_graphs(hb, maker, n, p):
+    _check(hb, maker(n), p, 0)
+
+
+def test_single_node(hb):
+    g = synth.from_edges(1, [], name="single")
+    res, ref = _check(hb, g, 10, 0)
+    assert res.passes == 1 and res.converged
+
+
+def test_isolated_nodes(hb):
+    g = synth.random_graph(300, 0.004, seed=5)
+    assert (g.degrees == 0).any()
+    _check(hb, g, 9, 0)
+
+
+@pytest.mark.parametrize("W,H,seed", [(64, 64, 0), (100, 80, 3)])
+@pytest.mark.parametrize("p", [8, 10, 12])
+@pytest.mark.parametrize("depth", [3, 0])
+def test_rect_rasters(hb, W, H, seed, p, depth):
+    _check(hb, synth.grid_graph(seed, W, H), p, depth)
+
+
+def test_prefix_property(hb):
+    """Registers of a depth-t run equal step t of a longer run (oracle: exact balls)."""
+    g = synth.tiny(3)
+    csr = oracle.from_graph(g)
+    dist = oracle.bfs_all(csr)
+    with _load(hb, g) as G:
+        for t in (1, 2, 3, 4):
+            res = G.run(10, t, 0, registers=True)
+            for v in range(0, g.n, 7):
+                ball = oracle.ball_registers(dist[v], t, 10, 0)
+                assert np.array_equal(res.registers[v], ball), (t, v)
