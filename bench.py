@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""HyperBall throughput on one GPU: edge-unions/s and the HBM roofline fraction.
+
+One step is one whole HyperBall run through the C ABI (hb_run): init, one fused
+decode/union/estimate/accumulate launch per step t until the depth limit, and the
+FP64 outputs copied back.  Inputs (the compressed CSR) are resident in device memory
+before the timed region.  The default workload is the city-scale graph: the seeded
+street/building raster of 541x541 cells (about 236,000 nodes and 4.7e9 directed
+edges, the shape of the paper's largest T2 row), p = 10, depth limit 3.
+
+Output: one JSON line (plus progress lines on stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "HLL edge-unions/s + % HBM roofline (236k cells, p=10); p50/p99 latency, mixed load"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_kernel_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_08374_amd", "csrc", "hb_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_graph(config: str, seed: int):
+    import synth
+
+    t0 = time.perf_counter()
+    if config == "city":
+        g = synth.city(seed, device="gpu")
+    elif config == "urban":
+        g = synth.urban(seed, device="gpu")
+    elif config == "tiny":
+        g = synth.tiny(seed)
+    else:
+        raise SystemExit(f"unknown config {config}")
+    log(f"generated {g.name}: n={g.n} edges={g.n_edges} in {time.perf_counter() - t0:.1f}s")
+    return g
+
+
+def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int) -> int:
+    """Bytes one union launch must move at minimum without reuse.
+
+    Per directed edge: one neighbour counter (m bytes) plus its LEB128 bytes; per
+    node: the offsets entry (8 B), its own counter read and next[v] written (2m),
+    and the FP64 state c_prev and sum_d read and written (32 B).
+    """
+    m = 1 << p
+    return n_edges * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
+
+
+def kernel_traffic(per_launch_algo: int):
+    """Measured HBM bytes per union launch from the committed counter summary."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            src_hash = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != src_hash:
+        return None  # the kernel changed since the counters were taken
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
+    """The oracle's union + estimate on a bounded, seeded sample of nodes."""
+    import oracle
+
+    csr = oracle.CSR(n=n, offsets=csr_off, degrees=csr_deg, bytes=csr_bytes)
+    cur = oracle.initial_registers(n, p, seed)
+    rng = np.random.default_rng(1234)
+    order = rng.permutation(n)
+    # calibrate on a small sample, then size the timed sample to ~target_s
+    probe = order[:64]
+    t0 = time.perf_counter()
+    _, _, e0 = oracle.union_sample(csr, p, cur, probe)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate0 = e0 / dt
+    want_edges = rate0 * target_s
+    deg = csr_deg[order].astype(np.int64)
+    k = int(np.searchsorted(np.cumsum(deg), want_edges)) + 1
+    sample = order[64:64 + max(k, 64)]
+    t0 = time.perf_counter()
+    _, _, edges = oracle.union_sample(csr, p, cur, sample)
+    dt = time.perf_counter() - t0
+    return {
+        "value": edges / dt,
+        "unit": "edge-unions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one union step (Eq. 2) + estimate for {sample.size} seeded random nodes "
+                   f"({edges} directed edges, {dt:.1f} s) of the same graph, p={p}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="city", choices=["city", "urban", "tiny"])
+    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--depth", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 4 GiB device copy (measured bandwidth)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        raise SystemExit("bench.py runs on exactly one GPU: the HyperBall path here is a "
+                         "single-GPU library (multi-GPU sharding is designed, not built)")
+
+    import paper_2604_08374_amd as hb
+
+    if hb.device_count() < 1:
+        raise SystemExit("no GPU visible")
+    g = make_graph(args.config, args.seed)
+    t0 = time.perf_counter()
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    n, E = g.n, g.n_edges
+    log(f"encoded LEB128 CSR: {data.size} bytes ({data.size / max(E, 1):.3f} B/edge) "
+        f"in {time.perf_counter() - t0:.1f}s")
+    del g
+    t0 = time.perf_counter()
+    G = hb.graph_load(off, deg, data)
+    log(f"hb_graph_load (validate + copy to HBM) in {time.perf_counter() - t0:.1f}s")
+
+    p, depth = args.p, args.depth
+    for i in range(args.warmup):
+        r = G.run(p, depth, args.seed)
+        log(f"warmup {i}: passes={r.passes} run_ms={r.run_ms:.1f} iter_ms={r.iter_ms:.1f}")
+
+    passes = 0
+    iter_ms = 0.0
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = G.run(p, depth, args.seed)
+        results.append(r)
+        passes += r.passes
+        iter_ms += r.iter_ms
+        log(f"step {i}: passes={r.passes} converged={r.converged} run_ms={r.run_ms:.1f} "
+            f"iter_ms={r.iter_ms:.1f}")
+    elapsed = time.perf_counter() - t0
+
+    unions = passes * E
+    value = unions / elapsed
+    avg_launch_s = iter_ms / 1e3 / passes
+    per_launch = algorithmic_bytes(n, E, data.size, p)
+    achieved = per_launch / avg_launch_s / 1e9
+    traffic = kernel_traffic(per_launch)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-unions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config} street/building visibility graph, seed {args.seed}",
+            "nodes": n,
+            "directed_edges": E,
+            "leb128_bytes": int(data.size),
+            "p": p,
+            "depth_limit": depth,
+            "passes_per_step": results[-1].passes,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "union_kernel (fused decode + gather-max + estimate + accumulate)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+        },
+    }
+    if args.copy_probe:
+        nbytes = 4 << 30
+        ms = hb.copy_probe(nbytes, 10)
+        line["roofline"]["copy_probe_gbs"] = 2 * nbytes / (ms / 1e3) / 1e9
+        line["roofline"]["frac_of_copy"] = achieved / line["roofline"]["copy_probe_gbs"]
+        log(f"copy probe: {nbytes} B in {ms:.3f} ms -> {line['roofline']['copy_probe_gbs']:.0f} GB/s")
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(off, deg, data, n, p, args.seed, args.cpu_seconds)
+    G.free()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,16 @@ hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint6
 hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                  hb_result *out);
 
+/*
+ * Diagnostic: a plain streaming copy of `bytes` (a multiple of 16) between two
+ * fresh device buffers, repeated reps times after one warm-up; *avg_ms is the
+ * device time of one copy.  It reads and writes `bytes` each, so 2 * bytes /
+ * avg_ms is the achievable device-memory bandwidth, and the copy is the
+ * reference kernel for scaling hardware byte counters.  Allocates and frees
+ * its own buffers.
+ */
+hb_status hb_copy_probe(uint64_t bytes, uint32_t reps, double *avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

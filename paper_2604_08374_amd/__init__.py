@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "HBError", "Result", "Graph", "lib_path", "version", "device_count", "csr_encode",
-    "csr_validate", "graph_load", "run", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
+    "csr_validate", "graph_load", "run", "copy_probe", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
     "HB_ENOMEM", "HB_EDEVICE", "HB_ENOTFOUND", "HB_EBUSY",
 ]
 
@@ -84,6 +84,8 @@ def _lib():
         L.hb_run.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                              ctypes.POINTER(_Result)]
         L.hb_run.restype = st
+        L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
+        L.hb_copy_probe.restype = st
         _LIB = L
     return _LIB
 
@@ -230,6 +232,13 @@ class Graph:
         return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
                       int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.run_ms),
                       int(r.t_start_ns), int(r.t_end_ns))
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
+    """hb_copy_probe: average device ms of one streaming copy of nbytes."""
+    ms = ctypes.c_double(0.0)
+    _check(_lib().hb_copy_probe(int(nbytes), int(reps), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:

@@ -433,4 +433,35 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
     return HB_OK;
 }
 
+hb_status hb_copy_probe(uint64_t bytes, uint32_t reps, double *avg_ms) {
+    if (!avg_ms || reps == 0 || bytes < 16 || bytes % 16) return fail(HB_EINVAL, "bad probe size");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    hb_status st = have_device();
+    if (st != HB_OK) return st;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 1, bytes, s);
+    if (e == hipSuccess) e = hbk::launch_copy(a, b, bytes, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (uint32_t i = 0; e == hipSuccess && i < reps; ++i) e = hbk::launch_copy(a, b, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return hip_fail(e, "copy probe");
+    *avg_ms = ms / reps;
+    return HB_OK;
+}
+
 }  // extern "C"

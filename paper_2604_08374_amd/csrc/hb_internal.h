@@ -29,6 +29,9 @@ hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, co
                         uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
                         uint32_t n, uint32_t t, hipStream_t stream);
 
+// Streaming copy of bytes (a multiple of 16) from src to dst.
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+
 // Fill count u32 words with value (used instead of hipMemsetAsync so the
 // sequence stays capturable).
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream);

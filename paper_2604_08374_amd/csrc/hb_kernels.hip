@@ -34,6 +34,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "hb_internal.h"
 
 namespace hbk {
@@ -429,6 +431,15 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
     }
 }
 
+// Streaming copy, 16 B per lane, grid-stride: the reference kernel for
+// achievable HBM bandwidth and for scaling the HBM byte counters.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src,
+                                                   uint4 *__restrict__ dst, uint64_t count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = src[i];
+}
+
 __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = value;
@@ -511,6 +522,15 @@ hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, co
         default: return hipErrorInvalidValue;
     }
 #undef HB_CALL_UNION
+}
+
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream) {
+    const uint64_t count = bytes / 16;
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 256u * 64u);
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, stream,
+                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), count);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream) {

@@ -111,6 +111,12 @@ def _lib():
         L.syn_degrees_sample.restype = None
         L.syn_visible_pairs.argtypes = [c_u8p, i32, i32, c_i32p, c_i64p, c_i64p, i64, c_u8p]
         L.syn_visible_pairs.restype = None
+        L.syn_raster_bits.argtypes = [c_u8p, i32, i32, c_u32p]
+        L.syn_raster_bits.restype = None
+        L.syn_row_degrees.argtypes = [c_u32p, i64, i64, c_u64p]
+        L.syn_row_degrees.restype = None
+        L.syn_row_ids.argtypes = [c_u32p, i64, i64, c_u64p, c_u32p]
+        L.syn_row_ids.restype = None
         L.syn_num_threads.argtypes = []
         L.syn_num_threads.restype = ctypes.c_int
         _LIB = L
@@ -359,6 +365,14 @@ def random_graph(n: int, p_edge: float, seed: int) -> Graph:
 
 
 # ---------------------------------------------------------------- GPU generator
+def raster_bits(obst: np.ndarray) -> np.ndarray:
+    obst = np.ascontiguousarray(obst, dtype=np.uint8)
+    H, W = obst.shape
+    bits = np.zeros((W * H + 31) // 32, np.uint32)
+    _lib().syn_raster_bits(_p(obst, ctypes.c_uint8), W, H, _p(bits, ctypes.c_uint32))
+    return bits
+
+
 def _gpu_lib():
     global _GPU_LIB
     if _GPU_LIB is None:
@@ -366,30 +380,53 @@ def _gpu_lib():
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(path)
-        L.syng_adjacency.argtypes = [
-            ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
-            ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
-            ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_uint64]
-        L.syng_adjacency.restype = ctypes.c_int
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i32, u32 = ctypes.c_int32, ctypes.c_uint32
+        L.syng_rows.argtypes = [u32p, i32, i32, i32p, u32, u32, u32, u32p]
+        L.syng_rows.restype = ctypes.c_int
+        L.syng_visible_host.argtypes = [u32p, i32, i32, i32, i32, i32]
+        L.syng_visible_host.restype = ctypes.c_int
         L.syng_last_error.argtypes = []
         L.syng_last_error.restype = ctypes.c_char_p
         _GPU_LIB = L
     return _GPU_LIB
 
 
-def _gpu_adjacency(obst: np.ndarray, xy: np.ndarray):
+def gpu_walk_visible_host(obst: np.ndarray, a, b) -> int:
+    """The GPU generator's division-free walk, run on the host (for cross-checks)."""
+    bits = raster_bits(obst)
+    return int(_gpu_lib().syng_visible_host(_p(bits, ctypes.c_uint32), obst.shape[1],
+                                            int(a[0]), int(a[1]), int(b[0]), int(b[1])))
+
+
+def _gpu_adjacency(obst: np.ndarray, xy: np.ndarray, batch_bytes: int = 1 << 31):
+    """Adjacency from GPU-computed visibility bit rows (batched), expanded on the host."""
     L = _gpu_lib()
     H, W = obst.shape
     n = xy.shape[0]
+    bits = raster_bits(obst)
+    wpr = (n + 31) // 32
+    rows = np.empty((n, wpr), np.uint32)
+    batch = max(1, min(n, batch_bytes // (4 * wpr)))
+    import sys
+    import time
+    t0 = time.perf_counter()
+    for s0 in range(0, n, batch):
+        cnt = min(batch, n - s0)
+        rc = L.syng_rows(_p(bits, ctypes.c_uint32), W, H, _p(xy, ctypes.c_int32), n, s0, cnt,
+                         _p(rows[s0:], ctypes.c_uint32))
+        if rc != 0:
+            raise RuntimeError("GPU visibility generator: " + L.syng_last_error().decode())
+        if n > 20000:
+            print(f"[synth] visibility rows {s0 + cnt}/{n} ({time.perf_counter() - t0:.1f}s)",
+                  file=sys.stderr, flush=True)
+    deg = np.empty(n, np.uint64)
+    _lib().syn_row_degrees(_p(rows, ctypes.c_uint32), wpr, n, _p(deg, ctypes.c_uint64))
     off = np.zeros(n + 1, np.uint64)
-    # pass 1: degrees only (ids == NULL)
-    rc = L.syng_adjacency(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
-                          _p(off, ctypes.c_uint64), None, 0)
-    if rc != 0:
-        raise RuntimeError("GPU visibility generator: " + L.syng_last_error().decode())
+    np.cumsum(deg, out=off[1:])
     ids = np.empty(int(off[-1]), np.uint32)
-    rc = L.syng_adjacency(_p(obst, ctypes.c_uint8), W, H, _p(xy, ctypes.c_int32), n,
-                          _p(off, ctypes.c_uint64), ids.ctypes.data, ids.shape[0])
-    if rc != 0:
-        raise RuntimeError("GPU visibility generator: " + L.syng_last_error().decode())
+    _lib().syn_row_ids(_p(rows, ctypes.c_uint32), wpr, n, _p(off, ctypes.c_uint64),
+                       _p(ids, ctypes.c_uint32))
+    del rows
     return off, ids

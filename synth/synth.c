@@ -196,3 +196,42 @@ int syn_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ---- bit-row form used by the GPU generator ---- */
+
+/* Raster as bits: bit (y*W + x) & 31 of word (y*W + x) >> 5 set for obstacles. */
+void syn_raster_bits(const uint8_t *obst, int32_t W, int32_t H, uint32_t *bits) {
+    const int64_t C = (int64_t)W * H, nw = (C + 31) / 32;
+    memset(bits, 0, sizeof(uint32_t) * (size_t)nw);
+    for (int64_t c = 0; c < C; ++c)
+        if (obst[c]) bits[c >> 5] |= 1u << (c & 31);
+}
+
+/* Degrees (popcounts) of count bit rows of wpr words. */
+void syn_row_degrees(const uint32_t *rows, int64_t wpr, int64_t count, uint64_t *deg) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < count; ++s) {
+        uint64_t d = 0;
+        const uint32_t *r = rows + s * wpr;
+        for (int64_t k = 0; k < wpr; ++k) d += (uint64_t)__builtin_popcount(r[k]);
+        deg[s] = d;
+    }
+}
+
+/* Expand bit rows into ascending ids at ids[off[s] ..) (off indexed by row). */
+void syn_row_ids(const uint32_t *rows, int64_t wpr, int64_t count, const uint64_t *off,
+                 uint32_t *ids) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < count; ++s) {
+        const uint32_t *r = rows + s * wpr;
+        uint64_t k = off[s];
+        for (int64_t w = 0; w < wpr; ++w) {
+            uint32_t bitsw = r[w];
+            while (bitsw) {
+                const int b = __builtin_ctz(bitsw);
+                ids[k++] = (uint32_t)(w * 32 + b);
+                bitsw &= bitsw - 1;
+            }
+        }
+    }
+}

@@ -93,3 +93,48 @@ def test_prefix_property(hb):
             for v in range(0, g.n, 7):
                 ball = oracle.ball_registers(dist[v], t, 10, 0)
                 assert np.array_equal(res.registers[v], ball), (t, v)
+
+
+# ---------------------------------------------------------------- full-size graphs, sampled
+def _sampled_check(hb, g, p, depth, n_src=64, seed=0):
+    """GPU run on the whole graph; the oracle recomputes sampled nodes from exact balls."""
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    csr = oracle.CSR(n=g.n, offsets=off, degrees=deg, bytes=data)
+    with hb.graph_load(off, deg, data) as G:
+        res = G.run(p, depth, seed, registers=True)
+    T = res.passes
+    assert depth == 0 or T <= depth
+    src = np.sort(np.random.default_rng(99).choice(g.n, n_src, replace=False))
+    src = np.unique(np.concatenate([src, [0, g.n - 1, int(np.argmax(deg)), int(np.argmin(deg))]]))
+    regs, reach, sum_d, _ = oracle.sampled_hyperball(csr, src, T, p, seed)
+    bad = np.nonzero((res.registers[src] != regs).any(axis=1))[0]
+    assert bad.size == 0, f"registers differ at sampled nodes {src[bad][:8]}"
+    np.testing.assert_allclose(res.reach[src], reach, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(res.sum_d[src], sum_d, rtol=RTOL, atol=1e-9)
+    return res
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("p", [8, 10, 12])
+def test_urban_sampled_depth3(hb, p):
+    g = _urban_graph()
+    print(f"[parity] urban n={g.n} E={g.n_edges} p={p} depth=3", flush=True)
+    res = _sampled_check(hb, g, p, 3)
+    assert res.passes == 3
+
+
+@pytest.mark.slow
+def test_urban_sampled_unlimited(hb):
+    g = _urban_graph()
+    print(f"[parity] urban n={g.n} E={g.n_edges} p=10 unlimited", flush=True)
+    res = _sampled_check(hb, g, 10, 0, n_src=32)
+    assert res.converged
+
+
+_URBAN = {}
+
+
+def _urban_graph():
+    if "g" not in _URBAN:
+        _URBAN["g"] = synth.urban(0, device="gpu")
+    return _URBAN["g"]
