@@ -26,7 +26,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "HLL edge-unions/s + % HBM roofline (236k cells, p=10); p50/p99 latency, mixed load"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_kernel_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_kernel_city_p10_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_08374_amd", "csrc", "hb_kernels.hip")
 
 
@@ -61,18 +61,24 @@ def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int) -> int:
     return n_edges * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
 
 
-def kernel_traffic(per_launch_algo: int):
-    """Measured HBM bytes per union launch from the committed counter summary."""
+def kernel_traffic(config: str, p: int, depth: int):
+    """HBM bytes per union launch from the committed rocprofv3 counter summary.
+
+    The summary was taken on the default workload (city graph, p = 10, depth 3);
+    for any other workload, or once the kernel source has changed, it is None.
+    """
+    if (config, p, depth) != ("city", 10, 3):
+        return None
     try:
         with open(COUNTERS_FILE) as f:
-            rec = json.load(f)
+            rec = dict(line.split(None, 1) for line in f if line.strip())
         with open(KERNEL_SRC, "rb") as f:
             src_hash = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != src_hash:
+    if rec.get("kernel_source_sha256", "").strip() != src_hash:
         return None  # the kernel changed since the counters were taken
-    return rec.get("hbm_bytes_per_launch")
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
@@ -163,7 +169,7 @@ def main():
     avg_launch_s = iter_ms / 1e3 / passes
     per_launch = algorithmic_bytes(n, E, data.size, p)
     achieved = per_launch / avg_launch_s / 1e9
-    traffic = kernel_traffic(per_launch)
+    traffic = kernel_traffic(args.config, p, depth)
     line = {
         "metric": METRIC,
         "value": value,

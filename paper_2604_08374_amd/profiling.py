@@ -1,0 +1,136 @@
+"""Summaries of rocprofv3 output for the HyperBall kernels.
+
+Reads the CSV output of three rocprofv3 runs of the same command -- one with
+``--kernel-trace --stats``, one with ``--pmc FETCH_SIZE``, one with ``--pmc WRITE_SIZE``
+-- and writes a short text summary: per-kernel call counts and average durations,
+the byte counters per dispatch, the counter scale factors measured on the library's
+plain copy kernel (which moves a known number of bytes), and the resulting HBM bytes
+per union launch.  The summary also records the SHA-256 of the kernel source it was
+taken on, so a later benchmark reports the traffic only while the kernel is unchanged.
+
+Usage:
+    python -m paper_2604_08374_amd.profiling --trace DIR --fetch DIR --write DIR \\
+        --copy-bytes N --cmd "..." --out profiles/NAME.md --counters profiles/NAME.txt
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "hb_kernels.hip")
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def _short(name: str) -> str:
+    for key in ("union_kernel", "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
+        if key in name:
+            tmpl = name[name.index(key) + len(key):]
+            if tmpl.startswith("<"):
+                return key + tmpl[:tmpl.index(">") + 1]
+            return key
+    return name[:48]
+
+
+def kernel_stats(trace_dir: str):
+    rows = {}
+    with open(_find(trace_dir, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows[_short(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]),
+                                      float(r["TotalDurationNs"]))
+    return rows
+
+
+def counter_means(pmc_dir: str):
+    acc = defaultdict(list)
+    with open(_find(pmc_dir, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            acc[(_short(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def kernel_sha256() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--kernel", default="union_kernel<10>")
+    ap.add_argument("--algo-bytes", type=int, default=0,
+                    help="algorithmic bytes per launch of --kernel (from bench.py)")
+    ap.add_argument("--cmd", action="append", default=[])
+    ap.add_argument("--title", default="union kernel")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--counters", required=True)
+    args = ap.parse_args()
+
+    stats = kernel_stats(args.trace)
+    fetch = counter_means(args.fetch)
+    write = counter_means(args.write)
+    copy_kib = args.copy_bytes / 1024.0
+    f_fetch = copy_kib / fetch[("copy_kernel", "FETCH_SIZE")][1]
+    f_write = copy_kib / write[("copy_kernel", "WRITE_SIZE")][1]
+    k = args.kernel
+    calls, avg_ns, _ = stats[k]
+    fetch_kib = fetch[(k, "FETCH_SIZE")][1]
+    write_kib = write[(k, "WRITE_SIZE")][1]
+    read_b = fetch_kib * 1024 * f_fetch
+    write_b = write_kib * 1024 * f_write
+    traffic = read_b + write_b
+    sha = kernel_sha256()
+
+    lines = [f"# rocprofv3 summary: {args.title}", ""]
+    lines += ["Commands (run from the repository root; each writes CSV under gpurun_out/):", ""]
+    lines += [f"    {c}" for c in args.cmd]
+    lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
+              "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
+    for name, (c, a, t) in sorted(stats.items(), key=lambda kv: -kv[1][2]):
+        lines.append(f"| {name} | {c} | {a / 1e6:.3f} | {t / 1e6:.1f} |")
+    lines += ["", "## Byte counters per dispatch (KiB, mean over dispatches)", "",
+              "| kernel | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|"]
+    names = sorted({n for n, _ in fetch} | {n for n, _ in write})
+    for n in names:
+        fv = fetch.get((n, "FETCH_SIZE"), (0, float("nan")))[1]
+        wv = write.get((n, "WRITE_SIZE"), (0, float("nan")))[1]
+        lines.append(f"| {n} | {fv:.1f} | {wv:.1f} |")
+    lines += ["", "## Derived", "",
+              f"* copy kernel moves {args.copy_bytes} B each way per dispatch: FETCH_SIZE scale "
+              f"{f_fetch:.4f}, WRITE_SIZE scale {f_write:.4f}",
+              f"* {k}: average duration {avg_ns / 1e6:.3f} ms over {calls} calls",
+              f"* {k}: HBM read {read_b / 1e12:.4f} TB + write {write_b / 1e12:.4f} TB = "
+              f"{traffic / 1e12:.4f} TB per launch -> {traffic / (avg_ns * 1e-9) / 1e9:.0f} GB/s"]
+    if args.algo_bytes:
+        lines.append(f"* algorithmic bytes per launch {args.algo_bytes / 1e12:.4f} TB; measured "
+                     f"traffic / algorithmic = {traffic / args.algo_bytes:.3f}")
+    lines += [f"* kernel source sha256 {sha}", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    with open(args.counters, "w") as f:
+        f.write(f"kernel {k}\n")
+        f.write(f"kernel_source_sha256 {sha}\n")
+        f.write(f"avg_launch_ns {avg_ns:.0f}\n")
+        f.write(f"fetch_kib_per_launch {fetch_kib:.3f}\n")
+        f.write(f"write_kib_per_launch {write_kib:.3f}\n")
+        f.write(f"fetch_scale {f_fetch:.6f}\n")
+        f.write(f"write_scale {f_write:.6f}\n")
+        f.write(f"hbm_bytes_per_launch {traffic:.0f}\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
