@@ -50,18 +50,26 @@ def make_graph(config: str, seed: int):
     return g
 
 
-def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int) -> int:
+def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None) -> int:
     """Bytes one union launch must move at minimum without reuse.
 
-    Per directed edge: one neighbour counter (m bytes) plus its LEB128 bytes; per
+    Per gathered counter row: m bytes -- one per directed edge for the per-edge
+    kernel, or `rows` table rows for the run kernel; the whole LEB128 stream; per
     node: the offsets entry (8 B), its own counter read and next[v] written (2m),
     and the FP64 state c_prev and sum_d read and written (32 B).
     """
     m = 1 << p
-    return n_edges * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
+    gathered = n_edges if rows is None else rows
+    return gathered * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
 
 
-def kernel_traffic(config: str, p: int, depth: int):
+def table_bytes(n: int, p: int, levels: int) -> int:
+    """Range-max table build per step: level k reads two rows and writes one per i."""
+    m = 1 << p
+    return sum(3 * (n - (1 << k) + 1) * m for k in range(1, levels + 1))
+
+
+def kernel_traffic(config: str, p: int, depth: int, kernel: str):
     """HBM bytes per union launch from the committed rocprofv3 counter summary.
 
     The summary was taken on the default workload (city graph, p = 10, depth 3);
@@ -78,6 +86,8 @@ def kernel_traffic(config: str, p: int, depth: int):
         return None
     if rec.get("kernel_source_sha256", "").strip() != src_hash:
         return None  # the kernel changed since the counters were taken
+    if rec.get("kernel", "").strip() != kernel:
+        return None
     return float(rec["hbm_bytes_per_launch"])
 
 
@@ -123,6 +133,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "edges", "runs"],
+                    help="union kernel: per edge, per run from a range-max table, or the "
+                         "library's choice")
+    ap.add_argument("--table-levels", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 4 GiB device copy (measured bandwidth)")
     args = ap.parse_args()
@@ -145,31 +159,40 @@ def main():
     t0 = time.perf_counter()
     G = hb.graph_load(off, deg, data)
     log(f"hb_graph_load (validate + copy to HBM) in {time.perf_counter() - t0:.1f}s")
+    stats = G.stats()
 
     p, depth = args.p, args.depth
+    kw = dict(kernel=args.kernel, table_levels=args.table_levels)
     for i in range(args.warmup):
-        r = G.run(p, depth, args.seed)
-        log(f"warmup {i}: passes={r.passes} run_ms={r.run_ms:.1f} iter_ms={r.iter_ms:.1f}")
+        r = G.run(p, depth, args.seed, **kw)
+        log(f"warmup {i}: kernel={r.union_kernel} K={r.table_levels} passes={r.passes} "
+            f"run_ms={r.run_ms:.1f} iter_ms={r.iter_ms:.1f} table_ms={r.table_ms:.1f}")
 
     passes = 0
-    iter_ms = 0.0
+    iter_ms = table_ms = 0.0
     results = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = G.run(p, depth, args.seed)
+        r = G.run(p, depth, args.seed, **kw)
         results.append(r)
         passes += r.passes
         iter_ms += r.iter_ms
-        log(f"step {i}: passes={r.passes} converged={r.converged} run_ms={r.run_ms:.1f} "
-            f"iter_ms={r.iter_ms:.1f}")
+        table_ms += r.table_ms
+        log(f"step {i}: kernel={r.union_kernel} passes={r.passes} converged={r.converged} "
+            f"run_ms={r.run_ms:.1f} iter_ms={r.iter_ms:.1f} table_ms={r.table_ms:.1f}")
     elapsed = time.perf_counter() - t0
 
     unions = passes * E
     value = unions / elapsed
     avg_launch_s = iter_ms / 1e3 / passes
-    per_launch = algorithmic_bytes(n, E, data.size, p)
+    kernel = results[-1].union_kernel
+    levels = results[-1].table_levels
+    rows = stats["table_rows"][levels] if kernel == "runs" else None
+    per_launch = algorithmic_bytes(n, E, data.size, p, rows)
     achieved = per_launch / avg_launch_s / 1e9
-    traffic = kernel_traffic(args.config, p, depth)
+    kname = f"union_runs_kernel<{p}>" if kernel == "runs" else f"union_kernel<{p}>"
+    traffic = kernel_traffic(args.config, p, depth, kname)
+    edge_equiv = algorithmic_bytes(n, E, data.size, p) / avg_launch_s / 1e9
     line = {
         "metric": METRIC,
         "value": value,
@@ -191,19 +214,29 @@ def main():
             "p": p,
             "depth_limit": depth,
             "passes_per_step": results[-1].passes,
+            "union_kernel": kernel,
+            "table_levels": levels,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "union_kernel (fused decode + gather-max + estimate + accumulate)",
+            "kernel": f"{kname} (fused decode + gather-max + estimate + accumulate)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": per_launch,
+            "gathered_rows_per_launch": rows if rows is not None else E,
             "avg_launch_ms": avg_launch_s * 1e3,
+            "per_edge_equivalent_gbs": edge_equiv,
         },
     }
+    if kernel == "runs":
+        tb = table_bytes(n, p, levels)
+        t_s = table_ms / 1e3 / passes
+        line["table_build"] = {"bytes_per_step": tb, "avg_ms": t_s * 1e3,
+                               "achieved_gbs": tb / t_s / 1e9 if t_s > 0 else None,
+                               "runs": stats["n_runs"]}
     if args.copy_probe:
         nbytes = 4 << 30
         ms = hb.copy_probe(nbytes, 10)

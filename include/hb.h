@@ -83,10 +83,31 @@ typedef struct {
     uint64_t edge_unions;  /* passes * n_edges */
     double init_ms;        /* device time of the initialisation kernel */
     double iter_ms;        /* device time summed over the passes union kernels */
+    double table_ms;       /* device time summed over range-max table builds (run kernel) */
     double run_ms;         /* device time from init start to the last union end */
+    uint32_t union_kernel; /* kernel that ran: HB_UNION_EDGES or HB_UNION_RUNS */
+    uint32_t table_levels; /* table levels K used by the run kernel (0 otherwise) */
     uint64_t t_start_ns;   /* host CLOCK_MONOTONIC at call entry */
     uint64_t t_end_ns;     /* host CLOCK_MONOTONIC when results were written */
 } hb_result;
+
+/* Which union kernel a run uses. */
+#define HB_UNION_AUTO 0  /* the run kernel when p <= 12 and its table fits, else per edge */
+#define HB_UNION_EDGES 1 /* gather every neighbour's counter (Eq. 2 as written) */
+#define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table */
+
+/*
+ * Run options; an all-zero struct (or NULL) selects the defaults.
+ * table_levels: the run kernel builds, every step, table levels 1..K with
+ * T[k][i] = max of the counters i .. i + 2^k - 1 (K = table_levels, default 7,
+ * capped at floor(log2 n)), costing K * n * 2^p extra bytes per counter
+ * buffer.  A run of r <= 2^K consecutive neighbour ids then costs at most two
+ * counter-row loads instead of r.  The registers are identical either way.
+ */
+typedef struct {
+    uint32_t union_kernel; /* HB_UNION_* */
+    uint32_t table_levels; /* 0 = default */
+} hb_run_opts;
 
 /* Library version string. */
 const char *hb_version(void);
@@ -135,6 +156,23 @@ hb_status hb_graph_free(hb_graph *g);
 hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint64_t *n_bytes);
 
 /*
+ * Shape of a loaded graph, counted during hb_graph_load: runs are maximal
+ * sequences of consecutive neighbour ids in a row (joined across the row's own
+ * node); table_rows[K] is the number of counter rows one step of the run
+ * kernel loads with a table of depth K (1 per run whose length is a power of
+ * two <= 2^K, 2 per other run <= 2^K, ceil(length / 2^K) per longer run).
+ */
+typedef struct {
+    uint32_t n;
+    uint64_t n_edges;
+    uint64_t n_bytes;
+    uint64_t n_runs;
+    uint64_t table_rows[25];
+} hb_graph_stats_t;
+
+hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out);
+
+/*
  * Run HyperBall (Alg. 1) on a loaded graph: insert every node v into its own
  * counter, then for t = 1, 2, ...: union (Eq. 2), estimate, accumulate (Eq. 3),
  * stop after step t when no estimate grew by more than 0.5 or t ==
@@ -145,6 +183,13 @@ hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint6
  */
 hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                  hb_result *out);
+
+/*
+ * hb_run with explicit options (opts may be NULL).  HB_EINVAL if the run
+ * kernel is requested for p > 12 or table_levels > 24.
+ */
+hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                      const hb_run_opts *opts, hb_result *out);
 
 /*
  * Diagnostic: a plain streaming copy of `bytes` (a multiple of 16) between two

@@ -48,8 +48,22 @@ class _Result(ctypes.Structure):
                 ("passes", ctypes.c_uint32), ("converged", ctypes.c_uint32),
                 ("c0", ctypes.c_double), ("edge_unions", ctypes.c_uint64),
                 ("init_ms", ctypes.c_double), ("iter_ms", ctypes.c_double),
-                ("run_ms", ctypes.c_double), ("t_start_ns", ctypes.c_uint64),
-                ("t_end_ns", ctypes.c_uint64)]
+                ("table_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
+                ("t_start_ns", ctypes.c_uint64), ("t_end_ns", ctypes.c_uint64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("n_bytes", ctypes.c_uint64),
+                ("n_runs", ctypes.c_uint64), ("table_rows", ctypes.c_uint64 * 25)]
+
+
+class _RunOpts(ctypes.Structure):
+    _fields_ = [("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32)]
+
+
+UNION_AUTO, UNION_EDGES, UNION_RUNS = 0, 1, 2
+_KERNELS = {"auto": UNION_AUTO, "edges": UNION_EDGES, "runs": UNION_RUNS}
 
 
 def lib_path() -> str:
@@ -84,6 +98,12 @@ def _lib():
         L.hb_run.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                              ctypes.POINTER(_Result)]
         L.hb_run.restype = st
+        L.hb_graph_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Stats)]
+        L.hb_graph_stats.restype = st
+        L.hb_run_with.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint64, ctypes.POINTER(_RunOpts),
+                                  ctypes.POINTER(_Result)]
+        L.hb_run_with.restype = st
         L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
         L.hb_copy_probe.restype = st
         _LIB = L
@@ -178,7 +198,10 @@ class Result:
     edge_unions: int
     init_ms: float
     iter_ms: float
+    table_ms: float
     run_ms: float
+    union_kernel: str
+    table_levels: int
     t_start_ns: int
     t_end_ns: int
 
@@ -195,6 +218,13 @@ class Graph:
         n, e, b = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
         _check(_lib().hb_graph_info(h, ctypes.byref(n), ctypes.byref(e), ctypes.byref(b)))
         self.n, self.n_edges, self.n_bytes = int(n.value), int(e.value), int(b.value)
+
+    def stats(self) -> dict:
+        """hb_graph_stats: runs of consecutive ids and table rows per step for each depth K."""
+        st = _Stats()
+        _check(_lib().hb_graph_stats(self._h, ctypes.byref(st)))
+        return {"n": st.n, "n_edges": st.n_edges, "n_bytes": st.n_bytes, "n_runs": st.n_runs,
+                "table_rows": [int(x) for x in st.table_rows]}
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -214,8 +244,11 @@ class Graph:
         self.free()
 
     def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
-            outputs: bool = True) -> Result:
-        """hb_run: HyperBall with precision p; depth_limit 0 = until convergence."""
+            outputs: bool = True, kernel: str = "auto", table_levels: int = 0) -> Result:
+        """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
+
+        kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
+        """
         if self._h is None:
             raise HBError(HB_EINVAL, "graph was freed")
         n = self.n
@@ -228,10 +261,14 @@ class Graph:
         r.sum_d = _ptr(sum_d, ctypes.c_double)
         r.mean_depth = _ptr(md, ctypes.c_double)
         r.registers = _ptr(regs, ctypes.c_uint8)
-        _check(_lib().hb_run(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(r)))
+        o = _RunOpts(_KERNELS[kernel], table_levels)
+        _check(_lib().hb_run_with(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
+                                  ctypes.byref(o), ctypes.byref(r)))
+        name = {UNION_EDGES: "edges", UNION_RUNS: "runs"}.get(int(r.union_kernel), "?")
         return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
-                      int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.run_ms),
-                      int(r.t_start_ns), int(r.t_end_ns))
+                      int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
+                      float(r.run_ms), name, int(r.table_levels), int(r.t_start_ns),
+                      int(r.t_end_ns))
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
@@ -245,5 +282,6 @@ def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:
     return Graph(offsets, degrees, data, comp_size, n_edges)
 
 
-def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False) -> Result:
-    return g.run(p, depth_limit, seed, registers)
+def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
+        kernel: str = "auto", table_levels: int = 0) -> Result:
+    return g.run(p, depth_limit, seed, registers, kernel=kernel, table_levels=table_levels)

@@ -90,9 +90,34 @@ uint8_t *uleb_put(uint32_t v, uint8_t *out) {
     return out;
 }
 
-// Check one compressed row; returns true if valid.
-bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32_t degree) {
-    uint64_t prev = 0;
+constexpr int kMaxLevels = 24;
+
+// Runs of consecutive neighbour ids (joined across the node itself) and, for
+// every table depth K, the table rows the run kernel loads to cover them.
+struct RunCounts {
+    uint64_t runs = 0;
+    uint64_t lookups[kMaxLevels + 1] = {};
+    void add(uint64_t r) {
+        ++runs;
+        for (int k = 0; k <= kMaxLevels; ++k) {
+            const uint64_t top = 1ull << k;
+            if (r <= top) {
+                lookups[k] += (r & (r - 1)) == 0 ? 1 : 2;  // one row if r is a power of two
+            } else {
+                lookups[k] += (r + top - 1) / top;
+            }
+        }
+    }
+    void merge(const RunCounts &o) {
+        runs += o.runs;
+        for (int k = 0; k <= kMaxLevels; ++k) lookups[k] += o.lookups[k];
+    }
+};
+
+// Check one compressed row; returns true if valid.  Counts runs into rc.
+bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32_t degree,
+            RunCounts *rc = nullptr) {
+    uint64_t prev = 0, run_start = 0;
     uint32_t count = 0;
     while (p < end) {
         uint32_t val = 0;
@@ -113,9 +138,15 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
             id = prev + val;
         }
         if (id >= n || id == v) return false;
+        if (rc) {
+            const bool joins = count > 0 && (id == prev + 1 || (id == prev + 2 && prev + 1 == v));
+            if (count > 0 && !joins) rc->add(prev - run_start + 1);
+            if (count == 0 || !joins) run_start = id;
+        }
         prev = id;
         if (++count > degree) return false;
     }
+    if (rc && count > 0) rc->add(prev - run_start + 1);
     return count == degree;
 }
 
@@ -124,6 +155,7 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
 struct hb_graph {
     uint32_t n = 0;
     uint64_t n_edges = 0, n_bytes = 0;
+    RunCounts runs;
     int device = 0;
     std::vector<uint32_t> comp_size;  // empty: one component of n
     uint8_t *d_bytes = nullptr;
@@ -136,7 +168,7 @@ struct hb_graph {
     uint64_t n_flags = 0;
     uint32_t *h_flag = nullptr;  // pinned
     hipStream_t stream = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -166,6 +198,54 @@ hb_status have_device() {
     return HB_OK;
 }
 
+}  // namespace
+
+namespace {
+hb_status validate_impl(const hb_csr *csr, uint32_t *bad_node, RunCounts *rc_out) {
+    if (bad_node) *bad_node = 0;
+    if (!csr) return fail(HB_EINVAL, "csr is NULL");
+    const uint32_t n = csr->n;
+    if (n == 0) return fail(HB_EINVAL, "n must be >= 1");
+    if (!csr->offsets || !csr->degrees) return fail(HB_EINVAL, "offsets/degrees NULL");
+    if (csr->offsets[0] != 0) {
+        if (bad_node) *bad_node = 0;
+        return fail(HB_ECORRUPT, "offsets[0] != 0");
+    }
+    if (csr->offsets[n] > 0 && !csr->bytes) return fail(HB_EINVAL, "bytes is NULL");
+    std::atomic<uint32_t> bad{UINT32_MAX};
+    std::atomic<uint64_t> deg_sum{0};
+    std::mutex rc_mu;
+    parallel_ranges(n, [&](uint64_t lo, uint64_t hi) {
+        uint64_t s = 0;
+        RunCounts rc;
+        for (uint64_t v = lo; v < hi; ++v) {
+            const uint64_t a = csr->offsets[v], b = csr->offsets[v + 1];
+            s += csr->degrees[v];
+            if (b < a || !row_ok(csr->bytes + a, csr->bytes + b, (uint32_t)v, n, csr->degrees[v],
+                                 rc_out ? &rc : nullptr)) {
+                uint32_t cur = bad.load();
+                while ((uint32_t)v < cur && !bad.compare_exchange_weak(cur, (uint32_t)v)) {
+                }
+                return;
+            }
+        }
+        deg_sum += s;
+        if (rc_out) {
+            std::lock_guard<std::mutex> lk(rc_mu);
+            rc_out->merge(rc);
+        }
+    });
+    if (bad != UINT32_MAX) {
+        if (bad_node) *bad_node = bad;
+        return fail(HB_ECORRUPT, "row %u of the compressed CSR is malformed", (unsigned)bad.load());
+    }
+    if (deg_sum != csr->n_edges) {
+        if (bad_node) *bad_node = n;
+        return fail(HB_ECORRUPT, "degree sum %llu != n_edges %llu",
+                    (unsigned long long)deg_sum.load(), (unsigned long long)csr->n_edges);
+    }
+    return HB_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -239,48 +319,15 @@ hb_status hb_csr_encode(uint32_t n, const uint64_t *adj_offsets, const uint32_t 
 }
 
 hb_status hb_csr_validate(const hb_csr *csr, uint32_t *bad_node) {
-    if (bad_node) *bad_node = 0;
-    if (!csr) return fail(HB_EINVAL, "csr is NULL");
-    const uint32_t n = csr->n;
-    if (n == 0) return fail(HB_EINVAL, "n must be >= 1");
-    if (!csr->offsets || !csr->degrees) return fail(HB_EINVAL, "offsets/degrees NULL");
-    if (csr->offsets[0] != 0) {
-        if (bad_node) *bad_node = 0;
-        return fail(HB_ECORRUPT, "offsets[0] != 0");
-    }
-    if (csr->offsets[n] > 0 && !csr->bytes) return fail(HB_EINVAL, "bytes is NULL");
-    std::atomic<uint32_t> bad{UINT32_MAX};
-    std::atomic<uint64_t> deg_sum{0};
-    parallel_ranges(n, [&](uint64_t lo, uint64_t hi) {
-        uint64_t s = 0;
-        for (uint64_t v = lo; v < hi; ++v) {
-            const uint64_t a = csr->offsets[v], b = csr->offsets[v + 1];
-            s += csr->degrees[v];
-            if (b < a || !row_ok(csr->bytes + a, csr->bytes + b, (uint32_t)v, n, csr->degrees[v])) {
-                uint32_t cur = bad.load();
-                while ((uint32_t)v < cur && !bad.compare_exchange_weak(cur, (uint32_t)v)) {
-                }
-                return;
-            }
-        }
-        deg_sum += s;
-    });
-    if (bad != UINT32_MAX) {
-        if (bad_node) *bad_node = bad;
-        return fail(HB_ECORRUPT, "row %u of the compressed CSR is malformed", (unsigned)bad.load());
-    }
-    if (deg_sum != csr->n_edges) {
-        if (bad_node) *bad_node = n;
-        return fail(HB_ECORRUPT, "degree sum %llu != n_edges %llu",
-                    (unsigned long long)deg_sum.load(), (unsigned long long)csr->n_edges);
-    }
-    return HB_OK;
+    return validate_impl(csr, bad_node, nullptr);
 }
+
 
 hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
     if (!out) return fail(HB_EINVAL, "out is NULL");
     *out = nullptr;
-    hb_status st = hb_csr_validate(csr, nullptr);
+    RunCounts rc;
+    hb_status st = validate_impl(csr, nullptr, &rc);
     if (st != HB_OK) return st;
     if (csr->comp_size)
         for (uint32_t v = 0; v < csr->n; ++v)
@@ -293,6 +340,7 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
     g->n = csr->n;
     g->n_edges = csr->n_edges;
     g->n_bytes = csr->offsets[csr->n];
+    g->runs = rc;
     (void)hipGetDevice(&g->device);
     if (csr->comp_size) g->comp_size.assign(csr->comp_size, csr->comp_size + csr->n);
     auto bail = [&](hipError_t e, const char *what) {
@@ -343,16 +391,55 @@ hb_status hb_graph_info(const hb_graph *g, uint32_t *n, uint64_t *n_edges, uint6
     return HB_OK;
 }
 
+hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out) {
+    if (!g || !out) return fail(HB_EINVAL, "NULL argument");
+    out->n = g->n;
+    out->n_edges = g->n_edges;
+    out->n_bytes = g->n_bytes;
+    out->n_runs = g->runs.runs;
+    for (int k = 0; k <= kMaxLevels; ++k) out->table_rows[k] = g->runs.lookups[k];
+    return HB_OK;
+}
+
 hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                  hb_result *out) {
+    return hb_run_with(g, p, depth_limit, hash_seed, nullptr, out);
+}
+
+hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                      const hb_run_opts *opts, hb_result *out) {
     const uint64_t t_start = now_ns();
     if (!g || !out) return fail(HB_EINVAL, "NULL argument");
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
+    const hb_run_opts o = opts ? *opts : hb_run_opts{0u, 0u};
+    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
+    if (o.union_kernel == HB_UNION_RUNS && p > 12)
+        return fail(HB_EINVAL, "the run kernel supports p <= 12");
+    if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     std::lock_guard<std::mutex> lk(g_dev_mu);
     HB_HIP(hipSetDevice(g->device));
     const uint32_t n = g->n;
     const uint64_t m = 1ull << p;
-    const uint64_t need = (uint64_t)n * m;
+
+    // kernel choice and table depth
+    uint32_t levels = o.table_levels ? o.table_levels : 7u;
+    uint32_t lg = 0;
+    while ((2ull << lg) <= n) ++lg;  // floor(log2 n)
+    levels = std::min(levels, lg);
+    bool runs = (o.union_kernel == HB_UNION_RUNS) || (o.union_kernel == HB_UNION_AUTO && p <= 12);
+    if (runs && (uint64_t)(levels + 1) * n >= (1ull << 32)) {
+        if (o.union_kernel == HB_UNION_RUNS)
+            return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
+        runs = false;
+    }
+    if (runs && o.union_kernel == HB_UNION_AUTO) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            const uint64_t want = 2ull * (levels + 1) * n * m;
+            if (want > (uint64_t)free_b + g->cnt_bytes * 2 || want > (64ull << 30)) runs = false;
+        }
+    }
+    const uint64_t need = (uint64_t)n * m * (runs ? (levels + 1u) : 1u);
     if (g->cnt_bytes < need) {
         (void)hipFree(g->d_cnt[0]);
         (void)hipFree(g->d_cnt[1]);
@@ -377,19 +464,27 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
     HB_HIP(hbk::launch_init((int)p, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
     HB_HIP(hipEventRecord(g->ev[1], s));
 
-    double iter_ms = 0.0;
+    double iter_ms = 0.0, table_ms = 0.0;
     uint32_t t = 0, converged = 0;
     for (;;) {
         ++t;
         HB_HIP(hipEventRecord(g->ev[2], s));
-        HB_HIP(hbk::launch_union((int)p, g->d_bytes, g->d_offsets, cur, next, g->d_cprev,
-                                 g->d_sumd, g->d_flags + t, n, t, s));
+        if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
         HB_HIP(hipEventRecord(g->ev[3], s));
+        if (runs)
+            HB_HIP(hbk::launch_union_runs((int)p, g->d_bytes, g->d_offsets, cur, levels, next,
+                                          g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
+        else
+            HB_HIP(hbk::launch_union((int)p, g->d_bytes, g->d_offsets, cur, next, g->d_cprev,
+                                     g->d_sumd, g->d_flags + t, n, t, s));
+        HB_HIP(hipEventRecord(g->ev[4], s));
         HB_HIP(hipMemcpyAsync(g->h_flag, g->d_flags + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HB_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
-        HB_HIP(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
+        HB_HIP(hipEventElapsedTime(&ms, g->ev[3], g->ev[4]));
         iter_ms += ms;
+        HB_HIP(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
+        table_ms += ms;
         if (*g->h_flag == 0u) {
             converged = 1;
             break;
@@ -400,7 +495,7 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
     }
     float init_ms = 0.f, run_ms = 0.f;
     HB_HIP(hipEventElapsedTime(&init_ms, g->ev[0], g->ev[1]));
-    HB_HIP(hipEventElapsedTime(&run_ms, g->ev[0], g->ev[3]));
+    HB_HIP(hipEventElapsedTime(&run_ms, g->ev[0], g->ev[4]));
 
     if (out->reach)
         HB_HIP(hipMemcpy(out->reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -419,7 +514,7 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
             }
     }
     if (out->registers)
-        HB_HIP(hipMemcpy(out->registers, next, need, hipMemcpyDeviceToHost));
+        HB_HIP(hipMemcpy(out->registers, next, (uint64_t)n * m, hipMemcpyDeviceToHost));
     const double md = (double)m;
     out->passes = t;
     out->converged = converged;
@@ -427,7 +522,10 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
     out->edge_unions = (uint64_t)t * g->n_edges;
     out->init_ms = init_ms;
     out->iter_ms = iter_ms;
+    out->table_ms = table_ms;
     out->run_ms = run_ms;
+    out->union_kernel = runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+    out->table_levels = runs ? levels : 0u;
     out->t_start_ns = t_start;
     out->t_end_ns = now_ns();
     return HB_OK;

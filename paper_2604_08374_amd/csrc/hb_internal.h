@@ -29,6 +29,20 @@ hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, co
                         uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
                         uint32_t n, uint32_t t, hipStream_t stream);
 
+// The same step from a range-max table of cur (level-major, level 0 = cur,
+// levels 1..levels built by launch_table): each run of consecutive neighbour
+// ids is covered by at most two table rows.  p <= 12.
+hipError_t launch_union_runs(int p, const uint8_t *bytes, const uint64_t *offsets,
+                             const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
+                             double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
+                             hipStream_t stream);
+
+// Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
+// i <= n - 2^k, rows of m bytes (m a multiple of 16), T[k] at tbl + k n m.
+// Requires 2^levels <= n.
+hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
+                        hipStream_t stream);
+
 // Streaming copy of bytes (a multiple of 16) from src to dst.
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 

@@ -258,44 +258,22 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restri
     }
 }
 
-// ---------------------------------------------------------------- union step
-template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
-    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
-    const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
-    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
-    using C = Cfg<P>;
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
-    if (v >= n) return;  // uniform per workgroup when WAVES > 1
-
-    const uint32_t grp = lane / C::LPC;
-
-    // own counter seeds the accumulator (Alg. 1: next[v] <- cur[v])
-    Max4 acc[C::RPL][4];
-    {
-        const uint8_t *own = cur + (uint64_t)v * C::M;
-#pragma unroll
-        for (int s = 0; s < C::RPL; ++s) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(own + slot_offset<P>(slice, lane, s));
-            acc[s][0].init(x.x);
-            acc[s][1].init(x.y);
-            acc[s][2].init(x.z);
-            acc[s][3].init(x.w);
-        }
-    }
-
-    const uint64_t row_beg = offsets[v], row_end = offsets[v + 1];
-    uint32_t run = 0;        // last absolute id decoded (prefix sum of values)
-    uint32_t carry_val = 0;  // bits of a varint continued from the previous chunk
+// ---------------------------------------------------------------- row decoding
+// Wave-cooperative LEB128 decoder of one CSR row, 64 bytes per call.  The
+// carried state (wave-uniform) is the running id (the prefix sum of the first
+// id and the deltas) and the bits of a varint that straddles two chunks.
+struct RowDecoder {
+    uint32_t run = 0;        // last absolute id decoded
+    uint32_t carry_val = 0;  // low bits of a varint continued from the previous chunk
     uint32_t carry_sh = 0;   // bit position where the carried varint continues
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    for (uint64_t base = row_beg; base < row_end; base += kWave) {
-        // ---- cooperative decode of 64 bytes
-        const bool valid = base + lane < row_end;
+    // Decode bytes[base, min(base + 64, end)).  Returns the decoded ids packed
+    // into lanes 0..cnt-1 in increasing order (other lanes: unspecified).
+    __device__ __forceinline__ uint32_t chunk(const uint8_t *__restrict__ bytes, uint64_t base,
+                                              uint64_t end, uint32_t &cnt) {
+        const uint32_t lane = lane_id();
+        const uint64_t lt_mask = (1ull << lane) - 1ull;
+        const bool valid = base + lane < end;
         const uint32_t b = valid ? (uint32_t)bytes[base + lane] : 0u;
         const uint64_t term = ballot(valid && !(b & 0x80u));
         const uint64_t cont = ballot(valid && (b & 0x80u));
@@ -328,83 +306,82 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
             carry_val = 0u;
             carry_sh = 0u;
         }
-        // pack the ids into lanes 0..cnt-1 (non-terminators park on lane 63,
-        // which is free whenever some lane is not a terminator)
-        const uint32_t cnt = (uint32_t)__builtin_popcountll(term);
+        // pack: terminator of rank r goes to lane r; non-terminators park on
+        // lane 63, which is free whenever some lane is not a terminator
+        cnt = (uint32_t)__builtin_popcountll(term);
         const uint32_t rank = (uint32_t)__builtin_popcountll(below);
-        const uint32_t ids = (uint32_t)__builtin_amdgcn_ds_permute(
+        return (uint32_t)__builtin_amdgcn_ds_permute(
             (int)((is_term ? rank : (uint32_t)(kWave - 1)) << 2), (int)id);
+    }
+};
 
-        // ---- gather-max over the cnt neighbours of this chunk
-        if (C::G == 1) {
-            for (uint32_t k = 0; k < cnt; k += C::U) {
-                const uint8_t *src[C::U];
+// ---------------------------------------------------------------- accumulator
+// This lane's share of one node's running register-wise max.
+template <int P>
+struct NodeAcc {
+    using C = Cfg<P>;
+    Max4 m[C::RPL][4];
+
+    __device__ __forceinline__ void init(const uint8_t *row, uint32_t slice, uint32_t lane) {
 #pragma unroll
-                for (int u = 0; u < C::U; ++u) {
-                    const uint32_t l = (k + u < cnt) ? k + u : k;
-                    const uint32_t w = readlane(ids, l);
-                    src[u] = cur + (uint64_t)w * C::M;
-                }
-                uint4 x[C::U][C::RPL];
-#pragma unroll
-                for (int u = 0; u < C::U; ++u)
-#pragma unroll
-                    for (int s = 0; s < C::RPL; ++s)
-                        x[u][s] = *reinterpret_cast<const uint4 *>(src[u] +
-                                                                   slot_offset<P>(slice, lane, s));
-#pragma unroll
-                for (int u = 0; u < C::U; ++u)
-#pragma unroll
-                    for (int s = 0; s < C::RPL; ++s) {
-                        acc[s][0].add(x[u][s].x);
-                        acc[s][1].add(x[u][s].y);
-                        acc[s][2].add(x[u][s].z);
-                        acc[s][3].add(x[u][s].w);
-                    }
-            }
-        } else {
-            // G groups gather G different neighbours per load
-            for (uint32_t k = 0; k < cnt; k += C::U * C::G) {
-                uint4 x[C::U];
-#pragma unroll
-                for (int u = 0; u < C::U; ++u) {
-                    const uint32_t idx = k + (uint32_t)u * C::G + grp;
-                    const uint32_t l = idx < cnt ? idx : k;
-                    const uint32_t w = shfl_idx(ids, l);
-                    x[u] = *reinterpret_cast<const uint4 *>(cur + (uint64_t)w * C::M +
-                                                             slot_offset<P>(0, lane, 0));
-                }
-#pragma unroll
-                for (int u = 0; u < C::U; ++u) {
-                    acc[0][0].add(x[u].x);
-                    acc[0][1].add(x[u].y);
-                    acc[0][2].add(x[u].z);
-                    acc[0][3].add(x[u].w);
-                }
-            }
+        for (int s = 0; s < C::RPL; ++s) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(row + slot_offset<P>(slice, lane, s));
+            m[s][0].init(x.x);
+            m[s][1].init(x.y);
+            m[s][2].init(x.z);
+            m[s][3].init(x.w);
         }
     }
 
-    // ---- final registers of this lane
+    // max with the counter rows at src[u] (this lane's slots), U rows
+    __device__ __forceinline__ void gather(const uint8_t *const (&src)[C::U], uint32_t slice,
+                                           uint32_t lane) {
+        uint4 x[C::U][C::RPL];
+#pragma unroll
+        for (int u = 0; u < C::U; ++u)
+#pragma unroll
+            for (int s = 0; s < C::RPL; ++s)
+                x[u][s] = *reinterpret_cast<const uint4 *>(src[u] + slot_offset<P>(slice, lane, s));
+#pragma unroll
+        for (int u = 0; u < C::U; ++u)
+#pragma unroll
+            for (int s = 0; s < C::RPL; ++s) {
+                m[s][0].add(x[u][s].x);
+                m[s][1].add(x[u][s].y);
+                m[s][2].add(x[u][s].z);
+                m[s][3].add(x[u][s].w);
+            }
+    }
+};
+
+// Final registers of node v: reduce the neighbour groups, store next[v],
+// estimate it, apply Eq. 3 and the 0.5 test.
+template <int P>
+__device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_t slice,
+                                            uint8_t *__restrict__ next,
+                                            double *__restrict__ c_prev,
+                                            double *__restrict__ sum_d,
+                                            uint32_t *__restrict__ flag_t, uint32_t t) {
+    using C = Cfg<P>;
+    const uint32_t lane = lane_id();
+    const uint32_t grp = lane / C::LPC;
     uint32_t reg[C::RPL][4];
 #pragma unroll
     for (int s = 0; s < C::RPL; ++s)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) reg[s][k] = acc[s][k].value();
+        for (int k = 0; k < 4; ++k) reg[s][k] = acc.m[s][k].value();
     if (C::G > 1) {
         // max across the groups that gathered different neighbours
 #pragma unroll
         for (uint32_t mask = C::LPC; mask < kWave; mask <<= 1)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                Max4 m;
-                m.init(reg[0][k]);
-                m.add(shfl_xor(reg[0][k], mask));
-                reg[0][k] = m.value();
+                Max4 mm;
+                mm.init(reg[0][k]);
+                mm.add(shfl_xor(reg[0][k], mask));
+                reg[0][k] = mm.value();
             }
     }
-
-    // ---- store next[v] and estimate it
     EstPart e;
     e.clear();
     if (grp == 0) {
@@ -419,15 +396,225 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
     }
     e.wave_reduce();
     const EstPart tot = node_total<P>(e, slice);
-
-    // ---- Eq. 3 accumulation and the 0.5 stopping test
     if (slice == 0 && lane == 0) {
         const double est = estimate<P>(tot);
         const double delta = est - c_prev[v];
         sum_d[v] = sum_d[v] + (double)t * delta;
         c_prev[v] = est;
-        if (delta > 0.5 && __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        if (delta > 0.5 &&
+            __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
             __hip_atomic_store(flag_t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------- union step, per edge
+// Eq. 2 as written: every neighbour's counter is gathered once per node.
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
+    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
+    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
+    using C = Cfg<P>;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    const uint32_t grp = lane / C::LPC;
+
+    NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v]
+    acc.init(cur + (uint64_t)v * C::M, slice, lane);
+
+    const uint64_t row_end = offsets[v + 1];
+    RowDecoder dec;
+    for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
+        uint32_t cnt;
+        const uint32_t ids = dec.chunk(bytes, base, row_end, cnt);
+        // gather-max over the cnt neighbours of this chunk; tail slots repeat
+        // the batch's first id (max is idempotent)
+        for (uint32_t k = 0; k < cnt; k += C::U * C::G) {
+            const uint8_t *src[C::U];
+#pragma unroll
+            for (int u = 0; u < C::U; ++u) {
+                if (C::G == 1) {
+                    const uint32_t l = (k + u < cnt) ? k + u : k;
+                    src[u] = cur + (uint64_t)readlane(ids, l) * C::M;
+                } else {
+                    const uint32_t idx = k + (uint32_t)u * C::G + grp;
+                    src[u] = cur + (uint64_t)shfl_idx(ids, idx < cnt ? idx : k) * C::M;
+                }
+            }
+            acc.gather(src, slice, lane);
+        }
+    }
+    finish_node<P>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
+}
+
+// ---------------------------------------------------------------- union step, per run
+// In raster order most of a node's neighbours come in runs of consecutive ids
+// (cells of one street segment in one raster row).  The max over a run [a, b]
+// equals the max of two rows of a range-max table built from cur for this step:
+// level k, row i holds max(cur[i .. i + 2^k)), so with k = floor(log2(b-a+1))
+// the run is max(T[k][a], T[k][b - 2^k + 1]) -- the two blocks overlap, which
+// max tolerates.  Runs longer than 2^K are covered by several level-K blocks.
+// Node v itself may sit inside a run (it is no neighbour of itself, but its own
+// counter is in the union anyway), so runs are joined across v.  The table is
+// laid out level-major right after the counters, T[k][i] at tbl + (k n + i) m,
+// and level 0 is cur itself.  The result is the same registers as the
+// per-edge kernel.
+constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
+constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
+
+template <int P>
+struct RunGather {
+    using C = Cfg<P>;
+    const uint8_t *tbl;
+    uint32_t n, levels;
+    uint32_t *q;   // this wave's LDS queue of table-row indices (k n + i)
+    uint32_t qn;   // entries queued (wave-uniform)
+
+    __device__ __forceinline__ void flush(NodeAcc<P> &acc, uint32_t lane) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t grp = lane / C::LPC;
+        for (uint32_t k = 0; k < qn; k += C::U * C::G) {
+            const uint8_t *src[C::U];
+#pragma unroll
+            for (int u = 0; u < C::U; ++u) {
+                const uint32_t idx = k + (uint32_t)u * (uint32_t)C::G + (C::G == 1 ? 0u : grp);
+                uint32_t row = q[idx < qn ? idx : k];
+                if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
+                src[u] = tbl + (uint64_t)row * C::M;
+            }
+            acc.gather(src, 0, lane);
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn = 0;
+    }
+
+    // queue the table rows covering run [a, b] (wave-uniform a, b)
+    __device__ __forceinline__ void push_run(NodeAcc<P> &acc, uint32_t a, uint32_t b,
+                                             uint32_t lane) {
+        const uint32_t r = b - a + 1u;
+        const uint32_t top = 1u << levels;
+        if (r <= top) {
+            const uint32_t k = 31u - (uint32_t)__builtin_clz(r);
+            if (qn + 2u > kQueueCap) flush(acc, lane);
+            if (lane == 0) {
+                q[qn] = k * n + a;
+                q[qn + 1] = k * n + (b - (1u << k) + 1u);
+            }
+            qn += (r == (1u << k)) ? 1u : 2u;
+            return;
+        }
+        for (uint32_t j = a;; j += top) {
+            const uint32_t i = (j + top - 1u < b) ? j : b - top + 1u;
+            if (qn + 1u > kQueueCap) flush(acc, lane);
+            if (lane == 0) q[qn] = levels * n + i;
+            qn += 1u;
+            if (i != j) break;
+            if (j + top - 1u == b) break;
+        }
+    }
+};
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void union_runs_kernel(
+    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
+    double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
+    uint32_t n, uint32_t t) {
+    using C = Cfg<P>;
+    static_assert(C::WAVES == 1, "the run kernel keeps one wave per node");
+    __shared__ uint32_t s_queue[C::NODES][kQueueCap];
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = blk * C::NODES + wave;
+    if (v >= n) return;
+
+    NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v] (level 0 of the table is cur)
+    acc.init(tbl + (uint64_t)v * C::M, 0, lane);
+    RunGather<P> g{tbl, n, levels, s_queue[wave], 0u};
+    const uint32_t top = 1u << levels;
+
+    bool have = false;      // a run is open: [ra, rl]
+    uint32_t ra = 0, rl = 0;
+    const uint64_t row_end = offsets[v + 1];
+    RowDecoder dec;
+    for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
+        uint32_t cnt;
+        const uint32_t ids = dec.chunk(bytes, base, row_end, cnt);
+        if (cnt == 0) continue;
+        const bool in = lane < cnt;
+        uint32_t prev = shfl_up(ids, 1);
+        if (lane == 0) prev = rl;
+        const bool has_prev = lane > 0 || have;
+        const bool joins = in && has_prev &&
+                           (ids == prev + 1u || (ids == prev + 2u && prev + 1u == v));
+        const uint64_t starts = ballot(in && !joins);
+        if (have && (starts & 1ull)) g.push_run(acc, ra, rl, lane);  // the open run ends
+        // start id of the run holding each lane: id at the last start lane <= lane
+        const uint64_t le = starts & ((2ull << lane) - 1ull);
+        const uint32_t sl = le ? 63u - (uint32_t)__builtin_clzll(le) : 0u;
+        uint32_t sid = shfl_idx(ids, sl);
+        if (!le) sid = ra;
+        // runs that end inside this chunk: lane e with a start at lane e + 1
+        const bool ends = (lane + 1u < cnt) && ((starts >> (lane + 1u)) & 1ull);
+        const uint32_t r = ids - sid + 1u;
+        const bool longrun = ends && r > top;
+        const uint32_t k = 31u - (uint32_t)__builtin_clz(r | 1u);
+        const uint32_t nl = (ends && !longrun) ? ((r == (1u << k)) ? 1u : 2u) : 0u;
+        uint32_t pos = nl;  // inclusive prefix sum of the lookups per lane
+#pragma unroll
+        for (uint32_t d = 1; d < kWave; d <<= 1) {
+            const uint32_t x = shfl_up(pos, d);
+            if (lane >= d) pos += x;
+        }
+        const uint32_t total = readlane(pos, kWave - 1);
+        if (g.qn > kQueueFlush) g.flush(acc, lane);
+        if (nl) {
+            const uint32_t at = g.qn + pos - nl;
+            g.q[at] = k * n + sid;
+            if (nl == 2u) g.q[at + 1] = k * n + (ids - (1u << k) + 1u);
+        }
+        g.qn += total;
+        uint64_t lm = ballot(longrun);
+        while (lm) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(lm);
+            lm &= lm - 1ull;
+            g.push_run(acc, readlane(sid, l), readlane(ids, l), lane);
+        }
+        // the last run of the chunk stays open
+        ra = readlane(sid, cnt - 1u);
+        rl = readlane(ids, cnt - 1u);
+        have = true;
+    }
+    if (have) g.push_run(acc, ra, rl, lane);
+    if (g.qn) g.flush(acc, lane);
+    finish_node<P>(acc, v, 0, next, c_prev, sum_d, flag_t, t);
+}
+
+// Level k of the range-max table from level k - 1:
+// T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]) for i <= n - 2^k.
+__global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ tbl,
+                                                          uint64_t level_bytes, uint32_t k,
+                                                          uint64_t count16, uint64_t half16) {
+    const uint4 *prev = reinterpret_cast<const uint4 *>(tbl + (uint64_t)(k - 1) * level_bytes);
+    uint4 *out = reinterpret_cast<uint4 *>(tbl + (uint64_t)k * level_bytes);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16; i += stride) {
+        const uint4 a = prev[i], b = prev[i + half16];
+        Max4 x, y, z, w;
+        x.init(a.x);
+        x.add(b.x);
+        y.init(a.y);
+        y.add(b.y);
+        z.init(a.z);
+        z.add(b.z);
+        w.init(a.w);
+        w.add(b.w);
+        out[i] = make_uint4(x.value(), y.value(), z.value(), w.value());
     }
 }
 
@@ -464,6 +651,17 @@ hipError_t launch_union_p(const uint8_t *bytes, const uint64_t *offsets, const u
     const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
     hipLaunchKernelGGL((union_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, bytes,
                        offsets, cur, next, c_prev, sum_d, flag_t, n, t);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_union_runs_p(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *tbl,
+                               uint32_t levels, uint8_t *next, double *c_prev, double *sum_d,
+                               uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream) {
+    using C = Cfg<P>;
+    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
+    hipLaunchKernelGGL((union_runs_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, bytes,
+                       offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t);
     return hipGetLastError();
 }
 
@@ -522,6 +720,43 @@ hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, co
         default: return hipErrorInvalidValue;
     }
 #undef HB_CALL_UNION
+}
+
+hipError_t launch_union_runs(int p, const uint8_t *bytes, const uint64_t *offsets,
+                             const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
+                             double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
+                             hipStream_t stream) {
+#define HB_CALL_RUNS(P) \
+    launch_union_runs_p<P>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t, stream)
+    switch (p) {
+        case 4: return HB_CALL_RUNS(4);
+        case 5: return HB_CALL_RUNS(5);
+        case 6: return HB_CALL_RUNS(6);
+        case 7: return HB_CALL_RUNS(7);
+        case 8: return HB_CALL_RUNS(8);
+        case 9: return HB_CALL_RUNS(9);
+        case 10: return HB_CALL_RUNS(10);
+        case 11: return HB_CALL_RUNS(11);
+        case 12: return HB_CALL_RUNS(12);
+        default: return hipErrorInvalidValue;
+    }
+#undef HB_CALL_RUNS
+}
+
+hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
+                        hipStream_t stream) {
+    const uint64_t level_bytes = (uint64_t)n * m;
+    for (uint32_t k = 1; k <= levels; ++k) {
+        const uint64_t rows = (uint64_t)n - (1ull << k) + 1ull;
+        const uint64_t count16 = rows * (m / 16u);
+        const uint64_t half16 = (1ull << (k - 1)) * (m / 16u);
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((count16 + 255) / 256, 256u * 64u);
+        hipLaunchKernelGGL(table_level_kernel, dim3(blocks), dim3(256), 0, stream, tbl, level_bytes,
+                           k, count16, half16);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream) {

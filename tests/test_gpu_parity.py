@@ -30,12 +30,18 @@ def _compare(res, ref, what):
     np.testing.assert_allclose(res.sum_d, ref.sum_d, rtol=RTOL, atol=1e-9, err_msg=what)
 
 
-def _check(hb, g, p, depth, seed=0):
-    print(f"[parity] {g.name} n={g.n} E={g.n_edges} p={p} depth={depth} seed={seed}", flush=True)
+def _check(hb, g, p, depth, seed=0, kernels=("edges", "runs"), table_levels=0):
+    """Every union kernel that supports p against the oracle."""
     ref = oracle.hyperball(oracle.from_graph(g), p, depth, seed)
     with _load(hb, g) as G:
-        res = G.run(p, depth, seed, registers=True)
-    _compare(res, ref, f"{g.name} p={p} d={depth} seed={seed}")
+        for kernel in kernels:
+            if kernel == "runs" and p > 12:
+                continue
+            print(f"[parity] {g.name} n={g.n} E={g.n_edges} p={p} depth={depth} seed={seed} "
+                  f"kernel={kernel} K={table_levels}", flush=True)
+            res = G.run(p, depth, seed, registers=True, kernel=kernel, table_levels=table_levels)
+            assert res.union_kernel == kernel
+            _compare(res, ref, f"{g.name} p={p} d={depth} seed={seed} {kernel}")
     return res, ref
 
 
@@ -82,6 +88,26 @@ def test_rect_rasters(hb, W, H, seed, p, depth):
     _check(hb, synth.grid_graph(seed, W, H), p, depth)
 
 
+@pytest.mark.parametrize("levels", [1, 2, 3, 5, 12])
+@pytest.mark.parametrize("p", [4, 9, 10])
+def test_run_kernel_table_depths(hb, levels, p):
+    """Shallow tables force long runs to be tiled by many level-K blocks."""
+    g = synth.urban_raster(4, 120, 90, cell_m=2.0)
+    g = synth.graph_from_raster(g, name="urban120x90")
+    _check(hb, g, p, 0, kernels=("runs",), table_levels=levels)
+
+
+def test_runs_joined_across_own_node(hb):
+    """Rows that skip only the node itself: one run through v, including v's counter."""
+    n = 300
+    edges = [(i, j) for i in range(n) for j in range(i + 1, min(n, i + 40))]
+    g = synth.from_edges(n, edges, name="band40")
+    _check(hb, g, 10, 0, table_levels=3)
+    with _load(hb, g) as G:
+        st = G.stats()
+    assert st["n_runs"] == n  # every row is one run once v is joined in
+
+
 def test_prefix_property(hb):
     """Registers of a depth-t run equal step t of a longer run (oracle: exact balls)."""
     g = synth.tiny(3)
@@ -100,10 +126,18 @@ def _sampled_check(hb, g, p, depth, n_src=64, seed=0):
     """GPU run on the whole graph; the oracle recomputes sampled nodes from exact balls."""
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
     csr = oracle.CSR(n=g.n, offsets=off, degrees=deg, bytes=data)
+    results = {}
     with hb.graph_load(off, deg, data) as G:
-        res = G.run(p, depth, seed, registers=True)
+        for kernel in ("runs", "edges"):
+            results[kernel] = G.run(p, depth, seed, registers=True, kernel=kernel)
+            print(f"[parity] {kernel}: passes={results[kernel].passes} "
+                  f"iter_ms={results[kernel].iter_ms:.1f}", flush=True)
+    res = results["runs"]
     T = res.passes
     assert depth == 0 or T <= depth
+    assert results["edges"].passes == T
+    assert np.array_equal(results["edges"].registers, res.registers)
+    assert np.array_equal(results["edges"].sum_d, res.sum_d)
     src = np.sort(np.random.default_rng(99).choice(g.n, n_src, replace=False))
     src = np.unique(np.concatenate([src, [0, g.n - 1, int(np.argmax(deg)), int(np.argmin(deg))]]))
     regs, reach, sum_d, _ = oracle.sampled_hyperball(csr, src, T, p, seed)
@@ -138,3 +172,18 @@ def _urban_graph():
     if "g" not in _URBAN:
         _URBAN["g"] = synth.urban(0, device="gpu")
     return _URBAN["g"]
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_city_sampled_bench_config(hb):
+    """The benchmark's workload and launch configuration: city graph, p = 10, depth 3."""
+    g = synth.city(0, device="gpu")
+    print(f"[parity] city n={g.n} E={g.n_edges} p=10 depth=3", flush=True)
+    res = _sampled_check(hb, g, 10, 3, n_src=64)
+    assert res.passes == 3
+    # properties at any size: registers never below a node's own insert, values <= 65-p
+    assert int(res.registers.max()) <= 55
+    for v in np.random.default_rng(5).choice(g.n, 200, replace=False):
+        j, r = oracle.hll_insert(int(v), 0, 10)
+        assert res.registers[v, j] >= r
