@@ -26,7 +26,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "HLL edge-unions/s + % HBM roofline (236k cells, p=10); p50/p99 latency, mixed load"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_kernel_city_p10_counters.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_runs_kernel_city_p10_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_08374_amd", "csrc", "hb_kernels.hip")
 
 

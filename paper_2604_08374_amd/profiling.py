@@ -33,7 +33,8 @@ def _find(d: str, suffix: str) -> str:
 
 
 def _short(name: str) -> str:
-    for key in ("union_kernel", "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
+    for key in ("union_runs_kernel", "union_kernel", "table_level_kernel", "init_kernel",
+                "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
         if key in name:
             tmpl = name[name.index(key) + len(key):]
             if tmpl.startswith("<"):
@@ -69,6 +70,7 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
+    ap.add_argument("--hit", default=None, help="optional --pmc TCC_HIT_sum TCC_MISS_sum run")
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--kernel", default="union_kernel<10>")
     ap.add_argument("--algo-bytes", type=int, default=0,
@@ -114,6 +116,13 @@ def main():
               f"* {k}: average duration {avg_ns / 1e6:.3f} ms over {calls} calls",
               f"* {k}: HBM read {read_b / 1e12:.4f} TB + write {write_b / 1e12:.4f} TB = "
               f"{traffic / 1e12:.4f} TB per launch -> {traffic / (avg_ns * 1e-9) / 1e9:.0f} GB/s"]
+    if args.hit:
+        hit = counter_means(args.hit)
+        h = hit.get((k, "TCC_HIT_sum"), (0, 0.0))[1]
+        mi = hit.get((k, "TCC_MISS_sum"), (0, 0.0))[1]
+        if h + mi > 0:
+            lines.append(f"* {k}: L2 hits {h:.4g}, misses {mi:.4g} per launch -> hit rate "
+                         f"{h / (h + mi):.3f}")
     if args.algo_bytes:
         lines.append(f"* algorithmic bytes per launch {args.algo_bytes / 1e12:.4f} TB; measured "
                      f"traffic / algorithmic = {traffic / args.algo_bytes:.3f}")
