@@ -122,9 +122,252 @@ def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
     }
 
 
+def batch_bench(args):
+    """Batched workload: 64 seeded graphs of uneven sizes with their own p and depth.
+
+    Times the same jobs as 64 sequential hb_run calls and as one hb_run_batch, checks
+    that every job's reach and sums are bit-identical, and reports both rates.
+    """
+    import paper_2604_08374_amd as hb
+    import synth
+
+    t0 = time.perf_counter()
+    Gs, jobs, edges = [], [], []
+    for seed in range(args.batch_jobs):
+        spec = synth.batch_spec(seed)
+        g = synth.batch_graph(seed)
+        off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+        G = hb.graph_load(off, deg, data)
+        Gs.append(G)
+        jobs.append((G, spec["p"], spec["depth"], seed))
+        edges.append(g.n_edges)
+    log(f"built {len(jobs)} graphs (n {min(G.n for G in Gs)}..{max(G.n for G in Gs)}, "
+        f"{sum(edges):.3g} edges) in {time.perf_counter() - t0:.1f}s")
+
+    def sequential():
+        return [G.run(p, d, sd, kernel=args.kernel) for (G, p, d, sd) in jobs]
+
+    def batched():
+        return hb.run_batch(jobs, kernel=args.kernel)
+
+    for _ in range(args.warmup):
+        sequential()
+        batched()
+    seq_t, bat_t = [], []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        rs = sequential()
+        seq_t.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        rb = batched()
+        bat_t.append(time.perf_counter() - t0)
+        for a, b in zip(rs, rb):
+            if a.passes != b.passes or not np.array_equal(a.sum_d, b.sum_d) or \
+                    not np.array_equal(a.reach, b.reach):
+                raise SystemExit("batched results differ from sequential runs")
+        log(f"step {i}: sequential {seq_t[-1] * 1e3:.1f} ms, batched {bat_t[-1] * 1e3:.1f} ms")
+    unions = sum(r.passes * e for r, e in zip(rb, edges))
+    seq_s, bat_s = float(np.median(seq_t)), float(np.median(bat_t))
+    line = {
+        "metric": "batched HLL edge-unions/s (64 uneven graphs, mixed p and depth)",
+        "value": unions / bat_s,
+        "unit": "edge-unions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": bat_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{len(jobs)} street/building graphs, seeds 0..{len(jobs) - 1}",
+                   "nodes_total": int(sum(G.n for G in Gs)), "directed_edges_total": int(sum(edges)),
+                   "union_kernel": args.kernel},
+        "sequential": {"value": unions / seq_s, "ms": seq_s * 1e3},
+        "speedup_vs_sequential": seq_s / bat_s,
+        "identical_results": True,
+    }
+    for G in Gs:
+        G.free()
+    print(json.dumps(line), flush=True)
+
+
+def serve_bench(args):
+    """Served workload: Poisson arrivals over a seeded pool of graphs, continuous batching.
+
+    The pool holds street/building graphs of 1,000-120,000 open cells (log-uniform,
+    the urban generator at 3 m cells); each
+    request draws (graph, p in {8, 10, 12}, depth in {3, unlimited}) from a seeded
+    stream, and about 10 % name a graph not yet on the device, which is generated
+    beforehand but uploaded on demand inside the request's latency.  The same trace is
+    replayed by a sequential FIFO baseline (one hb_run at a time, arrivals respected).
+    Latency = completion - arrival.  Reports p50/p99 per arrival rate and the
+    edge-unions/s of both, and checks that served results equal the baseline's.
+    """
+    import threading
+
+    import paper_2604_08374_amd as hb
+    import synth
+
+    rng = np.random.default_rng(4242)
+    pool_n = args.pool
+    t0 = time.perf_counter()
+    graphs = []
+    for k in range(pool_n):
+        seed = 1000 + k
+        g = synth.serve_graph(seed, n_lo=1000, n_hi=args.pool_max_nodes)
+        off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+        graphs.append(dict(seed=seed, n=g.n, edges=g.n_edges, csr=(off, deg, data)))
+    log(f"pool of {pool_n} graphs (n {min(x['n'] for x in graphs)}..{max(x['n'] for x in graphs)})"
+        f" built in {time.perf_counter() - t0:.1f}s")
+    fresh = set(rng.choice(pool_n, size=max(1, pool_n // 10), replace=False).tolist())
+    resident = {}
+    for k in range(pool_n):
+        if k not in fresh:
+            resident[k] = hb.graph_load(*graphs[k]["csr"])
+    # request trace
+    nreq = args.requests
+    req_graph = rng.integers(0, pool_n, nreq)
+    req_p = rng.choice([8, 10, 12], nreq)
+    req_d = rng.choice([3, 0], nreq)
+    req_seed = rng.integers(0, 2**62, nreq)
+
+    def service(i, G):
+        return G.run(int(req_p[i]), int(req_d[i]), int(req_seed[i]))
+
+    # mean sequential service time sets the arrival rates
+    t0 = time.perf_counter()
+    probe = list(range(min(nreq, 40)))
+    for i in probe:
+        G = resident.get(int(req_graph[i])) or hb.graph_load(*graphs[int(req_graph[i])]["csr"])
+        service(i, G)
+    mean_s = (time.perf_counter() - t0) / len(probe)
+    lam_seq = 1.0 / mean_s
+    log(f"mean sequential service {mean_s * 1e3:.2f} ms -> lambda_seq {lam_seq:.1f}/s")
+
+    def run_trace(arrivals, served):
+        """Replay arrivals; returns (latencies s, results, wall s)."""
+        lat = [None] * nreq
+        results = [None] * nreq
+        t_start = time.perf_counter()
+        uploads = {}
+        if served:
+            tickets = [None] * nreq
+            lock = threading.Lock()
+            done = threading.Event()
+            pending = {}
+
+            def poller():
+                while not done.is_set() or pending:
+                    with lock:
+                        items = list(pending.items())
+                    if not items:
+                        time.sleep(0.0002)
+                        continue
+                    for i, tk in items:
+                        r = tk.poll()
+                        if r is not None:
+                            lat[i] = time.perf_counter() - (t_start + arrivals[i])
+                            results[i] = r
+                            with lock:
+                                del pending[i]
+                    time.sleep(0.0001)
+
+            th = threading.Thread(target=poller)
+            th.start()
+            for i in range(nreq):
+                now = time.perf_counter() - t_start
+                if arrivals[i] > now:
+                    time.sleep(arrivals[i] - now)
+                k = int(req_graph[i])
+                G = resident.get(k) or uploads.get(k)
+                if G is None:
+                    G = uploads[k] = hb.graph_load(*graphs[k]["csr"])
+                tk = hb.submit(G, int(req_p[i]), int(req_d[i]), int(req_seed[i]))
+                with lock:
+                    pending[i] = tk
+            done.set()
+            th.join()
+        else:
+            for i in range(nreq):
+                now = time.perf_counter() - t_start
+                if arrivals[i] > now:
+                    time.sleep(arrivals[i] - now)
+                k = int(req_graph[i])
+                G = resident.get(k) or uploads.get(k)
+                if G is None:
+                    G = uploads[k] = hb.graph_load(*graphs[k]["csr"])
+                results[i] = service(i, G)
+                lat[i] = time.perf_counter() - (t_start + arrivals[i])
+        wall = time.perf_counter() - t_start
+        for G in uploads.values():
+            G.free()
+        return np.array(lat), results, wall
+
+    hb.server_start(hbm_budget=int(args.serve_budget_gb * (1 << 30)))
+    rows = []
+    total_unions = None
+    for f in args.rates:
+        lam = f * lam_seq
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, nreq))
+        lat_s, res_s, wall_s = run_trace(arrivals, served=True)
+        lat_q, res_q, wall_q = run_trace(arrivals, served=False)
+        for a, b in zip(res_s, res_q):
+            if a.passes != b.passes or not np.array_equal(a.sum_d, b.sum_d):
+                raise SystemExit("served results differ from sequential runs")
+        unions = sum(r.edge_unions for r in res_s)
+        total_unions = unions
+        rows.append({"rate_x_seq": f, "rate_per_s": lam,
+                     "served": {"p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                                "p99_ms": float(np.percentile(lat_s, 99) * 1e3),
+                                "edge_unions_per_s": unions / wall_s, "wall_s": wall_s},
+                     "sequential": {"p50_ms": float(np.percentile(lat_q, 50) * 1e3),
+                                    "p99_ms": float(np.percentile(lat_q, 99) * 1e3),
+                                    "edge_unions_per_s": unions / wall_q, "wall_s": wall_q}})
+        log(f"rate {f:.2f}x: served p50 {rows[-1]['served']['p50_ms']:.1f} ms p99 "
+            f"{rows[-1]['served']['p99_ms']:.1f} ms | sequential p50 "
+            f"{rows[-1]['sequential']['p50_ms']:.1f} ms p99 {rows[-1]['sequential']['p99_ms']:.1f} ms")
+    stats = hb.server_stats()
+    hb.server_stop()
+    for G in resident.values():
+        G.free()
+    top = rows[-1]
+    line = {
+        "metric": "served HLL edge-unions/s with p50/p99 latency (Poisson arrivals, mixed load)",
+        "value": top["served"]["edge_unions_per_s"],
+        "unit": "edge-unions/s",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 0,
+        "ms_per_step": top["served"]["wall_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{nreq} requests over a pool of {pool_n} graphs "
+                               f"(1,000-{args.pool_max_nodes} nodes), 10% uploaded on demand",
+                   "lambda_seq_per_s": lam_seq, "edge_unions_per_trace": total_unions},
+        "rates": rows,
+        "server": stats,
+        "identical_results": True,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+                    help="single: one graph (default); batch: 64 graphs, batched vs "
+                         "sequential; serve: Poisson request stream, served vs sequential")
+    ap.add_argument("--batch-jobs", type=int, default=64)
+    ap.add_argument("--pool", type=int, default=200)
+    ap.add_argument("--pool-max-nodes", type=int, default=120000)
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 1.0, 1.25])
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="city", choices=["city", "urban", "tiny"])
@@ -149,6 +392,10 @@ def main():
 
     if hb.device_count() < 1:
         raise SystemExit("no GPU visible")
+    if args.mode == "batch":
+        return batch_bench(args)
+    if args.mode == "serve":
+        return serve_bench(args)
     g = make_graph(args.config, args.seed)
     t0 = time.perf_counter()
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)

@@ -87,8 +87,10 @@ typedef struct {
     double run_ms;         /* device time from init start to the last union end */
     uint32_t union_kernel; /* kernel that ran: HB_UNION_EDGES or HB_UNION_RUNS */
     uint32_t table_levels; /* table levels K used by the run kernel (0 otherwise) */
-    uint64_t t_start_ns;   /* host CLOCK_MONOTONIC at call entry */
-    uint64_t t_end_ns;     /* host CLOCK_MONOTONIC when results were written */
+    uint64_t t_submit_ns;  /* host CLOCK_MONOTONIC: hb_submit accepted it (else = t_start_ns) */
+    uint64_t t_admit_ns;   /* device memory granted, joined the running steps (else = t_start_ns) */
+    uint64_t t_start_ns;   /* call entry, or the first step of a served request */
+    uint64_t t_end_ns;     /* results complete */
 } hb_result;
 
 /* Which union kernel a run uses. */
@@ -190,6 +192,97 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
  */
 hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                       const hb_run_opts *opts, hb_result *out);
+
+/* One analysis of a batched run. */
+typedef struct {
+    hb_graph *g;           /* a loaded graph; several jobs may share one */
+    uint32_t p;            /* [4, 16] */
+    uint32_t depth_limit;  /* 0 = until convergence */
+    uint64_t hash_seed;
+} hb_job;
+
+/*
+ * Run n_jobs analyses together (blocking).  All jobs advance one HyperBall
+ * step per batched step: one launch per (p, union kernel) class covers the
+ * nodes of every running job of that class, one launch per table level builds
+ * the range-max tables of all run-kernel jobs, and a step-end kernel applies
+ * each job's own stop rule on the device, so jobs of different sizes, p and
+ * depth limits finish independently.  Each step is a captured HIP graph,
+ * replayed a few steps at a time between host checks.  outs[j] is filled as
+ * hb_run would fill it for job j alone, with identical registers and sums;
+ * run_ms is the device time of the whole batch and iter_ms / table_ms are 0.
+ * Device memory for all jobs' counters and state comes from a workspace the
+ * library keeps between batched calls and grows on demand (HB_ENOMEM if it
+ * does not fit); hb_release_cache returns it.  All graphs must live on one
+ * device.
+ */
+hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *opts,
+                       hb_result *outs);
+
+/*
+ * Serving: a request loop on a library thread.  hb_submit queues an analysis
+ * and returns at once; the loop admits queued requests in arrival order while
+ * their device footprint -- 2 (K+1) n 2^p bytes of counters and tables
+ * (K = 0 for the per-edge kernel), 16 n bytes of FP64 state and 4 (n+2) bytes
+ * of stop flags -- fits the memory budget, and advances every admitted
+ * request by one HyperBall step per batched step (continuous batching: a
+ * request that arrives while others run joins at the next step, and finished
+ * requests free their memory at once).  Results match hb_run for the same
+ * arguments bit for bit.  Graphs stay owned by the caller; hb_graph_free
+ * returns HB_EBUSY while a submitted request still uses the graph.
+ */
+typedef uint64_t hb_ticket;
+
+typedef struct {
+    uint64_t hbm_budget;   /* device bytes for running requests; 0 = 3/4 of free memory */
+    uint32_t max_running;  /* cap on admitted requests; 0 = none */
+    uint32_t union_kernel; /* HB_UNION_* for every request */
+    uint32_t table_levels; /* 0 = default */
+} hb_server_opts;
+
+typedef struct {
+    uint32_t running, queued;
+    uint64_t submitted, completed, steps;
+    uint64_t budget_bytes, used_bytes, peak_used_bytes;
+    uint64_t edge_unions;  /* summed over completed requests */
+} hb_server_stats_t;
+
+#define HB_SUBMIT_REGISTERS 1u /* keep the final registers for hb_poll */
+
+/* Start the request loop (HB_EBUSY if it runs).  opts may be NULL. */
+hb_status hb_server_start(const hb_server_opts *opts);
+
+/*
+ * Stop accepting requests, finish every queued and running one, release the
+ * budget and end the loop.  Finished results stay available to hb_poll.
+ */
+hb_status hb_server_stop(void);
+
+/*
+ * Queue one analysis (starts the loop with default options if needed).
+ * HB_ENOMEM if its footprint exceeds the whole budget (it could never run);
+ * HB_EINVAL for bad arguments (as hb_run_with).
+ */
+hb_status hb_submit(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                    uint32_t flags, hb_ticket *out);
+
+/*
+ * HB_PENDING while the request is queued or running.  When it has finished,
+ * fill out (its non-NULL arrays are written as by hb_run; registers only if
+ * submitted with HB_SUBMIT_REGISTERS, else HB_EINVAL) and forget the ticket:
+ * later calls return HB_ENOTFOUND.  A request that failed returns its error
+ * status once.
+ */
+hb_status hb_poll(hb_ticket t, hb_result *out);
+
+/* hb_poll that blocks until the request has finished. */
+hb_status hb_wait(hb_ticket t, hb_result *out);
+
+/* Counters of the request loop. */
+hb_status hb_server_stats(hb_server_stats_t *out);
+
+/* Free the workspace kept between batched calls. */
+hb_status hb_release_cache(void);
 
 /*
  * Diagnostic: a plain streaming copy of `bytes` (a multiple of 16) between two

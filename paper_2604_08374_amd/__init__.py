@@ -7,6 +7,7 @@ call raises ``HBError``.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -15,7 +16,8 @@ import numpy as np
 
 __all__ = [
     "HBError", "Result", "Graph", "lib_path", "version", "device_count", "csr_encode",
-    "csr_validate", "graph_load", "run", "copy_probe", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
+    "csr_validate", "graph_load", "run", "run_batch", "release_cache", "copy_probe", "server_start", "server_stop",
+    "server_stats", "submit", "Ticket", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
     "HB_ENOMEM", "HB_EDEVICE", "HB_ENOTFOUND", "HB_EBUSY",
 ]
 
@@ -50,7 +52,21 @@ class _Result(ctypes.Structure):
                 ("init_ms", ctypes.c_double), ("iter_ms", ctypes.c_double),
                 ("table_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_start_ns", ctypes.c_uint64), ("t_end_ns", ctypes.c_uint64)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_running", ctypes.c_uint32),
+                ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("running", ctypes.c_uint32), ("queued", ctypes.c_uint32),
+                ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("used_bytes", ctypes.c_uint64), ("peak_used_bytes", ctypes.c_uint64),
+                ("edge_unions", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -60,6 +76,11 @@ class _Stats(ctypes.Structure):
 
 class _RunOpts(ctypes.Structure):
     _fields_ = [("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("p", ctypes.c_uint32), ("depth_limit", ctypes.c_uint32),
+                ("hash_seed", ctypes.c_uint64)]
 
 
 UNION_AUTO, UNION_EDGES, UNION_RUNS = 0, 1, 2
@@ -104,6 +125,24 @@ def _lib():
                                   ctypes.c_uint64, ctypes.POINTER(_RunOpts),
                                   ctypes.POINTER(_Result)]
         L.hb_run_with.restype = st
+        L.hb_run_batch.argtypes = [ctypes.POINTER(_Job), ctypes.c_uint32, ctypes.POINTER(_RunOpts),
+                                   ctypes.POINTER(_Result)]
+        L.hb_run_batch.restype = st
+        L.hb_server_start.argtypes = [ctypes.POINTER(_ServerOpts)]
+        L.hb_server_start.restype = st
+        L.hb_server_stop.argtypes = []
+        L.hb_server_stop.restype = st
+        L.hb_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+        L.hb_submit.restype = st
+        L.hb_poll.argtypes = [ctypes.c_uint64, ctypes.POINTER(_Result)]
+        L.hb_poll.restype = st
+        L.hb_wait.argtypes = [ctypes.c_uint64, ctypes.POINTER(_Result)]
+        L.hb_wait.restype = st
+        L.hb_server_stats.argtypes = [ctypes.POINTER(_ServerStats)]
+        L.hb_server_stats.restype = st
+        L.hb_release_cache.argtypes = []
+        L.hb_release_cache.restype = st
         L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
         L.hb_copy_probe.restype = st
         _LIB = L
@@ -202,6 +241,8 @@ class Result:
     run_ms: float
     union_kernel: str
     table_levels: int
+    t_submit_ns: int
+    t_admit_ns: int
     t_start_ns: int
     t_end_ns: int
 
@@ -243,14 +284,7 @@ class Graph:
     def __exit__(self, *exc):
         self.free()
 
-    def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
-            outputs: bool = True, kernel: str = "auto", table_levels: int = 0) -> Result:
-        """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
-
-        kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
-        """
-        if self._h is None:
-            raise HBError(HB_EINVAL, "graph was freed")
+    def _out_arrays(self, p: int, registers: bool, outputs: bool):
         n = self.n
         reach = np.empty(n, np.float64) if outputs else None
         sum_d = np.empty(n, np.float64) if outputs else None
@@ -261,14 +295,21 @@ class Graph:
         r.sum_d = _ptr(sum_d, ctypes.c_double)
         r.mean_depth = _ptr(md, ctypes.c_double)
         r.registers = _ptr(regs, ctypes.c_uint8)
+        return r, (reach, sum_d, md, regs)
+
+    def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
+            outputs: bool = True, kernel: str = "auto", table_levels: int = 0) -> Result:
+        """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
+
+        kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
+        """
+        if self._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        r, arrays = self._out_arrays(p, registers, outputs)
         o = _RunOpts(_KERNELS[kernel], table_levels)
         _check(_lib().hb_run_with(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
                                   ctypes.byref(o), ctypes.byref(r)))
-        name = {UNION_EDGES: "edges", UNION_RUNS: "runs"}.get(int(r.union_kernel), "?")
-        return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
-                      int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
-                      float(r.run_ms), name, int(r.table_levels), int(r.t_start_ns),
-                      int(r.t_end_ns))
+        return _to_result(r, arrays)
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
@@ -276,6 +317,106 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
     ms = ctypes.c_double(0.0)
     _check(_lib().hb_copy_probe(int(nbytes), int(reps), ctypes.byref(ms)))
     return float(ms.value)
+
+
+def _to_result(r: _Result, arrays) -> Result:
+    reach, sum_d, md, regs = arrays
+    name = {UNION_EDGES: "edges", UNION_RUNS: "runs"}.get(int(r.union_kernel), "?")
+    return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
+                  int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
+                  float(r.run_ms), name, int(r.table_levels), int(r.t_submit_ns),
+                  int(r.t_admit_ns), int(r.t_start_ns), int(r.t_end_ns))
+
+
+def run_batch(jobs, registers: bool = False, outputs: bool = True, kernel: str = "auto",
+              table_levels: int = 0):
+    """hb_run_batch: jobs is a list of (Graph, p, depth_limit, seed); returns Results in order."""
+    n = len(jobs)
+    cj = (_Job * n)()
+    outs = (_Result * n)()
+    keep = []
+    for i, (g, p, depth, seed) in enumerate(jobs):
+        if g._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        cj[i].g = g._h.value
+        cj[i].p = p
+        cj[i].depth_limit = depth
+        cj[i].hash_seed = seed & 0xFFFFFFFFFFFFFFFF
+        r, arrays = g._out_arrays(p, registers, outputs)
+        outs[i] = r
+        keep.append(arrays)
+    o = _RunOpts(_KERNELS[kernel], table_levels)
+    _check(_lib().hb_run_batch(cj, n, ctypes.byref(o), outs))
+    return [_to_result(outs[i], keep[i]) for i in range(n)]
+
+
+SUBMIT_REGISTERS = 1
+_SERVER_STARTED = False
+
+
+def server_start(hbm_budget: int = 0, max_running: int = 0, kernel: str = "auto",
+                 table_levels: int = 0) -> None:
+    """hb_server_start: start the request loop (continuous batching)."""
+    global _SERVER_STARTED
+    o = _ServerOpts(hbm_budget, max_running, _KERNELS[kernel], table_levels)
+    _check(_lib().hb_server_start(ctypes.byref(o)))
+    _SERVER_STARTED = True
+
+
+def server_stop() -> None:
+    """hb_server_stop: finish queued and running requests, then end the loop."""
+    global _SERVER_STARTED
+    _check(_lib().hb_server_stop())
+    _SERVER_STARTED = False
+
+
+def server_stats() -> dict:
+    st = _ServerStats()
+    _check(_lib().hb_server_stats(ctypes.byref(st)))
+    return {k: int(getattr(st, k)) for k, _ in _ServerStats._fields_}
+
+
+class Ticket:
+    """A submitted request: poll() returns None while pending, then the Result once."""
+
+    def __init__(self, graph: "Graph", p: int, registers: bool, ticket: int):
+        self.graph, self.p, self.registers, self.id = graph, p, registers, ticket
+
+    def _collect(self, fn) -> "Result | None":
+        r, arrays = self.graph._out_arrays(self.p, self.registers, True)
+        st = fn(self.id, ctypes.byref(r))
+        if st == HB_PENDING:
+            return None
+        _check(st)
+        return _to_result(r, arrays)
+
+    def poll(self):
+        return self._collect(_lib().hb_poll)
+
+    def wait(self):
+        return self._collect(_lib().hb_wait)
+
+
+def submit(g: "Graph", p: int, depth_limit: int = 0, seed: int = 0,
+           registers: bool = False) -> Ticket:
+    """hb_submit: queue one analysis; returns a Ticket."""
+    global _SERVER_STARTED
+    t = ctypes.c_uint64(0)
+    _check(_lib().hb_submit(g._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
+                            SUBMIT_REGISTERS if registers else 0, ctypes.byref(t)))
+    _SERVER_STARTED = True
+    return Ticket(g, p, registers, int(t.value))
+
+
+@atexit.register
+def _stop_server_at_exit():
+    if _SERVER_STARTED and _LIB is not None:
+        _LIB.hb_server_stop()
+
+
+def release_cache() -> None:
+    """hb_release_cache: free the device workspace kept between batched calls."""
+    _check(_lib().hb_release_cache())
 
 
 def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:

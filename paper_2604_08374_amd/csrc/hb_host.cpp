@@ -18,11 +18,12 @@
 
 #include "hb.h"
 #include "hb_internal.h"
+#include "hb_runtime.h"
 
-namespace {
+namespace hbr {
 
 thread_local std::string g_err;
-std::mutex g_dev_mu;  // serialises every call that touches the GPU
+std::mutex g_dev_mu;
 
 hb_status fail(hb_status st, const char *fmt, ...) {
     char buf[512];
@@ -38,17 +39,23 @@ hb_status hip_fail(hipError_t e, const char *what) {
     return fail(HB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HB_HIP(call)                                   \
-    do {                                               \
-        hipError_t e_ = (call);                        \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
 uint64_t now_ns() {
     timespec ts;
     clock_gettime(CLOCK_MONOTONIC, &ts);
     return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
+
+uint32_t floor_log2(uint32_t n) {
+    uint32_t lg = 0;
+    while ((2ull << lg) <= n) ++lg;
+    return lg;
+}
+
+}  // namespace hbr
+
+using namespace hbr;
+
+namespace {
 
 unsigned host_threads() {
     unsigned h = std::thread::hardware_concurrency();
@@ -90,30 +97,6 @@ uint8_t *uleb_put(uint32_t v, uint8_t *out) {
     return out;
 }
 
-constexpr int kMaxLevels = 24;
-
-// Runs of consecutive neighbour ids (joined across the node itself) and, for
-// every table depth K, the table rows the run kernel loads to cover them.
-struct RunCounts {
-    uint64_t runs = 0;
-    uint64_t lookups[kMaxLevels + 1] = {};
-    void add(uint64_t r) {
-        ++runs;
-        for (int k = 0; k <= kMaxLevels; ++k) {
-            const uint64_t top = 1ull << k;
-            if (r <= top) {
-                lookups[k] += (r & (r - 1)) == 0 ? 1 : 2;  // one row if r is a power of two
-            } else {
-                lookups[k] += (r + top - 1) / top;
-            }
-        }
-    }
-    void merge(const RunCounts &o) {
-        runs += o.runs;
-        for (int k = 0; k <= kMaxLevels; ++k) lookups[k] += o.lookups[k];
-    }
-};
-
 // Check one compressed row; returns true if valid.  Counts runs into rc.
 bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32_t degree,
             RunCounts *rc = nullptr) {
@@ -151,25 +134,6 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
 }
 
 }  // namespace
-
-struct hb_graph {
-    uint32_t n = 0;
-    uint64_t n_edges = 0, n_bytes = 0;
-    RunCounts runs;
-    int device = 0;
-    std::vector<uint32_t> comp_size;  // empty: one component of n
-    uint8_t *d_bytes = nullptr;
-    uint64_t *d_offsets = nullptr;
-    // run state, kept between runs
-    uint8_t *d_cnt[2] = {nullptr, nullptr};
-    uint64_t cnt_bytes = 0;
-    double *d_cprev = nullptr, *d_sumd = nullptr;
-    uint32_t *d_flags = nullptr;
-    uint64_t n_flags = 0;
-    uint32_t *h_flag = nullptr;  // pinned
-    hipStream_t stream = nullptr;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-};
 
 namespace {
 
@@ -378,6 +342,9 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
 
 hb_status hb_graph_free(hb_graph *g) {
     if (!g) return fail(HB_EINVAL, "graph is NULL");
+    if (g->inflight.load() != 0)
+        return fail(HB_EBUSY, "graph has %u submitted requests that have not finished",
+                    g->inflight.load());
     std::lock_guard<std::mutex> lk(g_dev_mu);
     graph_release(g);
     return HB_OK;
@@ -526,8 +493,323 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     out->run_ms = run_ms;
     out->union_kernel = runs ? HB_UNION_RUNS : HB_UNION_EDGES;
     out->table_levels = runs ? levels : 0u;
+    out->t_submit_ns = t_start;
+    out->t_admit_ns = t_start;
     out->t_start_ns = t_start;
     out->t_end_ns = now_ns();
+    return HB_OK;
+}
+
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
+
+// Device buffers of batched calls, kept between calls (grown on demand, held
+// until hb_release_cache) so a batch does not pay for allocation every time.
+// Guarded by g_dev_mu.
+struct BatchCache {
+    int device = -1;
+    void *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    hbk::BatchJob *d_jobs = nullptr;
+    hbk::BatchJob *h_jobs = nullptr;  // pinned mirror for the done checks
+    uint32_t jobs_cap = 0;
+    uint32_t *d_lists = nullptr;
+    uint64_t lists_cap = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    void release() {
+        if (device < 0) return;
+        (void)hipSetDevice(device);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (stream) (void)hipStreamDestroy(stream);
+        if (h_jobs) (void)hipHostFree(h_jobs);
+        (void)hipFree(d_lists);
+        (void)hipFree(d_jobs);
+        (void)hipFree(arena);
+        *this = BatchCache{};
+    }
+
+    hipError_t reserve(int dev, uint64_t arena_need, uint32_t jobs_need, uint64_t lists_need) {
+        if (device != dev) release();
+        device = dev;
+        hipError_t e = hipSuccess;
+        if (!stream) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        for (auto &x : ev)
+            if (e == hipSuccess && !x) e = hipEventCreate(&x);
+        if (e == hipSuccess && arena_bytes < arena_need) {
+            (void)hipFree(arena);
+            arena = nullptr;
+            arena_bytes = 0;
+            e = hipMalloc(&arena, arena_need);
+            if (e == hipSuccess) arena_bytes = arena_need;
+        }
+        if (e == hipSuccess && jobs_cap < jobs_need) {
+            (void)hipFree(d_jobs);
+            if (h_jobs) (void)hipHostFree(h_jobs);
+            d_jobs = nullptr;
+            h_jobs = nullptr;
+            jobs_cap = 0;
+            e = hipMalloc(&d_jobs, sizeof(hbk::BatchJob) * jobs_need);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void **)&h_jobs, sizeof(hbk::BatchJob) * jobs_need,
+                                  hipHostMallocDefault);
+            if (e == hipSuccess) jobs_cap = jobs_need;
+        }
+        if (e == hipSuccess && lists_cap < lists_need) {
+            (void)hipFree(d_lists);
+            d_lists = nullptr;
+            lists_cap = 0;
+            e = hipMalloc(&d_lists, sizeof(uint32_t) * lists_need);
+            if (e == hipSuccess) lists_cap = lists_need;
+        }
+        return e;
+    }
+};
+BatchCache g_batch;
+
+// The captured step of one call, destroyed on every exit path.
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~StepGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+struct BatchClass {
+    uint32_t p;
+    bool runs;
+    std::vector<uint32_t> list, block_base;
+    uint32_t list_off = 0, base_off = 0, nblocks = 0;
+};
+
+}  // namespace
+
+hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *opts,
+                       hb_result *outs) {
+    const uint64_t t_start = now_ns();
+    if (!jobs || !outs || n_jobs == 0) return fail(HB_EINVAL, "NULL argument or no jobs");
+    if (n_jobs > 65535) return fail(HB_EINVAL, "at most 65535 jobs per batch");
+    const hb_run_opts o = opts ? *opts : hb_run_opts{0u, 0u};
+    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
+    if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        if (!jobs[j].g) return fail(HB_EINVAL, "job %u has no graph", j);
+        if (jobs[j].p < HB_P_MIN || jobs[j].p > HB_P_MAX)
+            return fail(HB_EINVAL, "job %u: p = %u outside [4, 16]", j, jobs[j].p);
+        if (o.union_kernel == HB_UNION_RUNS && jobs[j].p > 12)
+            return fail(HB_EINVAL, "job %u: the run kernel supports p <= 12", j);
+        if (jobs[j].g->device != jobs[0].g->device)
+            return fail(HB_EINVAL, "all graphs of a batch must live on one device");
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    HB_HIP(hipSetDevice(jobs[0].g->device));
+
+    // ---- per-job layout in one arena; all stop flags contiguous at the end
+    std::vector<hbk::BatchJob> hj(n_jobs);
+    std::vector<uint64_t> off_buf(n_jobs), off_state(n_jobs), off_flags(n_jobs);
+    uint64_t arena = 0, flags_words = 0;
+    uint32_t max_levels = 0, max_steps = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const hb_graph *g = jobs[j].g;
+        const uint32_t p = jobs[j].p;
+        const uint64_t m = 1ull << p;
+        uint32_t levels = std::min(o.table_levels ? o.table_levels : 7u, floor_log2(g->n));
+        bool runs = o.union_kernel == HB_UNION_RUNS || (o.union_kernel == HB_UNION_AUTO && p <= 12);
+        if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
+            if (o.union_kernel == HB_UNION_RUNS)
+                return fail(HB_EINVAL, "job %u: table rows (levels + 1) * n must stay below 2^32", j);
+            runs = false;
+        }
+        if (!runs) levels = 0;
+        hbk::BatchJob &b = hj[j];
+        b = hbk::BatchJob{};
+        b.bytes = g->d_bytes;
+        b.offsets = g->d_offsets;
+        b.seed = jobs[j].hash_seed;
+        b.n = g->n;
+        b.p = p;
+        b.depth = jobs[j].depth_limit;
+        b.levels = levels;
+        b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
+        b.runs = runs ? 1u : 0u;
+        off_buf[j] = arena;
+        arena += 2 * align256((uint64_t)g->n * m * (levels + 1u));
+        off_state[j] = arena;
+        arena += 2 * align256(sizeof(double) * g->n);
+        off_flags[j] = flags_words;
+        flags_words += b.n_flags;
+        max_levels = std::max(max_levels, levels);
+        max_steps = std::max(max_steps, b.depth ? b.depth : b.n_flags);
+    }
+    const uint64_t flags_at = arena;
+    arena += align256(sizeof(uint32_t) * flags_words);
+    {
+        // lists: all jobs, run-kernel jobs, per-level table bases, per-class list + bases
+        const uint64_t lists_need = 3ull * n_jobs + (uint64_t)(max_levels + 1) * (n_jobs + 1) +
+                                    16ull * (n_jobs + 1);
+        const hipError_t e = g_batch.reserve(jobs[0].g->device, arena, n_jobs, lists_need);
+        if (e == hipErrorOutOfMemory)
+            return fail(HB_ENOMEM, "batch needs %llu bytes of device memory", (unsigned long long)arena);
+        if (e != hipSuccess) return hip_fail(e, "batch workspace");
+    }
+    BatchCache &R = g_batch;
+    StepGraph SG;
+    uint8_t *base = static_cast<uint8_t *>(R.arena);
+    uint32_t *d_flags = reinterpret_cast<uint32_t *>(base + flags_at);
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const uint64_t m = 1ull << jobs[j].p;
+        const uint64_t bb = align256((uint64_t)hj[j].n * m * (hj[j].levels + 1u));
+        hj[j].buf[0] = base + off_buf[j];
+        hj[j].buf[1] = base + off_buf[j] + bb;
+        hj[j].c_prev = reinterpret_cast<double *>(base + off_state[j]);
+        hj[j].sum_d = reinterpret_cast<double *>(base + off_state[j] + align256(sizeof(double) * hj[j].n));
+        hj[j].flags = d_flags + off_flags[j];
+    }
+
+    // ---- classes by (p, kernel); list and block_base arrays in one buffer
+    std::vector<BatchClass> classes;
+    std::vector<uint32_t> all_list(n_jobs), runs_list;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        all_list[j] = j;
+        if (hj[j].runs) runs_list.push_back(j);
+        BatchClass *c = nullptr;
+        for (auto &x : classes)
+            if (x.p == hj[j].p && x.runs == (hj[j].runs != 0)) c = &x;
+        if (!c) {
+            classes.push_back(BatchClass{hj[j].p, hj[j].runs != 0, {}, {0u}});
+            c = &classes.back();
+        }
+        const uint32_t npb = hbk::shape_for((int)hj[j].p).nodes_per_block;
+        c->list.push_back(j);
+        c->block_base.push_back(c->block_base.back() + (hj[j].n + npb - 1) / npb);
+    }
+    std::vector<uint32_t> lists(all_list);
+    const uint32_t runs_off = (uint32_t)lists.size();
+    lists.insert(lists.end(), runs_list.begin(), runs_list.end());
+    // table level k: job runs_list[i] owns workgroups [tb[k][i], tb[k][i+1])
+    std::vector<uint32_t> table_off(max_levels + 1, 0), table_blocks(max_levels + 1, 0);
+    for (uint32_t k = 1; k <= max_levels; ++k) {
+        table_off[k] = (uint32_t)lists.size();
+        uint32_t acc = 0;
+        lists.push_back(0);
+        for (uint32_t j : runs_list) {
+            if (k <= hj[j].levels) acc += hbk::batch_table_blocks(hj[j].n, hj[j].p, k);
+            lists.push_back(acc);
+        }
+        table_blocks[k] = acc;
+    }
+    for (auto &c : classes) {
+        c.list_off = (uint32_t)lists.size();
+        lists.insert(lists.end(), c.list.begin(), c.list.end());
+        c.base_off = (uint32_t)lists.size();
+        lists.insert(lists.end(), c.block_base.begin(), c.block_base.end());
+        c.nblocks = c.block_base.back();
+    }
+    if (lists.size() > R.lists_cap) return fail(HB_EDEVICE, "batch list buffer too small");
+    hipStream_t s = R.stream;
+    HB_HIP(hipMemcpyAsync(R.d_jobs, hj.data(), sizeof(hbk::BatchJob) * n_jobs,
+                          hipMemcpyHostToDevice, s));
+    HB_HIP(hipMemcpyAsync(R.d_lists, lists.data(), sizeof(uint32_t) * lists.size(),
+                          hipMemcpyHostToDevice, s));
+
+    // ---- init
+    HB_HIP(hipEventRecord(R.ev[0], s));
+    HB_HIP(hbk::launch_fill_u32(d_flags, 0u, flags_words, s));
+    for (auto &c : classes)
+        HB_HIP(hbk::launch_batch_init((int)c.p, R.d_jobs, R.d_lists + c.list_off,
+                                      R.d_lists + c.base_off, (uint32_t)c.list.size(), c.nblocks, s));
+
+    // ---- one step, captured once, replayed until every job has stopped
+    HB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    {
+        hipError_t e = hipSuccess;
+        for (uint32_t k = 1; k <= max_levels && e == hipSuccess; ++k)
+            e = hbk::launch_batch_table(R.d_jobs, R.d_lists + runs_off, R.d_lists + table_off[k],
+                                        (uint32_t)runs_list.size(), table_blocks[k], k, s);
+        for (auto &c : classes) {
+            if (e != hipSuccess) break;
+            e = hbk::launch_batch_union((int)c.p, c.runs, R.d_jobs, R.d_lists + c.list_off,
+                                        R.d_lists + c.base_off, (uint32_t)c.list.size(), c.nblocks, s);
+        }
+        if (e == hipSuccess) e = hbk::launch_batch_step_end(R.d_jobs, R.d_lists, n_jobs, s);
+        const hipError_t e2 = hipStreamEndCapture(s, &SG.graph);
+        if (e != hipSuccess) return hip_fail(e, "batched step launch");
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    }
+    HB_HIP(hipGraphInstantiate(&SG.exec, SG.graph, nullptr, nullptr, 0));
+    const uint32_t steps_per_check = 4;
+    uint32_t steps = 0;
+    for (;;) {
+        for (uint32_t i = 0; i < steps_per_check; ++i) HB_HIP(hipGraphLaunch(SG.exec, s));
+        steps += steps_per_check;
+        HB_HIP(hipEventRecord(R.ev[1], s));
+        HB_HIP(hipMemcpyAsync(R.h_jobs, R.d_jobs, sizeof(hbk::BatchJob) * n_jobs,
+                              hipMemcpyDeviceToHost, s));
+        HB_HIP(hipStreamSynchronize(s));
+        bool all = true;
+        for (uint32_t j = 0; j < n_jobs; ++j) all = all && R.h_jobs[j].done != 0u;
+        if (all) break;
+        if (steps > max_steps + steps_per_check)
+            return fail(HB_EDEVICE, "batched run did not stop within %u steps", steps);
+    }
+    float run_ms = 0.f;
+    HB_HIP(hipEventElapsedTime(&run_ms, R.ev[0], R.ev[1]));
+
+    // ---- outputs
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const hbk::BatchJob &b = R.h_jobs[j];
+        hb_result *out = &outs[j];
+        const uint32_t n = b.n;
+        const uint64_t m = 1ull << b.p;
+        if (out->reach)
+            HB_HIP(hipMemcpy(out->reach, b.c_prev, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (out->sum_d || out->mean_depth) {
+            std::vector<double> tmp;
+            double *sd = out->sum_d;
+            if (!sd) {
+                tmp.resize(n);
+                sd = tmp.data();
+            }
+            HB_HIP(hipMemcpy(sd, b.sum_d, sizeof(double) * n, hipMemcpyDeviceToHost));
+            if (out->mean_depth) {
+                const hb_graph *g = jobs[j].g;
+                for (uint32_t v = 0; v < n; ++v) {
+                    const double nv = g->comp_size.empty() ? (double)n : (double)g->comp_size[v];
+                    out->mean_depth[v] = nv >= 2.0 ? sd[v] / (nv - 1.0) : NAN;
+                }
+            }
+        }
+        if (out->registers)
+            HB_HIP(hipMemcpy(out->registers, b.buf[b.done & 1u], (uint64_t)n * m,
+                             hipMemcpyDeviceToHost));
+        const double md = (double)m;
+        out->passes = b.done;
+        out->converged = b.converged;
+        out->c0 = md * std::log(md / (md - 1.0));
+        out->edge_unions = (uint64_t)b.done * jobs[j].g->n_edges;
+        out->init_ms = 0.0;
+        out->iter_ms = 0.0;
+        out->table_ms = 0.0;
+        out->run_ms = run_ms;
+        out->union_kernel = b.runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+        out->table_levels = b.levels;
+        out->t_submit_ns = t_start;
+        out->t_admit_ns = t_start;
+        out->t_start_ns = t_start;
+        out->t_end_ns = now_ns();
+    }
+    return HB_OK;
+}
+
+hb_status hb_release_cache(void) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    g_batch.release();
     return HB_OK;
 }
 

@@ -7,6 +7,43 @@
 
 namespace hbk {
 
+// One job of a batched run, in device memory.  The host fills every field
+// before the first step; the step-end kernel advances t, done and converged.
+struct BatchJob {
+    const uint8_t *bytes;     // LEB128 stream
+    const uint64_t *offsets;  // n + 1 row offsets
+    uint8_t *buf[2];          // ping-pong counters (with table levels for the run kernel)
+    double *c_prev;           // n estimates of the last step
+    double *sum_d;            // n Eq. 3 sums
+    uint32_t *flags;          // n_flags stop flags, one per step, zeroed before init
+    uint64_t seed;
+    uint32_t n, p, depth, levels, n_flags;
+    uint32_t runs;            // 1: run kernel, 0: per-edge kernel
+    uint32_t t;               // steps completed
+    uint32_t done;            // 0 while running, else the last step run
+    uint32_t converged;       // 1 if it stopped because no estimate grew by more than 0.5
+    uint32_t pad;
+};
+
+// Batched launches over a list of jobs of one precision p.  block_base has
+// nlist + 1 entries: job list[i] owns workgroups [block_base[i], block_base[i+1])
+// of the nblocks launched (shape_for(p).nodes_per_block nodes each).  Jobs
+// whose `done` is set are skipped.
+hipError_t launch_batch_init(int p, BatchJob *jobs, const uint32_t *list,
+                             const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                             hipStream_t stream);
+hipError_t launch_batch_union(int p, bool runs, BatchJob *jobs, const uint32_t *list,
+                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                              hipStream_t stream);
+// Table level k for listed run-kernel jobs with levels >= k; job list[i] owns
+// workgroups [block_base[i], block_base[i+1]), batch_table_blocks(n, p, k) of them.
+uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k);
+hipError_t launch_batch_table(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
+                              uint32_t nlist, uint32_t nblocks, uint32_t k, hipStream_t stream);
+// After a step: t += 1 and the stop decision for every listed running job.
+hipError_t launch_batch_step_end(BatchJob *jobs, const uint32_t *list, uint32_t nlist,
+                                 hipStream_t stream);
+
 // Counter layout and launch shape chosen for precision p (m = 2^p bytes per
 // counter, node-major rows).
 struct LaunchShape {

@@ -218,18 +218,14 @@ __device__ EstPart node_total(EstPart e, uint32_t slice) {
 }
 
 // ---------------------------------------------------------------- init
+// Zero node v's counter (this wave's slice), insert v, and set c_prev[v] to the
+// estimate of the one-element counter and sum_d[v] to 0.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restrict__ cur,
-                                                               double *__restrict__ c_prev,
-                                                               double *__restrict__ sum_d,
-                                                               uint32_t n, uint64_t seed) {
+__device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__restrict__ c_prev,
+                                          double *__restrict__ sum_d, uint32_t v, uint32_t slice,
+                                          uint64_t seed) {
     using C = Cfg<P>;
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
-    if (v >= n) return;  // uniform per workgroup when WAVES > 1
-
+    const uint32_t lane = lane_id();
     const uint64_t h = splitmix64((uint64_t)v ^ seed);
     const uint32_t j = (uint32_t)(h >> (64 - P));
     const uint64_t rest = h << P;
@@ -256,6 +252,20 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restri
         c_prev[v] = estimate<P>(tot);
         sum_d[v] = 0.0;
     }
+}
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restrict__ cur,
+                                                               double *__restrict__ c_prev,
+                                                               double *__restrict__ sum_d,
+                                                               uint32_t n, uint64_t seed) {
+    using C = Cfg<P>;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    init_node<P>(cur, c_prev, sum_d, v, slice, seed);
 }
 
 // ---------------------------------------------------------------- row decoding
@@ -410,21 +420,19 @@ __device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_
 // ---------------------------------------------------------------- union step, per edge
 // Eq. 2 as written: every neighbour's counter is gathered once per node.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
-    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
-    const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
-    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
+__device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ bytes,
+                                                 const uint64_t *__restrict__ offsets,
+                                                 const uint8_t *__restrict__ cur,
+                                                 uint8_t *__restrict__ next,
+                                                 double *__restrict__ c_prev,
+                                                 double *__restrict__ sum_d,
+                                                 uint32_t *__restrict__ flag_t, uint32_t v,
+                                                 uint32_t slice, uint32_t t) {
     using C = Cfg<P>;
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
-    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    const uint32_t lane = lane_id();
     const uint32_t grp = lane / C::LPC;
-
     NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v]
     acc.init(cur + (uint64_t)v * C::M, slice, lane);
-
     const uint64_t row_end = offsets[v + 1];
     RowDecoder dec;
     for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
@@ -448,6 +456,20 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
         }
     }
     finish_node<P>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
+}
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
+    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
+    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
+    using C = Cfg<P>;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    union_node_edges<P>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t);
 }
 
 // ---------------------------------------------------------------- union step, per run
@@ -520,22 +542,19 @@ struct RunGather {
 };
 
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void union_runs_kernel(
-    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
-    const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
-    double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
-    uint32_t n, uint32_t t) {
+__device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ bytes,
+                                                const uint64_t *__restrict__ offsets,
+                                                const uint8_t *__restrict__ tbl, uint32_t levels,
+                                                uint8_t *__restrict__ next,
+                                                double *__restrict__ c_prev,
+                                                double *__restrict__ sum_d,
+                                                uint32_t *__restrict__ flag_t, uint32_t n,
+                                                uint32_t v, uint32_t t, uint32_t *queue) {
     using C = Cfg<P>;
-    static_assert(C::WAVES == 1, "the run kernel keeps one wave per node");
-    __shared__ uint32_t s_queue[C::NODES][kQueueCap];
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = blk * C::NODES + wave;
-    if (v >= n) return;
-
+    const uint32_t lane = lane_id();
     NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v] (level 0 of the table is cur)
     acc.init(tbl + (uint64_t)v * C::M, 0, lane);
-    RunGather<P> g{tbl, n, levels, s_queue[wave], 0u};
+    RunGather<P> g{tbl, n, levels, queue, 0u};
     const uint32_t top = 1u << levels;
 
     bool have = false;      // a run is open: [ra, rl]
@@ -595,6 +614,23 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_runs_kernel(
     finish_node<P>(acc, v, 0, next, c_prev, sum_d, flag_t, t);
 }
 
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void union_runs_kernel(
+    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
+    double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
+    uint32_t n, uint32_t t) {
+    using C = Cfg<P>;
+    static_assert(C::WAVES == 1, "the run kernel keeps one wave per node");
+    __shared__ uint32_t s_queue[C::NODES][kQueueCap];
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t v = blk * C::NODES + wave;
+    if (v >= n) return;
+    union_node_runs<P>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, v, t,
+                       s_queue[wave]);
+}
+
 // Level k of the range-max table from level k - 1:
 // T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]) for i <= n - 2^k.
 __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ tbl,
@@ -615,6 +651,124 @@ __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ 
         w.init(a.w);
         w.add(b.w);
         out[i] = make_uint4(x.value(), y.value(), z.value(), w.value());
+    }
+}
+
+// ---------------------------------------------------------------- batched steps
+// Workgroup -> (job, node block): the largest i with block_base[i] <= blk.
+__device__ __forceinline__ uint32_t find_job(const uint32_t *__restrict__ block_base,
+                                             uint32_t nlist, uint32_t blk) {
+    uint32_t lo = 0, hi = nlist;  // block_base[lo] <= blk < block_base[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (block_base[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Workgroups are dispatched in index order, so a job's contiguous block range
+// runs on all XCDs together (its working set is shared, not eight jobs'); the
+// XCD of block base + l depends only on l mod 8, so remapping the local index
+// gives each XCD one contiguous node range of the job.
+__device__ __forceinline__ uint32_t job_block(uint32_t blk, const uint32_t *__restrict__ block_base,
+                                              uint32_t i) {
+    return xcd_block(blk - block_base[i], block_base[i + 1] - block_base[i]);
+}
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void batch_init_kernel(
+    BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ block_base, uint32_t nlist) {
+    using C = Cfg<P>;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t i = find_job(block_base, nlist, blockIdx.x);
+    const BatchJob &J = jobs[list[i]];
+    const uint32_t local = job_block(blockIdx.x, block_base, i);
+    const uint32_t v = (C::WAVES == 1) ? local * C::NODES + wave : local;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
+    init_node<P>(J.buf[0], J.c_prev, J.sum_d, v, slice, J.seed);
+}
+
+template <int P, bool RUNS>
+__global__ __launch_bounds__(Cfg<P>::THREADS) void batch_union_kernel(
+    BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ block_base, uint32_t nlist) {
+    using C = Cfg<P>;
+    __shared__ uint32_t s_queue[RUNS ? C::NODES : 1][RUNS ? kQueueCap : 1];
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t i = find_job(block_base, nlist, blockIdx.x);
+    const BatchJob &J = jobs[list[i]];
+    if (J.done) return;  // uniform per workgroup
+    const uint32_t t = J.t + 1u;
+    const uint32_t local = job_block(blockIdx.x, block_base, i);
+    const uint32_t v = (C::WAVES == 1) ? local * C::NODES + wave : local;
+    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
+    const uint8_t *cur = J.buf[(t - 1u) & 1u];
+    uint8_t *next = J.buf[t & 1u];
+    if constexpr (RUNS) {
+        union_node_runs<P>(J.bytes, J.offsets, cur, J.levels, next, J.c_prev, J.sum_d,
+                           J.flags + t, J.n, v, t, s_queue[wave]);
+    } else {
+        union_node_edges<P>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
+                            slice, t);
+    }
+}
+
+// Table level k for a list of jobs: workgroup blk handles 16-byte chunks
+// [(blk - block_base[i]) * kTableChunk, ...) of job list[i]'s level k.
+constexpr uint32_t kTableChunk = 256 * 4;  // chunks per workgroup (4 per thread)
+
+__global__ __launch_bounds__(256) void batch_table_kernel(BatchJob *__restrict__ jobs,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ block_base,
+                                                          uint32_t nlist, uint32_t k) {
+    const uint32_t blk = blockIdx.x;
+    const uint32_t i = find_job(block_base, nlist, blk);
+    const BatchJob &J = jobs[list[i]];
+    if (J.done || !J.runs || k > J.levels) return;
+    const uint32_t t = J.t + 1u;
+    uint8_t *tbl = J.buf[(t - 1u) & 1u];
+    const uint64_t m16 = (1ull << J.p) / 16u;
+    const uint64_t level16 = (uint64_t)J.n * m16;
+    const uint64_t count16 = ((uint64_t)J.n - (1ull << k) + 1ull) * m16;
+    const uint64_t half16 = (1ull << (k - 1u)) * m16;
+    const uint4 *prev = reinterpret_cast<const uint4 *>(tbl) + (uint64_t)(k - 1u) * level16;
+    uint4 *out = reinterpret_cast<uint4 *>(tbl) + (uint64_t)k * level16;
+    const uint64_t c0 = (uint64_t)(blk - block_base[i]) * kTableChunk;
+#pragma unroll
+    for (uint32_t r = 0; r < kTableChunk / 256; ++r) {
+        const uint64_t c = c0 + (uint64_t)r * 256u + threadIdx.x;
+        if (c >= count16) break;
+        const uint4 a = prev[c], b = prev[c + half16];
+        Max4 x, y, z, w;
+        x.init(a.x);
+        x.add(b.x);
+        y.init(a.y);
+        y.add(b.y);
+        z.init(a.z);
+        z.add(b.z);
+        w.init(a.w);
+        w.add(b.w);
+        out[c] = make_uint4(x.value(), y.value(), z.value(), w.value());
+    }
+}
+
+__global__ void batch_step_end_kernel(BatchJob *__restrict__ jobs,
+                                      const uint32_t *__restrict__ list, uint32_t nlist) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlist) return;
+    BatchJob &J = jobs[list[i]];
+    if (J.done) return;
+    const uint32_t t = J.t + 1u;
+    J.t = t;
+    if (J.flags[t] == 0u) {
+        J.converged = 1u;
+        J.done = t;
+    } else if ((J.depth != 0u && t == J.depth) || t + 1u >= J.n_flags) {
+        J.done = t;
     }
 }
 
@@ -757,6 +911,109 @@ hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+namespace {
+template <int P>
+hipError_t launch_batch_init_p(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
+                               uint32_t nlist, uint32_t nblocks, hipStream_t stream) {
+    hipLaunchKernelGGL((batch_init_kernel<P>), dim3(nblocks), dim3(Cfg<P>::THREADS), 0, stream,
+                       jobs, list, block_base, nlist);
+    return hipGetLastError();
+}
+
+template <int P, bool RUNS>
+hipError_t launch_batch_union_p(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
+                                uint32_t nlist, uint32_t nblocks, hipStream_t stream) {
+    hipLaunchKernelGGL((batch_union_kernel<P, RUNS>), dim3(nblocks), dim3(Cfg<P>::THREADS), 0,
+                       stream, jobs, list, block_base, nlist);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batch_init(int p, BatchJob *jobs, const uint32_t *list,
+                             const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                             hipStream_t stream) {
+    if (nblocks == 0) return hipSuccess;
+#define HB_CALL_BINIT(P) launch_batch_init_p<P>(jobs, list, block_base, nlist, nblocks, stream)
+    switch (p) {
+        case 4: return HB_CALL_BINIT(4);
+        case 5: return HB_CALL_BINIT(5);
+        case 6: return HB_CALL_BINIT(6);
+        case 7: return HB_CALL_BINIT(7);
+        case 8: return HB_CALL_BINIT(8);
+        case 9: return HB_CALL_BINIT(9);
+        case 10: return HB_CALL_BINIT(10);
+        case 11: return HB_CALL_BINIT(11);
+        case 12: return HB_CALL_BINIT(12);
+        case 13: return HB_CALL_BINIT(13);
+        case 14: return HB_CALL_BINIT(14);
+        case 15: return HB_CALL_BINIT(15);
+        case 16: return HB_CALL_BINIT(16);
+        default: return hipErrorInvalidValue;
+    }
+#undef HB_CALL_BINIT
+}
+
+hipError_t launch_batch_union(int p, bool runs, BatchJob *jobs, const uint32_t *list,
+                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                              hipStream_t stream) {
+    if (nblocks == 0) return hipSuccess;
+#define HB_CALL_BUNION(P, R) \
+    launch_batch_union_p<P, R>(jobs, list, block_base, nlist, nblocks, stream)
+    if (runs) {
+        switch (p) {
+            case 4: return HB_CALL_BUNION(4, true);
+            case 5: return HB_CALL_BUNION(5, true);
+            case 6: return HB_CALL_BUNION(6, true);
+            case 7: return HB_CALL_BUNION(7, true);
+            case 8: return HB_CALL_BUNION(8, true);
+            case 9: return HB_CALL_BUNION(9, true);
+            case 10: return HB_CALL_BUNION(10, true);
+            case 11: return HB_CALL_BUNION(11, true);
+            case 12: return HB_CALL_BUNION(12, true);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (p) {
+        case 4: return HB_CALL_BUNION(4, false);
+        case 5: return HB_CALL_BUNION(5, false);
+        case 6: return HB_CALL_BUNION(6, false);
+        case 7: return HB_CALL_BUNION(7, false);
+        case 8: return HB_CALL_BUNION(8, false);
+        case 9: return HB_CALL_BUNION(9, false);
+        case 10: return HB_CALL_BUNION(10, false);
+        case 11: return HB_CALL_BUNION(11, false);
+        case 12: return HB_CALL_BUNION(12, false);
+        case 13: return HB_CALL_BUNION(13, false);
+        case 14: return HB_CALL_BUNION(14, false);
+        case 15: return HB_CALL_BUNION(15, false);
+        case 16: return HB_CALL_BUNION(16, false);
+        default: return hipErrorInvalidValue;
+    }
+#undef HB_CALL_BUNION
+}
+
+uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k) {
+    if (k == 0 || (1ull << k) > n) return 0;
+    const uint64_t count16 = ((uint64_t)n - (1ull << k) + 1ull) * ((1ull << p) / 16u);
+    return (uint32_t)((count16 + kTableChunk - 1) / kTableChunk);
+}
+
+hipError_t launch_batch_table(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
+                              uint32_t nlist, uint32_t nblocks, uint32_t k, hipStream_t stream) {
+    if (nlist == 0 || nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_table_kernel, dim3(nblocks), dim3(256), 0, stream, jobs, list,
+                       block_base, nlist, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step_end(BatchJob *jobs, const uint32_t *list, uint32_t nlist,
+                                 hipStream_t stream) {
+    if (nlist == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_step_end_kernel, dim3((nlist + 255) / 256), dim3(256), 0, stream,
+                       jobs, list, nlist);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream) {

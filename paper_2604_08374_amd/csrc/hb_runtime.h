@@ -1,0 +1,74 @@
+// Internal host-side declarations shared by the runtime files (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hb.h"
+
+namespace hbr {
+
+extern thread_local std::string g_err;
+extern std::mutex g_dev_mu;  // serialises the blocking calls that touch the GPU
+
+hb_status fail(hb_status st, const char *fmt, ...);
+hb_status hip_fail(hipError_t e, const char *what);
+uint64_t now_ns();
+uint32_t floor_log2(uint32_t n);
+
+#define HB_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hbr::hip_fail(e_, #call); \
+    } while (0)
+
+constexpr int kMaxLevels = 24;
+
+// Runs of consecutive neighbour ids (joined across the node itself) and, for
+// every table depth K, the table rows the run kernel loads to cover them.
+struct RunCounts {
+    uint64_t runs = 0;
+    uint64_t lookups[kMaxLevels + 1] = {};
+    void add(uint64_t r) {
+        ++runs;
+        for (int k = 0; k <= kMaxLevels; ++k) {
+            const uint64_t top = 1ull << k;
+            if (r <= top) {
+                lookups[k] += (r & (r - 1)) == 0 ? 1 : 2;  // one row if r is a power of two
+            } else {
+                lookups[k] += (r + top - 1) / top;
+            }
+        }
+    }
+    void merge(const RunCounts &o) {
+        runs += o.runs;
+        for (int k = 0; k <= kMaxLevels; ++k) lookups[k] += o.lookups[k];
+    }
+};
+
+}  // namespace hbr
+
+struct hb_graph {
+    uint32_t n = 0;
+    uint64_t n_edges = 0, n_bytes = 0;
+    hbr::RunCounts runs;
+    int device = 0;
+    std::vector<uint32_t> comp_size;  // empty: one component of n
+    uint8_t *d_bytes = nullptr;
+    uint64_t *d_offsets = nullptr;
+    // run state, kept between runs
+    uint8_t *d_cnt[2] = {nullptr, nullptr};
+    uint64_t cnt_bytes = 0;
+    double *d_cprev = nullptr, *d_sumd = nullptr;
+    uint32_t *d_flags = nullptr;
+    uint64_t n_flags = 0;
+    uint32_t *h_flag = nullptr;  // pinned
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::atomic<uint32_t> inflight{0};  // served requests that still use this graph
+};

@@ -1,0 +1,583 @@
+// The served form: hb_submit / hb_poll over a request loop on a library thread.
+//
+// The loop keeps one device arena (the memory budget) and a table of running
+// requests.  Every iteration it (1) admits queued requests in arrival order
+// while a contiguous block for their footprint is free, (2) runs one batched
+// HyperBall step over all running requests -- init for the newly admitted,
+// range-max table levels for run-kernel requests, one union launch per
+// (p, kernel) class, and the per-request stop decision on the device -- and
+// (3) retires the requests that stopped: their reach, sums and optionally
+// registers are copied to host memory owned by the request record and their
+// block is freed at once.  Each request keeps its own step count, so requests
+// join and leave between any two steps (continuous batching at step
+// granularity).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hb.h"
+#include "hb_internal.h"
+#include "hb_runtime.h"
+
+using namespace hbr;
+
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
+
+// First-fit allocator of offsets in [0, size), 256-byte granularity.
+class Arena {
+public:
+    void reset(uint64_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+        used_ = 0;
+    }
+    bool take(uint64_t bytes, uint64_t &off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            off = it->first;
+            const uint64_t rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            used_ += bytes;
+            return true;
+        }
+        return false;
+    }
+    void give(uint64_t off, uint64_t bytes) {
+        bytes = align256(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return size_; }
+
+private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0, used_ = 0;
+};
+
+enum class State { Queued, Running, Done, Failed };
+
+struct Request {
+    hb_ticket ticket = 0;
+    hb_graph *g = nullptr;
+    uint32_t p = 0, depth = 0, flags = 0;
+    uint64_t seed = 0;
+    bool runs = false;
+    uint32_t levels = 0;
+    uint64_t footprint = 0, off = 0;
+    State state = State::Queued;
+    hb_status error = HB_OK;
+    std::string message;
+    hbk::BatchJob job{};
+    uint64_t t_submit = 0, t_admit = 0, t_start = 0, t_end = 0;
+    std::vector<double> reach, sum_d;
+    std::vector<uint8_t> regs;
+};
+
+class Server {
+public:
+    hb_status start(const hb_server_opts *opts);
+    hb_status stop();
+    hb_status submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed, uint32_t flags,
+                     hb_ticket *out);
+    hb_status poll(hb_ticket t, hb_result *out, bool block);
+    hb_status stats(hb_server_stats_t *out);
+    ~Server() {
+        // process exit without hb_server_stop: end the loop after its current step
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            abort_ = true;
+            stopping_ = true;
+        }
+        cv_work_.notify_all();
+        if (thread_.joinable()) thread_.join();
+    }
+
+private:
+    void loop();
+    hb_status step();
+    void fail_all(hb_status st, const std::string &msg);
+    void retire(Request *r);
+    hb_status footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
+                        uint64_t &bytes) const;
+
+    std::mutex mu_;  // guards everything below that client threads touch
+    std::condition_variable cv_work_, cv_done_;
+    std::thread thread_;
+    bool running_ = false, stopping_ = false, abort_ = false;
+    hb_server_opts opts_{};
+    int device_ = 0;
+    Arena arena_;
+    uint64_t peak_used_ = 0;
+    std::deque<Request *> queue_;
+    std::unordered_map<hb_ticket, std::unique_ptr<Request>> reqs_;
+    hb_ticket next_ticket_ = 1;
+    uint64_t submitted_ = 0, completed_ = 0, steps_ = 0, edge_unions_ = 0;
+    uint32_t n_running_ = 0;
+
+    // owned by the loop thread
+    std::vector<Request *> running_reqs_;
+    void *d_arena_ = nullptr;
+    hbk::BatchJob *d_jobs_ = nullptr, *h_jobs_ = nullptr;
+    uint32_t jobs_cap_ = 0;
+    uint32_t *d_lists_ = nullptr;
+    uint64_t lists_cap_ = 0;
+    hipStream_t stream_ = nullptr;
+};
+
+hb_status Server::footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
+                            uint64_t &bytes) const {
+    const uint64_t m = 1ull << p;
+    levels = std::min(opts_.table_levels ? opts_.table_levels : 7u, floor_log2(g->n));
+    runs = opts_.union_kernel == HB_UNION_RUNS || (opts_.union_kernel == HB_UNION_AUTO && p <= 12);
+    if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
+        if (opts_.union_kernel == HB_UNION_RUNS)
+            return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
+        runs = false;
+    }
+    if (!runs) levels = 0;
+    const uint64_t n_flags = (uint64_t)g->n + 2;
+    bytes = 2 * align256((uint64_t)g->n * m * (levels + 1u)) + 2 * align256(8ull * g->n) +
+            align256(4ull * n_flags);
+    return HB_OK;
+}
+
+hb_status Server::start(const hb_server_opts *opts) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (running_) return fail(HB_EBUSY, "the request loop is already running");
+    hb_server_opts o = opts ? *opts : hb_server_opts{0, 0, 0, 0};
+    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel");
+    if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels > 24");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(HB_EDEVICE, "no GPU available");
+    HB_HIP(hipGetDevice(&device_));
+    if (o.hbm_budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        HB_HIP(hipMemGetInfo(&free_b, &total_b));
+        o.hbm_budget = align256(free_b / 4 * 3 - 255);
+    }
+    o.hbm_budget = align256(o.hbm_budget);
+    hipError_t e = hipMalloc(&d_arena_, o.hbm_budget);
+    if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "budget of %llu bytes not available",
+                                              (unsigned long long)o.hbm_budget);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(server budget)");
+    e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(d_arena_);
+        d_arena_ = nullptr;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    opts_ = o;
+    arena_.reset(o.hbm_budget);
+    peak_used_ = 0;
+    running_ = true;
+    stopping_ = false;
+    abort_ = false;
+    thread_ = std::thread([this] { loop(); });
+    return HB_OK;
+}
+
+hb_status Server::stop() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!running_) return fail(HB_ENOTFOUND, "the request loop is not running");
+        stopping_ = true;
+    }
+    cv_work_.notify_all();
+    if (thread_.joinable()) thread_.join();
+    std::lock_guard<std::mutex> lk(mu_);
+    running_ = false;
+    return HB_OK;
+}
+
+hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed, uint32_t flags,
+                         hb_ticket *out) {
+    if (!g || !out) return fail(HB_EINVAL, "NULL argument");
+    if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
+    if (flags & ~HB_SUBMIT_REGISTERS) return fail(HB_EINVAL, "unknown submit flags");
+    bool need_start;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        need_start = !running_;
+    }
+    if (need_start) {
+        const hb_status st = start(nullptr);
+        if (st != HB_OK && st != HB_EBUSY) return st;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    if (!running_ || stopping_) return fail(HB_EBUSY, "the request loop is stopping");
+    if (g->device != device_) return fail(HB_EINVAL, "graph lives on another device");
+    auto r = std::make_unique<Request>();
+    if (opts_.union_kernel == HB_UNION_RUNS && p > 12)
+        return fail(HB_EINVAL, "the run kernel supports p <= 12");
+    hb_status st = footprint(g, p, r->runs, r->levels, r->footprint);
+    if (st != HB_OK) return st;
+    if (align256(r->footprint) > arena_.size())
+        return fail(HB_ENOMEM, "request needs %llu bytes, the budget is %llu",
+                    (unsigned long long)r->footprint, (unsigned long long)arena_.size());
+    r->ticket = next_ticket_++;
+    r->g = g;
+    r->p = p;
+    r->depth = depth;
+    r->seed = seed;
+    r->flags = flags;
+    r->t_submit = now_ns();
+    g->inflight.fetch_add(1);
+    *out = r->ticket;
+    queue_.push_back(r.get());
+    reqs_.emplace(r->ticket, std::move(r));
+    ++submitted_;
+    cv_work_.notify_one();
+    return HB_OK;
+}
+
+hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
+    if (!out) return fail(HB_EINVAL, "out is NULL");
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = reqs_.find(t);
+    if (it == reqs_.end()) return fail(HB_ENOTFOUND, "unknown or already collected ticket %llu",
+                                       (unsigned long long)t);
+    Request *r = it->second.get();
+    if (block)
+        cv_done_.wait(lk, [&] { return r->state == State::Done || r->state == State::Failed; });
+    if (r->state == State::Queued || r->state == State::Running) return HB_PENDING;
+    if (r->state == State::Failed) {
+        const hb_status st = r->error;
+        const std::string msg = r->message;
+        reqs_.erase(it);
+        return fail(st, "%s", msg.c_str());
+    }
+    if (out->registers && !(r->flags & HB_SUBMIT_REGISTERS))
+        return fail(HB_EINVAL, "registers were not kept (submit with HB_SUBMIT_REGISTERS)");
+    const uint32_t n = r->g->n;
+    const double md = (double)(1u << r->p);
+    if (out->reach) memcpy(out->reach, r->reach.data(), sizeof(double) * n);
+    if (out->sum_d) memcpy(out->sum_d, r->sum_d.data(), sizeof(double) * n);
+    if (out->mean_depth)
+        for (uint32_t v = 0; v < n; ++v) {
+            const double nv = r->g->comp_size.empty() ? (double)n : (double)r->g->comp_size[v];
+            out->mean_depth[v] = nv >= 2.0 ? r->sum_d[v] / (nv - 1.0) : NAN;
+        }
+    if (out->registers) memcpy(out->registers, r->regs.data(), r->regs.size());
+    out->passes = r->job.done;
+    out->converged = r->job.converged;
+    out->c0 = md * std::log(md / (md - 1.0));
+    out->edge_unions = (uint64_t)r->job.done * r->g->n_edges;
+    out->init_ms = out->iter_ms = out->table_ms = 0.0;
+    out->run_ms = (double)(r->t_end - r->t_admit) / 1e6;
+    out->union_kernel = r->runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+    out->table_levels = r->levels;
+    out->t_submit_ns = r->t_submit;
+    out->t_admit_ns = r->t_admit;
+    out->t_start_ns = r->t_start;
+    out->t_end_ns = r->t_end;
+    reqs_.erase(it);
+    return HB_OK;
+}
+
+hb_status Server::stats(hb_server_stats_t *out) {
+    if (!out) return fail(HB_EINVAL, "out is NULL");
+    std::lock_guard<std::mutex> lk(mu_);
+    out->running = n_running_;
+    out->queued = (uint32_t)queue_.size();
+    out->submitted = submitted_;
+    out->completed = completed_;
+    out->steps = steps_;
+    out->budget_bytes = arena_.size();
+    out->used_bytes = arena_.used();
+    out->peak_used_bytes = peak_used_;
+    out->edge_unions = edge_unions_;
+    return HB_OK;
+}
+
+void Server::fail_all(hb_status st, const std::string &msg) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto mark = [&](Request *r) {
+        r->state = State::Failed;
+        r->error = st;
+        r->message = msg;
+        r->g->inflight.fetch_sub(1);
+    };
+    for (Request *r : running_reqs_) mark(r);
+    for (Request *r : queue_) mark(r);
+    running_reqs_.clear();
+    queue_.clear();
+    n_running_ = 0;
+    arena_.reset(arena_.size());
+    stopping_ = true;
+    cv_done_.notify_all();
+}
+
+// Copy a stopped request's outputs to host memory and free its block.
+void Server::retire(Request *r) {
+    const uint32_t n = r->g->n;
+    r->reach.resize(n);
+    r->sum_d.resize(n);
+    (void)hipMemcpyAsync(r->reach.data(), r->job.c_prev, sizeof(double) * n, hipMemcpyDeviceToHost,
+                         stream_);
+    (void)hipMemcpyAsync(r->sum_d.data(), r->job.sum_d, sizeof(double) * n, hipMemcpyDeviceToHost,
+                         stream_);
+    if (r->flags & HB_SUBMIT_REGISTERS) {
+        r->regs.resize((uint64_t)n << r->p);
+        (void)hipMemcpyAsync(r->regs.data(), r->job.buf[r->job.done & 1u], r->regs.size(),
+                             hipMemcpyDeviceToHost, stream_);
+    }
+}
+
+hb_status Server::step() {
+    // ---- admit
+    std::vector<Request *> admitted;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        while (!queue_.empty() &&
+               (opts_.max_running == 0 ||
+                running_reqs_.size() + admitted.size() < opts_.max_running)) {
+            Request *r = queue_.front();
+            uint64_t off;
+            if (!arena_.take(r->footprint, off)) break;  // arrival order: no overtaking
+            queue_.pop_front();
+            r->off = off;
+            r->state = State::Running;
+            r->t_admit = now_ns();
+            admitted.push_back(r);
+        }
+        peak_used_ = std::max(peak_used_, arena_.used());
+        n_running_ = (uint32_t)(running_reqs_.size() + admitted.size());
+    }
+    uint8_t *base = static_cast<uint8_t *>(d_arena_);
+    for (Request *r : admitted) {
+        hb_graph *g = r->g;
+        const uint64_t m = 1ull << r->p;
+        const uint64_t bb = align256((uint64_t)g->n * m * (r->levels + 1u));
+        const uint64_t sb = align256(8ull * g->n);
+        hbk::BatchJob &b = r->job;
+        b = hbk::BatchJob{};
+        b.bytes = g->d_bytes;
+        b.offsets = g->d_offsets;
+        b.buf[0] = base + r->off;
+        b.buf[1] = base + r->off + bb;
+        b.c_prev = reinterpret_cast<double *>(base + r->off + 2 * bb);
+        b.sum_d = reinterpret_cast<double *>(base + r->off + 2 * bb + sb);
+        b.flags = reinterpret_cast<uint32_t *>(base + r->off + 2 * bb + 2 * sb);
+        b.seed = r->seed;
+        b.n = g->n;
+        b.p = r->p;
+        b.depth = r->depth;
+        b.levels = r->levels;
+        b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
+        b.runs = r->runs ? 1u : 0u;
+        running_reqs_.push_back(r);
+    }
+    const uint32_t nj = (uint32_t)running_reqs_.size();
+    if (nj == 0) return HB_OK;
+
+    // ---- job table and launch lists for this step
+    if (jobs_cap_ < nj) {
+        (void)hipFree(d_jobs_);
+        if (h_jobs_) (void)hipHostFree(h_jobs_);
+        d_jobs_ = nullptr;
+        h_jobs_ = nullptr;
+        jobs_cap_ = 0;
+        const uint32_t cap = std::max<uint32_t>(64, nj * 2);
+        HB_HIP(hipMalloc(&d_jobs_, sizeof(hbk::BatchJob) * cap));
+        HB_HIP(hipHostMalloc((void **)&h_jobs_, sizeof(hbk::BatchJob) * cap, hipHostMallocDefault));
+        jobs_cap_ = cap;
+    }
+    for (uint32_t j = 0; j < nj; ++j) h_jobs_[j] = running_reqs_[j]->job;
+    struct Cls {
+        uint32_t p;
+        bool runs;
+        std::vector<uint32_t> list, base;
+        uint32_t list_off, base_off;
+    };
+    std::vector<Cls> classes, inits;
+    std::vector<uint32_t> all(nj), runs_list, new_list;
+    uint32_t max_levels = 0;
+    auto add_to = [&](std::vector<Cls> &cs, uint32_t j, bool runs) {
+        Cls *c = nullptr;
+        for (auto &x : cs)
+            if (x.p == h_jobs_[j].p && x.runs == runs) c = &x;
+        if (!c) {
+            cs.push_back(Cls{h_jobs_[j].p, runs, {}, {0u}, 0, 0});
+            c = &cs.back();
+        }
+        const uint32_t npb = hbk::shape_for((int)h_jobs_[j].p).nodes_per_block;
+        c->list.push_back(j);
+        c->base.push_back(c->base.back() + (h_jobs_[j].n + npb - 1) / npb);
+    };
+    for (uint32_t j = 0; j < nj; ++j) {
+        all[j] = j;
+        const bool is_new = j >= nj - admitted.size();
+        if (is_new) {
+            new_list.push_back(j);
+            add_to(inits, j, false);
+        }
+        if (h_jobs_[j].runs) {
+            runs_list.push_back(j);
+            max_levels = std::max(max_levels, h_jobs_[j].levels);
+        }
+        add_to(classes, j, h_jobs_[j].runs != 0);
+    }
+    std::vector<uint32_t> lists(all);
+    const uint32_t runs_off = (uint32_t)lists.size();
+    lists.insert(lists.end(), runs_list.begin(), runs_list.end());
+    std::vector<uint32_t> table_off(max_levels + 1, 0), table_blocks(max_levels + 1, 0);
+    for (uint32_t k = 1; k <= max_levels; ++k) {
+        table_off[k] = (uint32_t)lists.size();
+        uint32_t acc = 0;
+        lists.push_back(0);
+        for (uint32_t j : runs_list) {
+            if (k <= h_jobs_[j].levels) acc += hbk::batch_table_blocks(h_jobs_[j].n, h_jobs_[j].p, k);
+            lists.push_back(acc);
+        }
+        table_blocks[k] = acc;
+    }
+    for (auto *cs : {&classes, &inits})
+        for (auto &c : *cs) {
+            c.list_off = (uint32_t)lists.size();
+            lists.insert(lists.end(), c.list.begin(), c.list.end());
+            c.base_off = (uint32_t)lists.size();
+            lists.insert(lists.end(), c.base.begin(), c.base.end());
+        }
+    if (lists_cap_ < lists.size()) {
+        (void)hipFree(d_lists_);
+        d_lists_ = nullptr;
+        lists_cap_ = 0;
+        const uint64_t cap = std::max<uint64_t>(4096, lists.size() * 2);
+        HB_HIP(hipMalloc(&d_lists_, sizeof(uint32_t) * cap));
+        lists_cap_ = cap;
+    }
+    hipStream_t s = stream_;
+    HB_HIP(hipMemcpyAsync(d_jobs_, h_jobs_, sizeof(hbk::BatchJob) * nj, hipMemcpyHostToDevice, s));
+    HB_HIP(hipMemcpyAsync(d_lists_, lists.data(), sizeof(uint32_t) * lists.size(),
+                          hipMemcpyHostToDevice, s));
+
+    // ---- init the newly admitted, then one step for everyone running
+    const uint64_t t_launch = now_ns();
+    for (uint32_t j : new_list) {
+        HB_HIP(hbk::launch_fill_u32(h_jobs_[j].flags, 0u, h_jobs_[j].n_flags, s));
+        running_reqs_[j]->t_start = t_launch;
+    }
+    for (auto &c : inits)
+        HB_HIP(hbk::launch_batch_init((int)c.p, d_jobs_, d_lists_ + c.list_off, d_lists_ + c.base_off,
+                                      (uint32_t)c.list.size(), c.base.back(), s));
+    for (uint32_t k = 1; k <= max_levels; ++k)
+        HB_HIP(hbk::launch_batch_table(d_jobs_, d_lists_ + runs_off, d_lists_ + table_off[k],
+                                       (uint32_t)runs_list.size(), table_blocks[k], k, s));
+    for (auto &c : classes)
+        HB_HIP(hbk::launch_batch_union((int)c.p, c.runs, d_jobs_, d_lists_ + c.list_off,
+                                       d_lists_ + c.base_off, (uint32_t)c.list.size(),
+                                       c.base.back(), s));
+    HB_HIP(hbk::launch_batch_step_end(d_jobs_, d_lists_, nj, s));
+    HB_HIP(hipMemcpyAsync(h_jobs_, d_jobs_, sizeof(hbk::BatchJob) * nj, hipMemcpyDeviceToHost, s));
+    HB_HIP(hipStreamSynchronize(s));
+
+    // ---- retire the requests that stopped
+    std::vector<Request *> done, still;
+    for (uint32_t j = 0; j < nj; ++j) {
+        Request *r = running_reqs_[j];
+        r->job = h_jobs_[j];
+        if (r->job.done) {
+            retire(r);
+            done.push_back(r);
+        } else {
+            still.push_back(r);
+        }
+    }
+    if (!done.empty()) HB_HIP(hipStreamSynchronize(s));
+    running_reqs_.swap(still);
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        ++steps_;
+        const uint64_t t_end = now_ns();
+        for (Request *r : done) {
+            r->t_end = t_end;
+            r->state = State::Done;
+            arena_.give(r->off, r->footprint);
+            r->g->inflight.fetch_sub(1);
+            ++completed_;
+            edge_unions_ += (uint64_t)r->job.done * r->g->n_edges;
+        }
+        n_running_ = (uint32_t)running_reqs_.size();
+    }
+    if (!done.empty()) cv_done_.notify_all();
+    return HB_OK;
+}
+
+void Server::loop() {
+    (void)hipSetDevice(device_);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_work_.wait(lk, [&] { return stopping_ || !queue_.empty() || !running_reqs_.empty(); });
+            if (abort_ || (stopping_ && queue_.empty() && running_reqs_.empty())) break;
+        }
+        const hb_status st = step();
+        if (st != HB_OK) {
+            fail_all(st, g_err);
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(stream_);
+    (void)hipFree(d_lists_);
+    (void)hipFree(d_jobs_);
+    if (h_jobs_) (void)hipHostFree(h_jobs_);
+    (void)hipFree(d_arena_);
+    (void)hipStreamDestroy(stream_);
+    d_lists_ = nullptr;
+    d_jobs_ = nullptr;
+    h_jobs_ = nullptr;
+    d_arena_ = nullptr;
+    stream_ = nullptr;
+    jobs_cap_ = 0;
+    lists_cap_ = 0;
+}
+
+Server g_server;
+
+}  // namespace
+
+extern "C" {
+
+hb_status hb_server_start(const hb_server_opts *opts) { return g_server.start(opts); }
+
+hb_status hb_server_stop(void) { return g_server.stop(); }
+
+hb_status hb_submit(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                    uint32_t flags, hb_ticket *out) {
+    return g_server.submit(g, p, depth_limit, hash_seed, flags, out);
+}
+
+hb_status hb_poll(hb_ticket t, hb_result *out) { return g_server.poll(t, out, false); }
+
+hb_status hb_wait(hb_ticket t, hb_result *out) { return g_server.poll(t, out, true); }
+
+hb_status hb_server_stats(hb_server_stats_t *out) { return g_server.stats(out); }
+
+}  // extern "C"

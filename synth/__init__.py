@@ -324,6 +324,42 @@ def city(seed: int = 0, device: str = "gpu") -> Graph:
                                          **URBAN))
 
 
+def batch_spec(seed: int, n_lo: int = 500, n_hi: int = 20000, ps=(8, 10, 12),
+               depths=(2, 3, 5, 0)) -> dict:
+    """Seeded analysis of the batched workload: target size, cell size, p and depth.
+
+    Sizes are log-uniform in [n_lo, n_hi] open cells; cells are 1 or 2 m (the
+    street/building generator's lengths are divided by the cell size); the raster
+    is square with about n / 0.8 cells (the generator leaves ~80 % of cells open).
+    """
+    rng = _rng(seed, 7)
+    n_target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+    cell_m = float(rng.choice([1.0, 2.0]))
+    side = max(8, int(round(np.sqrt(n_target / 0.8))))
+    return dict(seed=seed, n_target=n_target, cell_m=cell_m, side=side,
+                p=int(rng.choice(ps)), depth=int(rng.choice(depths)))
+
+
+def batch_graph(seed: int, device: str = "gpu", **kw) -> Graph:
+    """One graph of the batched workload (see batch_spec)."""
+    spec = batch_spec(seed, **kw)
+    obst = urban_raster(seed, spec["side"], spec["side"], cell_m=spec["cell_m"], **URBAN)
+    return graph_from_raster(obst, name=f"batch{spec['side']}-s{seed}", device=device,
+                             params=dict(kind="batch", **spec))
+
+
+def serve_graph(seed: int, n_lo: int = 1000, n_hi: int = 120000, device: str = "gpu") -> Graph:
+    """One graph of the served workload's pool: the urban generator (3 m cells) on a
+    square raster sized for a log-uniform target of n_lo..n_hi open cells."""
+    rng = _rng(seed, 11)
+    n_target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+    side = max(8, int(round(np.sqrt(n_target / 0.807))))
+    obst = urban_raster(seed, side, side, cell_m=URBAN_CELL_M, **URBAN)
+    return graph_from_raster(obst, name=f"pool{side}-s{seed}", device=device,
+                             params=dict(kind="serve", seed=seed, side=side, n_target=n_target,
+                                         cell_m=URBAN_CELL_M))
+
+
 # ---------------------------------------------------------------- special graphs
 def from_edges(n: int, edges, name: str = "") -> Graph:
     """Undirected graph from an edge list (for closed-form cases: paths, stars, cliques)."""

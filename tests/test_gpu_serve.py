@@ -1,0 +1,126 @@
+"""Served runs (hb_submit / hb_poll): continuous batching, admission by memory, identical results."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _load(hb, g):
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    return hb.graph_load(off, deg, data)
+
+
+def _same(a, b, what):
+    assert a.passes == b.passes, (what, a.passes, b.passes)
+    assert a.converged == b.converged, what
+    assert np.array_equal(a.reach, b.reach), what
+    assert np.array_equal(a.sum_d, b.sum_d), what
+    if a.registers is not None and b.registers is not None:
+        assert np.array_equal(a.registers, b.registers), what
+
+
+@pytest.fixture
+def server(hb):
+    started = []
+
+    def start(**kw):
+        hb.server_start(**kw)
+        started.append(True)
+
+    yield start
+    if started:
+        hb.server_stop()
+
+
+def test_served_mix_equals_single_runs(hb, server):
+    server()
+    graphs = [synth.tiny(0), synth.tiny(3), synth.grid_graph(2, 64, 48), synth.star_graph(60),
+              synth.random_graph(150, 0.02, 4)]
+    Gs = [_load(hb, g) for g in graphs]
+    specs = []
+    for i, G in enumerate(Gs):
+        for k, (p, depth) in enumerate([(10, 0), (8, 3), (13, 2), (4 + i, 1)]):
+            specs.append((G, p, depth, 77 * i + k))
+    tickets = [hb.submit(G, p, d, sd, registers=True) for (G, p, d, sd) in specs]
+    res = [t.wait() for t in tickets]
+    for (G, p, d, sd), r in zip(specs, res):
+        _same(r, G.run(p, d, sd, registers=True), f"p={p} d={d} seed={sd}")
+        assert r.t_submit_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_end_ns
+    st = hb.server_stats()
+    assert st["completed"] >= len(specs) and st["running"] == 0 and st["queued"] == 0
+    for G in Gs:
+        G.free()
+
+
+def test_requests_join_while_others_run(hb, server):
+    """A long request keeps running while short ones arrive, join and finish first."""
+    server()
+    big = _load(hb, synth.grid_graph(1, 120, 100))
+    small = _load(hb, synth.tiny(2))
+    tb = hb.submit(big, 12, 0, 5)
+    time.sleep(0.002)
+    ts = [hb.submit(small, 8, 2, s) for s in range(6)]
+    rs = [t.wait() for t in ts]
+    rb = tb.wait()
+    assert max(r.t_end_ns for r in rs) <= rb.t_end_ns
+    assert any(r.t_admit_ns > rb.t_admit_ns for r in rs)
+    _same(rb, big.run(12, 0, 5), "big")
+    for s, r in enumerate(rs):
+        _same(r, small.run(8, 2, s), f"small {s}")
+    big.free()
+    small.free()
+
+
+def test_admission_respects_the_budget(hb, server):
+    g = synth.tiny(4)
+    G = _load(hb, g)
+    per = 2 * ((g.n * 1024 * 8 + 255) // 256 * 256) + 2 * ((8 * g.n + 255) // 256 * 256) + \
+        (4 * (g.n + 2) + 255) // 256 * 256
+    server(hbm_budget=2 * per + 4096)  # room for two requests at a time
+    ts = [hb.submit(G, 10, 0, s) for s in range(7)]
+    rs = [t.wait() for t in ts]
+    st = hb.server_stats()
+    assert st["peak_used_bytes"] <= st["budget_bytes"]
+    assert st["peak_used_bytes"] >= per
+    for s, r in enumerate(rs):
+        _same(r, G.run(10, 0, s), f"seed {s}")
+    with pytest.raises(hb.HBError) as e:
+        hb.submit(_load(hb, synth.grid_graph(0, 64, 64)), 12, 0, 0)
+    assert e.value.status == hb.HB_ENOMEM
+    G.free()
+
+
+def test_poll_and_ticket_rules(hb, server):
+    server(max_running=1)  # one request at a time: the second one waits in the queue
+    big = _load(hb, synth.grid_graph(1, 120, 100))
+    G = _load(hb, synth.tiny(5))
+    tb = hb.submit(big, 12, 0, 3)
+    t = hb.submit(G, 9, 0, 1)
+    with pytest.raises(hb.HBError) as e:
+        G.free()  # queued behind the long request
+    assert e.value.status == hb.HB_EBUSY
+    r = None
+    for _ in range(2000000):
+        r = t.poll()
+        if r is not None:
+            break
+    assert r is not None
+    assert tb.poll() is not None or tb.wait() is not None
+    _same(r, G.run(9, 0, 1), "polled")
+    with pytest.raises(hb.HBError) as e:
+        t.poll()
+    assert e.value.status == hb.HB_ENOTFOUND
+    # registers were not kept for this ticket
+    t2 = hb.submit(G, 9, 1, 2)
+    t2.registers = True
+    with pytest.raises(hb.HBError) as e:
+        t2.wait()
+    assert e.value.status == hb.HB_EINVAL
+    t2.registers = False
+    assert t2.wait().passes == 1
+    G.free()
+    big.free()
