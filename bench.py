@@ -190,7 +190,7 @@ def batch_bench(args):
     }
     for G in Gs:
         G.free()
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def serve_bench(args):
@@ -247,13 +247,26 @@ def serve_bench(args):
     log(f"mean sequential service {mean_s * 1e3:.2f} ms -> lambda_seq {lam_seq:.1f}/s")
 
     def run_trace(arrivals, served):
-        """Replay arrivals; returns (latencies s, results, wall s)."""
-        lat = [None] * nreq
+        """Replay arrivals; returns (latencies s, results, wall s).
+
+        Latency is the library's completion timestamp (CLOCK_MONOTONIC, taken when
+        the results are ready) minus the scheduled arrival, so the client's own
+        polling delays do not count; uploads of fresh graphs do, since the single
+        client uploads before it submits.
+        """
         results = [None] * nreq
         t_start = time.perf_counter()
+        t0_ns = time.monotonic_ns()
+        arr_ns = t0_ns + (np.asarray(arrivals) * 1e9).astype(np.int64)
         uploads = {}
+
+        def graph_for(k):
+            G = resident.get(k) or uploads.get(k)
+            if G is None:
+                G = uploads[k] = hb.graph_load(*graphs[k]["csr"])
+            return G
+
         if served:
-            tickets = [None] * nreq
             lock = threading.Lock()
             done = threading.Event()
             pending = {}
@@ -262,28 +275,21 @@ def serve_bench(args):
                 while not done.is_set() or pending:
                     with lock:
                         items = list(pending.items())
-                    if not items:
-                        time.sleep(0.0002)
-                        continue
                     for i, tk in items:
                         r = tk.poll()
                         if r is not None:
-                            lat[i] = time.perf_counter() - (t_start + arrivals[i])
                             results[i] = r
                             with lock:
                                 del pending[i]
-                    time.sleep(0.0001)
+                    time.sleep(0.0005)
 
             th = threading.Thread(target=poller)
             th.start()
             for i in range(nreq):
-                now = time.perf_counter() - t_start
-                if arrivals[i] > now:
-                    time.sleep(arrivals[i] - now)
-                k = int(req_graph[i])
-                G = resident.get(k) or uploads.get(k)
-                if G is None:
-                    G = uploads[k] = hb.graph_load(*graphs[k]["csr"])
+                wait = (arr_ns[i] - time.monotonic_ns()) / 1e9
+                if wait > 0:
+                    time.sleep(wait)
+                G = graph_for(int(req_graph[i]))
                 tk = hb.submit(G, int(req_p[i]), int(req_d[i]), int(req_seed[i]))
                 with lock:
                     pending[i] = tk
@@ -291,19 +297,15 @@ def serve_bench(args):
             th.join()
         else:
             for i in range(nreq):
-                now = time.perf_counter() - t_start
-                if arrivals[i] > now:
-                    time.sleep(arrivals[i] - now)
-                k = int(req_graph[i])
-                G = resident.get(k) or uploads.get(k)
-                if G is None:
-                    G = uploads[k] = hb.graph_load(*graphs[k]["csr"])
-                results[i] = service(i, G)
-                lat[i] = time.perf_counter() - (t_start + arrivals[i])
+                wait = (arr_ns[i] - time.monotonic_ns()) / 1e9
+                if wait > 0:
+                    time.sleep(wait)
+                results[i] = service(i, graph_for(int(req_graph[i])))
         wall = time.perf_counter() - t_start
+        lat = np.array([(r.t_end_ns - a) / 1e9 for r, a in zip(results, arr_ns)])
         for G in uploads.values():
             G.free()
-        return np.array(lat), results, wall
+        return lat, results, wall
 
     hb.server_start(hbm_budget=int(args.serve_budget_gb * (1 << 30)))
     rows = []
@@ -353,7 +355,7 @@ def serve_bench(args):
         "server": stats,
         "identical_results": True,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def main():
@@ -368,6 +370,8 @@ def main():
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 1.0, 1.25])
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single mode: skip the short batched and served runs in the JSON line")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="city", choices=["city", "urban", "tiny"])
@@ -393,9 +397,11 @@ def main():
     if hb.device_count() < 1:
         raise SystemExit("no GPU visible")
     if args.mode == "batch":
-        return batch_bench(args)
+        print(json.dumps(batch_bench(args)), flush=True)
+        return
     if args.mode == "serve":
-        return serve_bench(args)
+        print(json.dumps(serve_bench(args)), flush=True)
+        return
     g = make_graph(args.config, args.seed)
     t0 = time.perf_counter()
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
@@ -494,6 +500,25 @@ def main():
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(off, deg, data, n, p, args.seed, args.cpu_seconds)
     G.free()
+    del off, deg, data
+    if not args.no_extras:
+        # short runs of the batched and served forms (their own modes run them in full)
+        log("batched form: 64 graphs, batched vs sequential ...")
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps, bargs.warmup = 3, 1
+        b = batch_bench(bargs)
+        line["batched"] = {"value": b["value"], "unit": b["unit"], "ms": b["ms_per_step"],
+                           "sequential_value": b["sequential"]["value"],
+                           "speedup_vs_sequential": b["speedup_vs_sequential"],
+                           "workload": b["config"]["workload"], "identical_results": True}
+        log("served form: Poisson mix, served vs sequential FIFO ...")
+        sargs = argparse.Namespace(**vars(args))
+        sargs.pool, sargs.pool_max_nodes, sargs.requests = 40, 60000, 300
+        sargs.rates = [0.5, 1.0, 1.5]
+        sv = serve_bench(sargs)
+        line["serving"] = {"workload": sv["config"]["workload"],
+                           "lambda_seq_per_s": sv["config"]["lambda_seq_per_s"],
+                           "rates": sv["rates"], "identical_results": True}
     print(json.dumps(line), flush=True)
 
 

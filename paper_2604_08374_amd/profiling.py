@@ -33,6 +33,11 @@ def _find(d: str, suffix: str) -> str:
 
 
 def _short(name: str) -> str:
+    for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
+                "batch_step_end_kernel"):
+        if key in name:
+            tmpl = name[name.index(key) + len(key):]
+            return key + (tmpl[:tmpl.index(">") + 1] if tmpl.startswith("<") else "")
     for key in ("union_runs_kernel", "union_kernel", "table_level_kernel", "init_kernel",
                 "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
         if key in name:
@@ -40,6 +45,11 @@ def _short(name: str) -> str:
             if tmpl.startswith("<"):
                 return key + tmpl[:tmpl.index(">") + 1]
             return key
+    for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
+                "batch_step_end_kernel"):
+        if key in name:
+            tmpl = name[name.index(key) + len(key):]
+            return key + (tmpl[:tmpl.index(">") + 1] if tmpl.startswith("<") else "")
     return name[:48]
 
 
@@ -68,20 +78,34 @@ def kernel_sha256() -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", default=None)
+    ap.add_argument("--write", default=None)
     ap.add_argument("--hit", default=None, help="optional --pmc TCC_HIT_sum TCC_MISS_sum run")
-    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--kernel", default="union_kernel<10>")
     ap.add_argument("--algo-bytes", type=int, default=0,
                     help="algorithmic bytes per launch of --kernel (from bench.py)")
     ap.add_argument("--cmd", action="append", default=[])
     ap.add_argument("--title", default="union kernel")
     ap.add_argument("--out", required=True)
-    ap.add_argument("--counters", required=True)
+    ap.add_argument("--counters", default=None)
     args = ap.parse_args()
 
     stats = kernel_stats(args.trace)
+    if not (args.fetch and args.write):
+        # trace only: the per-kernel table
+        lines = [f"# rocprofv3 summary: {args.title}", ""]
+        lines += ["Command (run from the repository root; writes CSV under gpurun_out/):", ""]
+        lines += [f"    {c}" for c in args.cmd]
+        lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
+                  "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
+        for name, (c, a, t) in sorted(stats.items(), key=lambda kv: -kv[1][2]):
+            lines.append(f"| {name} | {c} | {a / 1e6:.3f} | {t / 1e6:.1f} |")
+        lines += ["", f"* kernel source sha256 {kernel_sha256()}", ""]
+        with open(args.out, "w") as f:
+            f.write("\n".join(lines))
+        print("\n".join(lines))
+        return
     fetch = counter_means(args.fetch)
     write = counter_means(args.write)
     copy_kib = args.copy_bytes / 1024.0
