@@ -227,17 +227,23 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
  * of stop flags -- fits the memory budget, and advances every admitted
  * request by one HyperBall step per batched step (continuous batching: a
  * request that arrives while others run joins at the next step, and finished
- * requests free their memory at once).  Results match hb_run for the same
+ * requests free their memory at once).  Requests whose steps gather more than
+ * slow_lane_bytes run on a second lane with its own thread and stream, so
+ * short requests do not wait for the steps of very large ones.  Results match
+ * hb_run for the same
  * arguments bit for bit.  Graphs stay owned by the caller; hb_graph_free
  * returns HB_EBUSY while a submitted request still uses the graph.
  */
 typedef uint64_t hb_ticket;
 
 typedef struct {
-    uint64_t hbm_budget;   /* device bytes for running requests; 0 = 3/4 of free memory */
-    uint32_t max_running;  /* cap on admitted requests; 0 = none */
-    uint32_t union_kernel; /* HB_UNION_* for every request */
-    uint32_t table_levels; /* 0 = default */
+    uint64_t hbm_budget;      /* device bytes for running requests; 0 = 3/4 of free memory */
+    uint32_t max_running;     /* cap on admitted requests; 0 = none */
+    uint32_t union_kernel;    /* HB_UNION_* for every request */
+    uint32_t table_levels;    /* 0 = default */
+    uint64_t slow_lane_bytes; /* requests gathering more bytes per step run on a second lane
+                                 (own thread and stream, shared budget); 0 = 2 GiB,
+                                 UINT64_MAX = one lane */
 } hb_server_opts;
 
 typedef struct {

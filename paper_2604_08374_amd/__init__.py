@@ -58,7 +58,8 @@ class _Result(ctypes.Structure):
 
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_running", ctypes.c_uint32),
-                ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32)]
+                ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
+                ("slow_lane_bytes", ctypes.c_uint64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -355,10 +356,10 @@ _SERVER_STARTED = False
 
 
 def server_start(hbm_budget: int = 0, max_running: int = 0, kernel: str = "auto",
-                 table_levels: int = 0) -> None:
+                 table_levels: int = 0, slow_lane_bytes: int = 0) -> None:
     """hb_server_start: start the request loop (continuous batching)."""
     global _SERVER_STARTED
-    o = _ServerOpts(hbm_budget, max_running, _KERNELS[kernel], table_levels)
+    o = _ServerOpts(hbm_budget, max_running, _KERNELS[kernel], table_levels, slow_lane_bytes)
     _check(_lib().hb_server_start(ctypes.byref(o)))
     _SERVER_STARTED = True
 

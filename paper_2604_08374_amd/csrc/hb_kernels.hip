@@ -281,12 +281,19 @@ struct RowDecoder {
     // into lanes 0..cnt-1 in increasing order (other lanes: unspecified).
     __device__ __forceinline__ uint32_t chunk(const uint8_t *__restrict__ bytes, uint64_t base,
                                               uint64_t end, uint32_t &cnt) {
+        const bool valid = base + lane_id() < end;
+        const uint32_t b = valid ? (uint32_t)bytes[base + lane_id()] : 0u;
+        return chunk_of(b, valid, ballot(valid && !(b & 0x80u)), ballot(valid && (b & 0x80u)),
+                        cnt);
+    }
+
+    // The same from this lane's byte b (0 when !valid) and the chunk's
+    // terminator and continuation ballots.
+    __device__ __forceinline__ uint32_t chunk_of(uint32_t b, bool valid, uint64_t term,
+                                                 uint64_t cont, uint32_t &cnt) {
+        (void)valid;
         const uint32_t lane = lane_id();
         const uint64_t lt_mask = (1ull << lane) - 1ull;
-        const bool valid = base + lane < end;
-        const uint32_t b = valid ? (uint32_t)bytes[base + lane] : 0u;
-        const uint64_t term = ballot(valid && !(b & 0x80u));
-        const uint64_t cont = ballot(valid && (b & 0x80u));
         const uint64_t below = term & lt_mask;
         const uint32_t start = below ? 64u - (uint32_t)__builtin_clzll(below) : 0u;
         const uint32_t pos = lane - start;
@@ -485,6 +492,7 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
 // and level 0 is cur itself.  The result is the same registers as the
 // per-edge kernel.
 constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
+constexpr int kScalarWalk = 8;             // chunks with at most this many special varints
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
 template <int P>
@@ -557,13 +565,73 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     RunGather<P> g{tbl, n, levels, queue, 0u};
     const uint32_t top = 1u << levels;
 
-    bool have = false;      // a run is open: [ra, rl]
+    bool have = false;      // a run is open: [ra, rl]; rl is the last id decoded
     uint32_t ra = 0, rl = 0;
     const uint64_t row_end = offsets[v + 1];
     RowDecoder dec;
     for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
+        const bool valid = base + lane < row_end;
+        const uint32_t b = valid ? (uint32_t)bytes[base + lane] : 0u;
+        const uint64_t term = ballot(valid && !(b & 0x80u));
+        const uint64_t cont = ballot(valid && (b & 0x80u));
+        // Single-byte varints of value 1 after the row's first id are deltas of
+        // one: they only extend the open run.  When few varints in the chunk
+        // are anything else, walk those few in scalar code.
+        const uint64_t after_term = (term << 1) | (dec.carry_sh == 0u ? 1ull : 0ull);
+        uint64_t trivial = ballot(valid && b == 0x01u) & after_term;
+        if (!have) trivial &= ~(term & (0ull - term));  // the row's first id is absolute
+        const uint64_t special = term & ~trivial;
+        if (__builtin_popcountll(special) <= kScalarWalk) {
+            uint32_t id = rl;
+            uint32_t pos = 0;  // lanes below pos are accounted for
+            uint64_t rest = special;
+            while (rest) {
+                const uint32_t e = (uint32_t)__builtin_ctzll(rest);
+                rest &= rest - 1ull;
+                const uint64_t span = ((1ull << e) - 1ull) & ~((1ull << pos) - 1ull);
+                const uint32_t ones = (uint32_t)__builtin_popcountll(trivial & span);
+                id += ones;  // deltas of one extend the open run
+                const uint64_t below = term & ((1ull << e) - 1ull);
+                const uint32_t s0 = below ? 64u - (uint32_t)__builtin_clzll(below) : 0u;
+                uint32_t val = s0 == 0u ? dec.carry_val : 0u;
+                uint32_t sh = s0 == 0u ? dec.carry_sh : 0u;
+                for (uint32_t k = s0; k <= e; ++k, sh += 7u)
+                    if (sh < 32u) val |= (readlane(b, k) & 0x7Fu) << sh;
+                if (!have) {
+                    id = val;
+                    ra = id;
+                    have = true;
+                } else {
+                    const uint32_t nid = id + val;
+                    if (!(nid == id + 1u || (nid == id + 2u && id + 1u == v))) {
+                        g.push_run(acc, ra, id, lane);
+                        ra = nid;
+                    }
+                    id = nid;
+                }
+                pos = e + 1u;
+            }
+            const uint64_t tail = pos >= 64u ? 0ull : ~((1ull << pos) - 1ull);
+            id += (uint32_t)__builtin_popcountll(trivial & tail);
+            rl = id;
+            dec.run = id;
+            // a varint cut by the chunk's end carries into the next chunk
+            if ((cont >> (kWave - 1)) & 1ull) {
+                const uint32_t s0 = term ? 64u - (uint32_t)__builtin_clzll(term) : 0u;
+                uint32_t val = s0 == 0u ? dec.carry_val : 0u;
+                uint32_t sh = s0 == 0u ? dec.carry_sh : 0u;
+                for (uint32_t k = s0; k < kWave; ++k, sh += 7u)
+                    if (sh < 32u) val |= (readlane(b, k) & 0x7Fu) << sh;
+                dec.carry_val = val;
+                dec.carry_sh = sh;
+            } else {
+                dec.carry_val = 0u;
+                dec.carry_sh = 0u;
+            }
+            continue;
+        }
         uint32_t cnt;
-        const uint32_t ids = dec.chunk(bytes, base, row_end, cnt);
+        const uint32_t ids = dec.chunk_of(b, valid, term, cont, cnt);
         if (cnt == 0) continue;
         const bool in = lane < cnt;
         uint32_t prev = shfl_up(ids, 1);
@@ -614,8 +682,11 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     finish_node<P>(acc, v, 0, next, c_prev, sum_d, flag_t, t);
 }
 
+// Five waves per SIMD: the run kernel's latency hiding needs the occupancy more
+// than the few registers the bound takes away (measured: 33.5 ms per city step
+// against 39.3 ms at the four waves its natural register count allows).
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void union_runs_kernel(
+__global__ __launch_bounds__(Cfg<P>::THREADS, 5) void union_runs_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
@@ -692,7 +763,7 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void batch_init_kernel(
 }
 
 template <int P, bool RUNS>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void batch_union_kernel(
+__global__ __launch_bounds__(Cfg<P>::THREADS, RUNS ? 5 : 1) void batch_union_kernel(
     BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ block_base, uint32_t nlist) {
     using C = Cfg<P>;

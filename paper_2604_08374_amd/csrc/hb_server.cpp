@@ -10,11 +10,15 @@
 // registers are copied to host memory owned by the request record and their
 // block is freed at once.  Each request keeps its own step count, so requests
 // join and leave between any two steps (continuous batching at step
-// granularity).
+// granularity).  Requests are split over two lanes by the bytes one of their
+// steps gathers: each lane has its own thread, stream and running set, and both
+// share the budget arena, so short requests never wait for the step of a very
+// large one and the two kinds overlap on the device.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -100,6 +104,18 @@ struct Request {
     std::vector<uint8_t> regs;
 };
 
+struct Lane {
+    std::deque<Request *> queue;        // guarded by Server::mu_
+    std::vector<Request *> running;     // owned by the lane thread
+    hbk::BatchJob *d_jobs = nullptr, *h_jobs = nullptr;
+    uint32_t jobs_cap = 0;
+    uint32_t *d_lists = nullptr;
+    uint64_t lists_cap = 0;
+    hipStream_t stream = nullptr;
+    std::thread thread;
+    uint32_t n_running = 0;             // guarded by Server::mu_
+};
+
 class Server {
 public:
     hb_status start(const hb_server_opts *opts);
@@ -109,46 +125,38 @@ public:
     hb_status poll(hb_ticket t, hb_result *out, bool block);
     hb_status stats(hb_server_stats_t *out);
     ~Server() {
-        // process exit without hb_server_stop: end the loop after its current step
+        // process exit without hb_server_stop: end the loops after their current step
         {
             std::lock_guard<std::mutex> lk(mu_);
             abort_ = true;
             stopping_ = true;
         }
         cv_work_.notify_all();
-        if (thread_.joinable()) thread_.join();
+        for (auto &l : lanes_)
+            if (l.thread.joinable()) l.thread.join();
     }
 
 private:
-    void loop();
-    hb_status step();
-    void fail_all(hb_status st, const std::string &msg);
-    void retire(Request *r);
+    void loop(Lane &L);
+    hb_status step(Lane &L);
+    void fail_all(Lane &L, hb_status st, const std::string &msg);
+    void retire(Lane &L, Request *r);
     hb_status footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
                         uint64_t &bytes) const;
 
     std::mutex mu_;  // guards everything below that client threads touch
     std::condition_variable cv_work_, cv_done_;
-    std::thread thread_;
     bool running_ = false, stopping_ = false, abort_ = false;
     hb_server_opts opts_{};
+    uint64_t slow_bytes_ = 0;  // a request gathering more per step goes to the slow lane
     int device_ = 0;
     Arena arena_;
     uint64_t peak_used_ = 0;
-    std::deque<Request *> queue_;
+    Lane lanes_[2];  // 0: fast, 1: slow
     std::unordered_map<hb_ticket, std::unique_ptr<Request>> reqs_;
     hb_ticket next_ticket_ = 1;
     uint64_t submitted_ = 0, completed_ = 0, steps_ = 0, edge_unions_ = 0;
-    uint32_t n_running_ = 0;
-
-    // owned by the loop thread
-    std::vector<Request *> running_reqs_;
     void *d_arena_ = nullptr;
-    hbk::BatchJob *d_jobs_ = nullptr, *h_jobs_ = nullptr;
-    uint32_t jobs_cap_ = 0;
-    uint32_t *d_lists_ = nullptr;
-    uint64_t lists_cap_ = 0;
-    hipStream_t stream_ = nullptr;
 };
 
 hb_status Server::footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
@@ -171,7 +179,7 @@ hb_status Server::footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t 
 hb_status Server::start(const hb_server_opts *opts) {
     std::lock_guard<std::mutex> lk(mu_);
     if (running_) return fail(HB_EBUSY, "the request loop is already running");
-    hb_server_opts o = opts ? *opts : hb_server_opts{0, 0, 0, 0};
+    hb_server_opts o = opts ? *opts : hb_server_opts{0, 0, 0, 0, 0};
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels > 24");
     int count = 0;
@@ -187,19 +195,24 @@ hb_status Server::start(const hb_server_opts *opts) {
     if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "budget of %llu bytes not available",
                                               (unsigned long long)o.hbm_budget);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(server budget)");
-    e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        (void)hipFree(d_arena_);
-        d_arena_ = nullptr;
-        return hip_fail(e, "hipStreamCreate");
+    for (auto &l : lanes_) {
+        e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (auto &x : lanes_)
+                if (x.stream) (void)hipStreamDestroy(x.stream), x.stream = nullptr;
+            (void)hipFree(d_arena_);
+            d_arena_ = nullptr;
+            return hip_fail(e, "hipStreamCreate");
+        }
     }
     opts_ = o;
+    slow_bytes_ = o.slow_lane_bytes ? o.slow_lane_bytes : (2ull << 30);
     arena_.reset(o.hbm_budget);
     peak_used_ = 0;
     running_ = true;
     stopping_ = false;
     abort_ = false;
-    thread_ = std::thread([this] { loop(); });
+    for (auto &l : lanes_) l.thread = std::thread([this, &l] { loop(l); });
     return HB_OK;
 }
 
@@ -210,8 +223,11 @@ hb_status Server::stop() {
         stopping_ = true;
     }
     cv_work_.notify_all();
-    if (thread_.joinable()) thread_.join();
+    for (auto &l : lanes_)
+        if (l.thread.joinable()) l.thread.join();
     std::lock_guard<std::mutex> lk(mu_);
+    (void)hipFree(d_arena_);
+    d_arena_ = nullptr;
     running_ = false;
     return HB_OK;
 }
@@ -248,12 +264,15 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
     r->seed = seed;
     r->flags = flags;
     r->t_submit = now_ns();
+    // bytes one step gathers: counter rows (table rows for the run kernel) x 2^p
+    const uint64_t rows = r->runs ? g->runs.lookups[r->levels] : g->n_edges;
+    const int lane = rows * (1ull << p) > slow_bytes_ ? 1 : 0;
     g->inflight.fetch_add(1);
     *out = r->ticket;
-    queue_.push_back(r.get());
+    lanes_[lane].queue.push_back(r.get());
     reqs_.emplace(r->ticket, std::move(r));
     ++submitted_;
-    cv_work_.notify_one();
+    cv_work_.notify_all();
     return HB_OK;
 }
 
@@ -304,8 +323,8 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
 hb_status Server::stats(hb_server_stats_t *out) {
     if (!out) return fail(HB_EINVAL, "out is NULL");
     std::lock_guard<std::mutex> lk(mu_);
-    out->running = n_running_;
-    out->queued = (uint32_t)queue_.size();
+    out->running = lanes_[0].n_running + lanes_[1].n_running;
+    out->queued = (uint32_t)(lanes_[0].queue.size() + lanes_[1].queue.size());
     out->submitted = submitted_;
     out->completed = completed_;
     out->steps = steps_;
@@ -316,7 +335,7 @@ hb_status Server::stats(hb_server_stats_t *out) {
     return HB_OK;
 }
 
-void Server::fail_all(hb_status st, const std::string &msg) {
+void Server::fail_all(Lane &L, hb_status st, const std::string &msg) {
     std::lock_guard<std::mutex> lk(mu_);
     auto mark = [&](Request *r) {
         r->state = State::Failed;
@@ -324,51 +343,53 @@ void Server::fail_all(hb_status st, const std::string &msg) {
         r->message = msg;
         r->g->inflight.fetch_sub(1);
     };
-    for (Request *r : running_reqs_) mark(r);
-    for (Request *r : queue_) mark(r);
-    running_reqs_.clear();
-    queue_.clear();
-    n_running_ = 0;
-    arena_.reset(arena_.size());
-    stopping_ = true;
+    for (Request *r : L.running) {
+        mark(r);
+        arena_.give(r->off, r->footprint);
+    }
+    for (Request *r : L.queue) mark(r);
+    L.running.clear();
+    L.queue.clear();
+    L.n_running = 0;
     cv_done_.notify_all();
 }
 
 // Copy a stopped request's outputs to host memory and free its block.
-void Server::retire(Request *r) {
+void Server::retire(Lane &L, Request *r) {
     const uint32_t n = r->g->n;
     r->reach.resize(n);
     r->sum_d.resize(n);
     (void)hipMemcpyAsync(r->reach.data(), r->job.c_prev, sizeof(double) * n, hipMemcpyDeviceToHost,
-                         stream_);
+                         L.stream);
     (void)hipMemcpyAsync(r->sum_d.data(), r->job.sum_d, sizeof(double) * n, hipMemcpyDeviceToHost,
-                         stream_);
+                         L.stream);
     if (r->flags & HB_SUBMIT_REGISTERS) {
         r->regs.resize((uint64_t)n << r->p);
         (void)hipMemcpyAsync(r->regs.data(), r->job.buf[r->job.done & 1u], r->regs.size(),
-                             hipMemcpyDeviceToHost, stream_);
+                             hipMemcpyDeviceToHost, L.stream);
     }
 }
 
-hb_status Server::step() {
+hb_status Server::step(Lane &L) {
     // ---- admit
     std::vector<Request *> admitted;
     {
         std::lock_guard<std::mutex> lk(mu_);
-        while (!queue_.empty() &&
+        const uint32_t others = lanes_[0].n_running + lanes_[1].n_running - L.n_running;
+        while (!L.queue.empty() &&
                (opts_.max_running == 0 ||
-                running_reqs_.size() + admitted.size() < opts_.max_running)) {
-            Request *r = queue_.front();
+                others + L.running.size() + admitted.size() < opts_.max_running)) {
+            Request *r = L.queue.front();
             uint64_t off;
-            if (!arena_.take(r->footprint, off)) break;  // arrival order: no overtaking
-            queue_.pop_front();
+            if (!arena_.take(r->footprint, off)) break;  // arrival order within the lane
+            L.queue.pop_front();
             r->off = off;
             r->state = State::Running;
             r->t_admit = now_ns();
             admitted.push_back(r);
         }
         peak_used_ = std::max(peak_used_, arena_.used());
-        n_running_ = (uint32_t)(running_reqs_.size() + admitted.size());
+        L.n_running = (uint32_t)(L.running.size() + admitted.size());
     }
     uint8_t *base = static_cast<uint8_t *>(d_arena_);
     for (Request *r : admitted) {
@@ -392,24 +413,25 @@ hb_status Server::step() {
         b.levels = r->levels;
         b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
         b.runs = r->runs ? 1u : 0u;
-        running_reqs_.push_back(r);
+        L.running.push_back(r);
     }
-    const uint32_t nj = (uint32_t)running_reqs_.size();
+    const uint32_t nj = (uint32_t)L.running.size();
     if (nj == 0) return HB_OK;
 
     // ---- job table and launch lists for this step
-    if (jobs_cap_ < nj) {
-        (void)hipFree(d_jobs_);
-        if (h_jobs_) (void)hipHostFree(h_jobs_);
-        d_jobs_ = nullptr;
-        h_jobs_ = nullptr;
-        jobs_cap_ = 0;
+    if (L.jobs_cap < nj) {
+        (void)hipFree(L.d_jobs);
+        if (L.h_jobs) (void)hipHostFree(L.h_jobs);
+        L.d_jobs = nullptr;
+        L.h_jobs = nullptr;
+        L.jobs_cap = 0;
         const uint32_t cap = std::max<uint32_t>(64, nj * 2);
-        HB_HIP(hipMalloc(&d_jobs_, sizeof(hbk::BatchJob) * cap));
-        HB_HIP(hipHostMalloc((void **)&h_jobs_, sizeof(hbk::BatchJob) * cap, hipHostMallocDefault));
-        jobs_cap_ = cap;
+        HB_HIP(hipMalloc(&L.d_jobs, sizeof(hbk::BatchJob) * cap));
+        HB_HIP(hipHostMalloc((void **)&L.h_jobs, sizeof(hbk::BatchJob) * cap, hipHostMallocDefault));
+        L.jobs_cap = cap;
     }
-    for (uint32_t j = 0; j < nj; ++j) h_jobs_[j] = running_reqs_[j]->job;
+    hbk::BatchJob *h_jobs_ = L.h_jobs;
+    for (uint32_t j = 0; j < nj; ++j) h_jobs_[j] = L.running[j]->job;
     struct Cls {
         uint32_t p;
         bool runs;
@@ -465,15 +487,17 @@ hb_status Server::step() {
             c.base_off = (uint32_t)lists.size();
             lists.insert(lists.end(), c.base.begin(), c.base.end());
         }
-    if (lists_cap_ < lists.size()) {
-        (void)hipFree(d_lists_);
-        d_lists_ = nullptr;
-        lists_cap_ = 0;
+    if (L.lists_cap < lists.size()) {
+        (void)hipFree(L.d_lists);
+        L.d_lists = nullptr;
+        L.lists_cap = 0;
         const uint64_t cap = std::max<uint64_t>(4096, lists.size() * 2);
-        HB_HIP(hipMalloc(&d_lists_, sizeof(uint32_t) * cap));
-        lists_cap_ = cap;
+        HB_HIP(hipMalloc(&L.d_lists, sizeof(uint32_t) * cap));
+        L.lists_cap = cap;
     }
-    hipStream_t s = stream_;
+    hbk::BatchJob *d_jobs_ = L.d_jobs;
+    uint32_t *d_lists_ = L.d_lists;
+    hipStream_t s = L.stream;
     HB_HIP(hipMemcpyAsync(d_jobs_, h_jobs_, sizeof(hbk::BatchJob) * nj, hipMemcpyHostToDevice, s));
     HB_HIP(hipMemcpyAsync(d_lists_, lists.data(), sizeof(uint32_t) * lists.size(),
                           hipMemcpyHostToDevice, s));
@@ -482,7 +506,7 @@ hb_status Server::step() {
     const uint64_t t_launch = now_ns();
     for (uint32_t j : new_list) {
         HB_HIP(hbk::launch_fill_u32(h_jobs_[j].flags, 0u, h_jobs_[j].n_flags, s));
-        running_reqs_[j]->t_start = t_launch;
+        L.running[j]->t_start = t_launch;
     }
     for (auto &c : inits)
         HB_HIP(hbk::launch_batch_init((int)c.p, d_jobs_, d_lists_ + c.list_off, d_lists_ + c.base_off,
@@ -501,17 +525,17 @@ hb_status Server::step() {
     // ---- retire the requests that stopped
     std::vector<Request *> done, still;
     for (uint32_t j = 0; j < nj; ++j) {
-        Request *r = running_reqs_[j];
+        Request *r = L.running[j];
         r->job = h_jobs_[j];
         if (r->job.done) {
-            retire(r);
+            retire(L, r);
             done.push_back(r);
         } else {
             still.push_back(r);
         }
     }
     if (!done.empty()) HB_HIP(hipStreamSynchronize(s));
-    running_reqs_.swap(still);
+    L.running.swap(still);
     {
         std::lock_guard<std::mutex> lk(mu_);
         ++steps_;
@@ -524,39 +548,49 @@ hb_status Server::step() {
             ++completed_;
             edge_unions_ += (uint64_t)r->job.done * r->g->n_edges;
         }
-        n_running_ = (uint32_t)running_reqs_.size();
+        L.n_running = (uint32_t)L.running.size();
     }
-    if (!done.empty()) cv_done_.notify_all();
+    if (!done.empty()) {
+        cv_done_.notify_all();
+        cv_work_.notify_all();  // freed memory may let the other lane admit
+    }
     return HB_OK;
 }
 
-void Server::loop() {
+void Server::loop(Lane &L) {
     (void)hipSetDevice(device_);
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu_);
-            cv_work_.wait(lk, [&] { return stopping_ || !queue_.empty() || !running_reqs_.empty(); });
-            if (abort_ || (stopping_ && queue_.empty() && running_reqs_.empty())) break;
+            cv_work_.wait(lk, [&] { return stopping_ || !L.queue.empty() || !L.running.empty(); });
+            if (abort_ || (stopping_ && L.queue.empty() && L.running.empty())) break;
+            if (L.running.empty() && !L.queue.empty()) {
+                // nothing of ours runs: wait until the head request fits the budget
+                uint64_t off;
+                if (!arena_.take(L.queue.front()->footprint, off)) {
+                    cv_work_.wait_for(lk, std::chrono::milliseconds(1));
+                    continue;
+                }
+                arena_.give(off, L.queue.front()->footprint);
+            }
         }
-        const hb_status st = step();
+        const hb_status st = step(L);
         if (st != HB_OK) {
-            fail_all(st, g_err);
+            fail_all(L, st, g_err);
             break;
         }
     }
-    (void)hipStreamSynchronize(stream_);
-    (void)hipFree(d_lists_);
-    (void)hipFree(d_jobs_);
-    if (h_jobs_) (void)hipHostFree(h_jobs_);
-    (void)hipFree(d_arena_);
-    (void)hipStreamDestroy(stream_);
-    d_lists_ = nullptr;
-    d_jobs_ = nullptr;
-    h_jobs_ = nullptr;
-    d_arena_ = nullptr;
-    stream_ = nullptr;
-    jobs_cap_ = 0;
-    lists_cap_ = 0;
+    (void)hipStreamSynchronize(L.stream);
+    (void)hipFree(L.d_lists);
+    (void)hipFree(L.d_jobs);
+    if (L.h_jobs) (void)hipHostFree(L.h_jobs);
+    (void)hipStreamDestroy(L.stream);
+    L.d_lists = nullptr;
+    L.d_jobs = nullptr;
+    L.h_jobs = nullptr;
+    L.stream = nullptr;
+    L.jobs_cap = 0;
+    L.lists_cap = 0;
 }
 
 Server g_server;

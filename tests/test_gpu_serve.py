@@ -36,8 +36,10 @@ def server(hb):
         hb.server_stop()
 
 
-def test_served_mix_equals_single_runs(hb, server):
-    server()
+@pytest.mark.parametrize("slow_lane_bytes", [0, 1, 2**64 - 1],
+                         ids=["default-lanes", "all-slow-lane", "one-lane"])
+def test_served_mix_equals_single_runs(hb, server, slow_lane_bytes):
+    server(slow_lane_bytes=slow_lane_bytes)
     graphs = [synth.tiny(0), synth.tiny(3), synth.grid_graph(2, 64, 48), synth.star_graph(60),
               synth.random_graph(150, 0.02, 4)]
     Gs = [_load(hb, g) for g in graphs]
@@ -56,9 +58,10 @@ def test_served_mix_equals_single_runs(hb, server):
         G.free()
 
 
-def test_requests_join_while_others_run(hb, server):
+@pytest.mark.parametrize("slow_lane_bytes", [2**64 - 1, 1 << 20], ids=["one-lane", "two-lanes"])
+def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     """A long request keeps running while short ones arrive, join and finish first."""
-    server()
+    server(slow_lane_bytes=slow_lane_bytes)
     big = _load(hb, synth.grid_graph(1, 120, 100))
     small = _load(hb, synth.tiny(2))
     tb = hb.submit(big, 12, 0, 5)
