@@ -79,6 +79,9 @@ typedef struct {
     uint8_t *registers;
     uint32_t passes;       /* union steps run (T) */
     uint32_t converged;    /* 1 if step T changed no estimate by more than 0.5 */
+    uint32_t productive_iters; /* steps that changed some estimate by more than 0.5:
+                                  passes - 1 when converged (the last step only
+                                  detected the fixpoint), else passes */
     double c0;             /* estimate of a one-element counter */
     uint64_t edge_unions;  /* passes * n_edges */
     double init_ms;        /* device time of the initialisation kernel */

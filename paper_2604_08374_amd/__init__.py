@@ -48,6 +48,7 @@ class _CSR(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("reach", dblp), ("sum_d", dblp), ("mean_depth", dblp), ("registers", u8p),
                 ("passes", ctypes.c_uint32), ("converged", ctypes.c_uint32),
+                ("productive_iters", ctypes.c_uint32),
                 ("c0", ctypes.c_double), ("edge_unions", ctypes.c_uint64),
                 ("init_ms", ctypes.c_double), ("iter_ms", ctypes.c_double),
                 ("table_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
@@ -234,6 +235,7 @@ class Result:
     registers: np.ndarray | None
     passes: int
     converged: bool
+    productive_iters: int
     c0: float
     edge_unions: int
     init_ms: float
@@ -323,7 +325,8 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
 def _to_result(r: _Result, arrays) -> Result:
     reach, sum_d, md, regs = arrays
     name = {UNION_EDGES: "edges", UNION_RUNS: "runs"}.get(int(r.union_kernel), "?")
-    return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged), float(r.c0),
+    return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged),
+                  int(r.productive_iters), float(r.c0),
                   int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
                   float(r.run_ms), name, int(r.table_levels), int(r.t_submit_ns),
                   int(r.t_admit_ns), int(r.t_start_ns), int(r.t_end_ns))

@@ -485,6 +485,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     const double md = (double)m;
     out->passes = t;
     out->converged = converged;
+    out->productive_iters = converged ? t - 1u : t;
     out->c0 = md * std::log(md / (md - 1.0));
     out->edge_unions = (uint64_t)t * g->n_edges;
     out->init_ms = init_ms;
@@ -791,6 +792,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         const double md = (double)m;
         out->passes = b.done;
         out->converged = b.converged;
+        out->productive_iters = b.converged ? b.done - 1u : b.done;
         out->c0 = md * std::log(md / (md - 1.0));
         out->edge_unions = (uint64_t)b.done * jobs[j].g->n_edges;
         out->init_ms = 0.0;

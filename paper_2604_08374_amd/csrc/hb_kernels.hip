@@ -56,6 +56,9 @@ struct Cfg {
     static constexpr int NODES = WAVES == 1 ? 4 : 1;             // nodes per workgroup
     static constexpr int THREADS = WAVES == 1 ? 256 : WAVES * kWave;
     static constexpr int TOP = 65 - P;                           // largest register value
+    // waves per SIMD the run kernel is compiled for (its register budget):
+    // 80 VGPRs at p <= 10, 96 at p = 11, 168 at p = 12 (fewer spill)
+    static constexpr int RUN_OCC = RPL == 1 ? 6 : (RPL == 2 ? 5 : 3);
 };
 
 // ---------------------------------------------------------------- helpers
@@ -350,17 +353,18 @@ struct NodeAcc {
         }
     }
 
-    // max with the counter rows at src[u] (this lane's slots), U rows
-    __device__ __forceinline__ void gather(const uint8_t *const (&src)[C::U], uint32_t slice,
+    // max with the counter rows at src[u] (this lane's slots), N rows
+    template <int N>
+    __device__ __forceinline__ void gather(const uint8_t *const (&src)[N], uint32_t slice,
                                            uint32_t lane) {
-        uint4 x[C::U][C::RPL];
+        uint4 x[N][C::RPL];
 #pragma unroll
-        for (int u = 0; u < C::U; ++u)
+        for (int u = 0; u < N; ++u)
 #pragma unroll
             for (int s = 0; s < C::RPL; ++s)
                 x[u][s] = *reinterpret_cast<const uint4 *>(src[u] + slot_offset<P>(slice, lane, s));
 #pragma unroll
-        for (int u = 0; u < C::U; ++u)
+        for (int u = 0; u < N; ++u)
 #pragma unroll
             for (int s = 0; s < C::RPL; ++s) {
                 m[s][0].add(x[u][s].x);
@@ -492,6 +496,7 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
 // and level 0 is cur itself.  The result is the same registers as the
 // per-edge kernel.
 constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
+constexpr int kRunLoads = 4;               // 16 B/lane loads in flight per flush round
 constexpr int kScalarWalk = 8;             // chunks with at most this many special varints
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
@@ -508,10 +513,13 @@ struct RunGather {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const uint32_t grp = lane / C::LPC;
-        for (uint32_t k = 0; k < qn; k += C::U * C::G) {
-            const uint8_t *src[C::U];
+        // fewer loads in flight than the per-edge kernel: this kernel runs at
+        // six waves per SIMD, where the registers of eight would spill
+        constexpr int U = C::RPL >= kRunLoads ? 1 : kRunLoads / C::RPL;
+        for (uint32_t k = 0; k < qn; k += U * C::G) {
+            const uint8_t *src[U];
 #pragma unroll
-            for (int u = 0; u < C::U; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const uint32_t idx = k + (uint32_t)u * (uint32_t)C::G + (C::G == 1 ? 0u : grp);
                 uint32_t row = q[idx < qn ? idx : k];
                 if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
@@ -682,11 +690,14 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     finish_node<P>(acc, v, 0, next, c_prev, sum_d, flag_t, t);
 }
 
-// Five waves per SIMD: the run kernel's latency hiding needs the occupancy more
-// than the few registers the bound takes away (measured: 33.5 ms per city step
-// against 39.3 ms at the four waves its natural register count allows).
+// Six waves per SIMD (80 VGPRs): the run kernel hides its gather latency with
+// occupancy rather than with loads in flight.  Measured per city step at p = 10:
+// 39.4 ms at the four waves its natural register count allows, 33.5 ms at five,
+// 32.1 ms at six with four loads in flight; eight waves spill heavily (75 ms).
+// At p = 11 five waves beat four (58.0 against 60.2 ms); at p = 12 three waves
+// without spills match four with them (117.4 against 118.0 ms).
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS, 5) void union_runs_kernel(
+__global__ __launch_bounds__(Cfg<P>::THREADS, Cfg<P>::RUN_OCC) void union_runs_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
@@ -763,7 +774,7 @@ __global__ __launch_bounds__(Cfg<P>::THREADS) void batch_init_kernel(
 }
 
 template <int P, bool RUNS>
-__global__ __launch_bounds__(Cfg<P>::THREADS, RUNS ? 5 : 1) void batch_union_kernel(
+__global__ __launch_bounds__(Cfg<P>::THREADS, RUNS ? Cfg<P>::RUN_OCC : 1) void batch_union_kernel(
     BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ block_base, uint32_t nlist) {
     using C = Cfg<P>;

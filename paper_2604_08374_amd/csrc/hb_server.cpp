@@ -306,6 +306,7 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
     if (out->registers) memcpy(out->registers, r->regs.data(), r->regs.size());
     out->passes = r->job.done;
     out->converged = r->job.converged;
+    out->productive_iters = r->job.converged ? r->job.done - 1u : r->job.done;
     out->c0 = md * std::log(md / (md - 1.0));
     out->edge_unions = (uint64_t)r->job.done * r->g->n_edges;
     out->init_ms = out->iter_ms = out->table_ms = 0.0;

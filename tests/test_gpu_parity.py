@@ -23,6 +23,8 @@ def _load(hb, g):
 def _compare(res, ref, what):
     assert res.passes == ref.passes, (what, res.passes, ref.passes)
     assert res.converged == ref.converged, (what, res.converged, ref.converged)
+    # a converged run's last step only detected the fixpoint
+    assert res.productive_iters == ref.passes - int(ref.converged), what
     if ref.registers is not None:
         bad = np.nonzero((res.registers != ref.registers).any(axis=1))[0]
         assert bad.size == 0, f"{what}: registers differ at nodes {bad[:10]}"

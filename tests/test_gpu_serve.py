@@ -58,10 +58,11 @@ def test_served_mix_equals_single_runs(hb, server, slow_lane_bytes):
         G.free()
 
 
-@pytest.mark.parametrize("slow_lane_bytes", [2**64 - 1, 1 << 20], ids=["one-lane", "two-lanes"])
+@pytest.mark.parametrize("slow_lane_bytes", [2**64 - 1, 1 << 30], ids=["one-lane", "two-lanes"])
 def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     """A long request keeps running while short ones arrive, join and finish first."""
-    server(slow_lane_bytes=slow_lane_bytes)
+    # the per-edge kernel keeps the long request long: about 25 GB of gathers a step
+    server(slow_lane_bytes=slow_lane_bytes, kernel="edges")
     big = _load(hb, synth.grid_graph(1, 120, 100))
     small = _load(hb, synth.tiny(2))
     tb = hb.submit(big, 12, 0, 5)
@@ -71,9 +72,9 @@ def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     rb = tb.wait()
     assert max(r.t_end_ns for r in rs) <= rb.t_end_ns
     assert any(r.t_admit_ns > rb.t_admit_ns for r in rs)
-    _same(rb, big.run(12, 0, 5), "big")
+    _same(rb, big.run(12, 0, 5, kernel="edges"), "big")
     for s, r in enumerate(rs):
-        _same(r, small.run(8, 2, s), f"small {s}")
+        _same(r, small.run(8, 2, s, kernel="edges"), f"small {s}")
     big.free()
     small.free()
 
@@ -98,7 +99,7 @@ def test_admission_respects_the_budget(hb, server):
 
 
 def test_poll_and_ticket_rules(hb, server):
-    server(max_running=1)  # one request at a time: the second one waits in the queue
+    server(max_running=1, kernel="edges")  # one request at a time: the second one waits
     big = _load(hb, synth.grid_graph(1, 120, 100))
     G = _load(hb, synth.tiny(5))
     tb = hb.submit(big, 12, 0, 3)
@@ -113,7 +114,7 @@ def test_poll_and_ticket_rules(hb, server):
             break
     assert r is not None
     assert tb.poll() is not None or tb.wait() is not None
-    _same(r, G.run(9, 0, 1), "polled")
+    _same(r, G.run(9, 0, 1, kernel="edges"), "polled")
     with pytest.raises(hb.HBError) as e:
         t.poll()
     assert e.value.status == hb.HB_ENOTFOUND
