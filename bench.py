@@ -144,22 +144,24 @@ def batch_bench(args):
     log(f"built {len(jobs)} graphs (n {min(G.n for G in Gs)}..{max(G.n for G in Gs)}, "
         f"{sum(edges):.3g} edges) in {time.perf_counter() - t0:.1f}s")
 
-    def sequential():
-        return [G.run(p, d, sd, kernel=args.kernel) for (G, p, d, sd) in jobs]
+    def sequential(tune):
+        return [G.run(p, d, sd, kernel=args.kernel, tune=tune) for (G, p, d, sd) in jobs]
 
-    def batched():
-        return hb.run_batch(jobs, kernel=args.kernel)
+    def batched(tune):
+        return hb.run_batch(jobs, kernel=args.kernel, tune=tune)
 
+    # the warm-up measures the union schedules (both forms); timed steps use the picks
+    timed_tune = "cached" if args.tune == "measure" else args.tune
     for _ in range(args.warmup):
-        sequential()
-        batched()
+        sequential(args.tune)
+        batched(args.tune)
     seq_t, bat_t = [], []
     for i in range(args.steps):
         t0 = time.perf_counter()
-        rs = sequential()
+        rs = sequential(timed_tune)
         seq_t.append(time.perf_counter() - t0)
         t0 = time.perf_counter()
-        rb = batched()
+        rb = batched(timed_tune)
         bat_t.append(time.perf_counter() - t0)
         for a, b in zip(rs, rb):
             if a.passes != b.passes or not np.array_equal(a.sum_d, b.sum_d) or \
@@ -183,10 +185,16 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": f"{len(jobs)} street/building graphs, seeds 0..{len(jobs) - 1}",
                    "nodes_total": int(sum(G.n for G in Gs)), "directed_edges_total": int(sum(edges)),
-                   "union_kernel": args.kernel},
+                   "union_kernel": args.kernel, "tune": args.tune,
+                   "schedules": sorted({(p, r.union_kernel, r.lanes_per_node, r.nodes_per_block)
+                                        for (_, p, _, _), r in zip(jobs, rb)})},
         "sequential": {"value": unions / seq_s, "ms": seq_s * 1e3},
         "speedup_vs_sequential": seq_s / bat_s,
         "identical_results": True,
+        # the tuner's picks for the batch's (p, kernel) classes: one measured step each
+        "tuned_classes": [{k: e[k] for k in ("p", "union_kernel", "lanes_per_node",
+                                             "nodes_per_block", "best_ms", "default_ms")}
+                          for e in hb.tune_cache() if e["batched"] == 1],
     }
     for G in Gs:
         G.free()
@@ -384,6 +392,8 @@ def main():
                     help="union kernel: per edge, per run from a range-max table, or the "
                          "library's choice")
     ap.add_argument("--table-levels", type=int, default=0)
+    ap.add_argument("--tune", default="measure", choices=["measure", "cached", "off"],
+                    help="union schedule: measured in the warm-up (default), cached or default")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 4 GiB device copy (measured bandwidth)")
     args = ap.parse_args()
@@ -416,10 +426,14 @@ def main():
 
     p, depth = args.p, args.depth
     kw = dict(kernel=args.kernel, table_levels=args.table_levels)
+    tune_ms = 0.0
     for i in range(args.warmup):
-        r = G.run(p, depth, args.seed, **kw)
+        r = G.run(p, depth, args.seed, tune=args.tune, **kw)
+        tune_ms += r.tune_ms
         log(f"warmup {i}: kernel={r.union_kernel} K={r.table_levels} passes={r.passes} "
+            f"schedule={r.lanes_per_node}x{r.nodes_per_block} tune_ms={r.tune_ms:.0f} "
             f"run_ms={r.run_ms:.1f} iter_ms={r.iter_ms:.1f} table_ms={r.table_ms:.1f}")
+    kw["tune"] = "cached" if args.tune == "measure" else args.tune
 
     passes = 0
     iter_ms = table_ms = 0.0
@@ -443,7 +457,9 @@ def main():
     rows = stats["table_rows"][levels] if kernel == "runs" else None
     per_launch = algorithmic_bytes(n, E, data.size, p, rows)
     achieved = per_launch / avg_launch_s / 1e9
-    kname = f"union_runs_kernel<{p}>" if kernel == "runs" else f"union_kernel<{p}>"
+    lanes = results[-1].lanes_per_node
+    kname = (f"union_runs_kernel<{p},{lanes}>" if kernel == "runs"
+             else f"union_kernel<{p},{lanes}>")
     traffic = kernel_traffic(args.config, p, depth, kname)
     edge_equiv = algorithmic_bytes(n, E, data.size, p) / avg_launch_s / 1e9
     line = {
@@ -469,6 +485,13 @@ def main():
             "passes_per_step": results[-1].passes,
             "union_kernel": kernel,
             "table_levels": levels,
+            "schedule": {"lanes_per_node": lanes,
+                         "nodes_per_block": results[-1].nodes_per_block,
+                         "tune": args.tune, "tune_ms": tune_ms,
+                         "measured": [{k: e[k] for k in ("lanes_per_node", "nodes_per_block",
+                                                         "best_ms", "default_ms")}
+                                      for e in hb.tune_cache()
+                                      if e["batched"] == 0 and e["p"] == p]},
         },
         "roofline": {
             "bound": "hbm",
@@ -510,7 +533,8 @@ def main():
         line["batched"] = {"value": b["value"], "unit": b["unit"], "ms": b["ms_per_step"],
                            "sequential_value": b["sequential"]["value"],
                            "speedup_vs_sequential": b["speedup_vs_sequential"],
-                           "workload": b["config"]["workload"], "identical_results": True}
+                           "workload": b["config"]["workload"], "identical_results": True,
+                           "tuned_classes": b["tuned_classes"]}
         log("served form: Poisson mix, served vs sequential FIFO ...")
         sargs = argparse.Namespace(**vars(args))
         sargs.pool, sargs.pool_max_nodes, sargs.requests = 40, 60000, 300

@@ -90,6 +90,10 @@ typedef struct {
     double run_ms;         /* device time from init start to the last union end */
     uint32_t union_kernel; /* kernel that ran: HB_UNION_EDGES or HB_UNION_RUNS */
     uint32_t table_levels; /* table levels K used by the run kernel (0 otherwise) */
+    uint32_t lanes_per_node;  /* union schedule that ran (see hb_run_opts); for a batch,
+                                 that of the job's (p, kernel) class */
+    uint32_t nodes_per_block;
+    double tune_ms;        /* host time spent measuring schedules in this call (0 if none) */
     uint64_t t_submit_ns;  /* host CLOCK_MONOTONIC: hb_submit accepted it (else = t_start_ns) */
     uint64_t t_admit_ns;   /* device memory granted, joined the running steps (else = t_start_ns) */
     uint64_t t_start_ns;   /* call entry, or the first step of a served request */
@@ -110,9 +114,44 @@ typedef struct {
  * counter-row loads instead of r.  The registers are identical either way.
  */
 typedef struct {
-    uint32_t union_kernel; /* HB_UNION_* */
-    uint32_t table_levels; /* 0 = default */
+    uint32_t union_kernel;    /* HB_UNION_* */
+    uint32_t table_levels;    /* 0 = default */
+    uint32_t tune;            /* HB_TUNE_*: how the union schedule is chosen */
+    uint32_t lanes_per_node;  /* 0 = by `tune`; else this schedule (HB_EINVAL if not built) */
+    uint32_t nodes_per_block; /* with lanes_per_node: 1, 2 or 4 (0 = 4; must be 1 above 64 lanes) */
 } hb_run_opts;
+
+/*
+ * Union schedules.  A schedule is (lanes_per_node, nodes_per_block):
+ *  - lanes_per_node: lanes that share one node's counter of 2^p bytes, 16
+ *    bytes per lane slot, one to four slots per lane.  Up to 64 lanes the
+ *    node sits in one wavefront, whose 64 / lanes lane groups gather
+ *    different neighbours at once; above 64, lanes / 64 wavefronts of one
+ *    workgroup each own a slice of the counter and decode the row themselves.
+ *  - nodes_per_block: nodes per workgroup (1, 2 or 4) for one-wave shapes.
+ * Built lanes per p (the default first): p 4-7: 2^p / 16; p 8: 16, 8;
+ * p 9: 32, 16; p 10: 64, 32, 16; p 11: 64, 128, 32; p 12: 64, 128, 256;
+ * p 13: 128, 256; p 14: 256, 512; p 15: 512; p 16: 1024.  Every schedule
+ * gives identical registers and estimates; only the speed differs.
+ *
+ * The autotuner times one union step of every schedule built for p on the
+ * caller's own data (two launches each, the faster counts), keeps the
+ * fastest in a process-wide cache keyed by the shape class (p, kernel,
+ * single or batched, floor(log2 nodes), floor(log2 gathered rows per node)),
+ * then re-initialises and runs.  Tuning changes no result.
+ */
+#define HB_TUNE_CACHED 0  /* the cached pick for the shape class, else the default schedule */
+#define HB_TUNE_MEASURE 1 /* as HB_TUNE_CACHED, but measure first when nothing is cached */
+#define HB_TUNE_OFF 2     /* the default schedule */
+
+/* One autotuner cache entry. */
+typedef struct {
+    uint32_t p, union_kernel, batched;    /* shape class ... */
+    uint32_t log2_nodes, log2_rows_per_node;
+    uint32_t lanes_per_node, nodes_per_block; /* ... and its pick */
+    double best_ms;                       /* measured union step of the pick */
+    double default_ms;                    /* and of the default schedule */
+} hb_tune_entry;
 
 /* Library version string. */
 const char *hb_version(void);
@@ -292,6 +331,15 @@ hb_status hb_server_stats(hb_server_stats_t *out);
 
 /* Free the workspace kept between batched calls. */
 hb_status hb_release_cache(void);
+
+/*
+ * Copy up to cap autotuner cache entries to out (caller-owned; NULL with
+ * cap 0 only counts) and the number of entries to *count.  Host-only.
+ */
+hb_status hb_tune_cache(hb_tune_entry *out, uint32_t cap, uint32_t *count);
+
+/* Forget every cached schedule pick. */
+hb_status hb_tune_clear(void);
 
 /*
  * Diagnostic: a plain streaming copy of `bytes` (a multiple of 16) between two

@@ -16,7 +16,8 @@ import numpy as np
 
 __all__ = [
     "HBError", "Result", "Graph", "lib_path", "version", "device_count", "csr_encode",
-    "csr_validate", "graph_load", "run", "run_batch", "release_cache", "copy_probe", "server_start", "server_stop",
+    "csr_validate", "graph_load", "run", "run_batch", "release_cache", "tune_cache", "tune_clear",
+    "copy_probe", "server_start", "server_stop",
     "server_stats", "submit", "Ticket", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
     "HB_ENOMEM", "HB_EDEVICE", "HB_ENOTFOUND", "HB_EBUSY",
 ]
@@ -53,6 +54,8 @@ class _Result(ctypes.Structure):
                 ("init_ms", ctypes.c_double), ("iter_ms", ctypes.c_double),
                 ("table_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
+                ("lanes_per_node", ctypes.c_uint32), ("nodes_per_block", ctypes.c_uint32),
+                ("tune_ms", ctypes.c_double),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_start_ns", ctypes.c_uint64), ("t_end_ns", ctypes.c_uint64)]
 
@@ -77,7 +80,26 @@ class _Stats(ctypes.Structure):
 
 
 class _RunOpts(ctypes.Structure):
-    _fields_ = [("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32)]
+    _fields_ = [("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
+                ("tune", ctypes.c_uint32), ("lanes_per_node", ctypes.c_uint32),
+                ("nodes_per_block", ctypes.c_uint32)]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint32), ("union_kernel", ctypes.c_uint32),
+                ("batched", ctypes.c_uint32), ("log2_nodes", ctypes.c_uint32),
+                ("log2_rows_per_node", ctypes.c_uint32), ("lanes_per_node", ctypes.c_uint32),
+                ("nodes_per_block", ctypes.c_uint32), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
+
+
+TUNE_CACHED, TUNE_MEASURE, TUNE_OFF = 0, 1, 2
+_TUNE = {"cached": TUNE_CACHED, "measure": TUNE_MEASURE, "off": TUNE_OFF}
+
+
+def _run_opts(kernel: str, table_levels: int, tune: str, lanes_per_node: int,
+              nodes_per_block: int) -> _RunOpts:
+    return _RunOpts(_KERNELS[kernel], table_levels, _TUNE[tune], lanes_per_node, nodes_per_block)
 
 
 class _Job(ctypes.Structure):
@@ -145,6 +167,10 @@ def _lib():
         L.hb_server_stats.restype = st
         L.hb_release_cache.argtypes = []
         L.hb_release_cache.restype = st
+        L.hb_tune_cache.argtypes = [ctypes.POINTER(_TuneEntry), ctypes.c_uint32, u32p]
+        L.hb_tune_cache.restype = st
+        L.hb_tune_clear.argtypes = []
+        L.hb_tune_clear.restype = st
         L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
         L.hb_copy_probe.restype = st
         _LIB = L
@@ -244,6 +270,9 @@ class Result:
     run_ms: float
     union_kernel: str
     table_levels: int
+    lanes_per_node: int
+    nodes_per_block: int
+    tune_ms: float
     t_submit_ns: int
     t_admit_ns: int
     t_start_ns: int
@@ -301,15 +330,19 @@ class Graph:
         return r, (reach, sum_d, md, regs)
 
     def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
-            outputs: bool = True, kernel: str = "auto", table_levels: int = 0) -> Result:
+            outputs: bool = True, kernel: str = "auto", table_levels: int = 0,
+            tune: str = "cached", lanes_per_node: int = 0, nodes_per_block: int = 0) -> Result:
         """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
 
         kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
+        tune: "cached" (a cached schedule pick, else the default), "measure" (measure
+        the schedules first when nothing is cached) or "off"; lanes_per_node and
+        nodes_per_block name a schedule explicitly.
         """
         if self._h is None:
             raise HBError(HB_EINVAL, "graph was freed")
         r, arrays = self._out_arrays(p, registers, outputs)
-        o = _RunOpts(_KERNELS[kernel], table_levels)
+        o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block)
         _check(_lib().hb_run_with(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
                                   ctypes.byref(o), ctypes.byref(r)))
         return _to_result(r, arrays)
@@ -328,12 +361,14 @@ def _to_result(r: _Result, arrays) -> Result:
     return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged),
                   int(r.productive_iters), float(r.c0),
                   int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
-                  float(r.run_ms), name, int(r.table_levels), int(r.t_submit_ns),
+                  float(r.run_ms), name, int(r.table_levels), int(r.lanes_per_node),
+                  int(r.nodes_per_block), float(r.tune_ms), int(r.t_submit_ns),
                   int(r.t_admit_ns), int(r.t_start_ns), int(r.t_end_ns))
 
 
 def run_batch(jobs, registers: bool = False, outputs: bool = True, kernel: str = "auto",
-              table_levels: int = 0):
+              table_levels: int = 0, tune: str = "cached", lanes_per_node: int = 0,
+              nodes_per_block: int = 0):
     """hb_run_batch: jobs is a list of (Graph, p, depth_limit, seed); returns Results in order."""
     n = len(jobs)
     cj = (_Job * n)()
@@ -349,7 +384,7 @@ def run_batch(jobs, registers: bool = False, outputs: bool = True, kernel: str =
         r, arrays = g._out_arrays(p, registers, outputs)
         outs[i] = r
         keep.append(arrays)
-    o = _RunOpts(_KERNELS[kernel], table_levels)
+    o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block)
     _check(_lib().hb_run_batch(cj, n, ctypes.byref(o), outs))
     return [_to_result(outs[i], keep[i]) for i in range(n)]
 
@@ -418,6 +453,24 @@ def _stop_server_at_exit():
         _LIB.hb_server_stop()
 
 
+def tune_cache() -> list:
+    """hb_tune_cache: the autotuner's picks, one dict per shape class."""
+    cnt = ctypes.c_uint32(0)
+    _check(_lib().hb_tune_cache(None, 0, ctypes.byref(cnt)))
+    buf = (_TuneEntry * max(cnt.value, 1))()
+    _check(_lib().hb_tune_cache(buf, cnt.value, ctypes.byref(cnt)))
+    out = []
+    for e in buf[:cnt.value]:
+        out.append({f: getattr(e, f) for f, _ in _TuneEntry._fields_})
+        out[-1]["union_kernel"] = {UNION_EDGES: "edges", UNION_RUNS: "runs"}[e.union_kernel]
+    return out
+
+
+def tune_clear() -> None:
+    """hb_tune_clear: forget every schedule pick."""
+    _check(_lib().hb_tune_clear())
+
+
 def release_cache() -> None:
     """hb_release_cache: free the device workspace kept between batched calls."""
     _check(_lib().hb_release_cache())
@@ -428,5 +481,7 @@ def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:
 
 
 def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
-        kernel: str = "auto", table_levels: int = 0) -> Result:
-    return g.run(p, depth_limit, seed, registers, kernel=kernel, table_levels=table_levels)
+        kernel: str = "auto", table_levels: int = 0, tune: str = "cached",
+        lanes_per_node: int = 0, nodes_per_block: int = 0) -> Result:
+    return g.run(p, depth_limit, seed, registers, kernel=kernel, table_levels=table_levels,
+                 tune=tune, lanes_per_node=lanes_per_node, nodes_per_block=nodes_per_block)

@@ -210,6 +210,24 @@ hb_status validate_impl(const hb_csr *csr, uint32_t *bad_node, RunCounts *rc_out
     }
     return HB_OK;
 }
+
+// The schedule named in the options for precision p, or lanes = 0 when the
+// options leave it to the tuner.
+hb_status explicit_sched(const hb_run_opts &o, uint32_t p, hbk::Sched *out) {
+    *out = hbk::Sched{0u, 0u};
+    if (o.tune > HB_TUNE_OFF) return fail(HB_EINVAL, "unknown tune mode %u", o.tune);
+    if (o.lanes_per_node == 0) {
+        if (o.nodes_per_block) return fail(HB_EINVAL, "nodes_per_block needs lanes_per_node");
+        return HB_OK;
+    }
+    hbk::Sched s{o.lanes_per_node, o.nodes_per_block};
+    if (!s.nodes_per_block) s.nodes_per_block = s.lanes > 64u ? 1u : 4u;
+    if (!hbk::sched_ok((int)p, s))
+        return fail(HB_EINVAL, "no union schedule of %u lanes, %u nodes per workgroup for p = %u",
+                    s.lanes, s.nodes_per_block, p);
+    *out = s;
+    return HB_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -378,11 +396,14 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     const uint64_t t_start = now_ns();
     if (!g || !out) return fail(HB_EINVAL, "NULL argument");
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
-    const hb_run_opts o = opts ? *opts : hb_run_opts{0u, 0u};
+    const hb_run_opts o = opts ? *opts : hb_run_opts{};
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
+    hbk::Sched fixed{};
+    hb_status st = explicit_sched(o, p, &fixed);
+    if (st != HB_OK) return st;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     HB_HIP(hipSetDevice(g->device));
     const uint32_t n = g->n;
@@ -425,10 +446,41 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     }
     hipStream_t s = g->stream;
     uint8_t *cur = g->d_cnt[0], *next = g->d_cnt[1];
+    const hbk::Sched init_sched = hbk::default_sched((int)p);
+
+    // ---- union schedule: explicit, cached, measured here, or the default
+    hbk::Sched sched = init_sched;
+    double tune_ms = 0.0;
+    const TuneKey key = tune_key(p, runs, false, n, runs ? g->runs.lookups[levels] : g->n_edges);
+    if (fixed.lanes) {
+        sched = fixed;
+    } else if (o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
+        sched = init_sched;
+        if (o.tune == HB_TUNE_MEASURE) {
+            // step 1 of this very run, once per candidate; the state is
+            // initialised again below, so the trials leave no trace
+            const uint64_t t0 = now_ns();
+            HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
+            HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
+            if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
+            TunePick pick;
+            st = tune_measure((int)p, s, [&](const hbk::Sched &c) {
+                return runs ? hbk::launch_union_runs((int)p, c, g->d_bytes, g->d_offsets, cur,
+                                                     levels, next, g->d_cprev, g->d_sumd,
+                                                     g->d_flags + 1, n, 1u, s)
+                            : hbk::launch_union((int)p, c, g->d_bytes, g->d_offsets, cur, next,
+                                                g->d_cprev, g->d_sumd, g->d_flags + 1, n, 1u, s);
+            }, &pick);
+            if (st != HB_OK) return st;
+            tune_put(key, pick);
+            sched = pick.s;
+            tune_ms = (double)(now_ns() - t0) / 1e6;
+        }
+    }
 
     HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
     HB_HIP(hipEventRecord(g->ev[0], s));
-    HB_HIP(hbk::launch_init((int)p, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
+    HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
     HB_HIP(hipEventRecord(g->ev[1], s));
 
     double iter_ms = 0.0, table_ms = 0.0;
@@ -439,11 +491,11 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
         if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
         HB_HIP(hipEventRecord(g->ev[3], s));
         if (runs)
-            HB_HIP(hbk::launch_union_runs((int)p, g->d_bytes, g->d_offsets, cur, levels, next,
-                                          g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
+            HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_bytes, g->d_offsets, cur, levels,
+                                          next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
         else
-            HB_HIP(hbk::launch_union((int)p, g->d_bytes, g->d_offsets, cur, next, g->d_cprev,
-                                     g->d_sumd, g->d_flags + t, n, t, s));
+            HB_HIP(hbk::launch_union((int)p, sched, g->d_bytes, g->d_offsets, cur, next,
+                                     g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
         HB_HIP(hipEventRecord(g->ev[4], s));
         HB_HIP(hipMemcpyAsync(g->h_flag, g->d_flags + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HB_HIP(hipStreamSynchronize(s));
@@ -494,6 +546,9 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     out->run_ms = run_ms;
     out->union_kernel = runs ? HB_UNION_RUNS : HB_UNION_EDGES;
     out->table_levels = runs ? levels : 0u;
+    out->lanes_per_node = sched.lanes;
+    out->nodes_per_block = sched.nodes_per_block;
+    out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;
     out->t_admit_ns = t_start;
     out->t_start_ns = t_start;
@@ -582,11 +637,24 @@ struct StepGraph {
     }
 };
 
+// Jobs of one (p, kernel) class.  Initialisation uses the default schedule,
+// the union step the class's own; each has its own block bases.
 struct BatchClass {
     uint32_t p;
     bool runs;
-    std::vector<uint32_t> list, block_base;
-    uint32_t list_off = 0, base_off = 0, nblocks = 0;
+    std::vector<uint32_t> list;
+    uint64_t nodes = 0, rows = 0;           // tuner shape class
+    hbk::Sched sched{};                     // union schedule
+    bool measure = false;                   // pick it by measurement in this call
+    uint32_t list_off = 0, init_off = 0, init_blocks = 0, base_off = 0, nblocks = 0;
+
+    // Block bases under schedule s: job list[i] owns workgroups [b[i], b[i + 1]).
+    std::vector<uint32_t> bases(const std::vector<hbk::BatchJob> &hj, const hbk::Sched &s) const {
+        const uint32_t npb = hbk::shape_for((int)p, s).nodes_per_block;
+        std::vector<uint32_t> b(1, 0u);
+        for (uint32_t j : list) b.push_back(b.back() + (hj[j].n + npb - 1) / npb);
+        return b;
+    }
 };
 
 }  // namespace
@@ -596,10 +664,15 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     const uint64_t t_start = now_ns();
     if (!jobs || !outs || n_jobs == 0) return fail(HB_EINVAL, "NULL argument or no jobs");
     if (n_jobs > 65535) return fail(HB_EINVAL, "at most 65535 jobs per batch");
-    const hb_run_opts o = opts ? *opts : hb_run_opts{0u, 0u};
+    const hb_run_opts o = opts ? *opts : hb_run_opts{};
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     for (uint32_t j = 0; j < n_jobs; ++j) {
+        hbk::Sched fixed{};
+        if (jobs[j].p >= HB_P_MIN && jobs[j].p <= HB_P_MAX) {
+            const hb_status st = explicit_sched(o, jobs[j].p, &fixed);
+            if (st != HB_OK) return st;
+        }
         if (!jobs[j].g) return fail(HB_EINVAL, "job %u has no graph", j);
         if (jobs[j].p < HB_P_MIN || jobs[j].p > HB_P_MAX)
             return fail(HB_EINVAL, "job %u: p = %u outside [4, 16]", j, jobs[j].p);
@@ -652,8 +725,9 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     arena += align256(sizeof(uint32_t) * flags_words);
     {
         // lists: all jobs, run-kernel jobs, per-level table bases, per-class list + bases
+        // (+ tuning: the block bases of every candidate schedule of a class)
         const uint64_t lists_need = 3ull * n_jobs + (uint64_t)(max_levels + 1) * (n_jobs + 1) +
-                                    16ull * (n_jobs + 1);
+                                    16ull * (n_jobs + 1) + 16ull * (n_jobs + 64);
         const hipError_t e = g_batch.reserve(jobs[0].g->device, arena, n_jobs, lists_need);
         if (e == hipErrorOutOfMemory)
             return fail(HB_ENOMEM, "batch needs %llu bytes of device memory", (unsigned long long)arena);
@@ -673,7 +747,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         hj[j].flags = d_flags + off_flags[j];
     }
 
-    // ---- classes by (p, kernel); list and block_base arrays in one buffer
+    // ---- classes by (p, kernel) and their union schedules
     std::vector<BatchClass> classes;
     std::vector<uint32_t> all_list(n_jobs), runs_list;
     for (uint32_t j = 0; j < n_jobs; ++j) {
@@ -683,13 +757,28 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         for (auto &x : classes)
             if (x.p == hj[j].p && x.runs == (hj[j].runs != 0)) c = &x;
         if (!c) {
-            classes.push_back(BatchClass{hj[j].p, hj[j].runs != 0, {}, {0u}});
+            classes.push_back(BatchClass{hj[j].p, hj[j].runs != 0, {}});
             c = &classes.back();
         }
-        const uint32_t npb = hbk::shape_for((int)hj[j].p).nodes_per_block;
         c->list.push_back(j);
-        c->block_base.push_back(c->block_base.back() + (hj[j].n + npb - 1) / npb);
+        c->nodes += hj[j].n;
+        c->rows += hj[j].runs ? jobs[j].g->runs.lookups[hj[j].levels] : jobs[j].g->n_edges;
     }
+    bool any_measure = false;
+    for (auto &c : classes) {
+        hbk::Sched fixed{};
+        (void)explicit_sched(o, c.p, &fixed);
+        c.sched = hbk::default_sched((int)c.p);
+        if (fixed.lanes) {
+            c.sched = fixed;
+        } else if (o.tune != HB_TUNE_OFF &&
+                   !tune_get(tune_key(c.p, c.runs, true, c.nodes, c.rows), &c.sched)) {
+            c.sched = hbk::default_sched((int)c.p);
+            c.measure = o.tune == HB_TUNE_MEASURE;
+            any_measure = any_measure || c.measure;
+        }
+    }
+    // ---- lists: all jobs, run-kernel jobs, table bases, per class list + init bases
     std::vector<uint32_t> lists(all_list);
     const uint32_t runs_off = (uint32_t)lists.size();
     lists.insert(lists.end(), runs_list.begin(), runs_list.end());
@@ -708,23 +797,91 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     for (auto &c : classes) {
         c.list_off = (uint32_t)lists.size();
         lists.insert(lists.end(), c.list.begin(), c.list.end());
-        c.base_off = (uint32_t)lists.size();
-        lists.insert(lists.end(), c.block_base.begin(), c.block_base.end());
-        c.nblocks = c.block_base.back();
+        const std::vector<uint32_t> ib = c.bases(hj, hbk::default_sched((int)c.p));
+        c.init_off = (uint32_t)lists.size();
+        lists.insert(lists.end(), ib.begin(), ib.end());
+        c.init_blocks = ib.back();
     }
-    if (lists.size() > R.lists_cap) return fail(HB_EDEVICE, "batch list buffer too small");
+    // the candidates' block bases of every class measured in this call
+    std::vector<std::vector<hbk::Sched>> cands(classes.size());
+    std::vector<std::vector<uint32_t>> cand_off(classes.size()), cand_blocks(classes.size());
+    for (size_t ci = 0; ci < classes.size(); ++ci) {
+        if (!classes[ci].measure) continue;
+        cands[ci] = tune_candidates((int)classes[ci].p);
+        for (const auto &cs : cands[ci]) {
+            const std::vector<uint32_t> b = classes[ci].bases(hj, cs);
+            cand_off[ci].push_back((uint32_t)lists.size());
+            cand_blocks[ci].push_back(b.back());
+            lists.insert(lists.end(), b.begin(), b.end());
+        }
+    }
+    const size_t phase_a = lists.size();
+    if (phase_a > R.lists_cap) return fail(HB_EDEVICE, "batch list buffer too small");
+    // room for the union bases appended below: the copy of the first part may
+    // still read this buffer, so it must not move
+    lists.reserve(phase_a + n_jobs + classes.size());
     hipStream_t s = R.stream;
     HB_HIP(hipMemcpyAsync(R.d_jobs, hj.data(), sizeof(hbk::BatchJob) * n_jobs,
                           hipMemcpyHostToDevice, s));
     HB_HIP(hipMemcpyAsync(R.d_lists, lists.data(), sizeof(uint32_t) * lists.size(),
                           hipMemcpyHostToDevice, s));
+    auto init_all = [&]() -> hb_status {
+        HB_HIP(hbk::launch_fill_u32(d_flags, 0u, flags_words, s));
+        for (auto &c : classes)
+            HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p), R.d_jobs,
+                                          R.d_lists + c.list_off, R.d_lists + c.init_off,
+                                          (uint32_t)c.list.size(), c.init_blocks, s));
+        return HB_OK;
+    };
+
+    // ---- measure the union schedules of untuned classes on step 1 of this batch
+    double tune_ms = 0.0;
+    if (any_measure) {
+        const uint64_t t0 = now_ns();
+        hb_status st = init_all();
+        if (st != HB_OK) return st;
+        for (uint32_t k = 1; k <= max_levels; ++k)
+            HB_HIP(hbk::launch_batch_table(R.d_jobs, R.d_lists + runs_off, R.d_lists + table_off[k],
+                                           (uint32_t)runs_list.size(), table_blocks[k], k, s));
+        for (size_t ci = 0; ci < classes.size(); ++ci) {
+            BatchClass &c = classes[ci];
+            if (!c.measure) continue;
+            size_t idx = 0;
+            TunePick pick;
+            st = tune_measure((int)c.p, s, [&](const hbk::Sched &cs) {
+                idx = 0;
+                while (idx < cands[ci].size() && !(cands[ci][idx].lanes == cs.lanes &&
+                                                   cands[ci][idx].nodes_per_block == cs.nodes_per_block))
+                    ++idx;
+                if (idx == cands[ci].size()) return hipErrorInvalidValue;
+                return hbk::launch_batch_union((int)c.p, cs, c.runs, R.d_jobs,
+                                               R.d_lists + c.list_off, R.d_lists + cand_off[ci][idx],
+                                               (uint32_t)c.list.size(), cand_blocks[ci][idx], s);
+            }, &pick);
+            if (st != HB_OK) return st;
+            tune_put(tune_key(c.p, c.runs, true, c.nodes, c.rows), pick);
+            c.sched = pick.s;
+        }
+        HB_HIP(hipStreamSynchronize(s));
+        tune_ms = (double)(now_ns() - t0) / 1e6;
+    }
+    // ---- the union bases of the chosen schedules
+    for (auto &c : classes) {
+        const std::vector<uint32_t> b = c.bases(hj, c.sched);
+        c.base_off = (uint32_t)lists.size();
+        lists.insert(lists.end(), b.begin(), b.end());
+        c.nblocks = b.back();
+    }
+    if (lists.size() > R.lists_cap) return fail(HB_EDEVICE, "batch list buffer too small");
+    HB_HIP(hipMemcpyAsync(R.d_lists + phase_a, lists.data() + phase_a,
+                          sizeof(uint32_t) * (lists.size() - phase_a), hipMemcpyHostToDevice, s));
 
     // ---- init
     HB_HIP(hipEventRecord(R.ev[0], s));
-    HB_HIP(hbk::launch_fill_u32(d_flags, 0u, flags_words, s));
-    for (auto &c : classes)
-        HB_HIP(hbk::launch_batch_init((int)c.p, R.d_jobs, R.d_lists + c.list_off,
-                                      R.d_lists + c.base_off, (uint32_t)c.list.size(), c.nblocks, s));
+    {
+        const hb_status st = init_all();
+        if (st != HB_OK) return st;
+    }
 
     // ---- one step, captured once, replayed until every job has stopped
     HB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -735,8 +892,9 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
                                         (uint32_t)runs_list.size(), table_blocks[k], k, s);
         for (auto &c : classes) {
             if (e != hipSuccess) break;
-            e = hbk::launch_batch_union((int)c.p, c.runs, R.d_jobs, R.d_lists + c.list_off,
-                                        R.d_lists + c.base_off, (uint32_t)c.list.size(), c.nblocks, s);
+            e = hbk::launch_batch_union((int)c.p, c.sched, c.runs, R.d_jobs,
+                                        R.d_lists + c.list_off, R.d_lists + c.base_off,
+                                        (uint32_t)c.list.size(), c.nblocks, s);
         }
         if (e == hipSuccess) e = hbk::launch_batch_step_end(R.d_jobs, R.d_lists, n_jobs, s);
         const hipError_t e2 = hipStreamEndCapture(s, &SG.graph);
@@ -801,6 +959,12 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         out->run_ms = run_ms;
         out->union_kernel = b.runs ? HB_UNION_RUNS : HB_UNION_EDGES;
         out->table_levels = b.levels;
+        for (const auto &c : classes)
+            if (c.p == b.p && c.runs == (b.runs != 0)) {
+                out->lanes_per_node = c.sched.lanes;
+                out->nodes_per_block = c.sched.nodes_per_block;
+            }
+        out->tune_ms = tune_ms;
         out->t_submit_ns = t_start;
         out->t_admit_ns = t_start;
         out->t_start_ns = t_start;

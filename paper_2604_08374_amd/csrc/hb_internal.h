@@ -25,16 +25,40 @@ struct BatchJob {
     uint32_t pad;
 };
 
+// Launch schedule of the union kernels for one precision p:
+//  * lanes: lanes that share one node's counter.  Up to 64 the node sits in
+//    one wave, whose 64 / lanes lane groups gather different neighbours;
+//    above 64, lanes / 64 waves of one workgroup each own a slice of it.
+//  * nodes_per_block: nodes per workgroup for single-wave shapes (1, 2 or 4;
+//    always 1 when several waves share a node).
+// Every schedule gives the same registers; only the speed differs.
+struct Sched {
+    uint32_t lanes;
+    uint32_t nodes_per_block;
+};
+constexpr uint32_t kMaxLaneOptions = 4;
+// The lanes-per-node values compiled for p (the default first); returns the count.
+uint32_t lane_options(int p, uint32_t out[kMaxLaneOptions]);
+Sched default_sched(int p);
+bool sched_ok(int p, const Sched &s);
+
+struct LaunchShape {
+    uint32_t waves_per_node;  // waves sharing one counter
+    uint32_t nodes_per_block; // nodes handled by one workgroup
+    uint32_t threads;         // workgroup size
+};
+LaunchShape shape_for(int p, const Sched &s);
+
 // Batched launches over a list of jobs of one precision p.  block_base has
 // nlist + 1 entries: job list[i] owns workgroups [block_base[i], block_base[i+1])
-// of the nblocks launched (shape_for(p).nodes_per_block nodes each).  Jobs
+// of the nblocks launched (shape_for(p, s).nodes_per_block nodes each).  Jobs
 // whose `done` is set are skipped.
-hipError_t launch_batch_init(int p, BatchJob *jobs, const uint32_t *list,
+hipError_t launch_batch_init(int p, const Sched &s, BatchJob *jobs, const uint32_t *list,
                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
                              hipStream_t stream);
-hipError_t launch_batch_union(int p, bool runs, BatchJob *jobs, const uint32_t *list,
-                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
-                              hipStream_t stream);
+hipError_t launch_batch_union(int p, const Sched &s, bool runs, BatchJob *jobs,
+                              const uint32_t *list, const uint32_t *block_base, uint32_t nlist,
+                              uint32_t nblocks, hipStream_t stream);
 // Table level k for listed run-kernel jobs with levels >= k; job list[i] owns
 // workgroups [block_base[i], block_base[i+1]), batch_table_blocks(n, p, k) of them.
 uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k);
@@ -44,32 +68,23 @@ hipError_t launch_batch_table(BatchJob *jobs, const uint32_t *list, const uint32
 hipError_t launch_batch_step_end(BatchJob *jobs, const uint32_t *list, uint32_t nlist,
                                  hipStream_t stream);
 
-// Counter layout and launch shape chosen for precision p (m = 2^p bytes per
-// counter, node-major rows).
-struct LaunchShape {
-    uint32_t waves_per_node;  // waves sharing one counter (p >= 13)
-    uint32_t nodes_per_block; // nodes handled by one workgroup
-    uint32_t threads;         // workgroup size
-};
-LaunchShape shape_for(int p);
-
 // Zero every counter, insert node v into its own counter (SplitMix64 of
 // v ^ seed), write the one-element estimate to c_prev[v] and zero sum_d[v].
-hipError_t launch_init(int p, uint8_t *cur, double *c_prev, double *sum_d, uint32_t n,
-                       uint64_t seed, hipStream_t stream);
+hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, double *sum_d,
+                       uint32_t n, uint64_t seed, hipStream_t stream);
 
 // One HyperBall step t: for every node v, decode its LEB128 row, take the
 // byte-wise max of cur[v] and cur[w] over its neighbours w into next[v],
 // estimate next[v], accumulate sum_d[v] += t (est - c_prev[v]), store est in
 // c_prev[v], and set *flag_t = 1 when est - c_prev[v] > 0.5.
-hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
-                        uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
-                        uint32_t n, uint32_t t, hipStream_t stream);
+hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
+                        const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
+                        uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream);
 
 // The same step from a range-max table of cur (level-major, level 0 = cur,
 // levels 1..levels built by launch_table): each run of consecutive neighbour
 // ids is covered by at most two table rows.  p <= 12.
-hipError_t launch_union_runs(int p, const uint8_t *bytes, const uint64_t *offsets,
+hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
                              hipStream_t stream);

@@ -43,22 +43,37 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kXcds = 8;
+constexpr int kRunsMaxP = 12;  // the run kernel's tables are built for p <= 12
 
-template <int P>
+// Lanes that share one node's counter by default: one 16-byte slot per lane
+// up to p = 10, one wave (1 to 4 slots per lane) at p = 11 and 12, and 4 KB
+// wave slices beyond.
+constexpr int default_lanes(int p) {
+    return p <= 10 ? (1 << p) / 16 : (p <= 12 ? 64 : (1 << p) / 64);
+}
+
+// Shape of one node's work for precision P with L lanes per node.  L <= 64:
+// one wave holds 64 / L groups of L lanes; each group owns a whole counter
+// and the groups gather different neighbours, max-reduced at the end.
+// L > 64: L / 64 waves of one workgroup share the node, each owning a slice.
+template <int P, int L = default_lanes(P)>
 struct Cfg {
+    static constexpr int PREC = P;
+    static constexpr int LANES = L;
     static constexpr int M = 1 << P;
-    static constexpr int SLICE = M < 4096 ? M : 4096;           // bytes per wave
-    static constexpr int WAVES = M > 4096 ? M / 4096 : 1;        // waves per node
-    static constexpr int LPC = SLICE >= 1024 ? 64 : SLICE / 16;  // lanes per counter
+    static constexpr int WAVES = L > kWave ? L / kWave : 1;      // waves per node
+    static constexpr int LPC = L > kWave ? kWave : L;            // lanes per counter in a wave
     static constexpr int G = kWave / LPC;                        // neighbour groups
-    static constexpr int RPL = SLICE >= 1024 ? SLICE / 1024 : 1; // uint4 per lane
+    static constexpr int RPL = M / (16 * L);                     // uint4 slots per lane
+    static constexpr int SLICE = M / WAVES;                      // counter bytes per wave
     static constexpr int U = RPL >= 8 ? 1 : 8 / RPL;             // gathers in flight
-    static constexpr int NODES = WAVES == 1 ? 4 : 1;             // nodes per workgroup
+    static constexpr int NODES = WAVES == 1 ? 4 : 1;             // most nodes per workgroup
     static constexpr int THREADS = WAVES == 1 ? 256 : WAVES * kWave;
     static constexpr int TOP = 65 - P;                           // largest register value
     // waves per SIMD the run kernel is compiled for (its register budget):
-    // 80 VGPRs at p <= 10, 96 at p = 11, 168 at p = 12 (fewer spill)
+    // 80 VGPRs with one slot per lane, 96 with two, 168 with four
     static constexpr int RUN_OCC = RPL == 1 ? 6 : (RPL == 2 ? 5 : 3);
+    static_assert(RPL >= 1 && RPL <= 4 && M % (16 * L) == 0, "unsupported lanes per node");
 };
 
 // ---------------------------------------------------------------- helpers
@@ -184,18 +199,15 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t i, uint32_t nblocks) {
 }
 
 // Byte offset, within a counter, of lane-slot s (s < RPL) of this lane.
-template <int P>
+template <class C>
 __device__ __forceinline__ uint32_t slot_offset(uint32_t slice, uint32_t lane, int s) {
-    using C = Cfg<P>;
-    if (C::SLICE >= 1024) return slice * C::SLICE + (uint32_t)s * 1024u + lane * 16u;
-    return (lane % C::LPC) * 16u;
+    return slice * C::SLICE + (uint32_t)s * (C::LPC * 16u) + (lane % C::LPC) * 16u;
 }
 
-// Combine the estimator partials of the waves sharing a node (p >= 13) and
-// return the node total in every lane of wave 0 (others: unspecified).
-template <int P>
+// Combine the estimator partials of the waves sharing a node and return the
+// node total in every lane of wave 0 (others: unspecified).
+template <class C>
 __device__ EstPart node_total(EstPart e, uint32_t slice) {
-    using C = Cfg<P>;
     if (C::WAVES == 1) return e;
     __shared__ uint64_t s_lo[C::WAVES > 1 ? C::WAVES : 1];
     __shared__ uint64_t s_hi[C::WAVES > 1 ? C::WAVES : 1];
@@ -223,11 +235,11 @@ __device__ EstPart node_total(EstPart e, uint32_t slice) {
 // ---------------------------------------------------------------- init
 // Zero node v's counter (this wave's slice), insert v, and set c_prev[v] to the
 // estimate of the one-element counter and sum_d[v] to 0.
-template <int P>
+template <class C>
 __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__restrict__ c_prev,
                                           double *__restrict__ sum_d, uint32_t v, uint32_t slice,
                                           uint64_t seed) {
-    using C = Cfg<P>;
+    constexpr int P = C::PREC;
     const uint32_t lane = lane_id();
     const uint64_t h = splitmix64((uint64_t)v ^ seed);
     const uint32_t j = (uint32_t)(h >> (64 - P));
@@ -240,7 +252,7 @@ __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__r
     uint8_t *row = cur + (uint64_t)v * C::M;
 #pragma unroll
     for (int s = 0; s < C::RPL; ++s) {
-        const uint32_t off = slot_offset<P>(slice, lane, s);
+        const uint32_t off = slot_offset<C>(slice, lane, s);
         uint32_t w[4] = {0u, 0u, 0u, 0u};
         if (j >= off && j < off + 16u) w[(j - off) >> 2] = r << (8 * ((j - off) & 3u));
         if (owner) {
@@ -250,25 +262,31 @@ __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__r
         }
     }
     e.wave_reduce();
-    const EstPart tot = node_total<P>(e, slice);
+    const EstPart tot = node_total<C>(e, slice);
     if (slice == 0 && lane == 0) {
         c_prev[v] = estimate<P>(tot);
         sum_d[v] = 0.0;
     }
 }
 
-template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void init_kernel(uint8_t *__restrict__ cur,
-                                                               double *__restrict__ c_prev,
-                                                               double *__restrict__ sum_d,
-                                                               uint32_t n, uint64_t seed) {
-    using C = Cfg<P>;
+// Node and counter slice of this wave.  Single-wave shapes run blockDim / 64
+// nodes per workgroup (1, 2 or 4, chosen at launch).
+template <class C>
+__device__ __forceinline__ void node_of(uint32_t blk, uint32_t &v, uint32_t &slice) {
     const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    v = (C::WAVES == 1) ? blk * (blockDim.x / kWave) + wave : blk;
+    slice = (C::WAVES == 1) ? 0u : wave;
+}
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void init_kernel(uint8_t *__restrict__ cur,
+                                                          double *__restrict__ c_prev,
+                                                          double *__restrict__ sum_d, uint32_t n,
+                                                          uint64_t seed) {
+    uint32_t v, slice;
+    node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
-    init_node<P>(cur, c_prev, sum_d, v, slice, seed);
+    init_node<C>(cur, c_prev, sum_d, v, slice, seed);
 }
 
 // ---------------------------------------------------------------- row decoding
@@ -337,15 +355,14 @@ struct RowDecoder {
 
 // ---------------------------------------------------------------- accumulator
 // This lane's share of one node's running register-wise max.
-template <int P>
+template <class C>
 struct NodeAcc {
-    using C = Cfg<P>;
     Max4 m[C::RPL][4];
 
     __device__ __forceinline__ void init(const uint8_t *row, uint32_t slice, uint32_t lane) {
 #pragma unroll
         for (int s = 0; s < C::RPL; ++s) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(row + slot_offset<P>(slice, lane, s));
+            const uint4 x = *reinterpret_cast<const uint4 *>(row + slot_offset<C>(slice, lane, s));
             m[s][0].init(x.x);
             m[s][1].init(x.y);
             m[s][2].init(x.z);
@@ -362,7 +379,7 @@ struct NodeAcc {
         for (int u = 0; u < N; ++u)
 #pragma unroll
             for (int s = 0; s < C::RPL; ++s)
-                x[u][s] = *reinterpret_cast<const uint4 *>(src[u] + slot_offset<P>(slice, lane, s));
+                x[u][s] = *reinterpret_cast<const uint4 *>(src[u] + slot_offset<C>(slice, lane, s));
 #pragma unroll
         for (int u = 0; u < N; ++u)
 #pragma unroll
@@ -377,13 +394,13 @@ struct NodeAcc {
 
 // Final registers of node v: reduce the neighbour groups, store next[v],
 // estimate it, apply Eq. 3 and the 0.5 test.
-template <int P>
-__device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_t slice,
+template <class C>
+__device__ __forceinline__ void finish_node(NodeAcc<C> &acc, uint32_t v, uint32_t slice,
                                             uint8_t *__restrict__ next,
                                             double *__restrict__ c_prev,
                                             double *__restrict__ sum_d,
                                             uint32_t *__restrict__ flag_t, uint32_t t) {
-    using C = Cfg<P>;
+    constexpr int P = C::PREC;
     const uint32_t lane = lane_id();
     const uint32_t grp = lane / C::LPC;
     uint32_t reg[C::RPL][4];
@@ -396,12 +413,14 @@ __device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_
 #pragma unroll
         for (uint32_t mask = C::LPC; mask < kWave; mask <<= 1)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                Max4 mm;
-                mm.init(reg[0][k]);
-                mm.add(shfl_xor(reg[0][k], mask));
-                reg[0][k] = mm.value();
-            }
+            for (int s = 0; s < C::RPL; ++s)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    Max4 mm;
+                    mm.init(reg[s][k]);
+                    mm.add(shfl_xor(reg[s][k], mask));
+                    reg[s][k] = mm.value();
+                }
     }
     EstPart e;
     e.clear();
@@ -409,14 +428,14 @@ __device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_
         uint8_t *row = next + (uint64_t)v * C::M;
 #pragma unroll
         for (int s = 0; s < C::RPL; ++s) {
-            *reinterpret_cast<uint4 *>(row + slot_offset<P>(slice, lane, s)) =
+            *reinterpret_cast<uint4 *>(row + slot_offset<C>(slice, lane, s)) =
                 make_uint4(reg[s][0], reg[s][1], reg[s][2], reg[s][3]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) e.add_dword(reg[s][k], C::TOP);
         }
     }
     e.wave_reduce();
-    const EstPart tot = node_total<P>(e, slice);
+    const EstPart tot = node_total<C>(e, slice);
     if (slice == 0 && lane == 0) {
         const double est = estimate<P>(tot);
         const double delta = est - c_prev[v];
@@ -430,7 +449,7 @@ __device__ __forceinline__ void finish_node(NodeAcc<P> &acc, uint32_t v, uint32_
 
 // ---------------------------------------------------------------- union step, per edge
 // Eq. 2 as written: every neighbour's counter is gathered once per node.
-template <int P>
+template <class C>
 __device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ bytes,
                                                  const uint64_t *__restrict__ offsets,
                                                  const uint8_t *__restrict__ cur,
@@ -439,10 +458,9 @@ __device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ byt
                                                  double *__restrict__ sum_d,
                                                  uint32_t *__restrict__ flag_t, uint32_t v,
                                                  uint32_t slice, uint32_t t) {
-    using C = Cfg<P>;
     const uint32_t lane = lane_id();
     const uint32_t grp = lane / C::LPC;
-    NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v]
+    NodeAcc<C> acc;  // Alg. 1: next[v] <- cur[v]
     acc.init(cur + (uint64_t)v * C::M, slice, lane);
     const uint64_t row_end = offsets[v + 1];
     RowDecoder dec;
@@ -466,21 +484,18 @@ __device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ byt
             acc.gather(src, slice, lane);
         }
     }
-    finish_node<P>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
+    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
 }
 
-template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void union_kernel(
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void union_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
     double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
-    using C = Cfg<P>;
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = (C::WAVES == 1) ? blk * C::NODES + wave : blk;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    uint32_t v, slice;
+    node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
-    union_node_edges<P>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t);
+    union_node_edges<C>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t);
 }
 
 // ---------------------------------------------------------------- union step, per run
@@ -500,15 +515,16 @@ constexpr int kRunLoads = 4;               // 16 B/lane loads in flight per flus
 constexpr int kScalarWalk = 8;             // chunks with at most this many special varints
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
-template <int P>
+template <class C>
 struct RunGather {
-    using C = Cfg<P>;
     const uint8_t *tbl;
     uint32_t n, levels;
     uint32_t *q;   // this wave's LDS queue of table-row indices (k n + i)
     uint32_t qn;   // entries queued (wave-uniform)
 
-    __device__ __forceinline__ void flush(NodeAcc<P> &acc, uint32_t lane) {
+    uint32_t slice;  // this wave's counter slice
+
+    __device__ __forceinline__ void flush(NodeAcc<C> &acc, uint32_t lane) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -525,14 +541,14 @@ struct RunGather {
                 if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
                 src[u] = tbl + (uint64_t)row * C::M;
             }
-            acc.gather(src, 0, lane);
+            acc.gather(src, slice, lane);
         }
         __builtin_amdgcn_wave_barrier();
         qn = 0;
     }
 
     // queue the table rows covering run [a, b] (wave-uniform a, b)
-    __device__ __forceinline__ void push_run(NodeAcc<P> &acc, uint32_t a, uint32_t b,
+    __device__ __forceinline__ void push_run(NodeAcc<C> &acc, uint32_t a, uint32_t b,
                                              uint32_t lane) {
         const uint32_t r = b - a + 1u;
         const uint32_t top = 1u << levels;
@@ -557,7 +573,7 @@ struct RunGather {
     }
 };
 
-template <int P>
+template <class C>
 __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ bytes,
                                                 const uint64_t *__restrict__ offsets,
                                                 const uint8_t *__restrict__ tbl, uint32_t levels,
@@ -565,12 +581,12 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
                                                 double *__restrict__ c_prev,
                                                 double *__restrict__ sum_d,
                                                 uint32_t *__restrict__ flag_t, uint32_t n,
-                                                uint32_t v, uint32_t t, uint32_t *queue) {
-    using C = Cfg<P>;
+                                                uint32_t v, uint32_t slice, uint32_t t,
+                                                uint32_t *queue) {
     const uint32_t lane = lane_id();
-    NodeAcc<P> acc;  // Alg. 1: next[v] <- cur[v] (level 0 of the table is cur)
-    acc.init(tbl + (uint64_t)v * C::M, 0, lane);
-    RunGather<P> g{tbl, n, levels, queue, 0u};
+    NodeAcc<C> acc;  // Alg. 1: next[v] <- cur[v] (level 0 of the table is cur)
+    acc.init(tbl + (uint64_t)v * C::M, slice, lane);
+    RunGather<C> g{tbl, n, levels, queue, 0u, slice};
     const uint32_t top = 1u << levels;
 
     bool have = false;      // a run is open: [ra, rl]; rl is the last id decoded
@@ -687,7 +703,7 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     }
     if (have) g.push_run(acc, ra, rl, lane);
     if (g.qn) g.flush(acc, lane);
-    finish_node<P>(acc, v, 0, next, c_prev, sum_d, flag_t, t);
+    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
 }
 
 // Six waves per SIMD (80 VGPRs): the run kernel hides its gather latency with
@@ -696,21 +712,20 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
 // 32.1 ms at six with four loads in flight; eight waves spill heavily (75 ms).
 // At p = 11 five waves beat four (58.0 against 60.2 ms); at p = 12 three waves
 // without spills match four with them (117.4 against 118.0 ms).
-template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS, Cfg<P>::RUN_OCC) void union_runs_kernel(
+// With several waves per node every wave decodes the row and queues the same
+// table rows, then gathers its own slice of each.
+template <class C>
+__global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
     uint32_t n, uint32_t t) {
-    using C = Cfg<P>;
-    static_assert(C::WAVES == 1, "the run kernel keeps one wave per node");
-    __shared__ uint32_t s_queue[C::NODES][kQueueCap];
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t v = blk * C::NODES + wave;
-    if (v >= n) return;
-    union_node_runs<P>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, v, t,
-                       s_queue[wave]);
+    __shared__ uint32_t s_queue[C::THREADS / kWave][kQueueCap];
+    uint32_t v, slice;
+    node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
+    if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    union_node_runs<C>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
+                       s_queue[threadIdx.x / kWave]);
 }
 
 // Level k of the range-max table from level k - 1:
@@ -758,43 +773,37 @@ __device__ __forceinline__ uint32_t job_block(uint32_t blk, const uint32_t *__re
     return xcd_block(blk - block_base[i], block_base[i + 1] - block_base[i]);
 }
 
-template <int P>
-__global__ __launch_bounds__(Cfg<P>::THREADS) void batch_init_kernel(
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void batch_init_kernel(
     BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ block_base, uint32_t nlist) {
-    using C = Cfg<P>;
-    const uint32_t wave = threadIdx.x / kWave;
     const uint32_t i = find_job(block_base, nlist, blockIdx.x);
     const BatchJob &J = jobs[list[i]];
-    const uint32_t local = job_block(blockIdx.x, block_base, i);
-    const uint32_t v = (C::WAVES == 1) ? local * C::NODES + wave : local;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    uint32_t v, slice;
+    node_of<C>(job_block(blockIdx.x, block_base, i), v, slice);
     if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
-    init_node<P>(J.buf[0], J.c_prev, J.sum_d, v, slice, J.seed);
+    init_node<C>(J.buf[0], J.c_prev, J.sum_d, v, slice, J.seed);
 }
 
-template <int P, bool RUNS>
-__global__ __launch_bounds__(Cfg<P>::THREADS, RUNS ? Cfg<P>::RUN_OCC : 1) void batch_union_kernel(
+template <class C, bool RUNS>
+__global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union_kernel(
     BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ block_base, uint32_t nlist) {
-    using C = Cfg<P>;
-    __shared__ uint32_t s_queue[RUNS ? C::NODES : 1][RUNS ? kQueueCap : 1];
-    const uint32_t wave = threadIdx.x / kWave;
+    __shared__ uint32_t s_queue[RUNS ? C::THREADS / kWave : 1][RUNS ? kQueueCap : 1];
     const uint32_t i = find_job(block_base, nlist, blockIdx.x);
     const BatchJob &J = jobs[list[i]];
     if (J.done) return;  // uniform per workgroup
     const uint32_t t = J.t + 1u;
-    const uint32_t local = job_block(blockIdx.x, block_base, i);
-    const uint32_t v = (C::WAVES == 1) ? local * C::NODES + wave : local;
-    const uint32_t slice = (C::WAVES == 1) ? 0u : wave;
+    uint32_t v, slice;
+    node_of<C>(job_block(blockIdx.x, block_base, i), v, slice);
     if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
     const uint8_t *cur = J.buf[(t - 1u) & 1u];
     uint8_t *next = J.buf[t & 1u];
     if constexpr (RUNS) {
-        union_node_runs<P>(J.bytes, J.offsets, cur, J.levels, next, J.c_prev, J.sum_d,
-                           J.flags + t, J.n, v, t, s_queue[wave]);
+        union_node_runs<C>(J.bytes, J.offsets, cur, J.levels, next, J.c_prev, J.sum_d,
+                           J.flags + t, J.n, v, slice, t, s_queue[threadIdx.x / kWave]);
     } else {
-        union_node_edges<P>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
+        union_node_edges<C>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
                             slice, t);
     }
 }
@@ -869,114 +878,164 @@ __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
 }
 
 // ---------------------------------------------------------------- dispatch
-template <int P>
-hipError_t launch_init_p(uint8_t *cur, double *c_prev, double *sum_d, uint32_t n, uint64_t seed,
-                         hipStream_t stream) {
-    using C = Cfg<P>;
-    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
-    hipLaunchKernelGGL((init_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, cur, c_prev,
+// Compiled shapes: (p, lanes per node).  The first entry of each p is its
+// default; the others are the alternatives the tuner may pick.
+#define HB_SHAPES(X)                                                             \
+    X(4, 1) X(5, 2) X(6, 4) X(7, 8) X(8, 16) X(8, 8) X(9, 32) X(9, 16) X(10, 64) \
+    X(10, 32) X(10, 16) X(11, 64) X(11, 128) X(11, 32) X(12, 64) X(12, 128)     \
+    X(12, 256) X(13, 128) X(13, 256) X(14, 256) X(14, 512) X(15, 512) X(16, 1024)
+
+// Workgroups and threads of a launch over n nodes.
+template <class C>
+void grid_for(uint32_t n, uint32_t nb, uint32_t &blocks, uint32_t &threads) {
+    const uint32_t per = C::WAVES == 1 ? nb : 1u;
+    blocks = (uint32_t)(((uint64_t)n + per - 1) / per);
+    threads = C::WAVES == 1 ? nb * (uint32_t)kWave : (uint32_t)C::THREADS;
+}
+
+template <class C>
+hipError_t launch_init_c(uint8_t *cur, double *c_prev, double *sum_d, uint32_t n, uint64_t seed,
+                         uint32_t nb, hipStream_t stream) {
+    uint32_t blocks, threads;
+    grid_for<C>(n, nb, blocks, threads);
+    hipLaunchKernelGGL((init_kernel<C>), dim3(blocks), dim3(threads), 0, stream, cur, c_prev,
                        sum_d, n, seed);
     return hipGetLastError();
 }
 
-template <int P>
-hipError_t launch_union_p(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
+template <class C>
+hipError_t launch_union_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
                           uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
-                          uint32_t n, uint32_t t, hipStream_t stream) {
-    using C = Cfg<P>;
-    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
-    hipLaunchKernelGGL((union_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, bytes,
-                       offsets, cur, next, c_prev, sum_d, flag_t, n, t);
+                          uint32_t n, uint32_t t, uint32_t nb, hipStream_t stream) {
+    uint32_t blocks, threads;
+    grid_for<C>(n, nb, blocks, threads);
+    hipLaunchKernelGGL((union_kernel<C>), dim3(blocks), dim3(threads), 0, stream, bytes, offsets,
+                       cur, next, c_prev, sum_d, flag_t, n, t);
     return hipGetLastError();
 }
 
-template <int P>
-hipError_t launch_union_runs_p(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *tbl,
+template <class C>
+hipError_t launch_union_runs_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *tbl,
                                uint32_t levels, uint8_t *next, double *c_prev, double *sum_d,
-                               uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream) {
-    using C = Cfg<P>;
-    const uint32_t blocks = (uint32_t)(((uint64_t)n + C::NODES - 1) / C::NODES);
-    hipLaunchKernelGGL((union_runs_kernel<P>), dim3(blocks), dim3(C::THREADS), 0, stream, bytes,
-                       offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t);
+                               uint32_t *flag_t, uint32_t n, uint32_t t, uint32_t nb,
+                               hipStream_t stream) {
+    if constexpr (C::PREC <= kRunsMaxP) {
+        uint32_t blocks, threads;
+        grid_for<C>(n, nb, blocks, threads);
+        hipLaunchKernelGGL((union_runs_kernel<C>), dim3(blocks), dim3(threads), 0, stream,
+                           bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class C>
+hipError_t launch_batch_init_c(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
+                               uint32_t nlist, uint32_t nblocks, uint32_t nb, hipStream_t stream) {
+    uint32_t blocks, threads;
+    grid_for<C>(1u, nb, blocks, threads);
+    hipLaunchKernelGGL((batch_init_kernel<C>), dim3(nblocks), dim3(threads), 0, stream, jobs,
+                       list, block_base, nlist);
+    return hipGetLastError();
+}
+
+template <class C>
+hipError_t launch_batch_union_c(bool runs, BatchJob *jobs, const uint32_t *list,
+                                const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                                uint32_t nb, hipStream_t stream) {
+    uint32_t blocks, threads;
+    grid_for<C>(1u, nb, blocks, threads);
+    if (runs) {
+        if constexpr (C::PREC <= kRunsMaxP) {
+            hipLaunchKernelGGL((batch_union_kernel<C, true>), dim3(nblocks), dim3(threads), 0,
+                               stream, jobs, list, block_base, nlist);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL((batch_union_kernel<C, false>), dim3(nblocks), dim3(threads), 0,
+                           stream, jobs, list, block_base, nlist);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-LaunchShape shape_for(int p) {
-    LaunchShape s;
-    const uint32_t m = 1u << p;
-    s.waves_per_node = m > 4096 ? m / 4096 : 1;
-    s.nodes_per_block = s.waves_per_node == 1 ? 4 : 1;
-    s.threads = s.waves_per_node == 1 ? 256 : s.waves_per_node * kWave;
+uint32_t lane_options(int p, uint32_t out[kMaxLaneOptions]) {
+    uint32_t k = 0;
+#define HB_LANES(P, L) \
+    if (p == P && k < kMaxLaneOptions) out[k++] = L;
+    HB_SHAPES(HB_LANES)
+#undef HB_LANES
+    return k;
+}
+
+Sched default_sched(int p) {
+    Sched s;
+    s.lanes = (p >= 4 && p <= 16) ? (uint32_t)default_lanes(p) : 0u;
+    s.nodes_per_block = s.lanes > (uint32_t)kWave ? 1u : 4u;
     return s;
 }
 
-hipError_t launch_init(int p, uint8_t *cur, double *c_prev, double *sum_d, uint32_t n,
-                       uint64_t seed, hipStream_t stream) {
-#define HB_CALL_INIT(P) launch_init_p<P>(cur, c_prev, sum_d, n, seed, stream)
-    switch (p) {
-        case 4: return HB_CALL_INIT(4);
-        case 5: return HB_CALL_INIT(5);
-        case 6: return HB_CALL_INIT(6);
-        case 7: return HB_CALL_INIT(7);
-        case 8: return HB_CALL_INIT(8);
-        case 9: return HB_CALL_INIT(9);
-        case 10: return HB_CALL_INIT(10);
-        case 11: return HB_CALL_INIT(11);
-        case 12: return HB_CALL_INIT(12);
-        case 13: return HB_CALL_INIT(13);
-        case 14: return HB_CALL_INIT(14);
-        case 15: return HB_CALL_INIT(15);
-        case 16: return HB_CALL_INIT(16);
-        default: return hipErrorInvalidValue;
-    }
-#undef HB_CALL_INIT
+bool sched_ok(int p, const Sched &s) {
+    uint32_t opts[kMaxLaneOptions];
+    const uint32_t k = lane_options(p, opts);
+    bool lanes_ok = false;
+    for (uint32_t i = 0; i < k; ++i) lanes_ok |= opts[i] == s.lanes;
+    if (!lanes_ok) return false;
+    if (s.lanes > (uint32_t)kWave) return s.nodes_per_block == 1u;
+    return s.nodes_per_block == 1u || s.nodes_per_block == 2u || s.nodes_per_block == 4u;
 }
 
-hipError_t launch_union(int p, const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
-                        uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
-                        uint32_t n, uint32_t t, hipStream_t stream) {
-#define HB_CALL_UNION(P) \
-    launch_union_p<P>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, t, stream)
-    switch (p) {
-        case 4: return HB_CALL_UNION(4);
-        case 5: return HB_CALL_UNION(5);
-        case 6: return HB_CALL_UNION(6);
-        case 7: return HB_CALL_UNION(7);
-        case 8: return HB_CALL_UNION(8);
-        case 9: return HB_CALL_UNION(9);
-        case 10: return HB_CALL_UNION(10);
-        case 11: return HB_CALL_UNION(11);
-        case 12: return HB_CALL_UNION(12);
-        case 13: return HB_CALL_UNION(13);
-        case 14: return HB_CALL_UNION(14);
-        case 15: return HB_CALL_UNION(15);
-        case 16: return HB_CALL_UNION(16);
-        default: return hipErrorInvalidValue;
-    }
-#undef HB_CALL_UNION
+LaunchShape shape_for(int p, const Sched &s) {
+    LaunchShape r;
+    const uint32_t m = 1u << p;
+    (void)m;
+    r.waves_per_node = s.lanes > (uint32_t)kWave ? s.lanes / kWave : 1u;
+    r.nodes_per_block = r.waves_per_node == 1 ? s.nodes_per_block : 1u;
+    r.threads = r.waves_per_node == 1 ? r.nodes_per_block * kWave : r.waves_per_node * kWave;
+    return r;
 }
 
-hipError_t launch_union_runs(int p, const uint8_t *bytes, const uint64_t *offsets,
+#define HB_DISPATCH(CALL)                                                  \
+    do {                                                                   \
+        if (!sched_ok(p, s)) return hipErrorInvalidValue;                  \
+        const uint32_t nb = s.nodes_per_block;                             \
+        (void)nb;                                                          \
+        HB_SHAPES(CALL)                                                    \
+        return hipErrorInvalidValue;                                       \
+    } while (0)
+
+hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, double *sum_d,
+                       uint32_t n, uint64_t seed, hipStream_t stream) {
+#define HB_X(P, L) \
+    if (p == P && s.lanes == L) return launch_init_c<Cfg<P, L>>(cur, c_prev, sum_d, n, seed, nb, stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
+}
+
+hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
+                        const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
+                        uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream) {
+#define HB_X(P, L)                                                                            \
+    if (p == P && s.lanes == L)                                                               \
+        return launch_union_c<Cfg<P, L>>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, \
+                                         t, nb, stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
+}
+
+hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
                              hipStream_t stream) {
-#define HB_CALL_RUNS(P) \
-    launch_union_runs_p<P>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t, stream)
-    switch (p) {
-        case 4: return HB_CALL_RUNS(4);
-        case 5: return HB_CALL_RUNS(5);
-        case 6: return HB_CALL_RUNS(6);
-        case 7: return HB_CALL_RUNS(7);
-        case 8: return HB_CALL_RUNS(8);
-        case 9: return HB_CALL_RUNS(9);
-        case 10: return HB_CALL_RUNS(10);
-        case 11: return HB_CALL_RUNS(11);
-        case 12: return HB_CALL_RUNS(12);
-        default: return hipErrorInvalidValue;
-    }
-#undef HB_CALL_RUNS
+#define HB_X(P, L)                                                                          \
+    if (p == P && s.lanes == L)                                                             \
+        return launch_union_runs_c<Cfg<P, L>>(bytes, offsets, tbl, levels, next, c_prev,    \
+                                              sum_d, flag_t, n, t, nb, stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
 }
 
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
@@ -995,85 +1054,28 @@ hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
     return hipSuccess;
 }
 
-namespace {
-template <int P>
-hipError_t launch_batch_init_p(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
-                               uint32_t nlist, uint32_t nblocks, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_init_kernel<P>), dim3(nblocks), dim3(Cfg<P>::THREADS), 0, stream,
-                       jobs, list, block_base, nlist);
-    return hipGetLastError();
-}
-
-template <int P, bool RUNS>
-hipError_t launch_batch_union_p(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
-                                uint32_t nlist, uint32_t nblocks, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_union_kernel<P, RUNS>), dim3(nblocks), dim3(Cfg<P>::THREADS), 0,
-                       stream, jobs, list, block_base, nlist);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_batch_init(int p, BatchJob *jobs, const uint32_t *list,
+hipError_t launch_batch_init(int p, const Sched &s, BatchJob *jobs, const uint32_t *list,
                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
                              hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
-#define HB_CALL_BINIT(P) launch_batch_init_p<P>(jobs, list, block_base, nlist, nblocks, stream)
-    switch (p) {
-        case 4: return HB_CALL_BINIT(4);
-        case 5: return HB_CALL_BINIT(5);
-        case 6: return HB_CALL_BINIT(6);
-        case 7: return HB_CALL_BINIT(7);
-        case 8: return HB_CALL_BINIT(8);
-        case 9: return HB_CALL_BINIT(9);
-        case 10: return HB_CALL_BINIT(10);
-        case 11: return HB_CALL_BINIT(11);
-        case 12: return HB_CALL_BINIT(12);
-        case 13: return HB_CALL_BINIT(13);
-        case 14: return HB_CALL_BINIT(14);
-        case 15: return HB_CALL_BINIT(15);
-        case 16: return HB_CALL_BINIT(16);
-        default: return hipErrorInvalidValue;
-    }
-#undef HB_CALL_BINIT
+#define HB_X(P, L)                                                                          \
+    if (p == P && s.lanes == L)                                                             \
+        return launch_batch_init_c<Cfg<P, L>>(jobs, list, block_base, nlist, nblocks, nb,  \
+                                              stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
 }
 
-hipError_t launch_batch_union(int p, bool runs, BatchJob *jobs, const uint32_t *list,
-                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
-                              hipStream_t stream) {
+hipError_t launch_batch_union(int p, const Sched &s, bool runs, BatchJob *jobs,
+                              const uint32_t *list, const uint32_t *block_base, uint32_t nlist,
+                              uint32_t nblocks, hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
-#define HB_CALL_BUNION(P, R) \
-    launch_batch_union_p<P, R>(jobs, list, block_base, nlist, nblocks, stream)
-    if (runs) {
-        switch (p) {
-            case 4: return HB_CALL_BUNION(4, true);
-            case 5: return HB_CALL_BUNION(5, true);
-            case 6: return HB_CALL_BUNION(6, true);
-            case 7: return HB_CALL_BUNION(7, true);
-            case 8: return HB_CALL_BUNION(8, true);
-            case 9: return HB_CALL_BUNION(9, true);
-            case 10: return HB_CALL_BUNION(10, true);
-            case 11: return HB_CALL_BUNION(11, true);
-            case 12: return HB_CALL_BUNION(12, true);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (p) {
-        case 4: return HB_CALL_BUNION(4, false);
-        case 5: return HB_CALL_BUNION(5, false);
-        case 6: return HB_CALL_BUNION(6, false);
-        case 7: return HB_CALL_BUNION(7, false);
-        case 8: return HB_CALL_BUNION(8, false);
-        case 9: return HB_CALL_BUNION(9, false);
-        case 10: return HB_CALL_BUNION(10, false);
-        case 11: return HB_CALL_BUNION(11, false);
-        case 12: return HB_CALL_BUNION(12, false);
-        case 13: return HB_CALL_BUNION(13, false);
-        case 14: return HB_CALL_BUNION(14, false);
-        case 15: return HB_CALL_BUNION(15, false);
-        case 16: return HB_CALL_BUNION(16, false);
-        default: return hipErrorInvalidValue;
-    }
-#undef HB_CALL_BUNION
+#define HB_X(P, L)                                                                            \
+    if (p == P && s.lanes == L)                                                               \
+        return launch_batch_union_c<Cfg<P, L>>(runs, jobs, list, block_base, nlist, nblocks, \
+                                               nb, stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
 }
 
 uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k) {

@@ -313,6 +313,9 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
     out->run_ms = (double)(r->t_end - r->t_admit) / 1e6;
     out->union_kernel = r->runs ? HB_UNION_RUNS : HB_UNION_EDGES;
     out->table_levels = r->levels;
+    out->lanes_per_node = hbk::default_sched((int)r->p).lanes;
+    out->nodes_per_block = hbk::default_sched((int)r->p).nodes_per_block;
+    out->tune_ms = 0.0;
     out->t_submit_ns = r->t_submit;
     out->t_admit_ns = r->t_admit;
     out->t_start_ns = r->t_start;
@@ -450,7 +453,9 @@ hb_status Server::step(Lane &L) {
             cs.push_back(Cls{h_jobs_[j].p, runs, {}, {0u}, 0, 0});
             c = &cs.back();
         }
-        const uint32_t npb = hbk::shape_for((int)h_jobs_[j].p).nodes_per_block;
+        // the default schedule: a served step's class mix changes from step to step
+        const int p = (int)h_jobs_[j].p;
+        const uint32_t npb = hbk::shape_for(p, hbk::default_sched(p)).nodes_per_block;
         c->list.push_back(j);
         c->base.push_back(c->base.back() + (h_jobs_[j].n + npb - 1) / npb);
     };
@@ -510,13 +515,15 @@ hb_status Server::step(Lane &L) {
         L.running[j]->t_start = t_launch;
     }
     for (auto &c : inits)
-        HB_HIP(hbk::launch_batch_init((int)c.p, d_jobs_, d_lists_ + c.list_off, d_lists_ + c.base_off,
+        HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p), d_jobs_,
+                                      d_lists_ + c.list_off, d_lists_ + c.base_off,
                                       (uint32_t)c.list.size(), c.base.back(), s));
     for (uint32_t k = 1; k <= max_levels; ++k)
         HB_HIP(hbk::launch_batch_table(d_jobs_, d_lists_ + runs_off, d_lists_ + table_off[k],
                                        (uint32_t)runs_list.size(), table_blocks[k], k, s));
     for (auto &c : classes)
-        HB_HIP(hbk::launch_batch_union((int)c.p, c.runs, d_jobs_, d_lists_ + c.list_off,
+        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p), c.runs, d_jobs_,
+                                       d_lists_ + c.list_off,
                                        d_lists_ + c.base_off, (uint32_t)c.list.size(),
                                        c.base.back(), s));
     HB_HIP(hbk::launch_batch_step_end(d_jobs_, d_lists_, nj, s));

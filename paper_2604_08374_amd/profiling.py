@@ -19,6 +19,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,23 +34,30 @@ def _find(d: str, suffix: str) -> str:
 
 
 def _short(name: str) -> str:
+    """Kernel name without namespaces and parameters: union_runs_kernel<10,64>.
+
+    The union kernels are templates over Cfg<p, lanes per node> (and, batched,
+    the kernel kind), shown as <p,lanes> or <p,lanes,true|false>.
+    """
     for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
-                "batch_step_end_kernel"):
-        if key in name:
-            tmpl = name[name.index(key) + len(key):]
-            return key + (tmpl[:tmpl.index(">") + 1] if tmpl.startswith("<") else "")
-    for key in ("union_runs_kernel", "union_kernel", "table_level_kernel", "init_kernel",
-                "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
-        if key in name:
-            tmpl = name[name.index(key) + len(key):]
-            if tmpl.startswith("<"):
-                return key + tmpl[:tmpl.index(">") + 1]
+                "batch_step_end_kernel", "union_runs_kernel", "union_kernel", "table_level_kernel",
+                "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
+        at = name.find(key)
+        if at < 0 or (at > 0 and (name[at - 1].isalnum() or name[at - 1] == "_")):
+            continue
+        rest = name[at + len(key):]
+        if not rest.startswith("<"):
             return key
-    for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
-                "batch_step_end_kernel"):
-        if key in name:
-            tmpl = name[name.index(key) + len(key):]
-            return key + (tmpl[:tmpl.index(">") + 1] if tmpl.startswith("<") else "")
+        depth, end = 0, 0
+        for k, ch in enumerate(rest):
+            depth += ch == "<"
+            depth -= ch == ">"
+            if depth == 0:
+                end = k
+                break
+        args = rest[1:end].replace("hbk::(anonymous namespace)::", "")
+        args = re.sub(r"Cfg<([^>]*)>", r"\1", args).replace(" ", "")
+        return f"{key}<{args}>"
     return name[:48]
 
 

@@ -66,7 +66,10 @@ def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     big = _load(hb, synth.grid_graph(1, 120, 100))
     small = _load(hb, synth.tiny(2))
     tb = hb.submit(big, 12, 0, 5)
-    time.sleep(0.002)
+    for _ in range(200000):  # until the long request has been admitted
+        if hb.server_stats()["running"] >= 1:
+            break
+        time.sleep(0.0001)
     ts = [hb.submit(small, 8, 2, s) for s in range(6)]
     rs = [t.wait() for t in ts]
     rb = tb.wait()
