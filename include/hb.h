@@ -329,7 +329,11 @@ hb_status hb_wait(hb_ticket t, hb_result *out);
 /* Counters of the request loop. */
 hb_status hb_server_stats(hb_server_stats_t *out);
 
-/* Free the workspace kept between batched calls. */
+/*
+ * Free the device workspaces kept between calls: the counter buffers of
+ * blocking runs (one pair per device, shared by all graphs and sized for the
+ * largest run so far) and the batched runs' workspace.
+ */
 hb_status hb_release_cache(void);
 
 /*

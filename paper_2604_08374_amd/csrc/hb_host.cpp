@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -137,14 +138,41 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
 
 namespace {
 
+// Ping-pong counter buffers (with the run kernel's table levels) of blocking
+// runs, one pair per device, shared by every graph: runs on a device are
+// serialised by g_dev_mu, so the pair only has to fit the largest run, not
+// the sum over the graphs loaded.  Grown on demand, freed by hb_release_cache.
+struct RunWorkspace {
+    uint8_t *buf[2] = {nullptr, nullptr};
+    uint64_t bytes = 0;
+
+    void release() {
+        (void)hipFree(buf[0]);
+        (void)hipFree(buf[1]);
+        buf[0] = buf[1] = nullptr;
+        bytes = 0;
+    }
+    hipError_t reserve(uint64_t need) {
+        if (bytes >= need) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&buf[0], need);
+        if (e == hipSuccess) e = hipMalloc(&buf[1], need);
+        if (e != hipSuccess) {
+            release();
+            return e;
+        }
+        bytes = need;
+        return hipSuccess;
+    }
+};
+std::map<int, RunWorkspace> g_run_ws;  // by device, guarded by g_dev_mu
+
 void graph_release(hb_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     (void)hipFree(g->d_bytes);
     (void)hipFree(g->d_offsets);
-    (void)hipFree(g->d_cnt[0]);
-    (void)hipFree(g->d_cnt[1]);
     (void)hipFree(g->d_cprev);
     (void)hipFree(g->d_sumd);
     (void)hipFree(g->d_flags);
@@ -424,28 +452,20 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
             const uint64_t want = 2ull * (levels + 1) * n * m;
-            if (want > (uint64_t)free_b + g->cnt_bytes * 2 || want > (64ull << 30)) runs = false;
+            if (want > (uint64_t)free_b + g_run_ws[g->device].bytes * 2 || want > (64ull << 30))
+                runs = false;
         }
     }
     const uint64_t need = (uint64_t)n * m * (runs ? (levels + 1u) : 1u);
-    if (g->cnt_bytes < need) {
-        (void)hipFree(g->d_cnt[0]);
-        (void)hipFree(g->d_cnt[1]);
-        g->d_cnt[0] = g->d_cnt[1] = nullptr;
-        g->cnt_bytes = 0;
-        hipError_t e = hipMalloc(&g->d_cnt[0], need);
-        if (e == hipSuccess) e = hipMalloc(&g->d_cnt[1], need);
-        if (e != hipSuccess) {
-            (void)hipFree(g->d_cnt[0]);
-            g->d_cnt[0] = nullptr;
-            if (e == hipErrorOutOfMemory)
-                return fail(HB_ENOMEM, "counters need 2 x %llu bytes", (unsigned long long)need);
-            return hip_fail(e, "hipMalloc(counters)");
-        }
-        g->cnt_bytes = need;
+    RunWorkspace &ws = g_run_ws[g->device];
+    {
+        const hipError_t e = ws.reserve(need);
+        if (e == hipErrorOutOfMemory)
+            return fail(HB_ENOMEM, "counters need 2 x %llu bytes", (unsigned long long)need);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(counters)");
     }
     hipStream_t s = g->stream;
-    uint8_t *cur = g->d_cnt[0], *next = g->d_cnt[1];
+    uint8_t *cur = ws.buf[0], *next = ws.buf[1];
     const hbk::Sched init_sched = hbk::default_sched((int)p);
 
     // ---- union schedule: explicit, cached, measured here, or the default
@@ -976,6 +996,11 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
 hb_status hb_release_cache(void) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_batch.release();
+    for (auto &kv : g_run_ws) {
+        (void)hipSetDevice(kv.first);
+        kv.second.release();
+    }
+    g_run_ws.clear();
     return HB_OK;
 }
 

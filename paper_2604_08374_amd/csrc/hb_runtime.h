@@ -86,9 +86,7 @@ struct hb_graph {
     std::vector<uint32_t> comp_size;  // empty: one component of n
     uint8_t *d_bytes = nullptr;
     uint64_t *d_offsets = nullptr;
-    // run state, kept between runs
-    uint8_t *d_cnt[2] = {nullptr, nullptr};
-    uint64_t cnt_bytes = 0;
+    // run state, kept between runs (the counters live in a per-device workspace)
     double *d_cprev = nullptr, *d_sumd = nullptr;
     uint32_t *d_flags = nullptr;
     uint64_t n_flags = 0;
