@@ -50,6 +50,14 @@ def make_graph(config: str, seed: int):
     return g
 
 
+def node_order(g, args):
+    """Processing order handed to hb_graph_load: the cells along a Hilbert curve over the
+    raster (the paper's locality reordering, Sec. 3.2, without renumbering), or None."""
+    import synth
+
+    return synth.hilbert_order(g) if args.order == "hilbert" else None
+
+
 def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None) -> int:
     """Bytes one union launch must move at minimum without reuse.
 
@@ -69,11 +77,12 @@ def table_bytes(n: int, p: int, levels: int) -> int:
     return sum(3 * (n - (1 << k) + 1) * m for k in range(1, levels + 1))
 
 
-def kernel_traffic(config: str, p: int, depth: int, kernel: str):
+def kernel_traffic(config: str, p: int, depth: int, kernel: str, order: str):
     """HBM bytes per union launch from the committed rocprofv3 counter summary.
 
-    The summary was taken on the default workload (city graph, p = 10, depth 3);
-    for any other workload, or once the kernel source has changed, it is None.
+    The summary was taken on the default workload (city graph, p = 10, depth 3, in
+    the processing order it names); for any other workload, or once the kernel
+    source has changed, it is None.
     """
     if (config, p, depth) != ("city", 10, 3):
         return None
@@ -87,6 +96,8 @@ def kernel_traffic(config: str, p: int, depth: int, kernel: str):
     if rec.get("kernel_source_sha256", "").strip() != src_hash:
         return None  # the kernel changed since the counters were taken
     if rec.get("kernel", "").strip() != kernel:
+        return None
+    if rec.get("node_order", "raster").strip() != order:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
@@ -137,7 +148,7 @@ def batch_bench(args):
         spec = synth.batch_spec(seed)
         g = synth.batch_graph(seed)
         off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
-        G = hb.graph_load(off, deg, data)
+        G = hb.graph_load(off, deg, data, order=node_order(g, args))
         Gs.append(G)
         jobs.append((G, spec["p"], spec["depth"], seed))
         edges.append(g.n_edges)
@@ -185,7 +196,7 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": f"{len(jobs)} street/building graphs, seeds 0..{len(jobs) - 1}",
                    "nodes_total": int(sum(G.n for G in Gs)), "directed_edges_total": int(sum(edges)),
-                   "union_kernel": args.kernel, "tune": args.tune,
+                   "union_kernel": args.kernel, "tune": args.tune, "node_order": args.order,
                    "schedules": sorted({(p, r.union_kernel, r.lanes_per_node, r.nodes_per_block)
                                         for (_, p, _, _), r in zip(jobs, rb)})},
         "sequential": {"value": unions / seq_s, "ms": seq_s * 1e3},
@@ -226,7 +237,8 @@ def serve_bench(args):
         seed = 1000 + k
         g = synth.serve_graph(seed, n_lo=1000, n_hi=args.pool_max_nodes)
         off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
-        graphs.append(dict(seed=seed, n=g.n, edges=g.n_edges, csr=(off, deg, data)))
+        graphs.append(dict(seed=seed, n=g.n, edges=g.n_edges,
+                           csr=(off, deg, data, None, None, node_order(g, args))))
     log(f"pool of {pool_n} graphs (n {min(x['n'] for x in graphs)}..{max(x['n'] for x in graphs)})"
         f" built in {time.perf_counter() - t0:.1f}s")
     fresh = set(rng.choice(pool_n, size=max(1, pool_n // 10), replace=False).tolist())
@@ -392,6 +404,8 @@ def main():
                     help="union kernel: per edge, per run from a range-max table, or the "
                          "library's choice")
     ap.add_argument("--table-levels", type=int, default=0)
+    ap.add_argument("--order", default="hilbert", choices=["hilbert", "raster"],
+                    help="processing order of the nodes (results are identical either way)")
     ap.add_argument("--tune", default="measure", choices=["measure", "cached", "off"],
                     help="union schedule: measured in the warm-up (default), cached or default")
     ap.add_argument("--copy-probe", action="store_true",
@@ -418,9 +432,10 @@ def main():
     n, E = g.n, g.n_edges
     log(f"encoded LEB128 CSR: {data.size} bytes ({data.size / max(E, 1):.3f} B/edge) "
         f"in {time.perf_counter() - t0:.1f}s")
+    order = node_order(g, args)
     del g
     t0 = time.perf_counter()
-    G = hb.graph_load(off, deg, data)
+    G = hb.graph_load(off, deg, data, order=order)
     log(f"hb_graph_load (validate + copy to HBM) in {time.perf_counter() - t0:.1f}s")
     stats = G.stats()
 
@@ -460,7 +475,7 @@ def main():
     lanes = results[-1].lanes_per_node
     kname = (f"union_runs_kernel<{p},{lanes}>" if kernel == "runs"
              else f"union_kernel<{p},{lanes}>")
-    traffic = kernel_traffic(args.config, p, depth, kname)
+    traffic = kernel_traffic(args.config, p, depth, kname, args.order)
     edge_equiv = algorithmic_bytes(n, E, data.size, p) / avg_launch_s / 1e9
     line = {
         "metric": METRIC,
@@ -485,6 +500,7 @@ def main():
             "passes_per_step": results[-1].passes,
             "union_kernel": kernel,
             "table_levels": levels,
+            "node_order": args.order,
             "schedule": {"lanes_per_node": lanes,
                          "nodes_per_block": results[-1].nodes_per_block,
                          "tune": args.tune, "tune_ms": tune_ms,

@@ -55,6 +55,17 @@ typedef struct hb_graph hb_graph;
  * from the previous id, so the row lists the neighbours in increasing order.
  * All pointers are host memory, owned by the caller, read only during the
  * call.
+ *
+ * Two optional arrays serve the paper's locality reordering (Sec. 3.2,
+ * "Optional Hilbert reordering"):
+ *  - order: the order in which the union kernels process the nodes.  Nodes
+ *    processed together should share neighbours (e.g. the cells sorted along
+ *    a Hilbert curve), which raises cache reuse.  It changes no result.
+ *    hb_graph_load returns HB_EINVAL if it is not a permutation of 0..n-1.
+ *  - hash_ids: the element inserted into node v's own counter.  A graph whose
+ *    nodes were renumbered (its CSR rebuilt in the new numbering) gives the
+ *    same counters as the original, up to the renumbering, when hash_ids[v]
+ *    is node v's original id.
  */
 typedef struct {
     uint32_t n;                /* nodes, >= 1 */
@@ -63,6 +74,8 @@ typedef struct {
     const uint32_t *degrees;   /* n neighbour counts */
     const uint8_t *bytes;      /* offsets[n] bytes (may be NULL if offsets[n] = 0) */
     const uint32_t *comp_size; /* n exact component sizes N_v, or NULL = all n */
+    const uint32_t *order;     /* n: processing order, a permutation of 0..n-1, or NULL */
+    const uint32_t *hash_ids;  /* n: element inserted for node v (Alg. 1), or NULL = v */
 } hb_csr;
 
 /*

@@ -226,12 +226,16 @@ typedef struct {
 /*
  * Alg. 1 on the compressed CSR.  regs_out (n * 2^p, optional) receives the
  * registers after the last step, reach_out (n) the last estimates, sum_d_out
- * (n) the accumulated Eq. 3 sums.  depth_limit 0 means no limit.
+ * (n) the accumulated Eq. 3 sums.  depth_limit 0 means no limit.  Node v's
+ * counter starts with the element hash_ids[v] (NULL: v), as after a
+ * renumbering of the nodes that keeps hashing their original ids (the
+ * optional reordering of Sec. 3.2).
  * Returns 0, or -1 on allocation failure / malformed rows.
  */
 int or_hyperball(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
                  const uint8_t *bytes, int p, uint32_t depth_limit, uint64_t seed,
-                 uint8_t *regs_out, double *reach_out, double *sum_d_out, or_hb_info *info) {
+                 const uint32_t *hash_ids, uint8_t *regs_out, double *reach_out,
+                 double *sum_d_out, or_hb_info *info) {
     const uint64_t m = 1ull << p;
     uint8_t *cur = (uint8_t *)calloc((size_t)(n * m), 1);
     uint8_t *next = (uint8_t *)calloc((size_t)(n * m), 1);
@@ -245,7 +249,7 @@ int or_hyperball(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
         /* Insert v into its own counter. */
         for (int64_t v = 0; v < n; ++v) {
             uint32_t j, r;
-            or_hll_insert((uint64_t)v, seed, p, &j, &r);
+            or_hll_insert(hash_ids ? (uint64_t)hash_ids[v] : (uint64_t)v, seed, p, &j, &r);
             cur[v * m + j] = (uint8_t)r;
         }
         /* Initial estimates c_0. */

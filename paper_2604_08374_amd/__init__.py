@@ -43,7 +43,8 @@ class HBError(RuntimeError):
 
 class _CSR(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("offsets", u64p),
-                ("degrees", u32p), ("bytes", u8p), ("comp_size", u32p)]
+                ("degrees", u32p), ("bytes", u8p), ("comp_size", u32p), ("order", u32p),
+                ("hash_ids", u32p)]
 
 
 class _Result(ctypes.Structure):
@@ -219,7 +220,7 @@ def csr_encode(adj_offsets: np.ndarray, adj_ids: np.ndarray):
     return offsets, degrees, data[:int(blen.value)]
 
 
-def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None):
+def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None, order=None, hash_ids=None):
     offsets = np.ascontiguousarray(offsets, np.uint64)
     degrees = np.ascontiguousarray(degrees, np.uint32)
     data = np.ascontiguousarray(data, np.uint8)
@@ -233,12 +234,15 @@ def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None):
     c.offsets = _ptr(offsets, ctypes.c_uint64)
     c.degrees = _ptr(degrees, ctypes.c_uint32)
     c.bytes = _ptr(data, ctypes.c_uint8) if data.size else None
-    if comp_size is not None:
-        comp_size = np.ascontiguousarray(comp_size, np.uint32)
-        keep.append(comp_size)
-        c.comp_size = _ptr(comp_size, ctypes.c_uint32)
-    else:
-        c.comp_size = None
+    for name, arr in (("comp_size", comp_size), ("order", order), ("hash_ids", hash_ids)):
+        if arr is not None:
+            arr = np.ascontiguousarray(arr, np.uint32)
+            if arr.shape != (n,):
+                raise HBError(HB_EINVAL, f"{name} must have n entries")
+            keep.append(arr)
+            setattr(c, name, _ptr(arr, ctypes.c_uint32))
+        else:
+            setattr(c, name, None)
     return c, keep
 
 
@@ -282,8 +286,9 @@ class Result:
 class Graph:
     """A compressed CSR resident in device memory (hb_graph)."""
 
-    def __init__(self, offsets, degrees, data, comp_size=None, n_edges=None):
-        c, keep = _make_csr(offsets, degrees, data, comp_size, n_edges)
+    def __init__(self, offsets, degrees, data, comp_size=None, n_edges=None, order=None,
+                 hash_ids=None):
+        c, keep = _make_csr(offsets, degrees, data, comp_size, n_edges, order, hash_ids)
         h = ctypes.c_void_p()
         _check(_lib().hb_graph_load(ctypes.byref(c), ctypes.byref(h)))
         del keep
@@ -476,8 +481,11 @@ def release_cache() -> None:
     _check(_lib().hb_release_cache())
 
 
-def graph_load(offsets, degrees, data, comp_size=None, n_edges=None) -> Graph:
-    return Graph(offsets, degrees, data, comp_size, n_edges)
+def graph_load(offsets, degrees, data, comp_size=None, n_edges=None, order=None,
+               hash_ids=None) -> Graph:
+    """hb_graph_load.  order: processing order of the nodes (a permutation; changes no
+    result); hash_ids: element inserted for each node (its id before a renumbering)."""
+    return Graph(offsets, degrees, data, comp_size, n_edges, order, hash_ids)
 
 
 def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,

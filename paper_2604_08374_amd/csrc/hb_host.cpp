@@ -174,6 +174,8 @@ void graph_release(hb_graph *g) {
     (void)hipFree(g->d_bytes);
     (void)hipFree(g->d_offsets);
     (void)hipFree(g->d_cprev);
+    (void)hipFree(g->d_order);
+    (void)hipFree(g->d_hash_ids);
     (void)hipFree(g->d_sumd);
     (void)hipFree(g->d_flags);
     if (g->h_flag) (void)hipHostFree(g->h_flag);
@@ -343,6 +345,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
         for (uint32_t v = 0; v < csr->n; ++v)
             if (csr->comp_size[v] == 0 || csr->comp_size[v] > csr->n)
                 return fail(HB_EINVAL, "comp_size[%u] outside [1, n]", v);
+    if (csr->order) {
+        std::vector<uint8_t> seen(csr->n, 0);
+        for (uint32_t i = 0; i < csr->n; ++i) {
+            const uint32_t v = csr->order[i];
+            if (v >= csr->n || seen[v])
+                return fail(HB_EINVAL, "order is not a permutation of 0..n-1 (entry %u)", i);
+            seen[v] = 1;
+        }
+    }
     std::lock_guard<std::mutex> lk(g_dev_mu);
     if ((st = have_device()) != HB_OK) return st;
     hb_graph *g = new (std::nothrow) hb_graph;
@@ -382,6 +393,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
     if ((e = hipMemcpy(g->d_offsets, csr->offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(offsets)");
+    for (const auto &opt : {std::make_pair(csr->order, &g->d_order),
+                            std::make_pair(csr->hash_ids, &g->d_hash_ids)}) {
+        if (!opt.first) continue;
+        if ((e = hipMalloc(opt.second, sizeof(uint32_t) * g->n)) != hipSuccess)
+            return bail(e, "hipMalloc(order / hash ids)");
+        if ((e = hipMemcpy(*opt.second, opt.first, sizeof(uint32_t) * g->n,
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "hipMemcpy(order / hash ids)");
+    }
     *out = g;
     return HB_OK;
 }
@@ -481,15 +501,17 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
             // initialised again below, so the trials leave no trace
             const uint64_t t0 = now_ns();
             HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
-            HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
+            HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed,
+                                    g->d_hash_ids, s));
             if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
             TunePick pick;
             st = tune_measure((int)p, s, [&](const hbk::Sched &c) {
                 return runs ? hbk::launch_union_runs((int)p, c, g->d_bytes, g->d_offsets, cur,
                                                      levels, next, g->d_cprev, g->d_sumd,
-                                                     g->d_flags + 1, n, 1u, s)
+                                                     g->d_flags + 1, n, 1u, g->d_order, s)
                             : hbk::launch_union((int)p, c, g->d_bytes, g->d_offsets, cur, next,
-                                                g->d_cprev, g->d_sumd, g->d_flags + 1, n, 1u, s);
+                                                g->d_cprev, g->d_sumd, g->d_flags + 1, n, 1u,
+                                                g->d_order, s);
             }, &pick);
             if (st != HB_OK) return st;
             tune_put(key, pick);
@@ -500,7 +522,8 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
 
     HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
     HB_HIP(hipEventRecord(g->ev[0], s));
-    HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed, s));
+    HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed,
+                                    g->d_hash_ids, s));
     HB_HIP(hipEventRecord(g->ev[1], s));
 
     double iter_ms = 0.0, table_ms = 0.0;
@@ -512,10 +535,11 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
         HB_HIP(hipEventRecord(g->ev[3], s));
         if (runs)
             HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_bytes, g->d_offsets, cur, levels,
-                                          next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
+                                          next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t,
+                                          g->d_order, s));
         else
             HB_HIP(hbk::launch_union((int)p, sched, g->d_bytes, g->d_offsets, cur, next,
-                                     g->d_cprev, g->d_sumd, g->d_flags + t, n, t, s));
+                                     g->d_cprev, g->d_sumd, g->d_flags + t, n, t, g->d_order, s));
         HB_HIP(hipEventRecord(g->ev[4], s));
         HB_HIP(hipMemcpyAsync(g->h_flag, g->d_flags + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HB_HIP(hipStreamSynchronize(s));
@@ -725,6 +749,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         b = hbk::BatchJob{};
         b.bytes = g->d_bytes;
         b.offsets = g->d_offsets;
+        b.order = g->d_order;
+        b.hash_ids = g->d_hash_ids;
         b.seed = jobs[j].hash_seed;
         b.n = g->n;
         b.p = p;

@@ -12,6 +12,8 @@ namespace hbk {
 struct BatchJob {
     const uint8_t *bytes;     // LEB128 stream
     const uint64_t *offsets;  // n + 1 row offsets
+    const uint32_t *order;    // processing order (a permutation of 0..n-1) or null
+    const uint32_t *hash_ids; // id inserted for node v, or null for v
     uint8_t *buf[2];          // ping-pong counters (with table levels for the run kernel)
     double *c_prev;           // n estimates of the last step
     double *sum_d;            // n Eq. 3 sums
@@ -70,16 +72,19 @@ hipError_t launch_batch_step_end(BatchJob *jobs, const uint32_t *list, uint32_t 
 
 // Zero every counter, insert node v into its own counter (SplitMix64 of
 // v ^ seed), write the one-element estimate to c_prev[v] and zero sum_d[v].
+// hash_ids (n, or null): the element inserted for node v instead of v.
 hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, double *sum_d,
-                       uint32_t n, uint64_t seed, hipStream_t stream);
+                       uint32_t n, uint64_t seed, const uint32_t *hash_ids, hipStream_t stream);
 
 // One HyperBall step t: for every node v, decode its LEB128 row, take the
 // byte-wise max of cur[v] and cur[w] over its neighbours w into next[v],
 // estimate next[v], accumulate sum_d[v] += t (est - c_prev[v]), store est in
-// c_prev[v], and set *flag_t = 1 when est - c_prev[v] > 0.5.
+// c_prev[v], and set *flag_t = 1 when est - c_prev[v] > 0.5.  order (n, or
+// null): the processing order of the nodes, a permutation of 0..n-1.
 hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                         const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
-                        uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream);
+                        uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
+                        hipStream_t stream);
 
 // The same step from a range-max table of cur (level-major, level 0 = cur,
 // levels 1..levels built by launch_table): each run of consecutive neighbour
@@ -87,7 +92,7 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
-                             hipStream_t stream);
+                             const uint32_t *order, hipStream_t stream);
 
 // Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
 // i <= n - 2^k, rows of m bytes (m a multiple of 16), T[k] at tbl + k n m.

@@ -234,14 +234,16 @@ __device__ EstPart node_total(EstPart e, uint32_t slice) {
 
 // ---------------------------------------------------------------- init
 // Zero node v's counter (this wave's slice), insert v, and set c_prev[v] to the
-// estimate of the one-element counter and sum_d[v] to 0.
+// estimate of the one-element counter and sum_d[v] to 0.  The inserted element
+// is hash_ids[v] when given (the node's id before a relabelling), else v.
 template <class C>
 __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__restrict__ c_prev,
                                           double *__restrict__ sum_d, uint32_t v, uint32_t slice,
-                                          uint64_t seed) {
+                                          uint64_t seed, const uint32_t *__restrict__ hash_ids) {
     constexpr int P = C::PREC;
     const uint32_t lane = lane_id();
-    const uint64_t h = splitmix64((uint64_t)v ^ seed);
+    const uint32_t id = hash_ids ? hash_ids[v] : v;
+    const uint64_t h = splitmix64((uint64_t)id ^ seed);
     const uint32_t j = (uint32_t)(h >> (64 - P));
     const uint64_t rest = h << P;
     const uint32_t r = rest ? (uint32_t)__builtin_clzll(rest) + 1u : (uint32_t)(65 - P);
@@ -282,11 +284,12 @@ template <class C>
 __global__ __launch_bounds__(C::THREADS) void init_kernel(uint8_t *__restrict__ cur,
                                                           double *__restrict__ c_prev,
                                                           double *__restrict__ sum_d, uint32_t n,
-                                                          uint64_t seed) {
+                                                          uint64_t seed,
+                                                          const uint32_t *__restrict__ hash_ids) {
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
-    init_node<C>(cur, c_prev, sum_d, v, slice, seed);
+    init_node<C>(cur, c_prev, sum_d, v, slice, seed, hash_ids);
 }
 
 // ---------------------------------------------------------------- row decoding
@@ -491,10 +494,12 @@ template <class C>
 __global__ __launch_bounds__(C::THREADS) void union_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
-    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t) {
+    double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t,
+    const uint32_t *__restrict__ order) {
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    if (order) v = order[v];
     union_node_edges<C>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t);
 }
 
@@ -721,16 +726,22 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
 // without spills match four with them (117.4 against 118.0 ms).
 // With several waves per node every wave decodes the row and queues the same
 // table rows, then gathers its own slice of each.
+//
+// order (optional) is the processing order: logical node i is node order[i].
+// Nodes that are processed together (one XCD walks a contiguous stretch of the
+// order) gather overlapping table rows, so an order along a space-filling
+// curve over the raster raises cache reuse; the results do not depend on it.
 template <class C>
 __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
-    uint32_t n, uint32_t t) {
+    uint32_t n, uint32_t t, const uint32_t *__restrict__ order) {
     __shared__ uint32_t s_queue[C::THREADS / kWave][kQueueCap];
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
+    if (order) v = order[v];
     union_node_runs<C>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
                        s_queue[threadIdx.x / kWave]);
 }
@@ -789,7 +800,7 @@ __global__ __launch_bounds__(C::THREADS) void batch_init_kernel(
     uint32_t v, slice;
     node_of<C>(job_block(blockIdx.x, block_base, i), v, slice);
     if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
-    init_node<C>(J.buf[0], J.c_prev, J.sum_d, v, slice, J.seed);
+    init_node<C>(J.buf[0], J.c_prev, J.sum_d, v, slice, J.seed, J.hash_ids);
 }
 
 template <class C, bool RUNS>
@@ -804,6 +815,7 @@ __global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union
     uint32_t v, slice;
     node_of<C>(job_block(blockIdx.x, block_base, i), v, slice);
     if (v >= J.n) return;  // uniform per workgroup when WAVES > 1
+    if (J.order) v = J.order[v];
     const uint8_t *cur = J.buf[(t - 1u) & 1u];
     uint8_t *next = J.buf[t & 1u];
     if constexpr (RUNS) {
@@ -902,35 +914,36 @@ void grid_for(uint32_t n, uint32_t nb, uint32_t &blocks, uint32_t &threads) {
 
 template <class C>
 hipError_t launch_init_c(uint8_t *cur, double *c_prev, double *sum_d, uint32_t n, uint64_t seed,
-                         uint32_t nb, hipStream_t stream) {
+                         const uint32_t *hash_ids, uint32_t nb, hipStream_t stream) {
     uint32_t blocks, threads;
     grid_for<C>(n, nb, blocks, threads);
     hipLaunchKernelGGL((init_kernel<C>), dim3(blocks), dim3(threads), 0, stream, cur, c_prev,
-                       sum_d, n, seed);
+                       sum_d, n, seed, hash_ids);
     return hipGetLastError();
 }
 
 template <class C>
 hipError_t launch_union_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
                           uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
-                          uint32_t n, uint32_t t, uint32_t nb, hipStream_t stream) {
+                          uint32_t n, uint32_t t, const uint32_t *order, uint32_t nb,
+                          hipStream_t stream) {
     uint32_t blocks, threads;
     grid_for<C>(n, nb, blocks, threads);
     hipLaunchKernelGGL((union_kernel<C>), dim3(blocks), dim3(threads), 0, stream, bytes, offsets,
-                       cur, next, c_prev, sum_d, flag_t, n, t);
+                       cur, next, c_prev, sum_d, flag_t, n, t, order);
     return hipGetLastError();
 }
 
 template <class C>
 hipError_t launch_union_runs_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *tbl,
                                uint32_t levels, uint8_t *next, double *c_prev, double *sum_d,
-                               uint32_t *flag_t, uint32_t n, uint32_t t, uint32_t nb,
-                               hipStream_t stream) {
+                               uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
+                               uint32_t nb, hipStream_t stream) {
     if constexpr (C::PREC <= kRunsMaxP) {
         uint32_t blocks, threads;
         grid_for<C>(n, nb, blocks, threads);
         hipLaunchKernelGGL((union_runs_kernel<C>), dim3(blocks), dim3(threads), 0, stream,
-                           bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t);
+                           bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t, order);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -1015,20 +1028,22 @@ LaunchShape shape_for(int p, const Sched &s) {
     } while (0)
 
 hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, double *sum_d,
-                       uint32_t n, uint64_t seed, hipStream_t stream) {
-#define HB_X(P, L) \
-    if (p == P && s.lanes == L) return launch_init_c<Cfg<P, L>>(cur, c_prev, sum_d, n, seed, nb, stream);
+                       uint32_t n, uint64_t seed, const uint32_t *hash_ids, hipStream_t stream) {
+#define HB_X(P, L)                                                                          \
+    if (p == P && s.lanes == L)                                                             \
+        return launch_init_c<Cfg<P, L>>(cur, c_prev, sum_d, n, seed, hash_ids, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
 
 hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                         const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
-                        uint32_t *flag_t, uint32_t n, uint32_t t, hipStream_t stream) {
+                        uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
+                        hipStream_t stream) {
 #define HB_X(P, L)                                                                            \
     if (p == P && s.lanes == L)                                                               \
         return launch_union_c<Cfg<P, L>>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, \
-                                         t, nb, stream);
+                                         t, order, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
@@ -1036,11 +1051,11 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
-                             hipStream_t stream) {
+                             const uint32_t *order, hipStream_t stream) {
 #define HB_X(P, L)                                                                          \
     if (p == P && s.lanes == L)                                                             \
         return launch_union_runs_c<Cfg<P, L>>(bytes, offsets, tbl, levels, next, c_prev,    \
-                                              sum_d, flag_t, n, t, nb, stream);
+                                              sum_d, flag_t, n, t, order, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }

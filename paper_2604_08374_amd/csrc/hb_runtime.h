@@ -86,6 +86,8 @@ struct hb_graph {
     std::vector<uint32_t> comp_size;  // empty: one component of n
     uint8_t *d_bytes = nullptr;
     uint64_t *d_offsets = nullptr;
+    uint32_t *d_order = nullptr;     // processing order, or null
+    uint32_t *d_hash_ids = nullptr;  // inserted ids, or null
     // run state, kept between runs (the counters live in a per-device workspace)
     double *d_cprev = nullptr, *d_sumd = nullptr;
     uint32_t *d_flags = nullptr;

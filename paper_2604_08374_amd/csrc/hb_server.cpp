@@ -405,6 +405,8 @@ hb_status Server::step(Lane &L) {
         b = hbk::BatchJob{};
         b.bytes = g->d_bytes;
         b.offsets = g->d_offsets;
+        b.order = g->d_order;
+        b.hash_ids = g->d_hash_ids;
         b.buf[0] = base + r->off;
         b.buf[1] = base + r->off + bb;
         b.c_prev = reinterpret_cast<double *>(base + r->off + 2 * bb);

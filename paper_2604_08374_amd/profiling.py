@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--title", default="union kernel")
     ap.add_argument("--out", required=True)
     ap.add_argument("--counters", default=None)
+    ap.add_argument("--node-order", default="raster",
+                    help="processing order of the profiled run (recorded with the counters)")
     args = ap.parse_args()
 
     stats = kernel_stats(args.trace)
@@ -163,6 +165,7 @@ def main():
         f.write("\n".join(lines))
     with open(args.counters, "w") as f:
         f.write(f"kernel {k}\n")
+        f.write(f"node_order {args.node_order}\n")
         f.write(f"kernel_source_sha256 {sha}\n")
         f.write(f"avg_launch_ns {avg_ns:.0f}\n")
         f.write(f"fetch_kib_per_launch {fetch_kib:.3f}\n")

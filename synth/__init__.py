@@ -361,6 +361,63 @@ def serve_graph(seed: int, n_lo: int = 1000, n_hi: int = 120000, device: str = "
 
 
 # ---------------------------------------------------------------- special graphs
+# ---------------------------------------------------------------- locality orders
+def hilbert_index(x: np.ndarray, y: np.ndarray, bits: int) -> np.ndarray:
+    """Position of cell (x, y) along a Hilbert curve over a 2^bits x 2^bits grid.
+
+    The curve is built by quadrant recursion: at each scale s (from the largest),
+    the quadrant (rx, ry) adds s^2 (3 rx XOR ry), and the remaining coordinates are
+    reflected and transposed so that the sub-curve in that quadrant joins its
+    neighbours end to end.  Consecutive positions are 4-adjacent cells.
+    """
+    x = np.asarray(x, np.int64).copy()
+    y = np.asarray(y, np.int64).copy()
+    d = np.zeros_like(x)
+    s = 1 << (bits - 1)
+    while s > 0:
+        rx = (x & s) > 0
+        ry = (y & s) > 0
+        d += s * s * ((3 * rx.astype(np.int64)) ^ ry.astype(np.int64))
+        low = ~ry
+        flip = low & rx
+        x[flip] = s - 1 - x[flip]
+        y[flip] = s - 1 - y[flip]
+        x[low], y[low] = y[low].copy(), x[low].copy()
+        s >>= 1
+    return d
+
+
+def hilbert_order(g: "Graph") -> np.ndarray:
+    """Node ids sorted along a Hilbert curve over the raster (a processing order)."""
+    side = max(int(g.xy[:, 0].max(initial=0)), int(g.xy[:, 1].max(initial=0))) + 1
+    bits = max(1, int(np.ceil(np.log2(side))))
+    d = hilbert_index(g.xy[:, 0], g.xy[:, 1], bits)
+    return np.argsort(d, kind="stable").astype(np.uint32)
+
+
+def relabel(g: "Graph", order: np.ndarray) -> tuple:
+    """Renumber the nodes so that new node i is old node order[i].
+
+    Returns (graph, original_ids): the CSR is rebuilt in the new numbering (each
+    row re-sorted), and original_ids[i] = order[i] is what node i inserts into its
+    counter so that the results match the original numbering.
+    """
+    order = np.asarray(order, np.int64)
+    new_of = np.empty(g.n, np.int64)
+    new_of[order] = np.arange(g.n)
+    deg = g.degrees[order].astype(np.uint64)
+    off = np.zeros(g.n + 1, np.uint64)
+    off[1:] = np.cumsum(deg)
+    ids = np.empty(int(off[-1]), np.uint32)
+    for i, v in enumerate(order):
+        row = new_of[g.row(int(v))]
+        row.sort()
+        ids[int(off[i]):int(off[i + 1])] = row
+    h = Graph(n=g.n, adj_offsets=off, adj_ids=ids, obst=g.obst, xy=g.xy[order].copy(),
+              name=g.name + "-relabelled", params=dict(g.params, relabelled=True))
+    return h, order.astype(np.uint32)
+
+
 def from_edges(n: int, edges, name: str = "") -> Graph:
     """Undirected graph from an edge list (for closed-form cases: paths, stars, cliques)."""
     nbrs = [set() for _ in range(n)]

@@ -326,3 +326,55 @@ def test_hll_distance_sums_within_error_bound():
             reach_err.append(r.reach[0] / g.n - 1)
         assert math.sqrt(np.mean(np.square(reach_err))) < 1.5 * se
         assert np.mean(med) < 2.5 * se
+
+
+# ------------------------------------------------------------------ reordering (Sec. 3.2)
+def test_relabelled_graph_with_original_hash_ids_permutes_the_results():
+    """Renumbering the nodes and hashing their original ids permutes every output.
+
+    Node i of the renumbered graph is node perm[i] of the original; its ball is the
+    image of the original ball, so with the original ids inserted its registers,
+    estimates and sums must be those of perm[i], bit for bit.  Hashing the new ids
+    instead must not give them at a depth limit (so the hash_ids input is really
+    used).
+    """
+    g = synth.tiny(2)
+    perm = np.random.default_rng(3).permutation(g.n).astype(np.uint32)
+    h, orig = synth.relabel(g, perm)
+    assert np.array_equal(orig, perm)
+    for p, depth in ((8, 0), (10, 2)):
+        a = oracle.hyperball(oracle.from_graph(g), p, depth, 5)
+        b = oracle.hyperball(oracle.from_graph(h), p, depth, 5, hash_ids=orig)
+        assert (a.passes, a.converged) == (b.passes, b.converged)
+        assert np.array_equal(b.registers, a.registers[perm])
+        assert np.array_equal(b.reach, a.reach[perm])
+        assert np.array_equal(b.sum_d, a.sum_d[perm])
+        if depth:  # a converged run's balls are the whole component under any numbering
+            c = oracle.hyperball(oracle.from_graph(h), p, depth, 5)
+            assert not np.array_equal(c.registers, a.registers[perm])
+
+
+def test_identity_hash_ids_change_nothing():
+    g = synth.tiny(4)
+    a = oracle.hyperball(oracle.from_graph(g), 9, 0, 1)
+    b = oracle.hyperball(oracle.from_graph(g), 9, 0, 1, hash_ids=np.arange(g.n, dtype=np.uint32))
+    assert np.array_equal(a.registers, b.registers) and np.array_equal(a.sum_d, b.sum_d)
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 5])
+def test_hilbert_index_is_a_curve_of_adjacent_cells(bits):
+    """A bijection of the 2^bits x 2^bits grid onto 0..4^bits-1 whose steps are unit moves."""
+    side = 1 << bits
+    x, y = np.meshgrid(np.arange(side), np.arange(side))
+    d = synth.hilbert_index(x.ravel(), y.ravel(), bits)
+    assert np.array_equal(np.sort(d), np.arange(side * side))
+    order = np.argsort(d)
+    steps = np.abs(np.diff(x.ravel()[order])) + np.abs(np.diff(y.ravel()[order]))
+    assert np.all(steps == 1)
+    assert d[0] == 0  # the curve starts at the origin
+
+
+def test_hilbert_order_is_a_permutation():
+    g = synth.grid_graph(3, 40, 30)
+    o = synth.hilbert_order(g)
+    assert np.array_equal(np.sort(o), np.arange(g.n))
