@@ -80,7 +80,8 @@ typedef struct {
 
 /*
  * Results of one run.  Array pointers are caller-owned host buffers of n
- * doubles (n * 2^p bytes for registers), or NULL to skip that output.
+ * doubles (n * 2^p bytes for registers, n * 2^(p-1) with 4-bit registers),
+ * or NULL to skip that output.
  * reach[v] is the final estimate of |B(v, T)|, sum_d[v] the Eq. 3 sum and
  * mean_depth[v] = sum_d[v] / (N_v - 1) (NaN when N_v < 2), as Sec. 3.3
  * defines Visual Mean Depth with the exact component size.
@@ -106,6 +107,7 @@ typedef struct {
     uint32_t lanes_per_node;  /* union schedule that ran (see hb_run_opts); for a batch,
                                  that of the job's (p, kernel) class */
     uint32_t nodes_per_block;
+    uint32_t register_bits;   /* register width of the run: 8 or 4 */
     double tune_ms;        /* host time spent measuring schedules in this call (0 if none) */
     uint64_t t_submit_ns;  /* host CLOCK_MONOTONIC: hb_submit accepted it (else = t_start_ns) */
     uint64_t t_admit_ns;   /* device memory granted, joined the running steps (else = t_start_ns) */
@@ -132,7 +134,19 @@ typedef struct {
     uint32_t tune;            /* HB_TUNE_*: how the union schedule is chosen */
     uint32_t lanes_per_node;  /* 0 = by `tune`; else this schedule (HB_EINVAL if not built) */
     uint32_t nodes_per_block; /* with lanes_per_node: 1, 2 or 4 (0 = 4; must be 1 above 64 lanes) */
+    uint32_t register_bits;   /* 8 (0 = default) or 4: the paper's packed format, below */
 } hb_run_opts;
+
+/*
+ * Register width.  With register_bits = 8 every HLL register is a byte.  With
+ * 4 (Sec. 3.4: two registers per byte) register j of a counter is the low
+ * nibble of byte j/2 for even j and the high nibble for odd j, and a register
+ * saturates at 15: a rank above 15 is stored as 15.  Since the register-wise
+ * max commutes with that clamp, the 4-bit registers after any step are
+ * exactly min(8-bit registers, 15); the estimator is the same formula over
+ * them.  Counters take 2^(p-1) bytes instead of 2^p; p >= 5.  Registers
+ * returned in hb_result are in the width of the run.
+ */
 
 /*
  * Union schedules.  A schedule is (lanes_per_node, nodes_per_block):
@@ -144,8 +158,10 @@ typedef struct {
  *  - nodes_per_block: nodes per workgroup (1, 2 or 4) for one-wave shapes.
  * Built lanes per p (the default first): p 4-7: 2^p / 16; p 8: 16, 8;
  * p 9: 32, 16; p 10: 64, 32, 16; p 11: 64, 128, 32; p 12: 64, 128, 256;
- * p 13: 128, 256; p 14: 256, 512; p 15: 512; p 16: 1024.  Every schedule
- * gives identical registers and estimates; only the speed differs.
+ * p 13: 128, 256; p 14: 256, 512; p 15: 512; p 16: 1024.  With 4-bit
+ * registers one shape per p: p 5-11: 2^p / 32; p 12, 13: 64; p 14-16:
+ * 2^p / 128.  Every schedule gives identical registers and estimates; only
+ * the speed differs.
  *
  * The autotuner times one union step of every schedule built for p on the
  * caller's own data (two launches each, the faster counts), keeps the
@@ -159,7 +175,7 @@ typedef struct {
 
 /* One autotuner cache entry. */
 typedef struct {
-    uint32_t p, union_kernel, batched;    /* shape class ... */
+    uint32_t p, register_bits, union_kernel, batched; /* shape class ... */
     uint32_t log2_nodes, log2_rows_per_node;
     uint32_t lanes_per_node, nodes_per_block; /* ... and its pick */
     double best_ms;                       /* measured union step of the pick */
@@ -309,6 +325,7 @@ typedef struct {
 } hb_server_stats_t;
 
 #define HB_SUBMIT_REGISTERS 1u /* keep the final registers for hb_poll */
+#define HB_SUBMIT_REG4 2u      /* 4-bit registers (see hb_run_opts.register_bits); p >= 5 */
 
 /* Start the request loop (HB_EBUSY if it runs).  opts may be NULL. */
 hb_status hb_server_start(const hb_server_opts *opts);

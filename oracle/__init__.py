@@ -76,7 +76,8 @@ def _lib():
         L.or_hll_raw.restype = ctypes.c_double
         L.or_hll_estimate.argtypes = [u8p, ctypes.c_int]
         L.or_hll_estimate.restype = ctypes.c_double
-        L.or_hyperball.argtypes = [i64, u64p, u32p, u8p, ctypes.c_int, u32, u64, u32p, u8p, dp, dp,
+        L.or_hyperball.argtypes = [i64, u64p, u32p, u8p, ctypes.c_int, u32, u64, u32p, ctypes.c_int,
+                                   u8p, dp, dp,
                                    ctypes.POINTER(_Info)]
         L.or_hyperball.restype = ctypes.c_int
         L.or_hyperball_exact.argtypes = [i64, u64p, u32p, u8p, u32, dp, dp, ctypes.POINTER(_Info)]
@@ -227,11 +228,14 @@ class HBResult:
 
 
 def hyperball(csr: CSR, p: int, depth_limit: int = 0, seed: int = 0,
-              registers: bool = True, hash_ids=None) -> HBResult:
+              registers: bool = True, hash_ids=None, register_bits: int = 8) -> HBResult:
     """Alg. 1 (Eq. 2 union, HLL estimate, Eq. 3 accumulation, 0.5 stopping rule).
 
     hash_ids (n, optional): the element inserted for node v instead of v.
+    register_bits: 8, or 4 for registers that saturate at 15 (returned one per byte).
     """
+    if register_bits not in (8, 4):
+        raise ValueError("register_bits must be 8 or 4")
     n, m = csr.n, 1 << p
     hid = None if hash_ids is None else np.ascontiguousarray(hash_ids, np.uint32)
     if hid is not None and hid.shape != (n,):
@@ -242,7 +246,7 @@ def hyperball(csr: CSR, p: int, depth_limit: int = 0, seed: int = 0,
     info = _Info()
     rc = _lib().or_hyperball(n, _u64(csr.offsets), _u32(csr.degrees), _bytes_ptr(csr), p,
                              depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
-                             _u32(hid) if hid is not None else None,
+                             _u32(hid) if hid is not None else None, register_bits,
                              _u8(regs) if registers else None,
                              _p(reach, ctypes.c_double), _p(sum_d, ctypes.c_double),
                              ctypes.byref(info))

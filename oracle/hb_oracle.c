@@ -229,12 +229,15 @@ typedef struct {
  * (n) the accumulated Eq. 3 sums.  depth_limit 0 means no limit.  Node v's
  * counter starts with the element hash_ids[v] (NULL: v), as after a
  * renumbering of the nodes that keeps hashing their original ids (the
- * optional reordering of Sec. 3.2).
+ * optional reordering of Sec. 3.2).  reg_bits is 8 or 4: 4-bit registers
+ * (the paper's packed format, Sec. 3.4) hold at most 15, so an inserted rank
+ * above 15 is stored as 15; every later value is a max of inserted values
+ * and stays below 16 by itself.  Registers are returned one per byte.
  * Returns 0, or -1 on allocation failure / malformed rows.
  */
 int or_hyperball(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
                  const uint8_t *bytes, int p, uint32_t depth_limit, uint64_t seed,
-                 const uint32_t *hash_ids, uint8_t *regs_out, double *reach_out,
+                 const uint32_t *hash_ids, int reg_bits, uint8_t *regs_out, double *reach_out,
                  double *sum_d_out, or_hb_info *info) {
     const uint64_t m = 1ull << p;
     uint8_t *cur = (uint8_t *)calloc((size_t)(n * m), 1);
@@ -250,6 +253,7 @@ int or_hyperball(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
         for (int64_t v = 0; v < n; ++v) {
             uint32_t j, r;
             or_hll_insert(hash_ids ? (uint64_t)hash_ids[v] : (uint64_t)v, seed, p, &j, &r);
+            if (reg_bits == 4 && r > 15) r = 15;
             cur[v * m + j] = (uint8_t)r;
         }
         /* Initial estimates c_0. */

@@ -17,7 +17,7 @@ import numpy as np
 __all__ = [
     "HBError", "Result", "Graph", "lib_path", "version", "device_count", "csr_encode",
     "csr_validate", "graph_load", "run", "run_batch", "release_cache", "tune_cache", "tune_clear",
-    "copy_probe", "server_start", "server_stop",
+    "copy_probe", "server_start", "server_stop", "unpack_nibbles",
     "server_stats", "submit", "Ticket", "HB_OK", "HB_PENDING", "HB_EINVAL", "HB_ECORRUPT",
     "HB_ENOMEM", "HB_EDEVICE", "HB_ENOTFOUND", "HB_EBUSY",
 ]
@@ -56,7 +56,7 @@ class _Result(ctypes.Structure):
                 ("table_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
                 ("lanes_per_node", ctypes.c_uint32), ("nodes_per_block", ctypes.c_uint32),
-                ("tune_ms", ctypes.c_double),
+                ("register_bits", ctypes.c_uint32), ("tune_ms", ctypes.c_double),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_start_ns", ctypes.c_uint64), ("t_end_ns", ctypes.c_uint64)]
 
@@ -83,12 +83,12 @@ class _Stats(ctypes.Structure):
 class _RunOpts(ctypes.Structure):
     _fields_ = [("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
                 ("tune", ctypes.c_uint32), ("lanes_per_node", ctypes.c_uint32),
-                ("nodes_per_block", ctypes.c_uint32)]
+                ("nodes_per_block", ctypes.c_uint32), ("register_bits", ctypes.c_uint32)]
 
 
 class _TuneEntry(ctypes.Structure):
-    _fields_ = [("p", ctypes.c_uint32), ("union_kernel", ctypes.c_uint32),
-                ("batched", ctypes.c_uint32), ("log2_nodes", ctypes.c_uint32),
+    _fields_ = [("p", ctypes.c_uint32), ("register_bits", ctypes.c_uint32),
+                ("union_kernel", ctypes.c_uint32), ("batched", ctypes.c_uint32), ("log2_nodes", ctypes.c_uint32),
                 ("log2_rows_per_node", ctypes.c_uint32), ("lanes_per_node", ctypes.c_uint32),
                 ("nodes_per_block", ctypes.c_uint32), ("best_ms", ctypes.c_double),
                 ("default_ms", ctypes.c_double)]
@@ -99,8 +99,18 @@ _TUNE = {"cached": TUNE_CACHED, "measure": TUNE_MEASURE, "off": TUNE_OFF}
 
 
 def _run_opts(kernel: str, table_levels: int, tune: str, lanes_per_node: int,
-              nodes_per_block: int) -> _RunOpts:
-    return _RunOpts(_KERNELS[kernel], table_levels, _TUNE[tune], lanes_per_node, nodes_per_block)
+              nodes_per_block: int, register_bits: int = 8) -> _RunOpts:
+    return _RunOpts(_KERNELS[kernel], table_levels, _TUNE[tune], lanes_per_node, nodes_per_block,
+                    register_bits)
+
+
+def unpack_nibbles(regs: np.ndarray) -> np.ndarray:
+    """4-bit registers (n, 2^(p-1) bytes) -> one register per byte (n, 2^p): register
+    2k is the low nibble of byte k, register 2k + 1 the high nibble."""
+    out = np.empty((regs.shape[0], regs.shape[1] * 2), np.uint8)
+    out[:, 0::2] = regs & 0x0F
+    out[:, 1::2] = regs >> 4
+    return out
 
 
 class _Job(ctypes.Structure):
@@ -276,6 +286,7 @@ class Result:
     table_levels: int
     lanes_per_node: int
     nodes_per_block: int
+    register_bits: int
     tune_ms: float
     t_submit_ns: int
     t_admit_ns: int
@@ -321,12 +332,14 @@ class Graph:
     def __exit__(self, *exc):
         self.free()
 
-    def _out_arrays(self, p: int, registers: bool, outputs: bool):
+    def _out_arrays(self, p: int, registers: bool, outputs: bool, register_bits: int = 8):
         n = self.n
         reach = np.empty(n, np.float64) if outputs else None
         sum_d = np.empty(n, np.float64) if outputs else None
         md = np.empty(n, np.float64) if outputs else None
-        regs = np.empty((n, 1 << p), np.uint8) if (registers and P_MIN <= p <= P_MAX) else None
+        width = (1 << p) * register_bits // 8 if register_bits in (4, 8) else 0
+        regs = np.empty((n, width), np.uint8) if (registers and P_MIN <= p <= P_MAX and width) \
+            else None
         r = _Result()
         r.reach = _ptr(reach, ctypes.c_double)
         r.sum_d = _ptr(sum_d, ctypes.c_double)
@@ -336,7 +349,8 @@ class Graph:
 
     def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
             outputs: bool = True, kernel: str = "auto", table_levels: int = 0,
-            tune: str = "cached", lanes_per_node: int = 0, nodes_per_block: int = 0) -> Result:
+            tune: str = "cached", lanes_per_node: int = 0, nodes_per_block: int = 0,
+            register_bits: int = 8) -> Result:
         """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
 
         kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
@@ -346,8 +360,8 @@ class Graph:
         """
         if self._h is None:
             raise HBError(HB_EINVAL, "graph was freed")
-        r, arrays = self._out_arrays(p, registers, outputs)
-        o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block)
+        r, arrays = self._out_arrays(p, registers, outputs, register_bits)
+        o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block, register_bits)
         _check(_lib().hb_run_with(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
                                   ctypes.byref(o), ctypes.byref(r)))
         return _to_result(r, arrays)
@@ -367,13 +381,14 @@ def _to_result(r: _Result, arrays) -> Result:
                   int(r.productive_iters), float(r.c0),
                   int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),
                   float(r.run_ms), name, int(r.table_levels), int(r.lanes_per_node),
-                  int(r.nodes_per_block), float(r.tune_ms), int(r.t_submit_ns),
+                  int(r.nodes_per_block), int(r.register_bits), float(r.tune_ms),
+                  int(r.t_submit_ns),
                   int(r.t_admit_ns), int(r.t_start_ns), int(r.t_end_ns))
 
 
 def run_batch(jobs, registers: bool = False, outputs: bool = True, kernel: str = "auto",
               table_levels: int = 0, tune: str = "cached", lanes_per_node: int = 0,
-              nodes_per_block: int = 0):
+              nodes_per_block: int = 0, register_bits: int = 8):
     """hb_run_batch: jobs is a list of (Graph, p, depth_limit, seed); returns Results in order."""
     n = len(jobs)
     cj = (_Job * n)()
@@ -386,15 +401,16 @@ def run_batch(jobs, registers: bool = False, outputs: bool = True, kernel: str =
         cj[i].p = p
         cj[i].depth_limit = depth
         cj[i].hash_seed = seed & 0xFFFFFFFFFFFFFFFF
-        r, arrays = g._out_arrays(p, registers, outputs)
+        r, arrays = g._out_arrays(p, registers, outputs, register_bits)
         outs[i] = r
         keep.append(arrays)
-    o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block)
+    o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block, register_bits)
     _check(_lib().hb_run_batch(cj, n, ctypes.byref(o), outs))
     return [_to_result(outs[i], keep[i]) for i in range(n)]
 
 
 SUBMIT_REGISTERS = 1
+SUBMIT_REG4 = 2
 _SERVER_STARTED = False
 
 
@@ -423,11 +439,13 @@ def server_stats() -> dict:
 class Ticket:
     """A submitted request: poll() returns None while pending, then the Result once."""
 
-    def __init__(self, graph: "Graph", p: int, registers: bool, ticket: int):
+    def __init__(self, graph: "Graph", p: int, registers: bool, ticket: int,
+                 register_bits: int = 8):
         self.graph, self.p, self.registers, self.id = graph, p, registers, ticket
+        self.register_bits = register_bits
 
     def _collect(self, fn) -> "Result | None":
-        r, arrays = self.graph._out_arrays(self.p, self.registers, True)
+        r, arrays = self.graph._out_arrays(self.p, self.registers, True, self.register_bits)
         st = fn(self.id, ctypes.byref(r))
         if st == HB_PENDING:
             return None
@@ -442,14 +460,15 @@ class Ticket:
 
 
 def submit(g: "Graph", p: int, depth_limit: int = 0, seed: int = 0,
-           registers: bool = False) -> Ticket:
+           registers: bool = False, register_bits: int = 8) -> Ticket:
     """hb_submit: queue one analysis; returns a Ticket."""
     global _SERVER_STARTED
     t = ctypes.c_uint64(0)
-    _check(_lib().hb_submit(g._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
-                            SUBMIT_REGISTERS if registers else 0, ctypes.byref(t)))
+    flags = (SUBMIT_REGISTERS if registers else 0) | (SUBMIT_REG4 if register_bits == 4 else 0)
+    _check(_lib().hb_submit(g._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF, flags,
+                            ctypes.byref(t)))
     _SERVER_STARTED = True
-    return Ticket(g, p, registers, int(t.value))
+    return Ticket(g, p, registers, int(t.value), register_bits)
 
 
 @atexit.register

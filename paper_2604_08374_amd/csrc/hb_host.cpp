@@ -244,13 +244,16 @@ hb_status validate_impl(const hb_csr *csr, uint32_t *bad_node, RunCounts *rc_out
 // The schedule named in the options for precision p, or lanes = 0 when the
 // options leave it to the tuner.
 hb_status explicit_sched(const hb_run_opts &o, uint32_t p, hbk::Sched *out) {
-    *out = hbk::Sched{0u, 0u};
+    const uint32_t bits = o.register_bits ? o.register_bits : 8u;
+    *out = hbk::Sched{0u, 0u, bits};
     if (o.tune > HB_TUNE_OFF) return fail(HB_EINVAL, "unknown tune mode %u", o.tune);
+    if (bits != 8u && bits != 4u) return fail(HB_EINVAL, "register_bits %u is not 8 or 4", bits);
+    if (bits == 4u && p < 5) return fail(HB_EINVAL, "4-bit registers need p >= 5");
     if (o.lanes_per_node == 0) {
         if (o.nodes_per_block) return fail(HB_EINVAL, "nodes_per_block needs lanes_per_node");
         return HB_OK;
     }
-    hbk::Sched s{o.lanes_per_node, o.nodes_per_block};
+    hbk::Sched s{o.lanes_per_node, o.nodes_per_block, bits};
     if (!s.nodes_per_block) s.nodes_per_block = s.lanes > 64u ? 1u : 4u;
     if (!hbk::sched_ok((int)p, s))
         return fail(HB_EINVAL, "no union schedule of %u lanes, %u nodes per workgroup for p = %u",
@@ -452,10 +455,11 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     hbk::Sched fixed{};
     hb_status st = explicit_sched(o, p, &fixed);
     if (st != HB_OK) return st;
+    const uint32_t bits = fixed.bits;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     HB_HIP(hipSetDevice(g->device));
     const uint32_t n = g->n;
-    const uint64_t m = 1ull << p;
+    const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
 
     // kernel choice and table depth
     uint32_t levels = o.table_levels ? o.table_levels : 7u;
@@ -486,12 +490,13 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     }
     hipStream_t s = g->stream;
     uint8_t *cur = ws.buf[0], *next = ws.buf[1];
-    const hbk::Sched init_sched = hbk::default_sched((int)p);
+    const hbk::Sched init_sched = hbk::default_sched((int)p, bits);
 
     // ---- union schedule: explicit, cached, measured here, or the default
     hbk::Sched sched = init_sched;
     double tune_ms = 0.0;
-    const TuneKey key = tune_key(p, runs, false, n, runs ? g->runs.lookups[levels] : g->n_edges);
+    const TuneKey key =
+        tune_key(p, bits, runs, false, n, runs ? g->runs.lookups[levels] : g->n_edges);
     if (fixed.lanes) {
         sched = fixed;
     } else if (o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
@@ -503,9 +508,9 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
             HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
             HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed,
                                     g->d_hash_ids, s));
-            if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
+            if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
             TunePick pick;
-            st = tune_measure((int)p, s, [&](const hbk::Sched &c) {
+            st = tune_measure((int)p, bits, s, [&](const hbk::Sched &c) {
                 return runs ? hbk::launch_union_runs((int)p, c, g->d_bytes, g->d_offsets, cur,
                                                      levels, next, g->d_cprev, g->d_sumd,
                                                      g->d_flags + 1, n, 1u, g->d_order, s)
@@ -531,7 +536,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     for (;;) {
         ++t;
         HB_HIP(hipEventRecord(g->ev[2], s));
-        if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, s));
+        if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
         HB_HIP(hipEventRecord(g->ev[3], s));
         if (runs)
             HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_bytes, g->d_offsets, cur, levels,
@@ -578,7 +583,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     }
     if (out->registers)
         HB_HIP(hipMemcpy(out->registers, next, (uint64_t)n * m, hipMemcpyDeviceToHost));
-    const double md = (double)m;
+    const double md = (double)(1ull << p);
     out->passes = t;
     out->converged = converged;
     out->productive_iters = converged ? t - 1u : t;
@@ -592,6 +597,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     out->table_levels = runs ? levels : 0u;
     out->lanes_per_node = sched.lanes;
     out->nodes_per_block = sched.nodes_per_block;
+    out->register_bits = bits;
     out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;
     out->t_admit_ns = t_start;
@@ -725,6 +731,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         if (jobs[j].g->device != jobs[0].g->device)
             return fail(HB_EINVAL, "all graphs of a batch must live on one device");
     }
+    const uint32_t bits = o.register_bits ? o.register_bits : 8u;  // checked per job above
     std::lock_guard<std::mutex> lk(g_dev_mu);
     HB_HIP(hipSetDevice(jobs[0].g->device));
 
@@ -736,7 +743,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     for (uint32_t j = 0; j < n_jobs; ++j) {
         const hb_graph *g = jobs[j].g;
         const uint32_t p = jobs[j].p;
-        const uint64_t m = 1ull << p;
+        const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
         uint32_t levels = std::min(o.table_levels ? o.table_levels : 7u, floor_log2(g->n));
         bool runs = o.union_kernel == HB_UNION_RUNS || (o.union_kernel == HB_UNION_AUTO && p <= 12);
         if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
@@ -758,6 +765,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         b.levels = levels;
         b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
         b.runs = runs ? 1u : 0u;
+        b.bits = bits;
         off_buf[j] = arena;
         arena += 2 * align256((uint64_t)g->n * m * (levels + 1u));
         off_state[j] = arena;
@@ -784,7 +792,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     uint8_t *base = static_cast<uint8_t *>(R.arena);
     uint32_t *d_flags = reinterpret_cast<uint32_t *>(base + flags_at);
     for (uint32_t j = 0; j < n_jobs; ++j) {
-        const uint64_t m = 1ull << jobs[j].p;
+        const uint64_t m = (1ull << jobs[j].p) * bits / 8u;
         const uint64_t bb = align256((uint64_t)hj[j].n * m * (hj[j].levels + 1u));
         hj[j].buf[0] = base + off_buf[j];
         hj[j].buf[1] = base + off_buf[j] + bb;
@@ -814,12 +822,12 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     for (auto &c : classes) {
         hbk::Sched fixed{};
         (void)explicit_sched(o, c.p, &fixed);
-        c.sched = hbk::default_sched((int)c.p);
+        c.sched = hbk::default_sched((int)c.p, bits);
         if (fixed.lanes) {
             c.sched = fixed;
         } else if (o.tune != HB_TUNE_OFF &&
-                   !tune_get(tune_key(c.p, c.runs, true, c.nodes, c.rows), &c.sched)) {
-            c.sched = hbk::default_sched((int)c.p);
+                   !tune_get(tune_key(c.p, bits, c.runs, true, c.nodes, c.rows), &c.sched)) {
+            c.sched = hbk::default_sched((int)c.p, bits);
             c.measure = o.tune == HB_TUNE_MEASURE;
             any_measure = any_measure || c.measure;
         }
@@ -835,7 +843,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         uint32_t acc = 0;
         lists.push_back(0);
         for (uint32_t j : runs_list) {
-            if (k <= hj[j].levels) acc += hbk::batch_table_blocks(hj[j].n, hj[j].p, k);
+            if (k <= hj[j].levels)
+                acc += hbk::batch_table_blocks(hj[j].n, (1u << hj[j].p) * bits / 8u, k);
             lists.push_back(acc);
         }
         table_blocks[k] = acc;
@@ -843,7 +852,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     for (auto &c : classes) {
         c.list_off = (uint32_t)lists.size();
         lists.insert(lists.end(), c.list.begin(), c.list.end());
-        const std::vector<uint32_t> ib = c.bases(hj, hbk::default_sched((int)c.p));
+        const std::vector<uint32_t> ib = c.bases(hj, hbk::default_sched((int)c.p, bits));
         c.init_off = (uint32_t)lists.size();
         lists.insert(lists.end(), ib.begin(), ib.end());
         c.init_blocks = ib.back();
@@ -853,7 +862,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     std::vector<std::vector<uint32_t>> cand_off(classes.size()), cand_blocks(classes.size());
     for (size_t ci = 0; ci < classes.size(); ++ci) {
         if (!classes[ci].measure) continue;
-        cands[ci] = tune_candidates((int)classes[ci].p);
+        cands[ci] = tune_candidates((int)classes[ci].p, bits);
         for (const auto &cs : cands[ci]) {
             const std::vector<uint32_t> b = classes[ci].bases(hj, cs);
             cand_off[ci].push_back((uint32_t)lists.size());
@@ -874,7 +883,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     auto init_all = [&]() -> hb_status {
         HB_HIP(hbk::launch_fill_u32(d_flags, 0u, flags_words, s));
         for (auto &c : classes)
-            HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p), R.d_jobs,
+            HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p, bits), R.d_jobs,
                                           R.d_lists + c.list_off, R.d_lists + c.init_off,
                                           (uint32_t)c.list.size(), c.init_blocks, s));
         return HB_OK;
@@ -894,7 +903,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
             if (!c.measure) continue;
             size_t idx = 0;
             TunePick pick;
-            st = tune_measure((int)c.p, s, [&](const hbk::Sched &cs) {
+            st = tune_measure((int)c.p, bits, s, [&](const hbk::Sched &cs) {
                 idx = 0;
                 while (idx < cands[ci].size() && !(cands[ci][idx].lanes == cs.lanes &&
                                                    cands[ci][idx].nodes_per_block == cs.nodes_per_block))
@@ -905,7 +914,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
                                                (uint32_t)c.list.size(), cand_blocks[ci][idx], s);
             }, &pick);
             if (st != HB_OK) return st;
-            tune_put(tune_key(c.p, c.runs, true, c.nodes, c.rows), pick);
+            tune_put(tune_key(c.p, bits, c.runs, true, c.nodes, c.rows), pick);
             c.sched = pick.s;
         }
         HB_HIP(hipStreamSynchronize(s));
@@ -971,7 +980,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         const hbk::BatchJob &b = R.h_jobs[j];
         hb_result *out = &outs[j];
         const uint32_t n = b.n;
-        const uint64_t m = 1ull << b.p;
+        const uint64_t m = (1ull << b.p) * bits / 8u;
         if (out->reach)
             HB_HIP(hipMemcpy(out->reach, b.c_prev, sizeof(double) * n, hipMemcpyDeviceToHost));
         if (out->sum_d || out->mean_depth) {
@@ -993,7 +1002,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         if (out->registers)
             HB_HIP(hipMemcpy(out->registers, b.buf[b.done & 1u], (uint64_t)n * m,
                              hipMemcpyDeviceToHost));
-        const double md = (double)m;
+        const double md = (double)(1ull << b.p);
         out->passes = b.done;
         out->converged = b.converged;
         out->productive_iters = b.converged ? b.done - 1u : b.done;
@@ -1010,6 +1019,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
                 out->lanes_per_node = c.sched.lanes;
                 out->nodes_per_block = c.sched.nodes_per_block;
             }
+        out->register_bits = bits;
         out->tune_ms = tune_ms;
         out->t_submit_ns = t_start;
         out->t_admit_ns = t_start;

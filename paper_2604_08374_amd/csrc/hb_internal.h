@@ -21,10 +21,10 @@ struct BatchJob {
     uint64_t seed;
     uint32_t n, p, depth, levels, n_flags;
     uint32_t runs;            // 1: run kernel, 0: per-edge kernel
+    uint32_t bits;            // bits per register: 8, or 4 (two per byte, saturating at 15)
     uint32_t t;               // steps completed
     uint32_t done;            // 0 while running, else the last step run
     uint32_t converged;       // 1 if it stopped because no estimate grew by more than 0.5
-    uint32_t pad;
 };
 
 // Launch schedule of the union kernels for one precision p:
@@ -33,15 +33,18 @@ struct BatchJob {
 //    above 64, lanes / 64 waves of one workgroup each own a slice of it.
 //  * nodes_per_block: nodes per workgroup for single-wave shapes (1, 2 or 4;
 //    always 1 when several waves share a node).
-// Every schedule gives the same registers; only the speed differs.
+//  * bits: register width, 8 (one per byte) or 4 (two per byte, low nibble =
+//    even register, saturating at 15; the paper's packed format).
+// Every schedule of one width gives the same registers; only the speed differs.
 struct Sched {
     uint32_t lanes;
     uint32_t nodes_per_block;
+    uint32_t bits = 8;
 };
 constexpr uint32_t kMaxLaneOptions = 4;
-// The lanes-per-node values compiled for p (the default first); returns the count.
-uint32_t lane_options(int p, uint32_t out[kMaxLaneOptions]);
-Sched default_sched(int p);
+// The lanes-per-node values compiled for (p, bits), the default first; returns the count.
+uint32_t lane_options(int p, uint32_t bits, uint32_t out[kMaxLaneOptions]);
+Sched default_sched(int p, uint32_t bits = 8);
 bool sched_ok(int p, const Sched &s);
 
 struct LaunchShape {
@@ -63,7 +66,7 @@ hipError_t launch_batch_union(int p, const Sched &s, bool runs, BatchJob *jobs,
                               uint32_t nblocks, hipStream_t stream);
 // Table level k for listed run-kernel jobs with levels >= k; job list[i] owns
 // workgroups [block_base[i], block_base[i+1]), batch_table_blocks(n, p, k) of them.
-uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k);
+uint32_t batch_table_blocks(uint32_t n, uint32_t row_bytes, uint32_t k);
 hipError_t launch_batch_table(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
                               uint32_t nlist, uint32_t nblocks, uint32_t k, hipStream_t stream);
 // After a step: t += 1 and the stop decision for every listed running job.
@@ -95,9 +98,9 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const 
                              const uint32_t *order, hipStream_t stream);
 
 // Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
-// i <= n - 2^k, rows of m bytes (m a multiple of 16), T[k] at tbl + k n m.
-// Requires 2^levels <= n.
-hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
+// i <= n - 2^k, rows of m bytes (m a multiple of 16) of `bits`-bit registers,
+// T[k] at tbl + k n m.  Requires 2^levels <= n.
+hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
                         hipStream_t stream);
 
 // Streaming copy of bytes (a multiple of 16) from src to dst.

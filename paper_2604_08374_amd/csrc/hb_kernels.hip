@@ -47,20 +47,24 @@ constexpr int kRunsMaxP = 12;  // the run kernel's tables are built for p <= 12
 
 // Lanes that share one node's counter by default: one 16-byte slot per lane
 // up to p = 10, one wave (1 to 4 slots per lane) at p = 11 and 12, and 4 KB
-// wave slices beyond.
-constexpr int default_lanes(int p) {
-    return p <= 10 ? (1 << p) / 16 : (p <= 12 ? 64 : (1 << p) / 64);
+// wave slices beyond.  With 4-bit registers (two per byte, the paper's packed
+// format) a counter has half the bytes: one slot per lane up to p = 11, one
+// wave at p = 12 and 13, 4 KB slices beyond; p >= 5.
+constexpr int default_lanes(int p, int bits = 8) {
+    return bits == 8 ? (p <= 10 ? (1 << p) / 16 : (p <= 12 ? 64 : (1 << p) / 64))
+                     : (p <= 11 ? (1 << p) / 32 : (p <= 13 ? 64 : (1 << p) / 128));
 }
 
 // Shape of one node's work for precision P with L lanes per node.  L <= 64:
 // one wave holds 64 / L groups of L lanes; each group owns a whole counter
 // and the groups gather different neighbours, max-reduced at the end.
 // L > 64: L / 64 waves of one workgroup share the node, each owning a slice.
-template <int P, int L = default_lanes(P)>
+template <int P, int L = default_lanes(P), int B = 8>
 struct Cfg {
     static constexpr int PREC = P;
     static constexpr int LANES = L;
-    static constexpr int M = 1 << P;
+    static constexpr int BITS = B;                               // bits per register
+    static constexpr int M = (1 << P) * B / 8;                   // counter bytes
     static constexpr int WAVES = L > kWave ? L / kWave : 1;      // waves per node
     static constexpr int LPC = L > kWave ? kWave : L;            // lanes per counter in a wave
     static constexpr int G = kWave / LPC;                        // neighbour groups
@@ -71,8 +75,10 @@ struct Cfg {
     static constexpr int THREADS = WAVES == 1 ? 256 : WAVES * kWave;
     static constexpr int TOP = 65 - P;                           // largest register value
     // waves per SIMD the run kernel is compiled for (its register budget):
-    // 80 VGPRs with one slot per lane, 96 with two, 168 with four
-    static constexpr int RUN_OCC = RPL == 1 ? 6 : (RPL == 2 ? 5 : 3);
+    // 80 VGPRs with one slot per lane, 96 with two, 168 with four; 4-bit
+    // accumulators take twice the registers per slot
+    static constexpr int RUN_OCC = B == 8 ? (RPL == 1 ? 6 : (RPL == 2 ? 5 : 3))
+                                          : (RPL == 1 ? 4 : (RPL == 2 ? 3 : 2));
     static_assert(RPL >= 1 && RPL <= 4 && M % (16 * L) == 0, "unsupported lanes per node");
 };
 
@@ -107,6 +113,26 @@ __device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
                                                                   __builtin_bit_cast(u16x2, b)));
 }
 
+// Nibble-wise max accumulator for one dword of 8 4-bit registers.  a[k]
+// holds the dword shifted left by 12 - 4k, which puts nibble k at the top of
+// the low 16-bit half and nibble k + 4 at the top of the high half; a packed
+// 16-bit max then keeps the max of those two nibbles (lower bits are
+// don't-care).  7 VALU ops per 8 registers.
+struct Max8 {
+    uint32_t a[4];
+    __device__ __forceinline__ void init(uint32_t w) {
+        a[0] = w << 12;
+        a[1] = w << 8;
+        a[2] = w << 4;
+        a[3] = w;
+    }
+    __device__ __forceinline__ void add(uint32_t w);
+    __device__ __forceinline__ uint32_t value() const {
+        return ((a[0] >> 12) & 0x000F000Fu) | ((a[1] >> 8) & 0x00F000F0u) |
+               ((a[2] >> 4) & 0x0F000F00u) | (a[3] & 0xF000F000u);
+    }
+};
+
 // Byte-wise max accumulator for one dword of 4 registers.  hi tracks bytes
 // 1 and 3 (the high byte of each 16-bit half); lo tracks bytes 0 and 2 after
 // a left shift by 8 moves them into the high bytes.  The low bytes of both
@@ -122,6 +148,18 @@ struct Max4 {
         return ((lo >> 8) & 0x00FF00FFu) | (hi & 0xFF00FF00u);
     }
 };
+
+__device__ __forceinline__ void Max8::add(uint32_t w) {
+    a[0] = pk_max_u16(a[0], w << 12);
+    a[1] = pk_max_u16(a[1], w << 8);
+    a[2] = pk_max_u16(a[2], w << 4);
+    a[3] = pk_max_u16(a[3], w);
+}
+
+// The accumulator type of a register width.
+template <int BITS> struct AccOf;
+template <> struct AccOf<8> { using T = Max4; };
+template <> struct AccOf<4> { using T = Max8; };
 
 // SplitMix64 output function (Steele, Lea & Flood 2014).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -140,10 +178,12 @@ struct EstPart {
         lo += term;
         hi += (lo < term) ? 1u : 0u;
     }
+    template <int BITS>
     __device__ __forceinline__ void add_dword(uint32_t w, int top) {
+        constexpr uint32_t mask = (1u << BITS) - 1u;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t M = (w >> (8 * b)) & 0xFFu;
+        for (int b = 0; b < 32 / BITS; ++b) {
+            const uint32_t M = (w >> (BITS * b)) & mask;
             add_term(1ull << (top - (int)M));
             zeros += (M == 0u) ? 1u : 0u;
         }
@@ -246,7 +286,11 @@ __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__r
     const uint64_t h = splitmix64((uint64_t)id ^ seed);
     const uint32_t j = (uint32_t)(h >> (64 - P));
     const uint64_t rest = h << P;
-    const uint32_t r = rest ? (uint32_t)__builtin_clzll(rest) + 1u : (uint32_t)(65 - P);
+    uint32_t r = rest ? (uint32_t)__builtin_clzll(rest) + 1u : (uint32_t)(65 - P);
+    if (C::BITS == 4 && r > 15u) r = 15u;  // 4-bit registers saturate
+    // register j sits in byte jb; with 4 bits, odd j in the high nibble
+    const uint32_t jb = C::BITS == 8 ? j : j >> 1;
+    const uint32_t sub = C::BITS == 8 ? 0u : 4u * (j & 1u);
 
     const bool owner = (lane / C::LPC) == 0;  // group 0 holds the counter
     EstPart e;
@@ -256,11 +300,11 @@ __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__r
     for (int s = 0; s < C::RPL; ++s) {
         const uint32_t off = slot_offset<C>(slice, lane, s);
         uint32_t w[4] = {0u, 0u, 0u, 0u};
-        if (j >= off && j < off + 16u) w[(j - off) >> 2] = r << (8 * ((j - off) & 3u));
+        if (jb >= off && jb < off + 16u) w[(jb - off) >> 2] = r << (8 * ((jb - off) & 3u) + sub);
         if (owner) {
             *reinterpret_cast<uint4 *>(row + off) = make_uint4(w[0], w[1], w[2], w[3]);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) e.add_dword(w[k], C::TOP);
+            for (int k = 0; k < 4; ++k) e.template add_dword<C::BITS>(w[k], C::TOP);
         }
     }
     e.wave_reduce();
@@ -360,7 +404,7 @@ struct RowDecoder {
 // This lane's share of one node's running register-wise max.
 template <class C>
 struct NodeAcc {
-    Max4 m[C::RPL][4];
+    typename AccOf<C::BITS>::T m[C::RPL][4];
 
     __device__ __forceinline__ void init(const uint8_t *row, uint32_t slice, uint32_t lane) {
 #pragma unroll
@@ -419,7 +463,7 @@ __device__ __forceinline__ void finish_node(NodeAcc<C> &acc, uint32_t v, uint32_
             for (int s = 0; s < C::RPL; ++s)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    Max4 mm;
+                    typename AccOf<C::BITS>::T mm;
                     mm.init(reg[s][k]);
                     mm.add(shfl_xor(reg[s][k], mask));
                     reg[s][k] = mm.value();
@@ -434,7 +478,7 @@ __device__ __forceinline__ void finish_node(NodeAcc<C> &acc, uint32_t v, uint32_
             *reinterpret_cast<uint4 *>(row + slot_offset<C>(slice, lane, s)) =
                 make_uint4(reg[s][0], reg[s][1], reg[s][2], reg[s][3]);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) e.add_dword(reg[s][k], C::TOP);
+            for (int k = 0; k < 4; ++k) e.template add_dword<C::BITS>(reg[s][k], C::TOP);
         }
     }
     e.wave_reduce();
@@ -746,26 +790,33 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
                        s_queue[threadIdx.x / kWave]);
 }
 
+// Register-wise max of 16 bytes of two counters (8- or 4-bit registers).
+template <class A>
+__device__ __forceinline__ uint4 max16(const uint4 a, const uint4 b) {
+    A x, y, z, w;
+    x.init(a.x);
+    x.add(b.x);
+    y.init(a.y);
+    y.add(b.y);
+    z.init(a.z);
+    z.add(b.z);
+    w.init(a.w);
+    w.add(b.w);
+    return make_uint4(x.value(), y.value(), z.value(), w.value());
+}
+
 // Level k of the range-max table from level k - 1:
 // T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]) for i <= n - 2^k.
 __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ tbl,
                                                           uint64_t level_bytes, uint32_t k,
-                                                          uint64_t count16, uint64_t half16) {
+                                                          uint64_t count16, uint64_t half16,
+                                                          uint32_t bits) {
     const uint4 *prev = reinterpret_cast<const uint4 *>(tbl + (uint64_t)(k - 1) * level_bytes);
     uint4 *out = reinterpret_cast<uint4 *>(tbl + (uint64_t)k * level_bytes);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16; i += stride) {
         const uint4 a = prev[i], b = prev[i + half16];
-        Max4 x, y, z, w;
-        x.init(a.x);
-        x.add(b.x);
-        y.init(a.y);
-        y.add(b.y);
-        z.init(a.z);
-        z.add(b.z);
-        w.init(a.w);
-        w.add(b.w);
-        out[i] = make_uint4(x.value(), y.value(), z.value(), w.value());
+        out[i] = bits == 4u ? max16<Max8>(a, b) : max16<Max4>(a, b);
     }
 }
 
@@ -841,7 +892,7 @@ __global__ __launch_bounds__(256) void batch_table_kernel(BatchJob *__restrict__
     if (J.done || !J.runs || k > J.levels) return;
     const uint32_t t = J.t + 1u;
     uint8_t *tbl = J.buf[(t - 1u) & 1u];
-    const uint64_t m16 = (1ull << J.p) / 16u;
+    const uint64_t m16 = ((1ull << J.p) * J.bits / 8u) / 16u;  // 16-byte chunks per counter
     const uint64_t level16 = (uint64_t)J.n * m16;
     const uint64_t count16 = ((uint64_t)J.n - (1ull << k) + 1ull) * m16;
     const uint64_t half16 = (1ull << (k - 1u)) * m16;
@@ -853,16 +904,7 @@ __global__ __launch_bounds__(256) void batch_table_kernel(BatchJob *__restrict__
         const uint64_t c = c0 + (uint64_t)r * 256u + threadIdx.x;
         if (c >= count16) break;
         const uint4 a = prev[c], b = prev[c + half16];
-        Max4 x, y, z, w;
-        x.init(a.x);
-        x.add(b.x);
-        y.init(a.y);
-        y.add(b.y);
-        z.init(a.z);
-        z.add(b.z);
-        w.init(a.w);
-        w.add(b.w);
-        out[c] = make_uint4(x.value(), y.value(), z.value(), w.value());
+        out[c] = J.bits == 4u ? max16<Max8>(a, b) : max16<Max4>(a, b);
     }
 }
 
@@ -897,12 +939,16 @@ __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
 }
 
 // ---------------------------------------------------------------- dispatch
-// Compiled shapes: (p, lanes per node).  The first entry of each p is its
-// default; the others are the alternatives the tuner may pick.
-#define HB_SHAPES(X)                                                             \
-    X(4, 1) X(5, 2) X(6, 4) X(7, 8) X(8, 16) X(8, 8) X(9, 32) X(9, 16) X(10, 64) \
-    X(10, 32) X(10, 16) X(11, 64) X(11, 128) X(11, 32) X(12, 64) X(12, 128)     \
-    X(12, 256) X(13, 128) X(13, 256) X(14, 256) X(14, 512) X(15, 512) X(16, 1024)
+// Compiled shapes: (p, lanes per node, bits per register).  The first entry
+// of each (p, bits) is its default; the others are the alternatives the tuner
+// may pick.  4-bit registers have their default shape only.
+#define HB_SHAPES(X)                                                                          \
+    X(4, 1, 8) X(5, 2, 8) X(6, 4, 8) X(7, 8, 8) X(8, 16, 8) X(8, 8, 8) X(9, 32, 8)             \
+    X(9, 16, 8) X(10, 64, 8) X(10, 32, 8) X(10, 16, 8) X(11, 64, 8) X(11, 128, 8)              \
+    X(11, 32, 8) X(12, 64, 8) X(12, 128, 8) X(12, 256, 8) X(13, 128, 8) X(13, 256, 8)          \
+    X(14, 256, 8) X(14, 512, 8) X(15, 512, 8) X(16, 1024, 8) X(5, 1, 4) X(6, 2, 4) X(7, 4, 4)  \
+    X(8, 8, 4) X(9, 16, 4) X(10, 32, 4) X(11, 64, 4) X(12, 64, 4) X(13, 64, 4) X(14, 128, 4)  \
+    X(15, 256, 4) X(16, 512, 4)
 
 // Workgroups and threads of a launch over n nodes.
 template <class C>
@@ -982,25 +1028,27 @@ hipError_t launch_batch_union_c(bool runs, BatchJob *jobs, const uint32_t *list,
 
 }  // namespace
 
-uint32_t lane_options(int p, uint32_t out[kMaxLaneOptions]) {
+uint32_t lane_options(int p, uint32_t bits, uint32_t out[kMaxLaneOptions]) {
     uint32_t k = 0;
-#define HB_LANES(P, L) \
-    if (p == P && k < kMaxLaneOptions) out[k++] = L;
+#define HB_LANES(P, L, B) \
+    if (p == P && bits == B && k < kMaxLaneOptions) out[k++] = L;
     HB_SHAPES(HB_LANES)
 #undef HB_LANES
     return k;
 }
 
-Sched default_sched(int p) {
+Sched default_sched(int p, uint32_t bits) {
     Sched s;
-    s.lanes = (p >= 4 && p <= 16) ? (uint32_t)default_lanes(p) : 0u;
+    const bool ok = p <= 16 && ((bits == 8 && p >= 4) || (bits == 4 && p >= 5));
+    s.lanes = ok ? (uint32_t)default_lanes(p, (int)bits) : 0u;
     s.nodes_per_block = s.lanes > (uint32_t)kWave ? 1u : 4u;
+    s.bits = bits;
     return s;
 }
 
 bool sched_ok(int p, const Sched &s) {
     uint32_t opts[kMaxLaneOptions];
-    const uint32_t k = lane_options(p, opts);
+    const uint32_t k = lane_options(p, s.bits, opts);
     bool lanes_ok = false;
     for (uint32_t i = 0; i < k; ++i) lanes_ok |= opts[i] == s.lanes;
     if (!lanes_ok) return false;
@@ -1029,9 +1077,9 @@ LaunchShape shape_for(int p, const Sched &s) {
 
 hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, double *sum_d,
                        uint32_t n, uint64_t seed, const uint32_t *hash_ids, hipStream_t stream) {
-#define HB_X(P, L)                                                                          \
-    if (p == P && s.lanes == L)                                                             \
-        return launch_init_c<Cfg<P, L>>(cur, c_prev, sum_d, n, seed, hash_ids, nb, stream);
+#define HB_X(P, L, B)                                                                          \
+    if (p == P && s.lanes == L && s.bits == B)                                                             \
+        return launch_init_c<Cfg<P, L, B>>(cur, c_prev, sum_d, n, seed, hash_ids, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
@@ -1040,9 +1088,9 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
                         const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
                         uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
                         hipStream_t stream) {
-#define HB_X(P, L)                                                                            \
-    if (p == P && s.lanes == L)                                                               \
-        return launch_union_c<Cfg<P, L>>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, \
+#define HB_X(P, L, B)                                                                            \
+    if (p == P && s.lanes == L && s.bits == B)                                                               \
+        return launch_union_c<Cfg<P, L, B>>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, \
                                          t, order, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
@@ -1052,15 +1100,15 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const 
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
                              const uint32_t *order, hipStream_t stream) {
-#define HB_X(P, L)                                                                          \
-    if (p == P && s.lanes == L)                                                             \
-        return launch_union_runs_c<Cfg<P, L>>(bytes, offsets, tbl, levels, next, c_prev,    \
+#define HB_X(P, L, B)                                                                          \
+    if (p == P && s.lanes == L && s.bits == B)                                                             \
+        return launch_union_runs_c<Cfg<P, L, B>>(bytes, offsets, tbl, levels, next, c_prev,    \
                                               sum_d, flag_t, n, t, order, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
 
-hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
+hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
                         hipStream_t stream) {
     const uint64_t level_bytes = (uint64_t)n * m;
     for (uint32_t k = 1; k <= levels; ++k) {
@@ -1069,7 +1117,7 @@ hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels,
         const uint64_t half16 = (1ull << (k - 1)) * (m / 16u);
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((count16 + 255) / 256, 256u * 64u);
         hipLaunchKernelGGL(table_level_kernel, dim3(blocks), dim3(256), 0, stream, tbl, level_bytes,
-                           k, count16, half16);
+                           k, count16, half16, bits);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1080,9 +1128,9 @@ hipError_t launch_batch_init(int p, const Sched &s, BatchJob *jobs, const uint32
                              const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
                              hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
-#define HB_X(P, L)                                                                          \
-    if (p == P && s.lanes == L)                                                             \
-        return launch_batch_init_c<Cfg<P, L>>(jobs, list, block_base, nlist, nblocks, nb,  \
+#define HB_X(P, L, B)                                                                          \
+    if (p == P && s.lanes == L && s.bits == B)                                                             \
+        return launch_batch_init_c<Cfg<P, L, B>>(jobs, list, block_base, nlist, nblocks, nb,  \
                                               stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
@@ -1092,17 +1140,17 @@ hipError_t launch_batch_union(int p, const Sched &s, bool runs, BatchJob *jobs,
                               const uint32_t *list, const uint32_t *block_base, uint32_t nlist,
                               uint32_t nblocks, hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
-#define HB_X(P, L)                                                                            \
-    if (p == P && s.lanes == L)                                                               \
-        return launch_batch_union_c<Cfg<P, L>>(runs, jobs, list, block_base, nlist, nblocks, \
+#define HB_X(P, L, B)                                                                            \
+    if (p == P && s.lanes == L && s.bits == B)                                                               \
+        return launch_batch_union_c<Cfg<P, L, B>>(runs, jobs, list, block_base, nlist, nblocks, \
                                                nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
 
-uint32_t batch_table_blocks(uint32_t n, uint32_t p, uint32_t k) {
+uint32_t batch_table_blocks(uint32_t n, uint32_t row_bytes, uint32_t k) {
     if (k == 0 || (1ull << k) > n) return 0;
-    const uint64_t count16 = ((uint64_t)n - (1ull << k) + 1ull) * ((1ull << p) / 16u);
+    const uint64_t count16 = ((uint64_t)n - (1ull << k) + 1ull) * (row_bytes / 16u);
     return (uint32_t)((count16 + kTableChunk - 1) / kTableChunk);
 }
 

@@ -56,23 +56,24 @@ struct RunCounts {
 // ---- union-schedule autotuner (hb_tune.cpp)
 // Shape class of a union launch: the key of the process-wide pick cache.
 struct TuneKey {
-    uint32_t p, runs, batched, log_n, log_rows;
+    uint32_t p, bits, runs, batched, log_n, log_rows;
     bool operator<(const TuneKey &o) const;
 };
 // nodes: nodes the launch covers; rows: counter rows it gathers per step
 // (table rows for the run kernel, directed edges otherwise).
-TuneKey tune_key(uint32_t p, bool runs, bool batched, uint64_t nodes, uint64_t rows);
+TuneKey tune_key(uint32_t p, uint32_t bits, bool runs, bool batched, uint64_t nodes,
+                 uint64_t rows);
 struct TunePick {
     hbk::Sched s;
     double best_ms = 0.0, default_ms = 0.0;
 };
 bool tune_get(const TuneKey &k, hbk::Sched *s);
 void tune_put(const TuneKey &k, const TunePick &v);
-// Every schedule built for p, the default first.
-std::vector<hbk::Sched> tune_candidates(int p);
+// Every schedule built for (p, register bits), the default first.
+std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits);
 // Time one union step of every candidate with `launch` (which enqueues the
 // step on stream s): two launches each, the faster counts.  Fills the pick.
-hb_status tune_measure(int p, hipStream_t s,
+hb_status tune_measure(int p, uint32_t bits, hipStream_t s,
                        const std::function<hipError_t(const hbk::Sched &)> &launch,
                        TunePick *out);
 

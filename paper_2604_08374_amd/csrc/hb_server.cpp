@@ -91,6 +91,7 @@ struct Request {
     hb_ticket ticket = 0;
     hb_graph *g = nullptr;
     uint32_t p = 0, depth = 0, flags = 0;
+    uint32_t bits = 8;  // register width
     uint64_t seed = 0;
     bool runs = false;
     uint32_t levels = 0;
@@ -141,7 +142,7 @@ private:
     hb_status step(Lane &L);
     void fail_all(Lane &L, hb_status st, const std::string &msg);
     void retire(Lane &L, Request *r);
-    hb_status footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
+    hb_status footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs, uint32_t &levels,
                         uint64_t &bytes) const;
 
     std::mutex mu_;  // guards everything below that client threads touch
@@ -159,9 +160,9 @@ private:
     void *d_arena_ = nullptr;
 };
 
-hb_status Server::footprint(const hb_graph *g, uint32_t p, bool &runs, uint32_t &levels,
-                            uint64_t &bytes) const {
-    const uint64_t m = 1ull << p;
+hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs,
+                            uint32_t &levels, uint64_t &bytes) const {
+    const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
     levels = std::min(opts_.table_levels ? opts_.table_levels : 7u, floor_log2(g->n));
     runs = opts_.union_kernel == HB_UNION_RUNS || (opts_.union_kernel == HB_UNION_AUTO && p <= 12);
     if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
@@ -236,7 +237,9 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
                          hb_ticket *out) {
     if (!g || !out) return fail(HB_EINVAL, "NULL argument");
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
-    if (flags & ~HB_SUBMIT_REGISTERS) return fail(HB_EINVAL, "unknown submit flags");
+    if (flags & ~(HB_SUBMIT_REGISTERS | HB_SUBMIT_REG4)) return fail(HB_EINVAL, "unknown submit flags");
+    const uint32_t bits = (flags & HB_SUBMIT_REG4) ? 4u : 8u;
+    if (bits == 4u && p < 5) return fail(HB_EINVAL, "4-bit registers need p >= 5");
     bool need_start;
     {
         std::lock_guard<std::mutex> lk(mu_);
@@ -252,7 +255,7 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
     auto r = std::make_unique<Request>();
     if (opts_.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
-    hb_status st = footprint(g, p, r->runs, r->levels, r->footprint);
+    hb_status st = footprint(g, p, bits, r->runs, r->levels, r->footprint);
     if (st != HB_OK) return st;
     if (align256(r->footprint) > arena_.size())
         return fail(HB_ENOMEM, "request needs %llu bytes, the budget is %llu",
@@ -263,10 +266,11 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
     r->depth = depth;
     r->seed = seed;
     r->flags = flags;
+    r->bits = bits;
     r->t_submit = now_ns();
-    // bytes one step gathers: counter rows (table rows for the run kernel) x 2^p
+    // bytes one step gathers: counter rows (table rows for the run kernel) x counter bytes
     const uint64_t rows = r->runs ? g->runs.lookups[r->levels] : g->n_edges;
-    const int lane = rows * (1ull << p) > slow_bytes_ ? 1 : 0;
+    const int lane = rows * ((1ull << p) * bits / 8u) > slow_bytes_ ? 1 : 0;
     g->inflight.fetch_add(1);
     *out = r->ticket;
     lanes_[lane].queue.push_back(r.get());
@@ -313,8 +317,9 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
     out->run_ms = (double)(r->t_end - r->t_admit) / 1e6;
     out->union_kernel = r->runs ? HB_UNION_RUNS : HB_UNION_EDGES;
     out->table_levels = r->levels;
-    out->lanes_per_node = hbk::default_sched((int)r->p).lanes;
-    out->nodes_per_block = hbk::default_sched((int)r->p).nodes_per_block;
+    out->lanes_per_node = hbk::default_sched((int)r->p, r->bits).lanes;
+    out->nodes_per_block = hbk::default_sched((int)r->p, r->bits).nodes_per_block;
+    out->register_bits = r->bits;
     out->tune_ms = 0.0;
     out->t_submit_ns = r->t_submit;
     out->t_admit_ns = r->t_admit;
@@ -368,7 +373,7 @@ void Server::retire(Lane &L, Request *r) {
     (void)hipMemcpyAsync(r->sum_d.data(), r->job.sum_d, sizeof(double) * n, hipMemcpyDeviceToHost,
                          L.stream);
     if (r->flags & HB_SUBMIT_REGISTERS) {
-        r->regs.resize((uint64_t)n << r->p);
+        r->regs.resize(((uint64_t)n << r->p) * r->bits / 8u);
         (void)hipMemcpyAsync(r->regs.data(), r->job.buf[r->job.done & 1u], r->regs.size(),
                              hipMemcpyDeviceToHost, L.stream);
     }
@@ -398,7 +403,7 @@ hb_status Server::step(Lane &L) {
     uint8_t *base = static_cast<uint8_t *>(d_arena_);
     for (Request *r : admitted) {
         hb_graph *g = r->g;
-        const uint64_t m = 1ull << r->p;
+        const uint64_t m = (1ull << r->p) * r->bits / 8u;
         const uint64_t bb = align256((uint64_t)g->n * m * (r->levels + 1u));
         const uint64_t sb = align256(8ull * g->n);
         hbk::BatchJob &b = r->job;
@@ -419,6 +424,7 @@ hb_status Server::step(Lane &L) {
         b.levels = r->levels;
         b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
         b.runs = r->runs ? 1u : 0u;
+        b.bits = r->bits;
         L.running.push_back(r);
     }
     const uint32_t nj = (uint32_t)L.running.size();
@@ -441,6 +447,7 @@ hb_status Server::step(Lane &L) {
     struct Cls {
         uint32_t p;
         bool runs;
+        uint32_t bits;
         std::vector<uint32_t> list, base;
         uint32_t list_off, base_off;
     };
@@ -450,14 +457,15 @@ hb_status Server::step(Lane &L) {
     auto add_to = [&](std::vector<Cls> &cs, uint32_t j, bool runs) {
         Cls *c = nullptr;
         for (auto &x : cs)
-            if (x.p == h_jobs_[j].p && x.runs == runs) c = &x;
+            if (x.p == h_jobs_[j].p && x.runs == runs && x.bits == h_jobs_[j].bits) c = &x;
         if (!c) {
-            cs.push_back(Cls{h_jobs_[j].p, runs, {}, {0u}, 0, 0});
+            cs.push_back(Cls{h_jobs_[j].p, runs, h_jobs_[j].bits, {}, {0u}, 0, 0});
             c = &cs.back();
         }
         // the default schedule: a served step's class mix changes from step to step
         const int p = (int)h_jobs_[j].p;
-        const uint32_t npb = hbk::shape_for(p, hbk::default_sched(p)).nodes_per_block;
+        const uint32_t npb =
+            hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits)).nodes_per_block;
         c->list.push_back(j);
         c->base.push_back(c->base.back() + (h_jobs_[j].n + npb - 1) / npb);
     };
@@ -483,7 +491,9 @@ hb_status Server::step(Lane &L) {
         uint32_t acc = 0;
         lists.push_back(0);
         for (uint32_t j : runs_list) {
-            if (k <= h_jobs_[j].levels) acc += hbk::batch_table_blocks(h_jobs_[j].n, h_jobs_[j].p, k);
+            if (k <= h_jobs_[j].levels)
+                acc += hbk::batch_table_blocks(
+                    h_jobs_[j].n, (1u << h_jobs_[j].p) * h_jobs_[j].bits / 8u, k);
             lists.push_back(acc);
         }
         table_blocks[k] = acc;
@@ -517,14 +527,14 @@ hb_status Server::step(Lane &L) {
         L.running[j]->t_start = t_launch;
     }
     for (auto &c : inits)
-        HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p), d_jobs_,
+        HB_HIP(hbk::launch_batch_init((int)c.p, hbk::default_sched((int)c.p, c.bits), d_jobs_,
                                       d_lists_ + c.list_off, d_lists_ + c.base_off,
                                       (uint32_t)c.list.size(), c.base.back(), s));
     for (uint32_t k = 1; k <= max_levels; ++k)
         HB_HIP(hbk::launch_batch_table(d_jobs_, d_lists_ + runs_off, d_lists_ + table_off[k],
                                        (uint32_t)runs_list.size(), table_blocks[k], k, s));
     for (auto &c : classes)
-        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p), c.runs, d_jobs_,
+        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p, c.bits), c.runs, d_jobs_,
                                        d_lists_ + c.list_off,
                                        d_lists_ + c.base_off, (uint32_t)c.list.size(),
                                        c.base.back(), s));

@@ -18,8 +18,8 @@
 namespace hbr {
 
 bool TuneKey::operator<(const TuneKey &o) const {
-    return std::tie(p, runs, batched, log_n, log_rows) <
-           std::tie(o.p, o.runs, o.batched, o.log_n, o.log_rows);
+    return std::tie(p, bits, runs, batched, log_n, log_rows) <
+           std::tie(o.p, o.bits, o.runs, o.batched, o.log_n, o.log_rows);
 }
 
 namespace {
@@ -33,9 +33,11 @@ uint32_t log2_floor64(uint64_t x) {
 }
 }  // namespace
 
-TuneKey tune_key(uint32_t p, bool runs, bool batched, uint64_t nodes, uint64_t rows) {
+TuneKey tune_key(uint32_t p, uint32_t bits, bool runs, bool batched, uint64_t nodes,
+                 uint64_t rows) {
     TuneKey k;
     k.p = p;
+    k.bits = bits;
     k.runs = runs ? 1u : 0u;
     k.batched = batched ? 1u : 0u;
     k.log_n = log2_floor64(std::max<uint64_t>(nodes, 1));
@@ -56,16 +58,16 @@ void tune_put(const TuneKey &k, const TunePick &v) {
     g_tune[k] = v;
 }
 
-std::vector<hbk::Sched> tune_candidates(int p) {
+std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits) {
     std::vector<hbk::Sched> c;
-    const hbk::Sched d = hbk::default_sched(p);
+    const hbk::Sched d = hbk::default_sched(p, bits);
     c.push_back(d);
     uint32_t lanes[hbk::kMaxLaneOptions];
-    const uint32_t k = hbk::lane_options(p, lanes);
+    const uint32_t k = hbk::lane_options(p, bits, lanes);
     for (uint32_t i = 0; i < k; ++i) {
         const uint32_t nbs[3] = {4u, 2u, 1u};
         for (uint32_t nb : nbs) {
-            hbk::Sched s{lanes[i], nb};
+            hbk::Sched s{lanes[i], nb, bits};
             if (!hbk::sched_ok(p, s)) continue;
             if (s.lanes == d.lanes && s.nodes_per_block == d.nodes_per_block) continue;
             c.push_back(s);
@@ -74,13 +76,13 @@ std::vector<hbk::Sched> tune_candidates(int p) {
     return c;
 }
 
-hb_status tune_measure(int p, hipStream_t s,
+hb_status tune_measure(int p, uint32_t bits, hipStream_t s,
                        const std::function<hipError_t(const hbk::Sched &)> &launch,
                        TunePick *out) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const std::vector<hbk::Sched> cand = tune_candidates(p);
+    const std::vector<hbk::Sched> cand = tune_candidates(p, bits);
     TunePick best;
     best.best_ms = -1.0;
     for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
@@ -122,6 +124,7 @@ hb_status hb_tune_cache(hb_tune_entry *out, uint32_t cap, uint32_t *count) {
         if (i < cap) {
             hb_tune_entry &t = out[i];
             t.p = kv.first.p;
+            t.register_bits = kv.first.bits;
             t.union_kernel = kv.first.runs ? HB_UNION_RUNS : HB_UNION_EDGES;
             t.batched = kv.first.batched;
             t.log2_nodes = kv.first.log_n;

@@ -378,3 +378,49 @@ def test_hilbert_order_is_a_permutation():
     g = synth.grid_graph(3, 40, 30)
     o = synth.hilbert_order(g)
     assert np.array_equal(np.sort(o), np.arange(g.n))
+
+
+# ------------------------------------------------------------------ 4-bit registers (Sec. 3.4)
+def _high_rank_ids(p, seed, count, rank=16):
+    """Ids whose inserted rank is at least `rank` (found by search), to force saturation."""
+    out, x = [], 0
+    while len(out) < count:
+        if oracle.hll_insert(x, seed, p)[1] >= rank:
+            out.append(x)
+        x += 1
+    return out
+
+
+def test_4bit_registers_are_the_8bit_registers_clamped_at_15():
+    """max commutes with min(., 15), so after any step R4 = min(R8, 15), byte for byte.
+
+    Some nodes insert elements of rank >= 16 (chosen through hash_ids), so the clamp
+    really acts; the 8-bit run is stopped at the step where the 4-bit run stopped.
+    """
+    g = synth.grid_graph(5, 40, 30)
+    p, seed = 8, 3
+    special = _high_rank_ids(p, seed, 12)
+    hid = np.arange(g.n, dtype=np.uint32) + np.uint32(10 ** 6)
+    rng = np.random.default_rng(2)
+    hid[rng.choice(g.n, size=len(special), replace=False)] = special
+    csr = oracle.from_graph(g)
+    for depth in (0, 2):
+        r4 = oracle.hyperball(csr, p, depth, seed, hash_ids=hid, register_bits=4)
+        r8 = oracle.hyperball(csr, p, r4.passes, seed, hash_ids=hid)
+        assert r8.registers.max() >= 16  # the clamp matters in this case
+        assert r4.registers.max() == 15
+        assert np.array_equal(r4.registers, np.minimum(r8.registers, 15))
+        # the estimator is the same formula over the clamped registers
+        est = np.array([oracle.hll_estimate(row, p) for row in r4.registers])
+        assert np.array_equal(est, r4.reach)
+
+
+def test_4bit_equals_8bit_when_no_rank_exceeds_15():
+    g = synth.tiny(6)
+    csr = oracle.from_graph(g)
+    a = oracle.hyperball(csr, 10, 0, 0)
+    if a.registers.max() > 15:
+        pytest.skip("a rank above 15 occurs on this graph")
+    b = oracle.hyperball(csr, 10, 0, 0, register_bits=4)
+    assert np.array_equal(a.registers, b.registers)
+    assert np.array_equal(a.sum_d, b.sum_d) and a.passes == b.passes
