@@ -58,22 +58,24 @@ def node_order(g, args):
     return synth.hilbert_order(g) if args.order == "hilbert" else None
 
 
-def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None) -> int:
+def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None,
+                      bits: int = 8) -> int:
     """Bytes one union launch must move at minimum without reuse.
 
-    Per gathered counter row: m bytes -- one per directed edge for the per-edge
-    kernel, or `rows` table rows for the run kernel; the whole LEB128 stream; per
-    node: the offsets entry (8 B), its own counter read and next[v] written (2m),
-    and the FP64 state c_prev and sum_d read and written (32 B).
+    Per gathered counter row: m bytes (2^p registers of `bits` bits) -- one row per
+    directed edge for the per-edge kernel, or `rows` table rows for the run kernel;
+    the whole LEB128 stream; per node: the offsets entry (8 B), its own counter read
+    and next[v] written (2m), and the FP64 state c_prev and sum_d read and written
+    (32 B).
     """
-    m = 1 << p
+    m = (1 << p) * bits // 8
     gathered = n_edges if rows is None else rows
     return gathered * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
 
 
-def table_bytes(n: int, p: int, levels: int) -> int:
+def table_bytes(n: int, p: int, levels: int, bits: int = 8) -> int:
     """Range-max table build per step: level k reads two rows and writes one per i."""
-    m = 1 << p
+    m = (1 << p) * bits // 8
     return sum(3 * (n - (1 << k) + 1) * m for k in range(1, levels + 1))
 
 
@@ -404,6 +406,8 @@ def main():
                     help="union kernel: per edge, per run from a range-max table, or the "
                          "library's choice")
     ap.add_argument("--table-levels", type=int, default=0)
+    ap.add_argument("--register-bits", type=int, default=8, choices=[8, 4],
+                    help="8-bit registers (the default workload) or the paper's 4-bit format")
     ap.add_argument("--order", default="hilbert", choices=["hilbert", "raster"],
                     help="processing order of the nodes (results are identical either way)")
     ap.add_argument("--tune", default="measure", choices=["measure", "cached", "off"],
@@ -440,7 +444,7 @@ def main():
     stats = G.stats()
 
     p, depth = args.p, args.depth
-    kw = dict(kernel=args.kernel, table_levels=args.table_levels)
+    kw = dict(kernel=args.kernel, table_levels=args.table_levels, register_bits=args.register_bits)
     tune_ms = 0.0
     for i in range(args.warmup):
         r = G.run(p, depth, args.seed, tune=args.tune, **kw)
@@ -470,13 +474,14 @@ def main():
     kernel = results[-1].union_kernel
     levels = results[-1].table_levels
     rows = stats["table_rows"][levels] if kernel == "runs" else None
-    per_launch = algorithmic_bytes(n, E, data.size, p, rows)
+    bits = results[-1].register_bits
+    per_launch = algorithmic_bytes(n, E, data.size, p, rows, bits)
     achieved = per_launch / avg_launch_s / 1e9
     lanes = results[-1].lanes_per_node
-    kname = (f"union_runs_kernel<{p},{lanes}>" if kernel == "runs"
-             else f"union_kernel<{p},{lanes}>")
+    kname = (f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs"
+             else f"union_kernel<{p},{lanes},{bits}>")
     traffic = kernel_traffic(args.config, p, depth, kname, args.order)
-    edge_equiv = algorithmic_bytes(n, E, data.size, p) / avg_launch_s / 1e9
+    edge_equiv = algorithmic_bytes(n, E, data.size, p, None, bits) / avg_launch_s / 1e9
     line = {
         "metric": METRIC,
         "value": value,
@@ -488,7 +493,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "u8" if bits == 8 else "u4",
         "data": "synthetic",
         "config": {
             "workload": f"{args.config} street/building visibility graph, seed {args.seed}",
@@ -501,6 +506,7 @@ def main():
             "union_kernel": kernel,
             "table_levels": levels,
             "node_order": args.order,
+            "register_bits": bits,
             "schedule": {"lanes_per_node": lanes,
                          "nodes_per_block": results[-1].nodes_per_block,
                          "tune": args.tune, "tune_ms": tune_ms,
@@ -524,7 +530,7 @@ def main():
         },
     }
     if kernel == "runs":
-        tb = table_bytes(n, p, levels)
+        tb = table_bytes(n, p, levels, bits)
         t_s = table_ms / 1e3 / passes
         line["table_build"] = {"bytes_per_step": tb, "avg_ms": t_s * 1e3,
                                "achieved_gbs": tb / t_s / 1e9 if t_s > 0 else None,
