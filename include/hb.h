@@ -367,6 +367,30 @@ hb_status hb_server_stats(hb_server_stats_t *out);
 hb_status hb_release_cache(void);
 
 /*
+ * VGA metrics (Sec. 3.3, "Metric derivation"), n doubles each, caller-owned
+ * host arrays or NULL to skip.  k = deg(v), N = N_v (the exact component size
+ * given at load, else n), MD = sum_d[v] / (N - 1):
+ *  - connectivity: k;
+ *  - control: the sum over neighbours w of 1 / deg(w);
+ *  - mean_depth: MD (NaN if N < 2);
+ *  - relative_asymmetry: RA = 2 (MD - 1) / (N - 2) (NaN if N < 3);
+ *  - integration_hh: 1 / RRA with RRA = RA / D_N and Hillier & Hanson's
+ *    diamond value D_N = 2 (N (log2((N + 2) / 3) - 1) + 1) / ((N - 1)(N - 2))
+ *    (+inf when RA = 0; the paper names RRA but not D_N);
+ *  - integration_tekl: log2((MD + 2) / 3), as the paper states it;
+ *  - integration_pvalue: max(0, 1 - RA);
+ *  - point_first_moment: MD k.
+ * The first two are exact; the others inherit the HLL error of sum_d.
+ */
+typedef struct {
+    double *connectivity, *control, *mean_depth, *relative_asymmetry;
+    double *integration_hh, *integration_tekl, *integration_pvalue, *point_first_moment;
+} hb_vga_out;
+
+/* The metrics above for every node of g from the sums of one run (n doubles). */
+hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out);
+
+/*
  * Copy up to cap autotuner cache entries to out (caller-owned; NULL with
  * cap 0 only counts) and the number of entries to *count.  Host-only.
  */

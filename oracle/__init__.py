@@ -80,6 +80,8 @@ def _lib():
                                    u8p, dp, dp,
                                    ctypes.POINTER(_Info)]
         L.or_hyperball.restype = ctypes.c_int
+        L.or_vga_metrics.argtypes = [i64, u64p, u32p, u8p, u32p, dp, dp]
+        L.or_vga_metrics.restype = ctypes.c_int
         L.or_hyperball_exact.argtypes = [i64, u64p, u32p, u8p, u32, dp, dp, ctypes.POINTER(_Info)]
         L.or_hyperball_exact.restype = ctypes.c_int
         L.or_bfs.argtypes = [i64, u64p, u32p, u8p, i64, i32p]
@@ -358,3 +360,21 @@ def initial_registers(n: int, p: int, seed: int = 0) -> np.ndarray:
         j, r = hll_insert(v, seed, p)
         regs[v, j] = r
     return regs
+
+
+VGA_METRICS = ("connectivity", "control", "mean_depth", "relative_asymmetry", "integration_hh",
+               "integration_tekl", "integration_pvalue", "point_first_moment")
+
+
+def vga_metrics(csr: CSR, sum_d, comp_size=None) -> dict:
+    """VGA metrics from the 1-hop neighbourhood and the Eq. 3 sums (Sec. 3.3)."""
+    n = csr.n
+    sd = np.ascontiguousarray(sum_d, np.float64)
+    cs = None if comp_size is None else np.ascontiguousarray(comp_size, np.uint32)
+    out = np.empty((8, n), np.float64)
+    rc = _lib().or_vga_metrics(n, _u64(csr.offsets), _u32(csr.degrees), _bytes_ptr(csr),
+                               _u32(cs) if cs is not None else None,
+                               _p(sd, ctypes.c_double), _p(out, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle vga_metrics failed (malformed CSR)")
+    return {name: out[i] for i, name in enumerate(VGA_METRICS)}

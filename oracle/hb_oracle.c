@@ -595,3 +595,58 @@ int or_num_threads(void) {
     return 1;
 #endif
 }
+
+/*
+ * VGA metrics (Sec. 3.3, "Metric derivation") for every node, written out one
+ * by one: out holds 8 arrays of n doubles -- connectivity k = deg(v); control,
+ * the sum over the neighbours w (in row order) of 1 / deg(w); MD = sum_d /
+ * (N - 1) with N the exact component size (comp_size, or n); RA = 2 (MD - 1) /
+ * (N - 2); integration [HH] = D_N / RA, the reciprocal of RRA = RA / D_N with
+ * Hillier & Hanson's diamond value D_N = 2 (N (log2((N + 2) / 3) - 1) + 1) /
+ * ((N - 1)(N - 2)); integration [Tekl] = log2((MD + 2) / 3); integration
+ * [P-value] = max(0, 1 - RA); point first moment = MD k.  NaN where N is too
+ * small for a formula (MD: N < 2; RA-based: N < 3).  Returns 0, or -1 on a
+ * malformed row.
+ */
+int or_vga_metrics(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
+                   const uint8_t *bytes, const uint32_t *comp_size, const double *sum_d,
+                   double *out) {
+    int bad = 0;
+#pragma omp parallel
+    {
+        uint32_t *ids = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; ++v) {
+            if ((int64_t)degrees[v] > cap) {
+                free(ids);
+                cap = degrees[v];
+                ids = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+            }
+            const int64_t k = or_decode_row(bytes, offsets, v, ids, cap);
+            if (k != (int64_t)degrees[v]) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            double control = 0.0;
+            for (int64_t e = 0; e < k; ++e) control += 1.0 / (double)degrees[ids[e]];
+            const double N = comp_size ? (double)comp_size[v] : (double)n;
+            const double md = N >= 2.0 ? sum_d[v] / (N - 1.0) : NAN;
+            const double ra = N >= 3.0 ? 2.0 * (md - 1.0) / (N - 2.0) : NAN;
+            const double dk = N >= 3.0 ? 2.0 * (N * (log2((N + 2.0) / 3.0) - 1.0) + 1.0) /
+                                             ((N - 1.0) * (N - 2.0))
+                                       : NAN;
+            out[0 * n + v] = (double)k;
+            out[1 * n + v] = control;
+            out[2 * n + v] = md;
+            out[3 * n + v] = ra;
+            out[4 * n + v] = dk / ra;
+            out[5 * n + v] = N >= 2.0 ? log2((md + 2.0) / 3.0) : NAN;
+            out[6 * n + v] = N >= 3.0 ? fmax(0.0, 1.0 - ra) : NAN;
+            out[7 * n + v] = md * (double)k;
+        }
+        free(ids);
+    }
+    return bad ? -1 : 0;
+}

@@ -113,6 +113,14 @@ def unpack_nibbles(regs: np.ndarray) -> np.ndarray:
     return out
 
 
+VGA_METRICS = ("connectivity", "control", "mean_depth", "relative_asymmetry", "integration_hh",
+               "integration_tekl", "integration_pvalue", "point_first_moment")
+
+
+class _VgaOut(ctypes.Structure):
+    _fields_ = [(name, dblp) for name in VGA_METRICS]
+
+
 class _Job(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("p", ctypes.c_uint32), ("depth_limit", ctypes.c_uint32),
                 ("hash_seed", ctypes.c_uint64)]
@@ -182,6 +190,8 @@ def _lib():
         L.hb_tune_cache.restype = st
         L.hb_tune_clear.argtypes = []
         L.hb_tune_clear.restype = st
+        L.hb_vga_metrics.argtypes = [ctypes.c_void_p, dblp, ctypes.POINTER(_VgaOut)]
+        L.hb_vga_metrics.restype = st
         L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
         L.hb_copy_probe.restype = st
         _LIB = L
@@ -314,6 +324,18 @@ class Graph:
         _check(_lib().hb_graph_stats(self._h, ctypes.byref(st)))
         return {"n": st.n, "n_edges": st.n_edges, "n_bytes": st.n_bytes, "n_runs": st.n_runs,
                 "table_rows": [int(x) for x in st.table_rows]}
+
+    def vga_metrics(self, sum_d) -> dict:
+        """hb_vga_metrics: the VGA metrics of every node from a run's sum_d (Sec. 3.3)."""
+        if self._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        sd = np.ascontiguousarray(sum_d, np.float64)
+        if sd.shape != (self.n,):
+            raise HBError(HB_EINVAL, "sum_d must have n entries")
+        arrays = {name: np.empty(self.n, np.float64) for name in VGA_METRICS}
+        o = _VgaOut(*[_ptr(arrays[name], ctypes.c_double) for name in VGA_METRICS])
+        _check(_lib().hb_vga_metrics(self._h, _ptr(sd, ctypes.c_double), ctypes.byref(o)))
+        return arrays
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -176,6 +176,8 @@ void graph_release(hb_graph *g) {
     (void)hipFree(g->d_cprev);
     (void)hipFree(g->d_order);
     (void)hipFree(g->d_hash_ids);
+    (void)hipFree(g->d_degrees);
+    (void)hipFree(g->d_comp);
     (void)hipFree(g->d_sumd);
     (void)hipFree(g->d_flags);
     if (g->h_flag) (void)hipHostFree(g->h_flag);
@@ -397,13 +399,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(offsets)");
     for (const auto &opt : {std::make_pair(csr->order, &g->d_order),
-                            std::make_pair(csr->hash_ids, &g->d_hash_ids)}) {
+                            std::make_pair(csr->hash_ids, &g->d_hash_ids),
+                            std::make_pair(csr->degrees, &g->d_degrees),
+                            std::make_pair(csr->comp_size, &g->d_comp)}) {
         if (!opt.first) continue;
         if ((e = hipMalloc(opt.second, sizeof(uint32_t) * g->n)) != hipSuccess)
-            return bail(e, "hipMalloc(order / hash ids)");
+            return bail(e, "hipMalloc(per-node array)");
         if ((e = hipMemcpy(*opt.second, opt.first, sizeof(uint32_t) * g->n,
                            hipMemcpyHostToDevice)) != hipSuccess)
-            return bail(e, "hipMemcpy(order / hash ids)");
+            return bail(e, "hipMemcpy(per-node array)");
     }
     *out = g;
     return HB_OK;
@@ -1026,6 +1030,35 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         out->t_start_ns = t_start;
         out->t_end_ns = now_ns();
     }
+    return HB_OK;
+}
+
+hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out) {
+    if (!g || !sum_d || !out) return fail(HB_EINVAL, "NULL argument");
+    double *dst[8] = {out->connectivity, out->control, out->mean_depth, out->relative_asymmetry,
+                      out->integration_hh, out->integration_tekl, out->integration_pvalue,
+                      out->point_first_moment};
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    HB_HIP(hipSetDevice(g->device));
+    const uint64_t n = g->n;
+    double *d_sum = nullptr, *d_out = nullptr;
+    hipError_t e = hipMalloc(&d_sum, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * 8 * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_sum, sum_d, sizeof(double) * n, hipMemcpyHostToDevice,
+                                            g->stream);
+    if (e == hipSuccess)
+        e = hbk::launch_vga(g->d_bytes, g->d_offsets, g->d_degrees, g->d_comp, d_sum, g->n, d_out,
+                            g->stream);
+    for (int i = 0; i < 8 && e == hipSuccess; ++i)
+        if (dst[i])
+            e = hipMemcpyAsync(dst[i], d_out + (uint64_t)i * n, sizeof(double) * n,
+                               hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
+    (void)hipFree(d_out);
+    (void)hipFree(d_sum);
+    if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "VGA metrics: out of device memory");
+    if (e != hipSuccess) return hip_fail(e, "VGA metrics");
     return HB_OK;
 }
 

@@ -106,6 +106,14 @@ hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, u
 // Streaming copy of bytes (a multiple of 16) from src to dst.
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 
+// VGA metrics of every node (Sec. 3.3): out holds 8 arrays of n doubles --
+// connectivity, control, mean depth, RA, integration [HH], [Tekl], [P-value],
+// point first moment -- from the CSR, the degrees, the exact component sizes
+// (null: all n) and the Eq. 3 sums.
+hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint32_t *degrees,
+                      const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
+                      hipStream_t stream);
+
 // Fill count u32 words with value (used instead of hipMemsetAsync so the
 // sequence stays capturable).
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream);

@@ -933,6 +933,58 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src
         dst[i] = src[i];
 }
 
+// ---------------------------------------------------------------- VGA metrics
+// Sec. 3.3, "Metric derivation": connectivity and control from the 1-hop
+// neighbourhood (exact), the other metrics in closed form from the Eq. 3 sum.
+// One wave per node decodes its row; each lane adds 1 / deg(w) for the
+// neighbours it holds, and a fixed butterfly sums the lanes.
+__device__ __forceinline__ double shfl_xor_f64(double x, uint32_t mask) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = shfl_xor((uint32_t)b, mask), hi = shfl_xor((uint32_t)(b >> 32), mask);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ bytes,
+                                                  const uint64_t *__restrict__ offsets,
+                                                  const uint32_t *__restrict__ degrees,
+                                                  const uint32_t *__restrict__ comp_size,
+                                                  const double *__restrict__ sum_d, uint32_t n,
+                                                  double *__restrict__ out) {
+    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t v = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (v >= n) return;
+    double part = 0.0;
+    uint32_t k = 0;
+    RowDecoder dec;
+    const uint64_t row_end = offsets[v + 1];
+    for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
+        uint32_t cnt;
+        const uint32_t ids = dec.chunk(bytes, base, row_end, cnt);
+        if (lane < cnt) part += 1.0 / (double)degrees[ids];
+        k += cnt;
+    }
+#pragma unroll
+    for (uint32_t mask = 1; mask < kWave; mask <<= 1) part += shfl_xor_f64(part, mask);
+    if (lane != 0) return;
+    const double nan = __builtin_nan("");
+    const double N = comp_size ? (double)comp_size[v] : (double)n;  // exact N_v
+    const double md = N >= 2.0 ? sum_d[v] / (N - 1.0) : nan;
+    const double ra = N >= 3.0 ? 2.0 * (md - 1.0) / (N - 2.0) : nan;
+    // Hillier & Hanson's diamond value D_k (k = N_v) normalises RA to RRA
+    const double dk = N >= 3.0 ? 2.0 * (N * (log2((N + 2.0) / 3.0) - 1.0) + 1.0) /
+                                     ((N - 1.0) * (N - 2.0))
+                               : nan;
+    double *o = out + v;
+    o[0 * (uint64_t)n] = (double)k;                             // connectivity
+    o[1 * (uint64_t)n] = part;                                  // control
+    o[2 * (uint64_t)n] = md;                                    // Visual Mean Depth
+    o[3 * (uint64_t)n] = ra;                                    // relative asymmetry
+    o[4 * (uint64_t)n] = dk / ra;                               // integration [HH] = 1 / RRA
+    o[5 * (uint64_t)n] = N >= 2.0 ? log2((md + 2.0) / 3.0) : nan;  // integration [Tekl]
+    o[6 * (uint64_t)n] = N >= 3.0 ? fmax(0.0, 1.0 - ra) : nan;     // integration [P-value]
+    o[7 * (uint64_t)n] = md * (double)k;                        // point first moment
+}
+
 __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = value;
@@ -1176,6 +1228,15 @@ hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 256u * 64u);
     hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, stream,
                        static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), count);
+    return hipGetLastError();
+}
+
+hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint32_t *degrees,
+                      const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
+                      hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(vga_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, bytes, offsets,
+                       degrees, comp_size, sum_d, n, out);
     return hipGetLastError();
 }
 

@@ -88,6 +88,8 @@ struct hb_graph {
     uint8_t *d_bytes = nullptr;
     uint64_t *d_offsets = nullptr;
     uint32_t *d_order = nullptr;     // processing order, or null
+    uint32_t *d_degrees = nullptr;   // n neighbour counts
+    uint32_t *d_comp = nullptr;      // exact component sizes, or null (all n)
     uint32_t *d_hash_ids = nullptr;  // inserted ids, or null
     // run state, kept between runs (the counters live in a per-device workspace)
     double *d_cprev = nullptr, *d_sumd = nullptr;

@@ -424,3 +424,72 @@ def test_4bit_equals_8bit_when_no_rank_exceeds_15():
     b = oracle.hyperball(csr, 10, 0, 0, register_bits=4)
     assert np.array_equal(a.registers, b.registers)
     assert np.array_equal(a.sum_d, b.sum_d) and a.passes == b.passes
+
+
+# ------------------------------------------------------------------ VGA metrics (Sec. 3.3)
+def _exact_sums(g):
+    csr = oracle.from_graph(g)
+    return csr, oracle.hyperball_exact(csr).sum_d
+
+
+def test_vga_metrics_star_closed_forms():
+    """Star of n nodes: centre k = n-1, control n-1, MD 1, RA 0; leaf k = 1,
+    control 1/(n-1), MD (2n-3)/(n-1), RA 2/(n-1)."""
+    n = 9
+    csr, sd = _exact_sums(synth.star_graph(n))
+    m = oracle.vga_metrics(csr, sd)
+    assert m["connectivity"][0] == n - 1 and np.all(m["connectivity"][1:] == 1)
+    assert m["control"][0] == n - 1
+    np.testing.assert_allclose(m["control"][1:], 1.0 / (n - 1), rtol=1e-15)
+    assert m["mean_depth"][0] == 1.0 and m["relative_asymmetry"][0] == 0.0
+    assert m["integration_pvalue"][0] == 1.0 and m["integration_tekl"][0] == 0.0
+    assert np.isinf(m["integration_hh"][0])
+    np.testing.assert_allclose(m["mean_depth"][1:], (2 * n - 3) / (n - 1), rtol=1e-15)
+    np.testing.assert_allclose(m["relative_asymmetry"][1:], 2 / (n - 1), rtol=1e-14)
+    np.testing.assert_allclose(m["integration_pvalue"][1:], 1 - 2 / (n - 1), rtol=1e-14)
+    np.testing.assert_allclose(m["point_first_moment"], m["mean_depth"] * m["connectivity"])
+
+
+def test_vga_metrics_complete_and_path():
+    csr, sd = _exact_sums(synth.complete_graph(7))
+    m = oracle.vga_metrics(csr, sd)
+    np.testing.assert_allclose(m["control"], 1.0, rtol=1e-15)  # six neighbours of degree 6
+    assert np.all(m["relative_asymmetry"] == 0.0)
+    n = 12
+    csr, sd = _exact_sums(synth.path_graph(n))
+    m = oracle.vga_metrics(csr, sd)
+    # ends: one neighbour of degree 2; next to an end: 1/1 + 1/2; interior: 1/2 + 1/2
+    np.testing.assert_allclose(m["control"][[0, -1]], 0.5)
+    np.testing.assert_allclose(m["control"][[1, -2]], 1.5)
+    np.testing.assert_allclose(m["control"][2:-2], 1.0)
+    i = np.arange(n)
+    md = (i * (i + 1) / 2 + (n - 1 - i) * (n - i) / 2) / (n - 1)
+    np.testing.assert_allclose(m["mean_depth"], md, rtol=1e-15)
+    np.testing.assert_allclose(m["integration_tekl"], np.log2((md + 2) / 3), rtol=1e-14)
+
+
+def _diamond(levels):
+    """Justified 'diamond': levels of 1, 2, 4, ..., 4, 2, 1 nodes, each level joined
+    completely to the next, so the root's depth of a node is its level."""
+    sizes = [2 ** i for i in range(levels + 1)] + [2 ** i for i in range(levels - 1, -1, -1)]
+    start = np.cumsum([0] + sizes)
+    edges = [(a, b) for L in range(len(sizes) - 1)
+             for a in range(start[L], start[L + 1]) for b in range(start[L + 1], start[L + 2])]
+    return synth.from_edges(int(start[-1]), edges, name=f"diamond{int(start[-1])}")
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+def test_integration_hh_is_one_at_the_root_of_a_diamond(levels):
+    """Hillier & Hanson's D_k is the RA of the root of the k-node diamond, so there
+    RRA = 1 and integration [HH] = 1 (k = 4, 10, 22, 46)."""
+    csr, sd = _exact_sums(_diamond(levels))
+    m = oracle.vga_metrics(csr, sd)
+    np.testing.assert_allclose(m["integration_hh"][0], 1.0, rtol=1e-13)
+    assert m["integration_hh"][-1] == pytest.approx(1.0, rel=1e-13)  # the other apex
+
+
+def test_vga_metrics_small_components_are_nan():
+    csr, sd = _exact_sums(synth.from_edges(3, [(0, 1)]))
+    m = oracle.vga_metrics(csr, sd, comp_size=np.array([2, 2, 1], np.uint32))
+    assert m["mean_depth"][0] == 1.0 and np.isnan(m["relative_asymmetry"][0])
+    assert np.isnan(m["mean_depth"][2]) and m["connectivity"][2] == 0 and m["control"][2] == 0
