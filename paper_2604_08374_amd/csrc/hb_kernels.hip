@@ -16,7 +16,9 @@
 //    continuation bits marks varint ends, a segmented OR joins the 7-bit
 //    groups (at most five per varint), a wave prefix sum turns the first id
 //    and the deltas into absolute ids, and a lane permute packs them into
-//    lanes 0..k-1.  Varints that straddle 64-byte chunks carry over.
+//    lanes 0..k-1.  Varints that straddle 64-byte chunks carry over.  The
+//    shifts and prefix sums are DPP moves (row shifts, row broadcasts and the
+//    wave shift by one), which stay in the VALU.
 //  * Neighbour ids are read out with readlane into scalar registers, so each
 //    gather uses a scalar base address; eight gathers are kept in flight per
 //    wave.  Tail slots repeat an id already gathered (max is idempotent).
@@ -89,9 +91,29 @@ __device__ __forceinline__ uint64_t ballot(bool pred) {
     return __builtin_amdgcn_ballot_w64(pred);
 }
 
-__device__ __forceinline__ uint32_t shfl_up(uint32_t x, uint32_t d) {
-    const int src = (int)lane_id() - (int)d;
-    return (uint32_t)__builtin_amdgcn_ds_bpermute((src < 0 ? 0 : src) << 2, (int)x);
+// Data-parallel-primitive moves (VALU, no LDS round trip).  CTRL: 0x111-0x11F
+// shift right within rows of 16 lanes, 0x138 shift right by one across the
+// wave, 0x142 / 0x143 broadcast lane 15 / 31 of a row to the next row(s).
+// Lanes with no source lane read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Value of lane - 1 (0 in lane 0).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x) { return dpp<0x138>(x); }
+
+// Inclusive prefix sum over the wave: doubling steps inside each row of 16
+// lanes, then row 0's total into row 1 and row 2's into row 3, then the sum of
+// rows 0-1 into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t x) {
+    x += dpp<0x111>(x);
+    x += dpp<0x112>(x);
+    x += dpp<0x114>(x);
+    x += dpp<0x118>(x);
+    x += dpp<0x142, 0xa>(x);
+    x += dpp<0x143, 0xc>(x);
+    return x;
 }
 
 __device__ __forceinline__ uint32_t shfl_idx(uint32_t x, uint32_t src) {
@@ -368,20 +390,16 @@ struct RowDecoder {
         const uint32_t sh = (below ? 0u : carry_sh) + 7u * pos;
         const uint32_t contrib = (sh < 32u) ? ((b & 0x7Fu) << sh) : 0u;
         uint32_t val = contrib;
+        uint32_t x = contrib;
 #pragma unroll
         for (uint32_t k = 1; k <= 4; ++k) {
-            const uint32_t x = shfl_up(contrib, k);
+            x = wave_shr1(x);  // contrib of lane - k
             if (pos >= k) val |= x;
         }
         if (!below) val |= carry_val;
         const bool is_term = (term >> lane) & 1ull;
         // inclusive prefix sum of the terminated values: first id, then deltas
-        uint32_t sum = is_term ? val : 0u;
-#pragma unroll
-        for (uint32_t d = 1; d < kWave; d <<= 1) {
-            const uint32_t x = shfl_up(sum, d);
-            if (lane >= d) sum += x;
-        }
+        const uint32_t sum = wave_scan(is_term ? val : 0u);
         const uint32_t id = run + sum;
         run = readlane(id, kWave - 1);
         if ((cont >> (kWave - 1)) & 1ull) {
@@ -561,7 +579,12 @@ __global__ __launch_bounds__(C::THREADS) void union_kernel(
 // per-edge kernel.
 constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
 constexpr int kRunLoads = 4;               // 16 B/lane loads in flight per flush round
-constexpr int kScalarWalk = 8;             // chunks with at most this many special varints
+// chunks with at most this many special varints take the scalar walk; the
+// rest take the vector path.  The walk runs on the scalar unit, which the four
+// SIMDs of a CU share, so a low threshold balances it against the VALU
+// (city, p = 10, one launch: 27.1 ms at 8, 26.0 at 4, 25.2 at 3, 24.9 at 2,
+// 25.6 at 1)
+constexpr int kScalarWalk = 2;
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
 template <class C>
@@ -714,7 +737,7 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
         const uint32_t ids = dec.chunk_of(b, valid, term, cont, cnt);
         if (cnt == 0) continue;
         const bool in = lane < cnt;
-        uint32_t prev = shfl_up(ids, 1);
+        uint32_t prev = wave_shr1(ids);
         if (lane == 0) prev = rl;
         const bool has_prev = lane > 0 || have;
         const bool joins = in && has_prev &&
@@ -732,12 +755,7 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
         const bool longrun = ends && r > top;
         const uint32_t k = 31u - (uint32_t)__builtin_clz(r | 1u);
         const uint32_t nl = (ends && !longrun) ? ((r == (1u << k)) ? 1u : 2u) : 0u;
-        uint32_t pos = nl;  // inclusive prefix sum of the lookups per lane
-#pragma unroll
-        for (uint32_t d = 1; d < kWave; d <<= 1) {
-            const uint32_t x = shfl_up(pos, d);
-            if (lane >= d) pos += x;
-        }
+        const uint32_t pos = wave_scan(nl);  // inclusive prefix sum of the lookups per lane
         const uint32_t total = readlane(pos, kWave - 1);
         if (g.qn > kQueueFlush) g.flush(acc, lane);
         if (nl) {
