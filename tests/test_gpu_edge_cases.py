@@ -77,3 +77,26 @@ def test_wide_open_area(hb):
     g = synth.graph_from_raster(np.zeros((40, 50), np.uint8), name="open50x40")
     for levels in (2, 7):
         _check(hb, g, 8, 0, seed=1, levels=levels)
+
+
+def test_very_long_row(hb):
+    """A 100,001-node star: the centre's row holds 100,000 ids (about 100 KB of LEB128,
+    1,563 chunks), every leaf row one id; both kernels and several shapes."""
+    n = 100_001
+    off = np.zeros(n + 1, np.uint64)
+    off[1] = n - 1
+    off[2:] = n - 1 + np.arange(1, n, dtype=np.uint64)
+    ids = np.concatenate([np.arange(1, n, dtype=np.uint32), np.zeros(n - 1, np.uint32)])
+    g = synth.Graph(n=n, adj_offsets=off, adj_ids=ids, obst=np.zeros((1, 1), np.uint8),
+                    xy=np.zeros((n, 2), np.int32), name="star100k")
+    for p, depth in ((10, 0), (4, 2), (12, 1)):
+        ref = oracle.hyperball(oracle.from_graph(g), p, depth, 3)
+        off_b, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+        assert int(off_b[1]) >= 99_000  # the centre row spans ~1,560 chunks
+        with hb.graph_load(off_b, deg, data) as G:
+            for kernel in ("runs", "edges"):
+                print(f"[edge] star100k p={p} d={depth} {kernel}", flush=True)
+                r = G.run(p, depth, 3, registers=True, kernel=kernel, tune="off")
+                assert r.passes == ref.passes and r.converged == ref.converged
+                assert np.array_equal(r.registers, ref.registers), (p, kernel)
+                np.testing.assert_allclose(r.sum_d, ref.sum_d, rtol=RTOL, atol=1e-9)
