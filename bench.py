@@ -13,7 +13,6 @@ Output: one JSON line (plus progress lines on stderr).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -88,11 +87,12 @@ def kernel_traffic(config: str, p: int, depth: int, kernel: str, order: str):
     """
     if (config, p, depth) != ("city", 10, 3):
         return None
+    from paper_2604_08374_amd.profiling import kernel_sha256
+
     try:
         with open(COUNTERS_FILE) as f:
             rec = dict(line.split(None, 1) for line in f if line.strip())
-        with open(KERNEL_SRC, "rb") as f:
-            src_hash = hashlib.sha256(f.read()).hexdigest()
+        src_hash = kernel_sha256(KERNEL_SRC)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256", "").strip() != src_hash:

@@ -6,12 +6,14 @@
 // Eq. 3 accumulation fused into its epilogue, so one launch is one whole
 // HyperBall step.  Design on gfx950:
 //
-//  * One wavefront per node (p <= 12).  A counter of m = 2^p uint8 registers
-//    is spread over the wave in 16-byte lane slices, so every neighbour
-//    gather is one coalesced 16 B/lane load: at p = 10 a single 1 KB wave
-//    load.  For p < 10 the wave splits into groups that gather different
+//  * By default one wavefront per node (p <= 12).  A counter of m = 2^p uint8
+//    registers is spread over the wave in 16-byte lane slices, so every
+//    neighbour gather is one coalesced 16 B/lane load: at p = 10 a single 1 KB
+//    wave load.  For p < 10 the wave splits into groups that gather different
 //    neighbours at once and are max-reduced at the end; for p >= 13 several
-//    waves of a workgroup share a node, each owning a 4 KB slice.
+//    waves of a workgroup share a node, each owning a 4 KB slice.  Other
+//    shapes (lanes per node, nodes per workgroup) are built for the autotuner,
+//    and 4-bit registers (two per byte) have shapes of their own.
 //  * The row is decoded cooperatively 64 bytes at a time: a ballot of the
 //    continuation bits marks varint ends, a segmented OR joins the 7-bit
 //    groups (at most five per varint), a wave prefix sum turns the first id
@@ -20,8 +22,9 @@
 //    shifts and prefix sums are DPP moves (row shifts, row broadcasts and the
 //    wave shift by one), which stay in the VALU.
 //  * Neighbour ids are read out with readlane into scalar registers, so each
-//    gather uses a scalar base address; eight gathers are kept in flight per
-//    wave.  Tail slots repeat an id already gathered (max is idempotent).
+//    gather uses a scalar base address; the per-edge kernel keeps eight
+//    gathers in flight per wave, the run kernel four at higher occupancy.
+//    Tail slots repeat an id already gathered (max is idempotent).
 //  * Byte-wise max without unpacking: v_pk_max_u16 on the raw dword keeps
 //    the max of bytes 1 and 3 in the high byte of each half, and on the
 //    dword shifted left by 8 the max of bytes 0 and 2; 3 VALU ops per 4
@@ -30,8 +33,9 @@
 //    integer (wave butterfly with carries) and converts it to double with a
 //    single rounding, so the estimate is independent of the reduction order.
 //  * Workgroups are remapped so that each of the 8 XCDs (which take
-//    workgroups round-robin) works on one contiguous node range: adjacent
-//    nodes share most neighbours, so their gathers hit the same L2.
+//    workgroups round-robin) works on one contiguous range of the processing
+//    order: nodes close in that order (along a Hilbert curve, when the caller
+//    gives one) share most neighbours, so their gathers hit the same L2.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>

@@ -78,9 +78,16 @@ def counter_means(pmc_dir: str):
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
-def kernel_sha256() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def kernel_sha256(path: str = KERNEL_SRC) -> str:
+    """SHA-256 of the kernel source without comments and blank lines, so that the
+    counters stay attached to the code they were taken on, not to its comments."""
+    code = []
+    with open(path) as f:
+        for line in f:
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
 def main():
