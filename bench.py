@@ -101,7 +101,8 @@ def kernel_traffic(config: str, p: int, depth: int, kernel: str, order: str):
         return None
     if rec.get("node_order", "raster").strip() != order:
         return None
-    return float(rec["hbm_bytes_per_launch"])
+    return {k: float(v) for k, v in rec.items()
+            if k.endswith("_per_launch") or k == "avg_launch_ns"}
 
 
 def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
@@ -480,7 +481,8 @@ def main():
     lanes = results[-1].lanes_per_node
     kname = (f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs"
              else f"union_kernel<{p},{lanes},{bits}>")
-    traffic = kernel_traffic(args.config, p, depth, kname, args.order)
+    counters = kernel_traffic(args.config, p, depth, kname, args.order)
+    traffic = counters["hbm_bytes_per_launch"] if counters else None
     edge_equiv = algorithmic_bytes(n, E, data.size, p, None, bits) / avg_launch_s / 1e9
     line = {
         "metric": METRIC,
@@ -529,6 +531,18 @@ def main():
             "per_edge_equivalent_gbs": edge_equiv,
         },
     }
+    if counters and "sq_insts_valu_per_launch" in counters:
+        # what the counters say limits the launch: VALU issue (a wave64 VALU
+        # instruction occupies one of the 1,024 SIMDs for 4 cycles at 2.4 GHz)
+        valu = counters["sq_insts_valu_per_launch"]
+        peak_issue = 256 * 4 * 2.4e9 / 4
+        line["roofline"]["issue"] = {
+            "valu_insts_per_launch": valu,
+            "salu_insts_per_launch": counters.get("sq_insts_salu_per_launch"),
+            "valu_issue_peak_per_s": peak_issue,
+            "valu_issue_frac": valu / peak_issue / avg_launch_s,
+            "hbm_traffic_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+        }
     if kernel == "runs":
         tb = table_bytes(n, p, levels, bits)
         t_s = table_ms / 1e3 / passes

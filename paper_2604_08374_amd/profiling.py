@@ -23,6 +23,10 @@ import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 VALU instruction takes 4 cycles
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_CYCLES = 4
 KERNEL_SRC = os.path.join(HERE, "csrc", "hb_kernels.hip")
 
 
@@ -104,6 +108,9 @@ def main():
     ap.add_argument("--title", default="union kernel")
     ap.add_argument("--out", required=True)
     ap.add_argument("--counters", default=None)
+    ap.add_argument("--sq", default=None,
+                    help="optional --pmc run of SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
+                         "SQ_INSTS_VMEM_RD (instruction mix of --kernel)")
     ap.add_argument("--node-order", default="raster",
                     help="processing order of the profiled run (recorded with the counters)")
     args = ap.parse_args()
@@ -167,6 +174,19 @@ def main():
     if args.algo_bytes:
         lines.append(f"* algorithmic bytes per launch {args.algo_bytes / 1e12:.4f} TB; measured "
                      f"traffic / algorithmic = {traffic / args.algo_bytes:.3f}")
+    mix = {}
+    if args.sq:
+        sq = counter_means(args.sq)
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD"):
+            if (k, c) in sq:
+                mix[c] = sq[(k, c)][1]
+        if "SQ_INSTS_VALU" in mix:
+            # a wave64 VALU instruction occupies a SIMD for 4 cycles
+            t_valu = mix["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ)
+            lines.append(f"* {k}: wave instructions per launch: " + ", ".join(
+                f"{c[9:]} {v:.4g}" for c, v in mix.items()) +
+                f"; VALU issue alone needs {t_valu * 1e3:.1f} ms "
+                f"({t_valu / (avg_ns * 1e-9):.2f} of the launch)")
     lines += [f"* kernel source sha256 {sha}", ""]
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
@@ -180,6 +200,8 @@ def main():
         f.write(f"fetch_scale {f_fetch:.6f}\n")
         f.write(f"write_scale {f_write:.6f}\n")
         f.write(f"hbm_bytes_per_launch {traffic:.0f}\n")
+        for c, v in mix.items():
+            f.write(f"{c.lower()}_per_launch {v:.0f}\n")
     print("\n".join(lines))
 
 
