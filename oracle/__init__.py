@@ -82,6 +82,8 @@ def _lib():
         L.or_hyperball.restype = ctypes.c_int
         L.or_vga_metrics.argtypes = [i64, u64p, u32p, u8p, u32p, dp, dp]
         L.or_vga_metrics.restype = ctypes.c_int
+        L.or_local_metrics.argtypes = [i64, u64p, u32p, u8p, u32p, i64, u64p, u32p, dp, dp]
+        L.or_local_metrics.restype = ctypes.c_int
         L.or_hyperball_exact.argtypes = [i64, u64p, u32p, u8p, u32, dp, dp, ctypes.POINTER(_Info)]
         L.or_hyperball_exact.restype = ctypes.c_int
         L.or_bfs.argtypes = [i64, u64p, u32p, u8p, i64, i32p]
@@ -378,3 +380,21 @@ def vga_metrics(csr: CSR, sum_d, comp_size=None) -> dict:
     if rc != 0:
         raise RuntimeError("oracle vga_metrics failed (malformed CSR)")
     return {name: out[i] for i, name in enumerate(VGA_METRICS)}
+
+
+def local_metrics(csr: CSR, nodes=None) -> dict:
+    """Exact local metrics of the listed nodes (all when nodes is None), Sec. 3.3
+    "Metric derivation": ordered adjacent neighbour pairs, two-step ball size
+    (without v), clustering coefficient and controllability."""
+    count = csr.n if nodes is None else len(nodes)
+    nd = None if nodes is None else np.ascontiguousarray(nodes, np.uint32)
+    pairs = np.empty(count, np.uint64)
+    ball2 = np.empty(count, np.uint32)
+    clus = np.empty(count, np.float64)
+    ctrl = np.empty(count, np.float64)
+    rc = _lib().or_local_metrics(csr.n, _u64(csr.offsets), _u32(csr.degrees), _bytes_ptr(csr),
+                                 _u32(nd) if nd is not None else None, count, _u64(pairs),
+                                 _u32(ball2), _p(clus, ctypes.c_double), _p(ctrl, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle local_metrics failed (malformed CSR)")
+    return {"pairs": pairs, "ball2": ball2, "clustering": clus, "controllability": ctrl}

@@ -650,3 +650,91 @@ int or_vga_metrics(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
     }
     return bad ? -1 : 0;
 }
+
+/*
+ * Local VGA metrics from the neighbourhoods (Sec. 3.3, "Metric derivation":
+ * computed exactly, without the HLL), for the nodes listed in nodes[0..count)
+ * (nodes = NULL: every node, count = n), written out one by one per listed
+ * node i:
+ *   pairs[i]  = ordered pairs (a, b) of neighbours of v that are adjacent,
+ *               i.e. the sum over neighbours a of |N(a) intersect N(v)|
+ *               (each link among the neighbours counts twice);
+ *   ball2[i]  = nodes u != v within two steps of v, |B(v, 2)| - 1;
+ *   clustering[i] = pairs / (k (k - 1)) with k = deg(v), the Watts & Strogatz
+ *               (1998) coefficient; NaN for k < 2;
+ *   controllability[i] = k / ball2, the first-step neighbourhood over the
+ *               two-step one (Turner et al. 2001); NaN for an isolated node.
+ * Membership uses per-thread arrays stamped with i + 1, so a node listed twice
+ * is counted afresh each time.  Any NULL output is
+ * skipped.  Returns 0, or -1 on a malformed row.
+ */
+int or_local_metrics(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
+                     const uint8_t *bytes, const uint32_t *nodes, int64_t count,
+                     uint64_t *pairs, uint32_t *ball2, double *clustering,
+                     double *controllability) {
+    int bad = 0;
+    if (!nodes) count = n;
+#pragma omp parallel
+    {
+        uint32_t *in_nv = (uint32_t *)calloc((size_t)n, sizeof(uint32_t));
+        uint32_t *in_b2 = (uint32_t *)calloc((size_t)n, sizeof(uint32_t));
+        uint32_t *row = NULL, *row2 = NULL;
+        int64_t cap = 0, cap2 = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < count; ++i) {
+            const int64_t v = nodes ? (int64_t)nodes[i] : i;
+            const uint32_t stamp = (uint32_t)i + 1u;
+            if ((int64_t)degrees[v] > cap) {
+                free(row);
+                cap = degrees[v];
+                row = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+            }
+            const int64_t k = or_decode_row(bytes, offsets, v, row, cap);
+            if (k != (int64_t)degrees[v]) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            for (int64_t e = 0; e < k; ++e) in_nv[row[e]] = stamp;
+            uint64_t links = 0;
+            uint32_t reach2 = 0;
+            for (int64_t e = 0; e < k; ++e) {
+                const uint32_t a = row[e];
+                if (in_b2[a] != stamp) {
+                    in_b2[a] = stamp;
+                    ++reach2;
+                }
+                if ((int64_t)degrees[a] > cap2) {
+                    free(row2);
+                    cap2 = degrees[a];
+                    row2 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap2);
+                }
+                const int64_t ka = or_decode_row(bytes, offsets, a, row2, cap2);
+                if (ka != (int64_t)degrees[a]) {
+#pragma omp atomic write
+                    bad = 1;
+                    break;
+                }
+                for (int64_t f = 0; f < ka; ++f) {
+                    const uint32_t b = row2[f];
+                    if (in_nv[b] == stamp) ++links;
+                    if ((int64_t)b != v && in_b2[b] != stamp) {
+                        in_b2[b] = stamp;
+                        ++reach2;
+                    }
+                }
+            }
+            if (pairs) pairs[i] = links;
+            if (ball2) ball2[i] = reach2;
+            if (clustering)
+                clustering[i] = k >= 2 ? (double)links / ((double)k * (double)(k - 1)) : NAN;
+            if (controllability)
+                controllability[i] = reach2 >= 1 ? (double)k / (double)reach2 : NAN;
+        }
+        free(row);
+        free(row2);
+        free(in_nv);
+        free(in_b2);
+    }
+    return bad ? -1 : 0;
+}

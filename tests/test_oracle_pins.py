@@ -493,3 +493,76 @@ def test_vga_metrics_small_components_are_nan():
     m = oracle.vga_metrics(csr, sd, comp_size=np.array([2, 2, 1], np.uint32))
     assert m["mean_depth"][0] == 1.0 and np.isnan(m["relative_asymmetry"][0])
     assert np.isnan(m["mean_depth"][2]) and m["connectivity"][2] == 0 and m["control"][2] == 0
+
+
+# ------------------------------------------------- local metrics (Sec. 3.3, exact)
+def _adjacency(g):
+    A = np.zeros((g.n, g.n), np.int64)
+    for v in range(g.n):
+        A[v, g.adj_ids[g.adj_offsets[v]:g.adj_offsets[v + 1]]] = 1
+    return A
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_local_metrics_match_matrix_powers(seed):
+    """On random graphs: the ordered adjacent neighbour pairs of v are the closed
+    walks of length 3 through v, diag(A^3); the two-step ball is the support of
+    row v of A + A^2, without v."""
+    rng = np.random.default_rng(seed)
+    n = 60
+    pairs = rng.integers(0, n, size=(400 + 200 * seed, 2))
+    g = synth.from_edges(n, [(int(a), int(b)) for a, b in pairs if a != b], name="rand")
+    A = _adjacency(g)
+    A2 = A @ A
+    walks3 = np.diag(A2 @ A)
+    reach = ((A + A2) > 0).astype(np.int64)
+    np.fill_diagonal(reach, 0)
+    k = A.sum(axis=1)
+    m = oracle.local_metrics(oracle.from_graph(g))
+    assert np.array_equal(m["pairs"], walks3)
+    assert np.array_equal(m["ball2"], reach.sum(axis=1))
+    ok = k >= 2
+    np.testing.assert_allclose(m["clustering"][ok], walks3[ok] / (k[ok] * (k[ok] - 1)),
+                               rtol=1e-15)
+    assert np.all(np.isnan(m["clustering"][~ok]))
+    np.testing.assert_allclose(m["controllability"], k / reach.sum(axis=1), rtol=1e-15)
+
+
+def test_local_metrics_closed_forms():
+    """K_n: clustering 1, controllability 1.  Star: centre 0 and 1; leaf NaN and
+    1/(n-1).  Path: no links among neighbours; interior two-step ball of 4.
+    Wheel (hub + rim cycle of r nodes): rim 2/3 and 1; hub 2/(r-1)."""
+    m = oracle.local_metrics(oracle.from_graph(synth.complete_graph(7)))
+    assert np.all(m["pairs"] == 30) and np.all(m["ball2"] == 6)
+    assert np.all(m["clustering"] == 1.0) and np.all(m["controllability"] == 1.0)
+    n = 9
+    m = oracle.local_metrics(oracle.from_graph(synth.star_graph(n)))
+    assert m["clustering"][0] == 0.0 and m["controllability"][0] == 1.0
+    assert np.all(np.isnan(m["clustering"][1:])) and np.all(m["ball2"][1:] == n - 1)
+    np.testing.assert_allclose(m["controllability"][1:], 1.0 / (n - 1), rtol=1e-15)
+    m = oracle.local_metrics(oracle.from_graph(synth.path_graph(10)))
+    assert np.all(m["pairs"] == 0)
+    assert list(m["ball2"]) == [2, 3] + [4] * 6 + [3, 2]
+    np.testing.assert_allclose(m["controllability"][2:-2], 0.5)
+    r = 8
+    edges = [(0, i) for i in range(1, r + 1)] + [(i, i % r + 1) for i in range(1, r + 1)]
+    m = oracle.local_metrics(oracle.from_graph(synth.from_edges(r + 1, edges, name="wheel")))
+    assert m["pairs"][0] == 2 * r and m["ball2"][0] == r
+    np.testing.assert_allclose(m["clustering"][0], 2 / (r - 1), rtol=1e-15)
+    assert np.all(m["pairs"][1:] == 4) and np.all(m["ball2"][1:] == r)
+    np.testing.assert_allclose(m["clustering"][1:], 2 / 3, rtol=1e-15)
+    np.testing.assert_allclose(m["controllability"][1:], 3 / r, rtol=1e-15)
+
+
+def test_local_metrics_isolated_nodes_and_subsets():
+    g = synth.from_edges(5, [(0, 1), (1, 2), (0, 2)], name="triangle+2")
+    m = oracle.local_metrics(oracle.from_graph(g))
+    assert list(m["pairs"]) == [2, 2, 2, 0, 0] and list(m["ball2"]) == [2, 2, 2, 0, 0]
+    assert np.all(np.isnan(m["clustering"][3:])) and np.all(np.isnan(m["controllability"][3:]))
+    g = synth.grid_graph(3, 40, 30)
+    csr = oracle.from_graph(g)
+    full = oracle.local_metrics(csr)
+    sub = np.array([g.n - 1, 0, 17, 17, g.n // 2], np.uint32)
+    part = oracle.local_metrics(csr, nodes=sub)
+    for key in ("pairs", "ball2"):
+        assert np.array_equal(part[key], full[key][sub])
