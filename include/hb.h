@@ -391,6 +391,34 @@ typedef struct {
 hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out);
 
 /*
+ * Local VGA metrics (Sec. 3.3, "Metric derivation": exact, from the
+ * neighbourhoods, independent of the HLL), per node v with k = deg(v); n
+ * entries each, caller-owned host arrays or NULL to skip:
+ *  - pairs: ordered pairs (a, b) of neighbours of v that are adjacent, i.e. the
+ *    sum over neighbours a of |N(a) intersect N(v)| (each link among the
+ *    neighbours counts twice);
+ *  - ball2: |B(v, 2)| - 1, the nodes other than v within two steps;
+ *  - clustering: pairs / (k (k - 1)), the Watts & Strogatz (1998) coefficient
+ *    (NaN for k < 2);
+ *  - controllability: k / ball2, the first-step neighbourhood over the
+ *    two-step one (Turner et al. 2001; NaN for an isolated node).
+ * The paper names these metrics without formulas; the definitions above are the
+ * standard ones it cites.  Work is the sum over edges (v, w) of the number of
+ * runs of consecutive ids in w's row.  Each workgroup keeps two bitmaps of n
+ * bits in LDS, so n is limited by the device's LDS per workgroup (HB_EINVAL
+ * beyond it: n <= 654,976 with 160 KiB).  Temporary device memory: the run list
+ * of the graph (8 bytes per run) plus 12 n bytes; HB_ENOMEM when it does not
+ * fit.  Blocking.
+ */
+typedef struct {
+    uint64_t *pairs;
+    uint32_t *ball2;
+    double *clustering, *controllability;
+} hb_local_out;
+
+hb_status hb_local_metrics(hb_graph *g, hb_local_out *out);
+
+/*
  * Copy up to cap autotuner cache entries to out (caller-owned; NULL with
  * cap 0 only counts) and the number of entries to *count.  Host-only.
  */

@@ -121,6 +121,12 @@ class _VgaOut(ctypes.Structure):
     _fields_ = [(name, dblp) for name in VGA_METRICS]
 
 
+class _LocalOut(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.POINTER(ctypes.c_uint64)),
+                ("ball2", ctypes.POINTER(ctypes.c_uint32)),
+                ("clustering", dblp), ("controllability", dblp)]
+
+
 class _Job(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("p", ctypes.c_uint32), ("depth_limit", ctypes.c_uint32),
                 ("hash_seed", ctypes.c_uint64)]
@@ -192,6 +198,8 @@ def _lib():
         L.hb_tune_clear.restype = st
         L.hb_vga_metrics.argtypes = [ctypes.c_void_p, dblp, ctypes.POINTER(_VgaOut)]
         L.hb_vga_metrics.restype = st
+        L.hb_local_metrics.argtypes = [ctypes.c_void_p, ctypes.POINTER(_LocalOut)]
+        L.hb_local_metrics.restype = st
         L.hb_copy_probe.argtypes = [ctypes.c_uint64, ctypes.c_uint32, dblp]
         L.hb_copy_probe.restype = st
         _LIB = L
@@ -336,6 +344,20 @@ class Graph:
         o = _VgaOut(*[_ptr(arrays[name], ctypes.c_double) for name in VGA_METRICS])
         _check(_lib().hb_vga_metrics(self._h, _ptr(sd, ctypes.c_double), ctypes.byref(o)))
         return arrays
+
+    def local_metrics(self) -> dict:
+        """hb_local_metrics: exact local metrics of every node (Sec. 3.3) -- ordered
+        adjacent neighbour pairs, |B(v, 2)| - 1, clustering, controllability."""
+        if self._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        out = {"pairs": np.empty(self.n, np.uint64), "ball2": np.empty(self.n, np.uint32),
+               "clustering": np.empty(self.n, np.float64),
+               "controllability": np.empty(self.n, np.float64)}
+        o = _LocalOut(_ptr(out["pairs"], ctypes.c_uint64), _ptr(out["ball2"], ctypes.c_uint32),
+                      _ptr(out["clustering"], ctypes.c_double),
+                      _ptr(out["controllability"], ctypes.c_double))
+        _check(_lib().hb_local_metrics(self._h, ctypes.byref(o)))
+        return out
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

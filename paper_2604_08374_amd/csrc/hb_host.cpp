@@ -1062,6 +1062,74 @@ hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out) {
     return HB_OK;
 }
 
+hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
+    if (!g || !out) return fail(HB_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    HB_HIP(hipSetDevice(g->device));
+    const uint32_t n = g->n;
+    int lim = 0;
+    HB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device));
+    const uint64_t lds = 8ull * ((n + 31ull) / 32ull);
+    if (lds + 96ull > (uint64_t)lim)
+        return fail(HB_EINVAL,
+                    "local metrics: n = %u needs %llu bytes of LDS per workgroup; the device "
+                    "has %d",
+                    n, (unsigned long long)(lds + 96ull), lim);
+    std::vector<uint32_t> cnt(n);
+    std::vector<uint64_t> off((size_t)n + 1);
+    uint32_t *d_cnt = nullptr, *d_ball = nullptr;
+    uint64_t *d_off = nullptr, *d_pairs = nullptr;
+    uint2 *d_runs = nullptr;
+    double *d_clus = nullptr, *d_ctrl = nullptr;
+    // pass 1: runs per row; the host sums them into offsets
+    hipError_t e = hipMalloc(&d_cnt, sizeof(uint32_t) * n);
+    if (e == hipSuccess)
+        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, d_cnt, nullptr, nullptr, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) {
+        off[0] = 0;
+        for (uint32_t v = 0; v < n; ++v) off[v + 1] = off[v] + cnt[v];
+        e = hipMalloc(&d_off, sizeof(uint64_t) * (n + 1ull));
+    }
+    if (e == hipSuccess) e = hipMalloc(&d_runs, sizeof(uint2) * std::max<uint64_t>(off[n], 1));
+    if (e == hipSuccess) e = hipMalloc(&d_pairs, sizeof(uint64_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_ball, sizeof(uint32_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_clus, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_ctrl, sizeof(double) * n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, off.data(), sizeof(uint64_t) * (n + 1ull),
+                           hipMemcpyHostToDevice, g->stream);
+    // pass 2: the runs, then the metrics
+    if (e == hipSuccess)
+        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, nullptr, d_off, d_runs, g->stream);
+    if (e == hipSuccess)
+        e = hbk::launch_local(d_runs, d_off, g->d_degrees, n, g->d_order, d_pairs, d_ball, d_clus,
+                              d_ctrl, g->stream);
+    if (e == hipSuccess && out->pairs)
+        e = hipMemcpyAsync(out->pairs, d_pairs, sizeof(uint64_t) * n, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess && out->ball2)
+        e = hipMemcpyAsync(out->ball2, d_ball, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess && out->clustering)
+        e = hipMemcpyAsync(out->clustering, d_clus, sizeof(double) * n, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess && out->controllability)
+        e = hipMemcpyAsync(out->controllability, d_ctrl, sizeof(double) * n,
+                           hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
+    for (void *p : {(void *)d_cnt, (void *)d_off, (void *)d_runs, (void *)d_pairs, (void *)d_ball,
+                    (void *)d_clus, (void *)d_ctrl})
+        (void)hipFree(p);
+    if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "local metrics: out of device memory");
+    if (e != hipSuccess) return hip_fail(e, "local metrics");
+    return HB_OK;
+}
+
 hb_status hb_release_cache(void) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_batch.release();

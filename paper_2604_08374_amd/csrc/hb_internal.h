@@ -114,6 +114,21 @@ hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint3
                       const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
                       hipStream_t stream);
 
+// Maximal runs of consecutive ids of every row.  runs == null: cnt[v] = the
+// number of runs of row v.  Otherwise runs[run_off[v] ...] = the runs of row v
+// as inclusive (first, last) pairs; run_off has n + 1 entries.
+hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
+                           uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
+                           hipStream_t stream);
+
+// Exact local metrics of every node from the run lists (null outputs skipped):
+// ordered adjacent neighbour pairs, |B(v, 2)| - 1, clustering, controllability.
+// Needs 8 (n + 31) / 32 bytes of LDS per workgroup of local_threads() threads.
+uint32_t local_threads();
+hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32_t *degrees,
+                        uint32_t n, const uint32_t *order, uint64_t *pairs, uint32_t *ball2,
+                        double *clustering, double *controllability, hipStream_t stream);
+
 // Fill count u32 words with value (used instead of hipMemsetAsync so the
 // sequence stays capturable).
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream);

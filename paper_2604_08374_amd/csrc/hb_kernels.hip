@@ -139,6 +139,21 @@ __device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
                                                                   __builtin_bit_cast(u16x2, b)));
 }
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Max of three packed 16-bit halves, per half, as one packed fp16 maximum3.
+// A half below 0x7C00 is a non-negative finite fp16 value, and on those the fp16
+// order is the unsigned integer order (the kernels keep fp16 denormals, so the
+// halves below 0x0400 compare exactly too).  8-bit registers are at most 61, so
+// every half an 8-bit accumulator forms stays below 0x3E00.
+__device__ __forceinline__ uint32_t pk_max3_u16(uint32_t a, uint32_t b, uint32_t c) {
+    const f16x2 x = __builtin_bit_cast(f16x2, a);
+    const f16x2 y = __builtin_bit_cast(f16x2, b);
+    const f16x2 z = __builtin_bit_cast(f16x2, c);
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+}
+
 // Nibble-wise max accumulator for one dword of 8 4-bit registers.  a[k]
 // holds the dword shifted left by 12 - 4k, which puts nibble k at the top of
 // the low 16-bit half and nibble k + 4 at the top of the high half; a packed
@@ -153,6 +168,10 @@ struct Max8 {
         a[3] = w;
     }
     __device__ __forceinline__ void add(uint32_t w);
+    __device__ __forceinline__ void add2(uint32_t w0, uint32_t w1) {
+        add(w0);
+        add(w1);
+    }
     __device__ __forceinline__ uint32_t value() const {
         return ((a[0] >> 12) & 0x000F000Fu) | ((a[1] >> 8) & 0x00F000F0u) |
                ((a[2] >> 4) & 0x0F000F00u) | (a[3] & 0xF000F000u);
@@ -162,13 +181,17 @@ struct Max8 {
 // Byte-wise max accumulator for one dword of 4 registers.  hi tracks bytes
 // 1 and 3 (the high byte of each 16-bit half); lo tracks bytes 0 and 2 after
 // a left shift by 8 moves them into the high bytes.  The low bytes of both
-// words are don't-care.
+// words are don't-care.  3 VALU ops per dword for one row, 4 for two.
 struct Max4 {
     uint32_t lo, hi;
     __device__ __forceinline__ void init(uint32_t w) { lo = w << 8; hi = w; }
     __device__ __forceinline__ void add(uint32_t w) {
         hi = pk_max_u16(hi, w);
         lo = pk_max_u16(lo, w << 8);
+    }
+    __device__ __forceinline__ void add2(uint32_t w0, uint32_t w1) {
+        hi = pk_max3_u16(hi, w0, w1);
+        lo = pk_max3_u16(lo, w0 << 8, w1 << 8);
     }
     __device__ __forceinline__ uint32_t value() const {
         return ((lo >> 8) & 0x00FF00FFu) | (hi & 0xFF00FF00u);
@@ -449,14 +472,23 @@ struct NodeAcc {
 #pragma unroll
             for (int s = 0; s < C::RPL; ++s)
                 x[u][s] = *reinterpret_cast<const uint4 *>(src[u] + slot_offset<C>(slice, lane, s));
+        // rows in pairs: a three-input max takes two rows per op
 #pragma unroll
-        for (int u = 0; u < N; ++u)
+        for (int u = 0; u + 1 < N; u += 2)
 #pragma unroll
             for (int s = 0; s < C::RPL; ++s) {
-                m[s][0].add(x[u][s].x);
-                m[s][1].add(x[u][s].y);
-                m[s][2].add(x[u][s].z);
-                m[s][3].add(x[u][s].w);
+                m[s][0].add2(x[u][s].x, x[u + 1][s].x);
+                m[s][1].add2(x[u][s].y, x[u + 1][s].y);
+                m[s][2].add2(x[u][s].z, x[u + 1][s].z);
+                m[s][3].add2(x[u][s].w, x[u + 1][s].w);
+            }
+        if (N % 2)
+#pragma unroll
+            for (int s = 0; s < C::RPL; ++s) {
+                m[s][0].add(x[N - 1][s].x);
+                m[s][1].add(x[N - 1][s].y);
+                m[s][2].add(x[N - 1][s].z);
+                m[s][3].add(x[N - 1][s].w);
             }
     }
 };
@@ -1007,6 +1039,161 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
     o[7 * (uint64_t)n] = md * (double)k;                        // point first moment
 }
 
+// ---------------------------------------------------------------- local metrics
+// Clustering and controllability need, for every node v, the neighbour lists of
+// all its neighbours.  Visibility rows are mostly runs of consecutive ids, so
+// each row is first turned into its maximal runs [a, b] (inclusive), and the
+// metrics then work run by run on two bitmaps of n bits in LDS: N(v), and the
+// union of the neighbours' rows.  One wave per node builds the run lists.
+//
+// Pass 1 (runs == nullptr): cnt[v] = number of runs of row v.  Pass 2: the runs
+// of row v at runs[run_off[v] ...].
+__global__ __launch_bounds__(256) void row_runs_kernel(const uint8_t *__restrict__ bytes,
+                                                       const uint64_t *__restrict__ offsets,
+                                                       uint32_t n, uint32_t *__restrict__ cnt,
+                                                       const uint64_t *__restrict__ run_off,
+                                                       uint2 *__restrict__ runs) {
+    const uint32_t lane = lane_id();
+    const uint32_t v = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (v >= n) return;
+    RowDecoder dec;
+    const uint64_t row_end = offsets[v + 1];
+    uint64_t at = runs ? run_off[v] : 0;  // index of the next run to start
+    bool open = false;                    // a run is open and ends at last
+    uint32_t last = 0;
+    for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
+        uint32_t c;
+        const uint32_t ids = dec.chunk(bytes, base, row_end, c);
+        if (c == 0) continue;
+        const bool in = lane < c;
+        uint32_t prev = wave_shr1(ids);
+        if (lane == 0) prev = last;
+        const bool joins = in && (lane > 0 || open) && ids == prev + 1u;
+        const uint64_t starts = ballot(in && !joins);
+        if (runs) {
+            const uint32_t before = (uint32_t)__builtin_popcountll(starts & ((1ull << lane) - 1ull));
+            if (in && !joins) runs[at + before].x = ids;
+            // lane e ends a run when lane e + 1 starts one; the chunk's last id
+            // stays open
+            const bool ends = lane + 1u < c && ((starts >> (lane + 1u)) & 1ull);
+            if (ends) runs[at + before + ((starts >> lane) & 1ull) - 1u].y = ids;
+            if (open && (starts & 1ull) && lane == 0) runs[at - 1u].y = last;
+        }
+        at += (uint64_t)__builtin_popcountll(starts);
+        last = readlane(ids, c - 1u);
+        open = true;
+    }
+    if (runs) {
+        if (open && lane == 0) runs[at - 1u].y = last;
+    } else if (lane == 0) {
+        cnt[v] = (uint32_t)at;
+    }
+}
+
+// Popcount of bits [a, b] of an LDS bitmap.
+__device__ __forceinline__ uint32_t range_popc(const uint32_t *bm, uint32_t a, uint32_t b) {
+    const uint32_t wa = a >> 5, wb = b >> 5;
+    const uint32_t lo = ~0u << (a & 31u), hi = ~0u >> (31u - (b & 31u));
+    if (wa == wb) return (uint32_t)__builtin_popcount(bm[wa] & lo & hi);
+    uint32_t c = (uint32_t)__builtin_popcount(bm[wa] & lo) + (uint32_t)__builtin_popcount(bm[wb] & hi);
+    for (uint32_t i = wa + 1u; i < wb; ++i) c += (uint32_t)__builtin_popcount(bm[i]);
+    return c;
+}
+
+// Set bits [a, b] of an LDS bitmap (other lanes may set overlapping ranges).
+__device__ __forceinline__ void range_set(uint32_t *bm, uint32_t a, uint32_t b) {
+    const uint32_t wa = a >> 5, wb = b >> 5;
+    const uint32_t lo = ~0u << (a & 31u), hi = ~0u >> (31u - (b & 31u));
+    if (wa == wb) {
+        atomicOr(&bm[wa], lo & hi);
+        return;
+    }
+    atomicOr(&bm[wa], lo);
+    for (uint32_t i = wa + 1u; i < wb; ++i) atomicOr(&bm[i], ~0u);
+    atomicOr(&bm[wb], hi);
+}
+
+// One workgroup per node v (in the processing order when given).  LDS holds two
+// bitmaps of `words` 32-bit words: N(v), and U = the union of the rows of v's
+// neighbours.  The pairs count is the sum over neighbours w of |N(w) & N(v)|,
+// taken run by run of N(w); B(v, 2) \ {v} is (N(v) | U) without v.  The waves
+// split the neighbours by id modulo the wave count; the lanes split a
+// neighbour's runs.
+constexpr uint32_t kLocalWaves = 8;
+
+__global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
+    const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
+    const uint32_t *__restrict__ degrees, uint32_t n, uint32_t words,
+    const uint32_t *__restrict__ order, uint64_t *__restrict__ pairs_out,
+    uint32_t *__restrict__ ball2_out, double *__restrict__ clustering,
+    double *__restrict__ controllability) {
+    extern __shared__ uint32_t s_bits[];
+    __shared__ uint64_t s_pairs[kLocalWaves];
+    __shared__ uint32_t s_reach[kLocalWaves];
+    uint32_t *nv = s_bits, *un = s_bits + words;
+    uint32_t v = xcd_block(blockIdx.x, gridDim.x);
+    if (v >= n) return;  // uniform per workgroup
+    if (order) v = order[v];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    constexpr uint32_t T = kLocalWaves * kWave;
+    for (uint32_t i = tid; i < 2u * words; i += T) s_bits[i] = 0u;
+    __syncthreads();
+    const uint64_t rs = run_off[v], re = run_off[v + 1];
+    // a run outside [0, n) or reversed is skipped (the loader validated the
+    // rows, so none occurs; the check keeps every LDS index in bounds)
+    for (uint64_t r = rs + tid; r < re; r += T) {
+        const uint2 x = runs[r];
+        if (x.x <= x.y && x.y < n) range_set(nv, x.x, x.y);
+    }
+    __syncthreads();
+    uint64_t pairs = 0;
+    for (uint64_t r = rs; r < re; ++r) {
+        const uint2 x = runs[r];
+        if (!(x.x <= x.y && x.y < n)) continue;
+        // first id >= x.x that is this wave's
+        for (uint64_t w = x.x + ((wave + kLocalWaves - x.x % kLocalWaves) % kLocalWaves); w <= x.y;
+             w += kLocalWaves) {
+            const uint64_t s = run_off[w], e = run_off[w + 1];
+            for (uint64_t q = s + lane; q < e; q += kWave) {
+                const uint2 y = runs[q];
+                if (!(y.x <= y.y && y.y < n)) continue;
+                pairs += range_popc(nv, y.x, y.y);
+                range_set(un, y.x, y.y);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t reach = 0;
+    for (uint32_t i = tid; i < words; i += T) reach += (uint32_t)__builtin_popcount(nv[i] | un[i]);
+#pragma unroll
+    for (uint32_t mask = 1; mask < kWave; mask <<= 1) {
+        reach += shfl_xor(reach, mask);
+        const uint32_t lo = shfl_xor((uint32_t)pairs, mask), hi = shfl_xor((uint32_t)(pairs >> 32), mask);
+        pairs += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0) {
+        s_pairs[wave] = pairs;
+        s_reach[wave] = reach;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    uint64_t links = 0;
+    uint32_t ball = 0;
+    for (uint32_t i = 0; i < kLocalWaves; ++i) {
+        links += s_pairs[i];
+        ball += s_reach[i];
+    }
+    ball -= ((nv[v >> 5] | un[v >> 5]) >> (v & 31u)) & 1u;  // v itself
+    const uint32_t k = degrees[v];
+    const double nan = __builtin_nan("");
+    if (pairs_out) pairs_out[v] = links;
+    if (ball2_out) ball2_out[v] = ball;
+    if (clustering)  // Watts & Strogatz: links among neighbours over k (k - 1)
+        clustering[v] = k >= 2u ? (double)links / ((double)k * (double)(k - 1u)) : nan;
+    if (controllability)  // first-step neighbourhood over the two-step one
+        controllability[v] = ball >= 1u ? (double)k / (double)ball : nan;
+}
+
 __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = value;
@@ -1259,6 +1446,32 @@ hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint3
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(vga_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, bytes, offsets,
                        degrees, comp_size, sum_d, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
+                           uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
+                           hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(row_runs_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, bytes, offsets, n,
+                       cnt, run_off, runs);
+    return hipGetLastError();
+}
+
+uint32_t local_threads() { return kLocalWaves * kWave; }
+
+hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32_t *degrees,
+                        uint32_t n, const uint32_t *order, uint64_t *pairs, uint32_t *ball2,
+                        double *clustering, double *controllability, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t words = (n + 31u) / 32u;
+    const size_t lds = sizeof(uint32_t) * 2u * words;
+    hipError_t e = hipFuncSetAttribute((const void *)local_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(local_kernel, dim3(n), dim3(kLocalWaves * kWave), lds, stream, runs,
+                       run_off, degrees, n, words, order, pairs, ball2, clustering,
+                       controllability);
     return hipGetLastError();
 }
 
