@@ -368,7 +368,9 @@ __device__ __forceinline__ void init_node(uint8_t *__restrict__ cur, double *__r
 // nodes per workgroup (1, 2 or 4, chosen at launch).
 template <class C>
 __device__ __forceinline__ void node_of(uint32_t blk, uint32_t &v, uint32_t &slice) {
-    const uint32_t wave = threadIdx.x / kWave;
+    // the wave index is the same in all lanes; readfirstlane tells the compiler
+    // so, which keeps v, the row bounds and every loop over the row scalar
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     v = (C::WAVES == 1) ? blk * (blockDim.x / kWave) + wave : blk;
     slice = (C::WAVES == 1) ? 0u : wave;
 }
@@ -640,12 +642,15 @@ struct RunGather {
         // fewer loads in flight than the per-edge kernel: this kernel runs at
         // six waves per SIMD, where the registers of eight would spill
         constexpr int U = C::RPL >= kRunLoads ? 1 : kRunLoads / C::RPL;
-        for (uint32_t k = 0; k < qn; k += U * C::G) {
+        // qn is wave-uniform; saying so keeps the loop control and the index
+        // clamp on the scalar unit
+        const uint32_t cnt = C::G == 1 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)qn) : qn;
+        for (uint32_t k = 0; k < cnt; k += U * C::G) {
             const uint8_t *src[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t idx = k + (uint32_t)u * (uint32_t)C::G + (C::G == 1 ? 0u : grp);
-                uint32_t row = q[idx < qn ? idx : k];
+                uint32_t row = q[idx < cnt ? idx : k];
                 if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
                 src[u] = tbl + (uint64_t)row * C::M;
             }
@@ -707,17 +712,21 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     uint64_t base = offsets[v];
     uint32_t b_next = base + lane < row_end ? (uint32_t)bytes[base + lane] : 0u;
     for (; base < row_end; base += kWave) {
-        const bool valid = base + lane < row_end;
+        // lanes past the row's end hold byte 0; the chunk's lane mask is scalar
+        const uint64_t left = row_end - base;
+        const uint64_t vmask = left >= kWave ? ~0ull : (1ull << left) - 1ull;
+        const bool valid = (vmask >> lane) & 1ull;
         const uint32_t b = b_next;
-        if (base + kWave < row_end)
-            b_next = base + kWave + lane < row_end ? (uint32_t)bytes[base + kWave + lane] : 0u;
-        const uint64_t term = ballot(valid && !(b & 0x80u));
-        const uint64_t cont = ballot(valid && (b & 0x80u));
+        if (left > kWave) b_next = lane < left - kWave ? (uint32_t)bytes[base + kWave + lane] : 0u;
+        const uint64_t term = ballot(b < 0x80u) & vmask;
+        const uint64_t cont = vmask & ~term;
         // Single-byte varints of value 1 after the row's first id are deltas of
         // one: they only extend the open run.  When few varints in the chunk
         // are anything else, walk those few in scalar code.
-        const uint64_t after_term = (term << 1) | (dec.carry_sh == 0u ? 1ull : 0ull);
-        uint64_t trivial = ballot(valid && b == 0x01u) & after_term;
+        // lane 0 starts a varint unless one is carried in (carry_sh is 0 or
+        // at least 7); the shift form keeps the test on the scalar unit
+        const uint64_t after_term = (term << 1) | (uint64_t)((dec.carry_sh - 1u) >> 31);
+        uint64_t trivial = ballot(b == 0x01u) & after_term;
         if (!have) trivial &= ~(term & (0ull - term));  // the row's first id is absolute
         const uint64_t special = term & ~trivial;
         if (__builtin_popcountll(special) <= kScalarWalk) {
@@ -1004,7 +1013,8 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
                                                   const uint32_t *__restrict__ comp_size,
                                                   const double *__restrict__ sum_d, uint32_t n,
                                                   double *__restrict__ out) {
-    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const uint32_t lane = lane_id();
     const uint32_t v = blockIdx.x * (blockDim.x / kWave) + wave;
     if (v >= n) return;
     double part = 0.0;
@@ -1054,7 +1064,8 @@ __global__ __launch_bounds__(256) void row_runs_kernel(const uint8_t *__restrict
                                                        const uint64_t *__restrict__ run_off,
                                                        uint2 *__restrict__ runs) {
     const uint32_t lane = lane_id();
-    const uint32_t v = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t v = blockIdx.x * (blockDim.x / kWave) +
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (v >= n) return;
     RowDecoder dec;
     const uint64_t row_end = offsets[v + 1];
