@@ -558,6 +558,19 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(off, deg, data, n, p, args.seed, args.cpu_seconds)
+    if not args.no_extras:
+        # exact local metrics (clustering, controllability) of the same graph: one
+        # blocking call, run lists built inside it
+        log("local metrics: clustering and controllability of every node ...")
+        t0 = time.perf_counter()
+        lm = G.local_metrics()
+        t1 = time.perf_counter()
+        line["local_metrics"] = {
+            "workload": line["config"]["workload"], "ms": (t1 - t0) * 1e3,
+            "nodes_per_s": n / (t1 - t0),
+            "median_clustering": float(np.nanmedian(lm["clustering"])),
+            "median_controllability": float(np.nanmedian(lm["controllability"]))}
+        log(f"local metrics: {(t1 - t0) * 1e3:.0f} ms")
     G.free()
     del off, deg, data
     if not args.no_extras:

@@ -406,7 +406,7 @@ hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out);
  * standard ones it cites.  Work is the sum over edges (v, w) of the number of
  * runs of consecutive ids in w's row.  Each workgroup keeps two bitmaps of n
  * bits in LDS, so n is limited by the device's LDS per workgroup (HB_EINVAL
- * beyond it: n <= 654,976 with 160 KiB).  Temporary device memory: the run list
+ * beyond it: n <= 654,592 with 160 KiB).  Temporary device memory: the run list
  * of the graph (8 bytes per run) plus 12 n bytes; HB_ENOMEM when it does not
  * fit.  Blocking.
  */

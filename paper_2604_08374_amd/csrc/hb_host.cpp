@@ -1069,12 +1069,13 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
     const uint32_t n = g->n;
     int lim = 0;
     HB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device));
-    const uint64_t lds = 8ull * ((n + 31ull) / 32ull);
-    if (lds + 96ull > (uint64_t)lim)
+    // two bitmaps of n bits, plus 12 bytes of partial sums per wave
+    const uint64_t lds = 8ull * ((n + 31ull) / 32ull) + 12ull * (hbk::local_threads() / 64u);
+    if (lds > (uint64_t)lim)
         return fail(HB_EINVAL,
                     "local metrics: n = %u needs %llu bytes of LDS per workgroup; the device "
                     "has %d",
-                    n, (unsigned long long)(lds + 96ull), lim);
+                    n, (unsigned long long)lds, lim);
     std::vector<uint32_t> cnt(n);
     std::vector<uint64_t> off((size_t)n + 1);
     uint32_t *d_cnt = nullptr, *d_ball = nullptr;

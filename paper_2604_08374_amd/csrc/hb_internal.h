@@ -123,7 +123,8 @@ hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32
 
 // Exact local metrics of every node from the run lists (null outputs skipped):
 // ordered adjacent neighbour pairs, |B(v, 2)| - 1, clustering, controllability.
-// Needs 8 (n + 31) / 32 bytes of LDS per workgroup of local_threads() threads.
+// Needs 8 (n + 31) / 32 bytes of LDS, plus 12 per wave, per workgroup of
+// local_threads() threads.
 uint32_t local_threads();
 hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32_t *degrees,
                         uint32_t n, const uint32_t *order, uint64_t *pairs, uint32_t *ball2,

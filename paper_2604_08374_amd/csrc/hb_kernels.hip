@@ -616,13 +616,14 @@ __global__ __launch_bounds__(C::THREADS) void union_kernel(
 // and level 0 is cur itself.  The result is the same registers as the
 // per-edge kernel.
 constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
+static_assert(kQueueCap % 4 == 0, "the flush reads the queue 16 bytes at a time");
 constexpr int kRunLoads = 4;               // 16 B/lane loads in flight per flush round
 // chunks with at most this many special varints take the scalar walk; the
 // rest take the vector path.  The walk runs on the scalar unit, which the four
 // SIMDs of a CU share, so a low threshold balances it against the VALU
-// (city, p = 10, one launch: 27.1 ms at 8, 26.0 at 4, 25.2 at 3, 24.9 at 2,
-// 25.6 at 1)
-constexpr int kScalarWalk = 2;
+// (city, p = 10, one launch: 24.0 ms at 3, 21.7 at 2, 20.6 at 1, 21.3 at 0,
+// with the chunk and flush loops already on the scalar unit)
+constexpr int kScalarWalk = 1;
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
 template <class C>
@@ -647,12 +648,28 @@ struct RunGather {
         const uint32_t cnt = C::G == 1 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)qn) : qn;
         for (uint32_t k = 0; k < cnt; k += U * C::G) {
             const uint8_t *src[U];
+            if constexpr (C::G == 1 && U == 4) {
+                // the four entries in one 16-byte LDS read (k is a multiple of
+                // 4 and the queue is 16-byte aligned); entries at cnt and past
+                // it are stale, so they repeat entry k
+                const uint4 r = *reinterpret_cast<const uint4 *>(q + k);
+                const uint32_t e[4] = {r.x, r.y, r.z, r.w};
+                const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)e[0]);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t idx = k + (uint32_t)u * (uint32_t)C::G + (C::G == 1 ? 0u : grp);
-                uint32_t row = q[idx < cnt ? idx : k];
-                if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
-                src[u] = tbl + (uint64_t)row * C::M;
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t ru =
+                        u == 0 ? r0 : (uint32_t)__builtin_amdgcn_readfirstlane((int)e[u]);
+                    src[u] = tbl + (uint64_t)(k + (uint32_t)u < cnt ? ru : r0) * C::M;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t idx =
+                        k + (uint32_t)u * (uint32_t)C::G + (C::G == 1 ? 0u : grp);
+                    uint32_t row = q[idx < cnt ? idx : k];
+                    if (C::G == 1) row = (uint32_t)__builtin_amdgcn_readfirstlane((int)row);
+                    src[u] = tbl + (uint64_t)row * C::M;
+                }
             }
             acc.gather(src, slice, lane);
         }
@@ -844,7 +861,7 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
     uint32_t n, uint32_t t, const uint32_t *__restrict__ order) {
-    __shared__ uint32_t s_queue[C::THREADS / kWave][kQueueCap];
+    __shared__ __attribute__((aligned(16))) uint32_t s_queue[C::THREADS / kWave][kQueueCap];
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
@@ -921,7 +938,8 @@ template <class C, bool RUNS>
 __global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union_kernel(
     BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ block_base, uint32_t nlist) {
-    __shared__ uint32_t s_queue[RUNS ? C::THREADS / kWave : 1][RUNS ? kQueueCap : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t
+        s_queue[RUNS ? C::THREADS / kWave : 1][RUNS ? kQueueCap : 1];
     const uint32_t i = find_job(block_base, nlist, blockIdx.x);
     const BatchJob &J = jobs[list[i]];
     if (J.done) return;  // uniform per workgroup
@@ -1128,9 +1146,11 @@ __device__ __forceinline__ void range_set(uint32_t *bm, uint32_t a, uint32_t b) 
 // bitmaps of `words` 32-bit words: N(v), and U = the union of the rows of v's
 // neighbours.  The pairs count is the sum over neighbours w of |N(w) & N(v)|,
 // taken run by run of N(w); B(v, 2) \ {v} is (N(v) | U) without v.  The waves
-// split the neighbours by id modulo the wave count; the lanes split a
-// neighbour's runs.
-constexpr uint32_t kLocalWaves = 8;
+// split the neighbours; the lanes split a neighbour's runs.
+// city graph, all nodes: 18.5 s at 8 waves and 1 load in flight per lane,
+// 16.1 s at 8 and 4, 10.2 s at 16 and 4
+constexpr uint32_t kLocalWaves = 16;
+constexpr uint32_t kLocalLoads = 4;
 
 __global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
@@ -1145,7 +1165,8 @@ __global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
     uint32_t v = xcd_block(blockIdx.x, gridDim.x);
     if (v >= n) return;  // uniform per workgroup
     if (order) v = order[v];
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid / kWave));
     constexpr uint32_t T = kLocalWaves * kWave;
     for (uint32_t i = tid; i < 2u * words; i += T) s_bits[i] = 0u;
     __syncthreads();
@@ -1158,18 +1179,26 @@ __global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
     }
     __syncthreads();
     uint64_t pairs = 0;
+    // wave i takes the neighbours w = i mod kLocalWaves, so the waves work on
+    // adjacent rows at the same time; its lanes take the neighbour's runs,
+    // kLocalLoads per lane in flight
     for (uint64_t r = rs; r < re; ++r) {
         const uint2 x = runs[r];
         if (!(x.x <= x.y && x.y < n)) continue;
-        // first id >= x.x that is this wave's
-        for (uint64_t w = x.x + ((wave + kLocalWaves - x.x % kLocalWaves) % kLocalWaves); w <= x.y;
-             w += kLocalWaves) {
+        const uint32_t w0 = x.x + (wave + kLocalWaves - x.x % kLocalWaves) % kLocalWaves;
+        for (uint64_t w = w0; w <= x.y; w += kLocalWaves) {
             const uint64_t s = run_off[w], e = run_off[w + 1];
-            for (uint64_t q = s + lane; q < e; q += kWave) {
-                const uint2 y = runs[q];
-                if (!(y.x <= y.y && y.y < n)) continue;
-                pairs += range_popc(nv, y.x, y.y);
-                range_set(un, y.x, y.y);
+            for (uint64_t q = s + lane; q < e; q += kLocalLoads * kWave) {
+                uint2 y[kLocalLoads];
+#pragma unroll
+                for (uint32_t u = 0; u < kLocalLoads; ++u)
+                    y[u] = q + u * kWave < e ? runs[q + u * kWave] : make_uint2(1u, 0u);
+#pragma unroll
+                for (uint32_t u = 0; u < kLocalLoads; ++u) {
+                    if (!(y[u].x <= y[u].y && y[u].y < n)) continue;
+                    pairs += range_popc(nv, y[u].x, y[u].y);
+                    range_set(un, y[u].x, y[u].y);
+                }
             }
         }
     }
