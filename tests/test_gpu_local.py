@@ -40,7 +40,7 @@ def _wheel(r):
 
 
 @pytest.mark.parametrize("gname", ["tiny", "rect90x70", "star", "complete", "path", "wheel",
-                                   "random", "isolated"])
+                                   "random", "isolated", "single", "pair"])
 def test_local_metrics_match_oracle(hb, gname):
     g = {"tiny": lambda: synth.tiny(5),
          "rect90x70": lambda: synth.grid_graph(4, 90, 70),
@@ -51,6 +51,8 @@ def test_local_metrics_match_oracle(hb, gname):
          # rows of several 64-byte chunks, runs of every length, many gaps
          "random": lambda: _random_graph(3, 3000, 120000, "random3000"),
          "isolated": lambda: synth.from_edges(9, [(0, 1), (1, 2), (0, 2), (4, 5)], name="iso"),
+         "single": lambda: synth.from_edges(1, [], name="single"),
+         "pair": lambda: synth.from_edges(2, [(0, 1)], name="pair"),
          }[gname]()
     ref = oracle.local_metrics(oracle.from_graph(g))
     for order in (None, "hilbert") if gname in ("tiny", "rect90x70") else (None,):
