@@ -100,3 +100,18 @@ def test_local_metrics_refuses_graphs_beyond_lds(hb):
         G.local_metrics()
     assert e.value.status == hb.HB_EINVAL
     G.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_local_metrics_city_sampled(hb):
+    """The city graph (235,770 nodes, 4.94e9 directed edges), the size and order
+    the benchmark uses: every node on the device, 16 seeded nodes in the oracle."""
+    g = synth.city(0, device="gpu")
+    print(f"[local] city n={g.n}", flush=True)
+    G = _load(hb, g, order=synth.hilbert_order(g))
+    got = G.local_metrics()
+    G.free()
+    nodes = np.random.default_rng(4).choice(g.n, size=16, replace=False).astype(np.uint32)
+    ref = oracle.local_metrics(oracle.from_graph(g), nodes=nodes)
+    _compare(got, ref, g.name, nodes)

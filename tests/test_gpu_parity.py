@@ -124,12 +124,15 @@ def test_prefix_property(hb):
 
 
 # ---------------------------------------------------------------- full-size graphs, sampled
-def _sampled_check(hb, g, p, depth, n_src=64, seed=0):
+def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None):
     """GPU run on the whole graph; the oracle recomputes sampled nodes from exact balls."""
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
-    csr = oracle.CSR(n=g.n, offsets=off, degrees=deg, bytes=data)
+    # the oracle reads its own encoding of the graph (the same bytes, checked)
+    csr = oracle.from_graph(g)
+    assert np.array_equal(csr.offsets, off) and np.array_equal(csr.degrees, deg)
+    assert np.array_equal(csr.bytes, data)
     results = {}
-    with hb.graph_load(off, deg, data) as G:
+    with hb.graph_load(off, deg, data, order=order) as G:
         for kernel in ("runs", "edges"):
             results[kernel] = G.run(p, depth, seed, registers=True, kernel=kernel)
             print(f"[parity] {kernel}: passes={results[kernel].passes} "
@@ -179,10 +182,11 @@ def _urban_graph():
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
 def test_city_sampled_bench_config(hb):
-    """The benchmark's workload and launch configuration: city graph, p = 10, depth 3."""
+    """The benchmark's workload and launch configuration: city graph, p = 10, depth 3,
+    Hilbert processing order, default schedule."""
     g = synth.city(0, device="gpu")
     print(f"[parity] city n={g.n} E={g.n_edges} p=10 depth=3", flush=True)
-    res = _sampled_check(hb, g, 10, 3, n_src=64)
+    res = _sampled_check(hb, g, 10, 3, n_src=64, order=synth.hilbert_order(g))
     assert res.passes == 3
     # properties at any size: registers never below a node's own insert, values <= 65-p
     assert int(res.registers.max()) <= 55
