@@ -58,18 +58,20 @@ def node_order(g, args):
 
 
 def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None,
-                      bits: int = 8) -> int:
+                      bits: int = 8, n_runs: int = 0) -> int:
     """Bytes one union launch must move at minimum without reuse.
 
     Per gathered counter row: m bytes (2^p registers of `bits` bits) -- one row per
     directed edge for the per-edge kernel, or `rows` table rows for the run kernel;
-    the whole LEB128 stream; per node: the offsets entry (8 B), its own counter read
-    and next[v] written (2m), and the FP64 state c_prev and sum_d read and written
-    (32 B).
+    the adjacency it reads: the whole LEB128 stream for the per-edge kernel, the run
+    list (8 B per run) for the run kernel; per node: the offsets entry (8 B), its
+    own counter read and next[v] written (2m), and the FP64 state c_prev and sum_d
+    read and written (32 B).
     """
     m = (1 << p) * bits // 8
     gathered = n_edges if rows is None else rows
-    return gathered * m + n_bytes + 8 * (n + 1) + n * (2 * m + 32)
+    adjacency = n_bytes if rows is None else 8 * n_runs
+    return gathered * m + adjacency + 8 * (n + 1) + n * (2 * m + 32)
 
 
 def table_bytes(n: int, p: int, levels: int, bits: int = 8) -> int:
@@ -476,7 +478,7 @@ def main():
     levels = results[-1].table_levels
     rows = stats["table_rows"][levels] if kernel == "runs" else None
     bits = results[-1].register_bits
-    per_launch = algorithmic_bytes(n, E, data.size, p, rows, bits)
+    per_launch = algorithmic_bytes(n, E, data.size, p, rows, bits, stats["n_runs"])
     achieved = per_launch / avg_launch_s / 1e9
     lanes = results[-1].lanes_per_node
     kname = (f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs"

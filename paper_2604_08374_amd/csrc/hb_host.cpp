@@ -178,6 +178,8 @@ void graph_release(hb_graph *g) {
     (void)hipFree(g->d_hash_ids);
     (void)hipFree(g->d_degrees);
     (void)hipFree(g->d_comp);
+    (void)hipFree(g->d_runs);
+    (void)hipFree(g->d_run_off);
     (void)hipFree(g->d_sumd);
     (void)hipFree(g->d_flags);
     if (g->h_flag) (void)hipHostFree(g->h_flag);
@@ -185,6 +187,49 @@ void graph_release(hb_graph *g) {
         if (e) (void)hipEventDestroy(e);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+// Run lists of g's rows, decoded on the device from the uploaded LEB128 rows:
+// *runs (inclusive first/last pairs) and *off (n + 1 offsets), allocated here;
+// *total runs.  join_self joins the runs on both sides of v itself.
+hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **off,
+                          uint64_t *total) {
+    const uint32_t n = g->n;
+    *runs = nullptr;
+    *off = nullptr;
+    std::vector<uint32_t> cnt(n);
+    std::vector<uint64_t> h_off((size_t)n + 1);
+    uint32_t *d_cnt = nullptr;
+    hipError_t e = hipMalloc(&d_cnt, sizeof(uint32_t) * n);
+    if (e == hipSuccess)
+        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, join_self, d_cnt, nullptr, nullptr,
+                                 g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipFree(d_cnt);
+    if (e != hipSuccess) return e;
+    h_off[0] = 0;
+    for (uint32_t v = 0; v < n; ++v) h_off[v + 1] = h_off[v] + cnt[v];
+    *total = h_off[n];
+    e = hipMalloc(off, sizeof(uint64_t) * (n + 1ull));
+    if (e == hipSuccess) e = hipMalloc(runs, sizeof(uint2) * std::max<uint64_t>(h_off[n], 1));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(*off, h_off.data(), sizeof(uint64_t) * (n + 1ull),
+                           hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess)
+        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, join_self, nullptr, *off, *runs,
+                                 g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);  // h_off is read by the copy
+    if (e != hipSuccess) {
+        (void)hipFree(*off);
+        (void)hipFree(*runs);
+        *off = nullptr;
+        *runs = nullptr;
+    }
+    return e;
 }
 
 hb_status have_device() {
@@ -409,6 +454,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                            hipMemcpyHostToDevice)) != hipSuccess)
             return bail(e, "hipMemcpy(per-node array)");
     }
+    // the run kernel reads each row as its list of runs, decoded here once
+    uint64_t total = 0;
+    if ((e = build_run_list(g, true, &g->d_runs, &g->d_run_off, &total)) != hipSuccess)
+        return bail(e, "run list");
+    if (total != g->runs.runs) {
+        graph_release(g);
+        return fail(HB_EDEVICE, "run list: %llu runs on the device, %llu on the host",
+                    (unsigned long long)total, (unsigned long long)rc.runs);
+    }
     *out = g;
     return HB_OK;
 }
@@ -515,7 +569,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
             if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
             TunePick pick;
             st = tune_measure((int)p, bits, s, [&](const hbk::Sched &c) {
-                return runs ? hbk::launch_union_runs((int)p, c, g->d_bytes, g->d_offsets, cur,
+                return runs ? hbk::launch_union_runs((int)p, c, g->d_runs, g->d_run_off, cur,
                                                      levels, next, g->d_cprev, g->d_sumd,
                                                      g->d_flags + 1, n, 1u, g->d_order, s)
                             : hbk::launch_union((int)p, c, g->d_bytes, g->d_offsets, cur, next,
@@ -543,7 +597,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
         if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
         HB_HIP(hipEventRecord(g->ev[3], s));
         if (runs)
-            HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_bytes, g->d_offsets, cur, levels,
+            HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_runs, g->d_run_off, cur, levels,
                                           next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t,
                                           g->d_order, s));
         else
@@ -760,6 +814,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         b = hbk::BatchJob{};
         b.bytes = g->d_bytes;
         b.offsets = g->d_offsets;
+        b.run_list = g->d_runs;
+        b.run_off = g->d_run_off;
         b.order = g->d_order;
         b.hash_ids = g->d_hash_ids;
         b.seed = jobs[j].hash_seed;
@@ -1076,36 +1132,17 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
                     "local metrics: n = %u needs %llu bytes of LDS per workgroup; the device "
                     "has %d",
                     n, (unsigned long long)lds, lim);
-    std::vector<uint32_t> cnt(n);
-    std::vector<uint64_t> off((size_t)n + 1);
-    uint32_t *d_cnt = nullptr, *d_ball = nullptr;
+    uint32_t *d_ball = nullptr;
     uint64_t *d_off = nullptr, *d_pairs = nullptr;
     uint2 *d_runs = nullptr;
     double *d_clus = nullptr, *d_ctrl = nullptr;
-    // pass 1: runs per row; the host sums them into offsets
-    hipError_t e = hipMalloc(&d_cnt, sizeof(uint32_t) * n);
-    if (e == hipSuccess)
-        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, d_cnt, nullptr, nullptr, g->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
-                           g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e == hipSuccess) {
-        off[0] = 0;
-        for (uint32_t v = 0; v < n; ++v) off[v + 1] = off[v] + cnt[v];
-        e = hipMalloc(&d_off, sizeof(uint64_t) * (n + 1ull));
-    }
-    if (e == hipSuccess) e = hipMalloc(&d_runs, sizeof(uint2) * std::max<uint64_t>(off[n], 1));
+    // the plain maximal runs of every row (v is no neighbour of itself)
+    uint64_t total = 0;
+    hipError_t e = build_run_list(g, false, &d_runs, &d_off, &total);
     if (e == hipSuccess) e = hipMalloc(&d_pairs, sizeof(uint64_t) * n);
     if (e == hipSuccess) e = hipMalloc(&d_ball, sizeof(uint32_t) * n);
     if (e == hipSuccess) e = hipMalloc(&d_clus, sizeof(double) * n);
     if (e == hipSuccess) e = hipMalloc(&d_ctrl, sizeof(double) * n);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_off, off.data(), sizeof(uint64_t) * (n + 1ull),
-                           hipMemcpyHostToDevice, g->stream);
-    // pass 2: the runs, then the metrics
-    if (e == hipSuccess)
-        e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, nullptr, d_off, d_runs, g->stream);
     if (e == hipSuccess)
         e = hbk::launch_local(d_runs, d_off, g->d_degrees, n, g->d_order, d_pairs, d_ball, d_clus,
                               d_ctrl, g->stream);
@@ -1123,7 +1160,7 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
                            hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     (void)hipStreamSynchronize(g->stream);
-    for (void *p : {(void *)d_cnt, (void *)d_off, (void *)d_runs, (void *)d_pairs, (void *)d_ball,
+    for (void *p : {(void *)d_off, (void *)d_runs, (void *)d_pairs, (void *)d_ball,
                     (void *)d_clus, (void *)d_ctrl})
         (void)hipFree(p);
     if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "local metrics: out of device memory");

@@ -12,6 +12,8 @@ namespace hbk {
 struct BatchJob {
     const uint8_t *bytes;     // LEB128 stream
     const uint64_t *offsets;  // n + 1 row offsets
+    const uint2 *run_list;    // run list of the rows, v joined in (run kernel)
+    const uint64_t *run_off;  // n + 1 offsets into runs
     const uint32_t *order;    // processing order (a permutation of 0..n-1) or null
     const uint32_t *hash_ids; // id inserted for node v, or null for v
     uint8_t *buf[2];          // ping-pong counters (with table levels for the run kernel)
@@ -91,8 +93,9 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 
 // The same step from a range-max table of cur (level-major, level 0 = cur,
 // levels 1..levels built by launch_table): each run of consecutive neighbour
-// ids is covered by at most two table rows.  p <= 12.
-hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
+// ids is covered by at most two table rows.  runs / run_off: the rows' run
+// lists with v joined in (launch_row_runs with join_self).  p <= 12.
+hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uint64_t *run_off,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
                              const uint32_t *order, hipStream_t stream);
@@ -114,11 +117,12 @@ hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint3
                       const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
                       hipStream_t stream);
 
-// Maximal runs of consecutive ids of every row.  runs == null: cnt[v] = the
+// Maximal runs of consecutive ids of every row (join_self: runs through v
+// itself count as one).  runs == null: cnt[v] = the
 // number of runs of row v.  Otherwise runs[run_off[v] ...] = the runs of row v
 // as inclusive (first, last) pairs; run_off has n + 1 entries.
 hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
-                           uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
+                           bool join_self, uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
                            hipStream_t stream);
 
 // Exact local metrics of every node from the run lists (null outputs skipped):

@@ -615,15 +615,13 @@ __global__ __launch_bounds__(C::THREADS) void union_kernel(
 // laid out level-major right after the counters, T[k][i] at tbl + (k n + i) m,
 // and level 0 is cur itself.  The result is the same registers as the
 // per-edge kernel.
+//
+// The runs come from a run list that the loader decodes once from the LEB128
+// rows (row_runs_kernel); decoding the rows in every step, as the per-edge
+// kernel does, cost more issue slots than the gathers themselves.
 constexpr uint32_t kQueueCap = 384;        // table rows queued per wave (LDS)
 static_assert(kQueueCap % 4 == 0, "the flush reads the queue 16 bytes at a time");
 constexpr int kRunLoads = 4;               // 16 B/lane loads in flight per flush round
-// chunks with at most this many special varints take the scalar walk; the
-// rest take the vector path.  The walk runs on the scalar unit, which the four
-// SIMDs of a CU share, so a low threshold balances it against the VALU
-// (city, p = 10, one launch: 24.0 ms at 3, 21.7 at 2, 20.6 at 1, 21.3 at 0,
-// with the chunk and flush loops already on the scalar unit)
-constexpr int kScalarWalk = 1;
 constexpr uint32_t kQueueFlush = kQueueCap - 2 * kWave;
 
 template <class C>
@@ -703,9 +701,14 @@ struct RunGather {
     }
 };
 
+// Node v's step from its run list: runs[run_off[v] ..] are the maximal runs of
+// its row with v itself joined in (a run that stops at v - 1 and one that
+// starts at v + 1 form one run, since v's own counter is in the union anyway).
+// Each lane takes one run: its table level and one or two rows go to the
+// queue at offsets from a wave prefix sum.
 template <class C>
-__device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ bytes,
-                                                const uint64_t *__restrict__ offsets,
+__device__ __forceinline__ void union_node_runs(const uint2 *__restrict__ runs,
+                                                const uint64_t *__restrict__ run_off,
                                                 const uint8_t *__restrict__ tbl, uint32_t levels,
                                                 uint8_t *__restrict__ next,
                                                 double *__restrict__ c_prev,
@@ -718,126 +721,36 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
     acc.init(tbl + (uint64_t)v * C::M, slice, lane);
     RunGather<C> g{tbl, n, levels, queue, 0u, slice};
     const uint32_t top = 1u << levels;
-
-    bool have = false;      // a run is open: [ra, rl]; rl is the last id decoded
-    uint32_t ra = 0, rl = 0;
-    const uint64_t row_end = offsets[v + 1];
-    RowDecoder dec;
-    // each chunk's bytes are loaded one chunk ahead, so the load overlaps the
-    // decode and the gathers of the chunk before (measured: 31.8 -> 29.9 ms
-    // per city step at p = 10)
-    uint64_t base = offsets[v];
-    uint32_t b_next = base + lane < row_end ? (uint32_t)bytes[base + lane] : 0u;
-    for (; base < row_end; base += kWave) {
-        // lanes past the row's end hold byte 0; the chunk's lane mask is scalar
-        const uint64_t left = row_end - base;
-        const uint64_t vmask = left >= kWave ? ~0ull : (1ull << left) - 1ull;
-        const bool valid = (vmask >> lane) & 1ull;
-        const uint32_t b = b_next;
-        if (left > kWave) b_next = lane < left - kWave ? (uint32_t)bytes[base + kWave + lane] : 0u;
-        const uint64_t term = ballot(b < 0x80u) & vmask;
-        const uint64_t cont = vmask & ~term;
-        // Single-byte varints of value 1 after the row's first id are deltas of
-        // one: they only extend the open run.  When few varints in the chunk
-        // are anything else, walk those few in scalar code.
-        // lane 0 starts a varint unless one is carried in (carry_sh is 0 or
-        // at least 7); the shift form keeps the test on the scalar unit
-        const uint64_t after_term = (term << 1) | (uint64_t)((dec.carry_sh - 1u) >> 31);
-        uint64_t trivial = ballot(b == 0x01u) & after_term;
-        if (!have) trivial &= ~(term & (0ull - term));  // the row's first id is absolute
-        const uint64_t special = term & ~trivial;
-        if (__builtin_popcountll(special) <= kScalarWalk) {
-            uint32_t id = rl;
-            uint32_t pos = 0;  // lanes below pos are accounted for
-            uint64_t rest = special;
-            while (rest) {
-                const uint32_t e = (uint32_t)__builtin_ctzll(rest);
-                rest &= rest - 1ull;
-                const uint64_t span = ((1ull << e) - 1ull) & ~((1ull << pos) - 1ull);
-                const uint32_t ones = (uint32_t)__builtin_popcountll(trivial & span);
-                id += ones;  // deltas of one extend the open run
-                const uint64_t below = term & ((1ull << e) - 1ull);
-                const uint32_t s0 = below ? 64u - (uint32_t)__builtin_clzll(below) : 0u;
-                uint32_t val = s0 == 0u ? dec.carry_val : 0u;
-                uint32_t sh = s0 == 0u ? dec.carry_sh : 0u;
-                for (uint32_t k = s0; k <= e; ++k, sh += 7u)
-                    if (sh < 32u) val |= (readlane(b, k) & 0x7Fu) << sh;
-                if (!have) {
-                    id = val;
-                    ra = id;
-                    have = true;
-                } else {
-                    const uint32_t nid = id + val;
-                    if (!(nid == id + 1u || (nid == id + 2u && id + 1u == v))) {
-                        g.push_run(acc, ra, id, lane);
-                        ra = nid;
-                    }
-                    id = nid;
-                }
-                pos = e + 1u;
-            }
-            const uint64_t tail = pos >= 64u ? 0ull : ~((1ull << pos) - 1ull);
-            id += (uint32_t)__builtin_popcountll(trivial & tail);
-            rl = id;
-            dec.run = id;
-            // a varint cut by the chunk's end carries into the next chunk
-            if ((cont >> (kWave - 1)) & 1ull) {
-                const uint32_t s0 = term ? 64u - (uint32_t)__builtin_clzll(term) : 0u;
-                uint32_t val = s0 == 0u ? dec.carry_val : 0u;
-                uint32_t sh = s0 == 0u ? dec.carry_sh : 0u;
-                for (uint32_t k = s0; k < kWave; ++k, sh += 7u)
-                    if (sh < 32u) val |= (readlane(b, k) & 0x7Fu) << sh;
-                dec.carry_val = val;
-                dec.carry_sh = sh;
-            } else {
-                dec.carry_val = 0u;
-                dec.carry_sh = 0u;
-            }
-            continue;
-        }
-        uint32_t cnt;
-        const uint32_t ids = dec.chunk_of(b, valid, term, cont, cnt);
-        if (cnt == 0) continue;
-        const bool in = lane < cnt;
-        uint32_t prev = wave_shr1(ids);
-        if (lane == 0) prev = rl;
-        const bool has_prev = lane > 0 || have;
-        const bool joins = in && has_prev &&
-                           (ids == prev + 1u || (ids == prev + 2u && prev + 1u == v));
-        const uint64_t starts = ballot(in && !joins);
-        if (have && (starts & 1ull)) g.push_run(acc, ra, rl, lane);  // the open run ends
-        // start id of the run holding each lane: id at the last start lane <= lane
-        const uint64_t le = starts & ((2ull << lane) - 1ull);
-        const uint32_t sl = le ? 63u - (uint32_t)__builtin_clzll(le) : 0u;
-        uint32_t sid = shfl_idx(ids, sl);
-        if (!le) sid = ra;
-        // runs that end inside this chunk: lane e with a start at lane e + 1
-        const bool ends = (lane + 1u < cnt) && ((starts >> (lane + 1u)) & 1ull);
-        const uint32_t r = ids - sid + 1u;
-        const bool longrun = ends && r > top;
+    const uint64_t re = run_off[v + 1];
+    uint64_t base = run_off[v];
+    // each chunk's runs are loaded one chunk ahead
+    uint2 x_next = base + lane < re ? runs[base + lane] : make_uint2(1u, 0u);
+    for (; base < re; base += kWave) {
+        const uint64_t left = re - base;
+        const uint2 x = x_next;
+        if (left > kWave)
+            x_next = lane < left - kWave ? runs[base + kWave + lane] : make_uint2(1u, 0u);
+        const bool in = (left >= kWave ? ~0ull : (1ull << left) - 1ull) >> lane & 1ull;
+        const uint32_t r = x.y - x.x + 1u;  // run length (0 past the list's end)
+        const bool longrun = in && r > top;
         const uint32_t k = 31u - (uint32_t)__builtin_clz(r | 1u);
-        const uint32_t nl = (ends && !longrun) ? ((r == (1u << k)) ? 1u : 2u) : 0u;
-        const uint32_t pos = wave_scan(nl);  // inclusive prefix sum of the lookups per lane
+        const uint32_t nl = (in && !longrun) ? ((r == (1u << k)) ? 1u : 2u) : 0u;
+        const uint32_t pos = wave_scan(nl);  // inclusive prefix sum of the rows per lane
         const uint32_t total = readlane(pos, kWave - 1);
         if (g.qn > kQueueFlush) g.flush(acc, lane);
         if (nl) {
             const uint32_t at = g.qn + pos - nl;
-            g.q[at] = k * n + sid;
-            if (nl == 2u) g.q[at + 1] = k * n + (ids - (1u << k) + 1u);
+            g.q[at] = k * n + x.x;
+            if (nl == 2u) g.q[at + 1] = k * n + (x.y - (1u << k) + 1u);
         }
         g.qn += total;
         uint64_t lm = ballot(longrun);
         while (lm) {
             const uint32_t l = (uint32_t)__builtin_ctzll(lm);
             lm &= lm - 1ull;
-            g.push_run(acc, readlane(sid, l), readlane(ids, l), lane);
+            g.push_run(acc, readlane(x.x, l), readlane(x.y, l), lane);
         }
-        // the last run of the chunk stays open
-        ra = readlane(sid, cnt - 1u);
-        rl = readlane(ids, cnt - 1u);
-        have = true;
     }
-    if (have) g.push_run(acc, ra, rl, lane);
     if (g.qn) g.flush(acc, lane);
     finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
 }
@@ -848,7 +761,7 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
 // 32.1 ms at six with four loads in flight; eight waves spill heavily (75 ms).
 // At p = 11 five waves beat four (58.0 against 60.2 ms); at p = 12 three waves
 // without spills match four with them (117.4 against 118.0 ms).
-// With several waves per node every wave decodes the row and queues the same
+// With several waves per node every wave reads the run list and queues the same
 // table rows, then gathers its own slice of each.
 //
 // order (optional) is the processing order: logical node i is node order[i].
@@ -857,7 +770,7 @@ __device__ __forceinline__ void union_node_runs(const uint8_t *__restrict__ byte
 // curve over the raster raises cache reuse; the results do not depend on it.
 template <class C>
 __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
-    const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
+    const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
     uint32_t n, uint32_t t, const uint32_t *__restrict__ order) {
@@ -866,7 +779,7 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
     if (order) v = order[v];
-    union_node_runs<C>(bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
+    union_node_runs<C>(runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
                        s_queue[threadIdx.x / kWave]);
 }
 
@@ -951,7 +864,7 @@ __global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union
     const uint8_t *cur = J.buf[(t - 1u) & 1u];
     uint8_t *next = J.buf[t & 1u];
     if constexpr (RUNS) {
-        union_node_runs<C>(J.bytes, J.offsets, cur, J.levels, next, J.c_prev, J.sum_d,
+        union_node_runs<C>(J.run_list, J.run_off, cur, J.levels, next, J.c_prev, J.sum_d,
                            J.flags + t, J.n, v, slice, t, s_queue[threadIdx.x / kWave]);
     } else {
         union_node_edges<C>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
@@ -1075,10 +988,13 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
 // union of the neighbours' rows.  One wave per node builds the run lists.
 //
 // Pass 1 (runs == nullptr): cnt[v] = number of runs of row v.  Pass 2: the runs
-// of row v at runs[run_off[v] ...].
+// of row v at runs[run_off[v] ...].  join_self: a run that stops at v - 1 and
+// one that starts at v + 1 count as one run [a, b] through v (the run kernel's
+// form; the local metrics take the plain runs).
 __global__ __launch_bounds__(256) void row_runs_kernel(const uint8_t *__restrict__ bytes,
                                                        const uint64_t *__restrict__ offsets,
-                                                       uint32_t n, uint32_t *__restrict__ cnt,
+                                                       uint32_t n, uint32_t join_self,
+                                                       uint32_t *__restrict__ cnt,
                                                        const uint64_t *__restrict__ run_off,
                                                        uint2 *__restrict__ runs) {
     const uint32_t lane = lane_id();
@@ -1097,7 +1013,8 @@ __global__ __launch_bounds__(256) void row_runs_kernel(const uint8_t *__restrict
         const bool in = lane < c;
         uint32_t prev = wave_shr1(ids);
         if (lane == 0) prev = last;
-        const bool joins = in && (lane > 0 || open) && ids == prev + 1u;
+        const bool joins = in && (lane > 0 || open) &&
+                           (ids == prev + 1u || (join_self && ids == prev + 2u && prev + 1u == v));
         const uint64_t starts = ballot(in && !joins);
         if (runs) {
             const uint32_t before = (uint32_t)__builtin_popcountll(starts & ((1ull << lane) - 1ull));
@@ -1282,7 +1199,7 @@ hipError_t launch_union_c(const uint8_t *bytes, const uint64_t *offsets, const u
 }
 
 template <class C>
-hipError_t launch_union_runs_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *tbl,
+hipError_t launch_union_runs_c(const uint2 *runs, const uint64_t *run_off, const uint8_t *tbl,
                                uint32_t levels, uint8_t *next, double *c_prev, double *sum_d,
                                uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
                                uint32_t nb, hipStream_t stream) {
@@ -1290,7 +1207,7 @@ hipError_t launch_union_runs_c(const uint8_t *bytes, const uint64_t *offsets, co
         uint32_t blocks, threads;
         grid_for<C>(n, nb, blocks, threads);
         hipLaunchKernelGGL((union_runs_kernel<C>), dim3(blocks), dim3(threads), 0, stream,
-                           bytes, offsets, tbl, levels, next, c_prev, sum_d, flag_t, n, t, order);
+                           runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, t, order);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -1397,13 +1314,13 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 #undef HB_X
 }
 
-hipError_t launch_union_runs(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
+hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uint64_t *run_off,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
                              const uint32_t *order, hipStream_t stream) {
 #define HB_X(P, L, B)                                                                          \
     if (p == P && s.lanes == L && s.bits == B)                                                             \
-        return launch_union_runs_c<Cfg<P, L, B>>(bytes, offsets, tbl, levels, next, c_prev,    \
+        return launch_union_runs_c<Cfg<P, L, B>>(runs, run_off, tbl, levels, next, c_prev,     \
                                               sum_d, flag_t, n, t, order, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
@@ -1490,11 +1407,11 @@ hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint3
 }
 
 hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
-                           uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
+                           bool join_self, uint32_t *cnt, const uint64_t *run_off, uint2 *runs,
                            hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(row_runs_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, bytes, offsets, n,
-                       cnt, run_off, runs);
+                       join_self ? 1u : 0u, cnt, run_off, runs);
     return hipGetLastError();
 }
 

@@ -410,6 +410,8 @@ hb_status Server::step(Lane &L) {
         b = hbk::BatchJob{};
         b.bytes = g->d_bytes;
         b.offsets = g->d_offsets;
+        b.run_list = g->d_runs;
+        b.run_off = g->d_run_off;
         b.order = g->d_order;
         b.hash_ids = g->d_hash_ids;
         b.buf[0] = base + r->off;
