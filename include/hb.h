@@ -154,11 +154,12 @@ typedef struct {
  *    bytes per lane slot, one to four slots per lane.  Up to 64 lanes the
  *    node sits in one wavefront, whose 64 / lanes lane groups gather
  *    different neighbours at once; above 64, lanes / 64 wavefronts of one
- *    workgroup each own a slice of the counter and decode the row themselves.
+ *    workgroup each own a slice of the counter and read the row themselves.
  *  - nodes_per_block: nodes per workgroup (1, 2 or 4) for one-wave shapes.
- * Built lanes per p (the default first): p 4-7: 2^p / 16; p 8: 16, 8;
- * p 9: 32, 16; p 10: 64, 32, 16; p 11: 64, 128, 32; p 12: 64, 128, 256;
- * p 13: 128, 256; p 14: 256, 512; p 15: 512; p 16: 1024.  With 4-bit
+ * Built lanes per p (the per-edge kernel's default first): p 4-7: 2^p / 16;
+ * p 8: 16, 8; p 9: 32, 16; p 10: 64, 32, 16; p 11: 64, 128, 32; p 12: 64,
+ * 128, 256; p 13: 128, 256; p 14: 256, 512; p 15: 512; p 16: 1024.  The run
+ * kernel's default differs at p 9, 10 (16 lanes) and p 11 (32).  With 4-bit
  * registers one shape per p: p 5-11: 2^p / 32; p 12, 13: 64; p 14-16:
  * 2^p / 128.  Every schedule gives identical registers and estimates; only
  * the speed differs.

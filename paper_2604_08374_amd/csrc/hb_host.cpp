@@ -551,14 +551,15 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     const hbk::Sched init_sched = hbk::default_sched((int)p, bits);
 
     // ---- union schedule: explicit, cached, measured here, or the default
-    hbk::Sched sched = init_sched;
+    const hbk::Sched union_default = hbk::default_sched((int)p, bits, runs);
+    hbk::Sched sched = union_default;
     double tune_ms = 0.0;
     const TuneKey key =
         tune_key(p, bits, runs, false, n, runs ? g->runs.lookups[levels] : g->n_edges);
     if (fixed.lanes) {
         sched = fixed;
     } else if (o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
-        sched = init_sched;
+        sched = union_default;
         if (o.tune == HB_TUNE_MEASURE) {
             // step 1 of this very run, once per candidate; the state is
             // initialised again below, so the trials leave no trace
@@ -568,7 +569,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
                                     g->d_hash_ids, s));
             if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
             TunePick pick;
-            st = tune_measure((int)p, bits, s, [&](const hbk::Sched &c) {
+            st = tune_measure((int)p, bits, runs, s, [&](const hbk::Sched &c) {
                 return runs ? hbk::launch_union_runs((int)p, c, g->d_runs, g->d_run_off, cur,
                                                      levels, next, g->d_cprev, g->d_sumd,
                                                      g->d_flags + 1, n, 1u, g->d_order, s)
@@ -882,12 +883,12 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     for (auto &c : classes) {
         hbk::Sched fixed{};
         (void)explicit_sched(o, c.p, &fixed);
-        c.sched = hbk::default_sched((int)c.p, bits);
+        c.sched = hbk::default_sched((int)c.p, bits, c.runs);
         if (fixed.lanes) {
             c.sched = fixed;
         } else if (o.tune != HB_TUNE_OFF &&
                    !tune_get(tune_key(c.p, bits, c.runs, true, c.nodes, c.rows), &c.sched)) {
-            c.sched = hbk::default_sched((int)c.p, bits);
+            c.sched = hbk::default_sched((int)c.p, bits, c.runs);
             c.measure = o.tune == HB_TUNE_MEASURE;
             any_measure = any_measure || c.measure;
         }
@@ -922,7 +923,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     std::vector<std::vector<uint32_t>> cand_off(classes.size()), cand_blocks(classes.size());
     for (size_t ci = 0; ci < classes.size(); ++ci) {
         if (!classes[ci].measure) continue;
-        cands[ci] = tune_candidates((int)classes[ci].p, bits);
+        cands[ci] = tune_candidates((int)classes[ci].p, bits, classes[ci].runs);
         for (const auto &cs : cands[ci]) {
             const std::vector<uint32_t> b = classes[ci].bases(hj, cs);
             cand_off[ci].push_back((uint32_t)lists.size());
@@ -963,7 +964,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
             if (!c.measure) continue;
             size_t idx = 0;
             TunePick pick;
-            st = tune_measure((int)c.p, bits, s, [&](const hbk::Sched &cs) {
+            st = tune_measure((int)c.p, bits, c.runs, s, [&](const hbk::Sched &cs) {
                 idx = 0;
                 while (idx < cands[ci].size() && !(cands[ci][idx].lanes == cs.lanes &&
                                                    cands[ci][idx].nodes_per_block == cs.nodes_per_block))

@@ -46,7 +46,8 @@ struct Sched {
 constexpr uint32_t kMaxLaneOptions = 4;
 // The lanes-per-node values compiled for (p, bits), the default first; returns the count.
 uint32_t lane_options(int p, uint32_t bits, uint32_t out[kMaxLaneOptions]);
-Sched default_sched(int p, uint32_t bits = 8);
+// runs: the default of the run kernel, which differs at p = 9..11 (8-bit).
+Sched default_sched(int p, uint32_t bits = 8, bool runs = false);
 bool sched_ok(int p, const Sched &s);
 
 struct LaunchShape {

@@ -1255,10 +1255,19 @@ uint32_t lane_options(int p, uint32_t bits, uint32_t out[kMaxLaneOptions]) {
     return k;
 }
 
-Sched default_sched(int p, uint32_t bits) {
+// The run kernel's default for 8-bit registers at p = 9..11: fewer lanes per
+// node, so each load instruction gathers several table rows (city graph, per
+// launch: p = 9 6.45 ms at 16 lanes against 6.63 at 32; p = 10 13.4 ms at 16
+// against 16.7 at 64; p = 11 30.6 ms at 32 against 43.2 at 64).
+constexpr int run_default_lanes(int p, int bits) {
+    return bits == 8 && p >= 9 && p <= 11 ? (p == 11 ? 32 : 16) : default_lanes(p, bits);
+}
+
+Sched default_sched(int p, uint32_t bits, bool runs) {
     Sched s;
     const bool ok = p <= 16 && ((bits == 8 && p >= 4) || (bits == 4 && p >= 5));
-    s.lanes = ok ? (uint32_t)default_lanes(p, (int)bits) : 0u;
+    s.lanes = !ok ? 0u
+                  : (uint32_t)(runs ? run_default_lanes(p, (int)bits) : default_lanes(p, (int)bits));
     s.nodes_per_block = s.lanes > (uint32_t)kWave ? 1u : 4u;
     s.bits = bits;
     return s;

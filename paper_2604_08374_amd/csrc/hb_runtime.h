@@ -70,10 +70,10 @@ struct TunePick {
 bool tune_get(const TuneKey &k, hbk::Sched *s);
 void tune_put(const TuneKey &k, const TunePick &v);
 // Every schedule built for (p, register bits), the default first.
-std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits);
+std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits, bool runs);
 // Time one union step of every candidate with `launch` (which enqueues the
 // step on stream s): two launches each, the faster counts.  Fills the pick.
-hb_status tune_measure(int p, uint32_t bits, hipStream_t s,
+hb_status tune_measure(int p, uint32_t bits, bool runs, hipStream_t s,
                        const std::function<hipError_t(const hbk::Sched &)> &launch,
                        TunePick *out);
 

@@ -317,8 +317,8 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
     out->run_ms = (double)(r->t_end - r->t_admit) / 1e6;
     out->union_kernel = r->runs ? HB_UNION_RUNS : HB_UNION_EDGES;
     out->table_levels = r->levels;
-    out->lanes_per_node = hbk::default_sched((int)r->p, r->bits).lanes;
-    out->nodes_per_block = hbk::default_sched((int)r->p, r->bits).nodes_per_block;
+    out->lanes_per_node = hbk::default_sched((int)r->p, r->bits, r->runs).lanes;
+    out->nodes_per_block = hbk::default_sched((int)r->p, r->bits, r->runs).nodes_per_block;
     out->register_bits = r->bits;
     out->tune_ms = 0.0;
     out->t_submit_ns = r->t_submit;
@@ -467,7 +467,7 @@ hb_status Server::step(Lane &L) {
         // the default schedule: a served step's class mix changes from step to step
         const int p = (int)h_jobs_[j].p;
         const uint32_t npb =
-            hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits)).nodes_per_block;
+            hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits, runs)).nodes_per_block;
         c->list.push_back(j);
         c->base.push_back(c->base.back() + (h_jobs_[j].n + npb - 1) / npb);
     };
@@ -536,7 +536,8 @@ hb_status Server::step(Lane &L) {
         HB_HIP(hbk::launch_batch_table(d_jobs_, d_lists_ + runs_off, d_lists_ + table_off[k],
                                        (uint32_t)runs_list.size(), table_blocks[k], k, s));
     for (auto &c : classes)
-        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p, c.bits), c.runs, d_jobs_,
+        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p, c.bits, c.runs),
+                                       c.runs, d_jobs_,
                                        d_lists_ + c.list_off,
                                        d_lists_ + c.base_off, (uint32_t)c.list.size(),
                                        c.base.back(), s));

@@ -58,9 +58,9 @@ void tune_put(const TuneKey &k, const TunePick &v) {
     g_tune[k] = v;
 }
 
-std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits) {
+std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits, bool runs) {
     std::vector<hbk::Sched> c;
-    const hbk::Sched d = hbk::default_sched(p, bits);
+    const hbk::Sched d = hbk::default_sched(p, bits, runs);
     c.push_back(d);
     uint32_t lanes[hbk::kMaxLaneOptions];
     const uint32_t k = hbk::lane_options(p, bits, lanes);
@@ -76,13 +76,13 @@ std::vector<hbk::Sched> tune_candidates(int p, uint32_t bits) {
     return c;
 }
 
-hb_status tune_measure(int p, uint32_t bits, hipStream_t s,
+hb_status tune_measure(int p, uint32_t bits, bool runs, hipStream_t s,
                        const std::function<hipError_t(const hbk::Sched &)> &launch,
                        TunePick *out) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const std::vector<hbk::Sched> cand = tune_candidates(p, bits);
+    const std::vector<hbk::Sched> cand = tune_candidates(p, bits, runs);
     TunePick best;
     best.best_ms = -1.0;
     for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
