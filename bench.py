@@ -560,6 +560,23 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(off, deg, data, n, p, args.seed, args.cpu_seconds)
+    if not args.no_extras and bits == 8:
+        # the paper's packed format on the same workload: 4-bit registers,
+        # saturating at 15 (other results, so a separate line, not `value`)
+        log("4-bit registers: the same workload ...")
+        kw4 = dict(kw, register_bits=4, tune="measure")
+        G.run(p, depth, args.seed, **kw4)
+        kw4["tune"] = "cached"
+        t4 = time.perf_counter()
+        r4 = [G.run(p, depth, args.seed, **kw4) for _ in range(args.steps)]
+        el4 = time.perf_counter() - t4
+        pas4 = sum(r.passes for r in r4)
+        line["register_bits_4"] = {
+            "value": pas4 * E / el4, "unit": "edge-unions/s", "ms_per_step": el4 * 1e3 / len(r4),
+            "avg_launch_ms": sum(r.iter_ms for r in r4) / pas4,
+            "schedule": {"lanes_per_node": r4[-1].lanes_per_node,
+                         "nodes_per_block": r4[-1].nodes_per_block}}
+        log(f"4-bit: {line['register_bits_4']['value']:.4g} edge-unions/s")
     if not args.no_extras:
         # exact local metrics (clustering, controllability) of the same graph: one
         # blocking call, run lists built inside it

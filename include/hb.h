@@ -219,7 +219,12 @@ hb_status hb_csr_validate(const hb_csr *csr, uint32_t *bad_node);
 /*
  * Validate csr (as hb_csr_validate) and copy it into device memory.  The
  * caller may free its arrays when this returns.  *out is library-owned until
- * hb_graph_free.
+ * hb_graph_free.  The rows are also decoded once, on the device, into the run
+ * list the run kernel reads: 8 bytes per run (hb_graph_stats_t.n_runs) plus
+ * 8 (n + 1) bytes of offsets.  When that list does not fit in device memory
+ * the graph loads without it, and only the per-edge kernel serves it (an
+ * explicit HB_UNION_RUNS request then fails with HB_ENOMEM).  HB_EDEVICE if the
+ * device's run count disagrees with the host validator's.
  */
 hb_status hb_graph_load(const hb_csr *csr, hb_graph **out);
 

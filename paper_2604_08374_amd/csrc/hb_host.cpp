@@ -454,11 +454,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                            hipMemcpyHostToDevice)) != hipSuccess)
             return bail(e, "hipMemcpy(per-node array)");
     }
-    // the run kernel reads each row as its list of runs, decoded here once
+    // the run kernel reads each row as its list of runs, decoded here once; a
+    // graph whose run list does not fit loads without it (per-edge kernel only)
     uint64_t total = 0;
-    if ((e = build_run_list(g, true, &g->d_runs, &g->d_run_off, &total)) != hipSuccess)
+    e = build_run_list(g, true, &g->d_runs, &g->d_run_off, &total);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+    } else if (e != hipSuccess) {
         return bail(e, "run list");
-    if (total != g->runs.runs) {
+    } else if (total != g->runs.runs) {
         graph_release(g);
         return fail(HB_EDEVICE, "run list: %llu runs on the device, %llu on the host",
                     (unsigned long long)total, (unsigned long long)rc.runs);
@@ -528,6 +532,11 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     if (runs && (uint64_t)(levels + 1) * n >= (1ull << 32)) {
         if (o.union_kernel == HB_UNION_RUNS)
             return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
+        runs = false;
+    }
+    if (runs && !g->d_runs) {
+        if (o.union_kernel == HB_UNION_RUNS)
+            return fail(HB_ENOMEM, "the graph's run list did not fit in device memory at load");
         runs = false;
     }
     if (runs && o.union_kernel == HB_UNION_AUTO) {
@@ -808,6 +817,11 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
             if (o.union_kernel == HB_UNION_RUNS)
                 return fail(HB_EINVAL, "job %u: table rows (levels + 1) * n must stay below 2^32", j);
+            runs = false;
+        }
+        if (runs && !g->d_runs) {
+            if (o.union_kernel == HB_UNION_RUNS)
+                return fail(HB_ENOMEM, "job %u: the graph's run list did not fit at load", j);
             runs = false;
         }
         if (!runs) levels = 0;

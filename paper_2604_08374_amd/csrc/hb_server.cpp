@@ -170,6 +170,11 @@ hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &
             return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
         runs = false;
     }
+    if (runs && !g->d_runs) {
+        if (opts_.union_kernel == HB_UNION_RUNS)
+            return fail(HB_ENOMEM, "the graph's run list did not fit in device memory at load");
+        runs = false;
+    }
     if (!runs) levels = 0;
     const uint64_t n_flags = (uint64_t)g->n + 2;
     bytes = 2 * align256((uint64_t)g->n * m * (levels + 1u)) + 2 * align256(8ull * g->n) +
