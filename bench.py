@@ -584,9 +584,13 @@ def main():
         t0 = time.perf_counter()
         lm = G.local_metrics()
         t1 = time.perf_counter()
+        reads = stats["local_run_reads"]
         line["local_metrics"] = {
             "workload": line["config"]["workload"], "ms": (t1 - t0) * 1e3,
             "nodes_per_s": n / (t1 - t0),
+            # every node reads the run list of each neighbour: 8 B per run
+            "run_list_bytes_read": 8 * reads,
+            "run_list_gbs": 8 * reads / (t1 - t0) / 1e9,
             "median_clustering": float(np.nanmedian(lm["clustering"])),
             "median_controllability": float(np.nanmedian(lm["controllability"]))}
         log(f"local metrics: {(t1 - t0) * 1e3:.0f} ms")

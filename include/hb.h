@@ -123,7 +123,7 @@ typedef struct {
 /*
  * Run options; an all-zero struct (or NULL) selects the defaults.
  * table_levels: the run kernel builds, every step, table levels 1..K with
- * T[k][i] = max of the counters i .. i + 2^k - 1 (K = table_levels, default 7,
+ * T[k][i] = max of the counters i .. i + 2^k - 1 (K = table_levels, default 8,
  * capped at floor(log2 n)), costing K * n * 2^p extra bytes per counter
  * buffer.  A run of r <= 2^K consecutive neighbour ids then costs at most two
  * counter-row loads instead of r.  The registers are identical either way.
@@ -247,6 +247,9 @@ typedef struct {
     uint64_t n_bytes;
     uint64_t n_runs;
     uint64_t table_rows[25];
+    uint64_t local_run_reads;  /* sum over rows w of deg(w) x the maximal runs of w
+                                  (v not joined in): the neighbour runs that
+                                  hb_local_metrics reads, 8 bytes each */
 } hb_graph_stats_t;
 
 hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out);

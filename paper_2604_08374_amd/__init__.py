@@ -77,7 +77,8 @@ class _ServerStats(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("n_bytes", ctypes.c_uint64),
-                ("n_runs", ctypes.c_uint64), ("table_rows", ctypes.c_uint64 * 25)]
+                ("n_runs", ctypes.c_uint64), ("table_rows", ctypes.c_uint64 * 25),
+                ("local_run_reads", ctypes.c_uint64)]
 
 
 class _RunOpts(ctypes.Structure):
@@ -331,7 +332,8 @@ class Graph:
         st = _Stats()
         _check(_lib().hb_graph_stats(self._h, ctypes.byref(st)))
         return {"n": st.n, "n_edges": st.n_edges, "n_bytes": st.n_bytes, "n_runs": st.n_runs,
-                "table_rows": [int(x) for x in st.table_rows]}
+                "table_rows": [int(x) for x in st.table_rows],
+                "local_run_reads": int(st.local_run_reads)}
 
     def vga_metrics(self, sum_d) -> dict:
         """hb_vga_metrics: the VGA metrics of every node from a run's sum_d (Sec. 3.3)."""

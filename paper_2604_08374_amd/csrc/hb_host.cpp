@@ -101,7 +101,7 @@ uint8_t *uleb_put(uint32_t v, uint8_t *out) {
 // Check one compressed row; returns true if valid.  Counts runs into rc.
 bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32_t degree,
             RunCounts *rc = nullptr) {
-    uint64_t prev = 0, run_start = 0;
+    uint64_t prev = 0, run_start = 0, plain_runs = 0;
     uint32_t count = 0;
     while (p < end) {
         uint32_t val = 0;
@@ -126,11 +126,13 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
             const bool joins = count > 0 && (id == prev + 1 || (id == prev + 2 && prev + 1 == v));
             if (count > 0 && !joins) rc->add(prev - run_start + 1);
             if (count == 0 || !joins) run_start = id;
+            if (count == 0 || id != prev + 1) ++plain_runs;
         }
         prev = id;
         if (++count > degree) return false;
     }
     if (rc && count > 0) rc->add(prev - run_start + 1);
+    if (rc) rc->local_reads += plain_runs * degree;
     return count == degree;
 }
 
@@ -496,6 +498,7 @@ hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out) {
     out->n_bytes = g->n_bytes;
     out->n_runs = g->runs.runs;
     for (int k = 0; k <= kMaxLevels; ++k) out->table_rows[k] = g->runs.lookups[k];
+    out->local_run_reads = g->runs.local_reads;
     return HB_OK;
 }
 
@@ -524,7 +527,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
 
     // kernel choice and table depth
-    uint32_t levels = o.table_levels ? o.table_levels : 7u;
+    uint32_t levels = o.table_levels ? o.table_levels : kDefaultLevels;
     uint32_t lg = 0;
     while ((2ull << lg) <= n) ++lg;  // floor(log2 n)
     levels = std::min(levels, lg);
@@ -812,7 +815,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         const hb_graph *g = jobs[j].g;
         const uint32_t p = jobs[j].p;
         const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
-        uint32_t levels = std::min(o.table_levels ? o.table_levels : 7u, floor_log2(g->n));
+        uint32_t levels = std::min(o.table_levels ? o.table_levels : kDefaultLevels, floor_log2(g->n));
         bool runs = o.union_kernel == HB_UNION_RUNS || (o.union_kernel == HB_UNION_AUTO && p <= 12);
         if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
             if (o.union_kernel == HB_UNION_RUNS)

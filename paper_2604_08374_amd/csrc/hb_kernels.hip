@@ -1036,13 +1036,27 @@ __global__ __launch_bounds__(256) void row_runs_kernel(const uint8_t *__restrict
     }
 }
 
-// Popcount of bits [a, b] of an LDS bitmap.
-__device__ __forceinline__ uint32_t range_popc(const uint32_t *bm, uint32_t a, uint32_t b) {
+// One neighbour run [a, b]: the popcount of nv over [a, b], and [a, b] set in
+// un (other lanes may set overlapping ranges).  The end words take no branch
+// (a run inside one word gets an empty mask for its second word); only runs
+// over three or more words loop, over their middle words.  A run outside
+// [0, n) or reversed counts nothing (the loader validated the rows, so none
+// occurs; the check keeps every LDS index in bounds).
+__device__ __forceinline__ uint32_t run_popc_set(const uint32_t *nv, uint32_t *un, uint32_t a,
+                                                 uint32_t b, uint32_t n) {
+    if (!(a <= b && b < n)) return 0u;
     const uint32_t wa = a >> 5, wb = b >> 5;
     const uint32_t lo = ~0u << (a & 31u), hi = ~0u >> (31u - (b & 31u));
-    if (wa == wb) return (uint32_t)__builtin_popcount(bm[wa] & lo & hi);
-    uint32_t c = (uint32_t)__builtin_popcount(bm[wa] & lo) + (uint32_t)__builtin_popcount(bm[wb] & hi);
-    for (uint32_t i = wa + 1u; i < wb; ++i) c += (uint32_t)__builtin_popcount(bm[i]);
+    const bool one = wa == wb;
+    const uint32_t m0 = one ? (lo & hi) : lo, m1 = one ? 0u : hi;
+    uint32_t c = (uint32_t)__builtin_popcount(nv[wa] & m0) +
+                 (uint32_t)__builtin_popcount(nv[wb] & m1);
+    atomicOr(&un[wa], m0);
+    atomicOr(&un[wb], m1);
+    for (uint32_t i = wa + 1u; i < wb; ++i) {
+        c += (uint32_t)__builtin_popcount(nv[i]);
+        atomicOr(&un[i], ~0u);
+    }
     return c;
 }
 
@@ -1104,18 +1118,16 @@ __global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
         if (!(x.x <= x.y && x.y < n)) continue;
         const uint32_t w0 = x.x + (wave + kLocalWaves - x.x % kLocalWaves) % kLocalWaves;
         for (uint64_t w = w0; w <= x.y; w += kLocalWaves) {
-            const uint64_t s = run_off[w], e = run_off[w + 1];
-            for (uint64_t q = s + lane; q < e; q += kLocalLoads * kWave) {
+            const uint2 *row = runs + run_off[w];
+            const uint32_t cnt = (uint32_t)(run_off[w + 1] - run_off[w]);  // < 2^32 per row
+            for (uint32_t q = lane; q < cnt; q += kLocalLoads * kWave) {
                 uint2 y[kLocalLoads];
 #pragma unroll
                 for (uint32_t u = 0; u < kLocalLoads; ++u)
-                    y[u] = q + u * kWave < e ? runs[q + u * kWave] : make_uint2(1u, 0u);
+                    y[u] = q + u * kWave < cnt ? row[q + u * kWave] : make_uint2(1u, 0u);
 #pragma unroll
-                for (uint32_t u = 0; u < kLocalLoads; ++u) {
-                    if (!(y[u].x <= y[u].y && y[u].y < n)) continue;
-                    pairs += range_popc(nv, y[u].x, y[u].y);
-                    range_set(un, y[u].x, y[u].y);
-                }
+                for (uint32_t u = 0; u < kLocalLoads; ++u)
+                    pairs += run_popc_set(nv, un, y[u].x, y[u].y, n);
             }
         }
     }

@@ -30,12 +30,20 @@ uint32_t floor_log2(uint32_t n);
     } while (0)
 
 constexpr int kMaxLevels = 24;
+// Default depth K of the run kernel's range-max table (city graph, p = 10, per
+// step of table build + union launch: 14.0 ms at K = 7, 13.7 at 8, 13.7 at 9,
+// 15.1 at 6; deeper tables cover long runs with fewer rows but cost a level of
+// build and n 2^p bytes of memory each).
+constexpr uint32_t kDefaultLevels = 8;
 
 // Runs of consecutive neighbour ids (joined across the node itself) and, for
 // every table depth K, the table rows the run kernel loads to cover them.
 struct RunCounts {
     uint64_t runs = 0;
     uint64_t lookups[kMaxLevels + 1] = {};
+    // sum over rows w of deg(w) x (maximal runs of w, v not joined in): the
+    // neighbour runs the local metrics read over all nodes
+    uint64_t local_reads = 0;
     void add(uint64_t r) {
         ++runs;
         for (int k = 0; k <= kMaxLevels; ++k) {
@@ -49,6 +57,7 @@ struct RunCounts {
     }
     void merge(const RunCounts &o) {
         runs += o.runs;
+        local_reads += o.local_reads;
         for (int k = 0; k <= kMaxLevels; ++k) lookups[k] += o.lookups[k];
     }
 };

@@ -163,7 +163,7 @@ private:
 hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs,
                             uint32_t &levels, uint64_t &bytes) const {
     const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
-    levels = std::min(opts_.table_levels ? opts_.table_levels : 7u, floor_log2(g->n));
+    levels = std::min(opts_.table_levels ? opts_.table_levels : kDefaultLevels, floor_log2(g->n));
     runs = opts_.union_kernel == HB_UNION_RUNS || (opts_.union_kernel == HB_UNION_AUTO && p <= 12);
     if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
         if (opts_.union_kernel == HB_UNION_RUNS)

@@ -55,10 +55,16 @@ def test_local_metrics_match_oracle(hb, gname):
          "pair": lambda: synth.from_edges(2, [(0, 1)], name="pair"),
          }[gname]()
     ref = oracle.local_metrics(oracle.from_graph(g))
+    # the neighbour runs the metrics read: sum over rows of degree x maximal runs
+    deg = np.diff(g.adj_offsets).astype(np.int64)
+    runs = np.array([int(np.count_nonzero(np.diff(r.astype(np.int64)) != 1)) + 1 if r.size else 0
+                     for r in (g.adj_ids[g.adj_offsets[v]:g.adj_offsets[v + 1]]
+                               for v in range(g.n))], np.int64)
     for order in (None, "hilbert") if gname in ("tiny", "rect90x70") else (None,):
         kw = {} if order is None else {"order": synth.hilbert_order(g)}
         G = _load(hb, g, **kw)
         print(f"[local] {g.name} order={order}", flush=True)
+        assert G.stats()["local_run_reads"] == int((deg * runs).sum())
         _compare(G.local_metrics(), ref, f"{g.name} order={order}")
         G.free()
 
