@@ -217,6 +217,36 @@ def batch_bench(args):
     return line
 
 
+def local_bench(args):
+    """One hb_local_metrics call on the configured graph (Hilbert order by default):
+    the run lists of every row are built inside the call, then every node reads the
+    run list of each neighbour (8 B per run)."""
+    import paper_2604_08374_amd as hb
+
+    g = make_graph(args.config, args.seed)
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    n = g.n
+    order = node_order(g, args)
+    del g
+    G = hb.graph_load(off, deg, data, order=order)
+    reads = G.stats()["local_run_reads"]
+    if args.copy_probe:
+        hb.copy_probe(4 << 30, 10)
+    t0 = time.perf_counter()
+    lm = G.local_metrics()
+    el = time.perf_counter() - t0
+    G.free()
+    log(f"local metrics: {el * 1e3:.0f} ms, {8 * reads / el / 1e9:.0f} GB/s of run-list reads")
+    return {"metric": "local metrics (clustering, controllability) nodes/s", "value": n / el,
+            "unit": "nodes/s", "n_gpus": 1, "ms": el * 1e3, "higher_is_better": True,
+            "data": "synthetic", "dtype": "u32",
+            "config": {"workload": f"{args.config} street/building visibility graph, seed "
+                                   f"{args.seed}", "nodes": n, "node_order": args.order},
+            "run_list_bytes_read": 8 * reads, "run_list_gbs": 8 * reads / el / 1e9,
+            "median_clustering": float(np.nanmedian(lm["clustering"])),
+            "median_controllability": float(np.nanmedian(lm["controllability"]))}
+
+
 def serve_bench(args):
     """Served workload: Poisson arrivals over a seeded pool of graphs, continuous batching.
 
@@ -386,9 +416,10 @@ def serve_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "local"],
                     help="single: one graph (default); batch: 64 graphs, batched vs "
-                         "sequential; serve: Poisson request stream, served vs sequential")
+                         "sequential; serve: Poisson request stream, served vs sequential; "
+                         "local: exact clustering and controllability of one graph")
     ap.add_argument("--batch-jobs", type=int, default=64)
     ap.add_argument("--pool", type=int, default=200)
     ap.add_argument("--pool-max-nodes", type=int, default=120000)
@@ -432,6 +463,9 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps(serve_bench(args)), flush=True)
+        return
+    if args.mode == "local":
+        print(json.dumps(local_bench(args)), flush=True)
         return
     g = make_graph(args.config, args.seed)
     t0 = time.perf_counter()

@@ -45,7 +45,8 @@ def _short(name: str) -> str:
     """
     for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
                 "batch_step_end_kernel", "union_runs_kernel", "union_kernel", "table_level_kernel",
-                "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel"):
+                "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel",
+                "local_kernel", "row_runs_kernel", "vga_kernel"):
         at = name.find(key)
         if at < 0 or (at > 0 and (name[at - 1].isalnum() or name[at - 1] == "_")):
             continue
