@@ -417,7 +417,9 @@ hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out);
  * bits in LDS, so n is limited by the device's LDS per workgroup (HB_EINVAL
  * beyond it: n <= 654,592 with 160 KiB).  Temporary device memory: the run list
  * of the graph (8 bytes per run) plus 12 n bytes; HB_ENOMEM when it does not
- * fit.  Blocking.
+ * fit.  Blocking: it holds the library's device lock for its whole duration
+ * (8.5 s for a 236k-node, 4.9e9-edge graph), so other blocking calls (runs,
+ * loads) wait for it; the served request loop does not.
  */
 typedef struct {
     uint64_t *pairs;
