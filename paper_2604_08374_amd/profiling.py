@@ -120,7 +120,7 @@ def main():
     if not (args.fetch and args.write):
         # trace only: the per-kernel table
         lines = [f"# rocprofv3 summary: {args.title}", ""]
-        lines += ["Command (run from the repository root; writes CSV under gpurun_out/):", ""]
+        lines += ["Command (run from the repository root; writes CSV under the -d directory):", ""]
         lines += [f"    {c}" for c in args.cmd]
         lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
                   "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
@@ -146,7 +146,7 @@ def main():
     sha = kernel_sha256()
 
     lines = [f"# rocprofv3 summary: {args.title}", ""]
-    lines += ["Commands (run from the repository root; each writes CSV under gpurun_out/):", ""]
+    lines += ["Commands (run from the repository root; each writes CSV under its -d directory):", ""]
     lines += [f"    {c}" for c in args.cmd]
     lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
