@@ -116,9 +116,12 @@ typedef struct {
 } hb_result;
 
 /* Which union kernel a run uses. */
-#define HB_UNION_AUTO 0  /* the run kernel when p <= 12 and its table fits, else per edge */
-#define HB_UNION_EDGES 1 /* gather every neighbour's counter (Eq. 2 as written) */
-#define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table */
+#define HB_UNION_AUTO 0  /* the run kernel when p <= 12, its table fits and the graph has
+                            its run list, else per edge */
+#define HB_UNION_EDGES 1 /* gather every neighbour's counter (Eq. 2 as written), decoding the
+                            LEB128 row in the kernel */
+#define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table,
+                            reading the run list decoded at load */
 
 /*
  * Run options; an all-zero struct (or NULL) selects the defaults.
