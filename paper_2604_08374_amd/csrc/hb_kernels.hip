@@ -1,34 +1,38 @@
 // HyperBall kernels for gfx950 (CDNA4, wave64).
 //
-// The hot loop is the paper's fused decode-union step (Sec. 3.4, "CUDA
-// kernels": LEB128 decode of a node's row, then the register-wise max of
-// Eq. 2 against every neighbour's counter), here with the estimator and the
-// Eq. 3 accumulation fused into its epilogue, so one launch is one whole
-// HyperBall step.  Design on gfx950:
+// One launch is one whole HyperBall step: the register-wise max of Eq. 2 for
+// every node, with the estimator and the Eq. 3 accumulation fused into its
+// epilogue.  Two union kernels give the same registers:
 //
-//  * By default one wavefront per node (p <= 12).  A counter of m = 2^p uint8
-//    registers is spread over the wave in 16-byte lane slices, so every
-//    neighbour gather is one coalesced 16 B/lane load: at p = 10 a single 1 KB
-//    wave load.  For p < 10 the wave splits into groups that gather different
-//    neighbours at once and are max-reduced at the end; for p >= 13 several
-//    waves of a workgroup share a node, each owning a 4 KB slice.  Other
-//    shapes (lanes per node, nodes per workgroup) are built for the autotuner,
+//  * the per-edge kernel is the paper's fused decode-union step (Sec. 3.4): it
+//    decodes the node's LEB128 row and gathers every neighbour's counter;
+//  * the run kernel (default, p <= 12) covers each run of consecutive
+//    neighbour ids with one or two rows of a range-max table of the counters,
+//    built every step, and reads the runs from a run list that the loader
+//    decodes once from the LEB128 rows.
+//
+// Design on gfx950:
+//
+//  * A counter of m = 2^p uint8 registers is spread over lanes in 16-byte
+//    slices, so every gather is a coalesced 16 B/lane load.  Lanes per node
+//    and nodes per workgroup form the schedule: up to 64 lanes a node sits in
+//    one wave, whose lane groups gather different rows at once and are
+//    max-reduced at the end; above 64, several waves of a workgroup share a
+//    node, each owning a slice.  Several shapes are built for the autotuner,
 //    and 4-bit registers (two per byte) have shapes of their own.
-//  * The row is decoded cooperatively 64 bytes at a time: a ballot of the
+//  * Rows are decoded cooperatively 64 bytes at a time: a ballot of the
 //    continuation bits marks varint ends, a segmented OR joins the 7-bit
 //    groups (at most five per varint), a wave prefix sum turns the first id
 //    and the deltas into absolute ids, and a lane permute packs them into
 //    lanes 0..k-1.  Varints that straddle 64-byte chunks carry over.  The
-//    shifts and prefix sums are DPP moves (row shifts, row broadcasts and the
-//    wave shift by one), which stay in the VALU.
-//  * Neighbour ids are read out with readlane into scalar registers, so each
-//    gather uses a scalar base address; the per-edge kernel keeps eight
-//    gathers in flight per wave, the run kernel four at higher occupancy.
-//    Tail slots repeat an id already gathered (max is idempotent).
-//  * Byte-wise max without unpacking: v_pk_max_u16 on the raw dword keeps
-//    the max of bytes 1 and 3 in the high byte of each half, and on the
-//    dword shifted left by 8 the max of bytes 0 and 2; 3 VALU ops per 4
-//    registers.
+//    shifts and prefix sums are DPP moves.
+//  * Gathered rows come from readlane or from an LDS queue of table rows, so a
+//    gather whose row serves the whole wave uses a scalar base address.  Tail
+//    slots repeat a row already gathered (max is idempotent).
+//  * Byte-wise max without unpacking: v_pk_max_u16 on the raw dword keeps the
+//    max of bytes 1 and 3 in the high byte of each half, and on the dword
+//    shifted left by 8 the max of bytes 0 and 2; two rows at a time go through
+//    one packed fp16 three-input maximum per half instead.
 //  * The estimator sums 2^(65-p-M) over the registers as an exact 128-bit
 //    integer (wave butterfly with carries) and converts it to double with a
 //    single rounding, so the estimate is independent of the reduction order.
@@ -36,6 +40,8 @@
 //    workgroups round-robin) works on one contiguous range of the processing
 //    order: nodes close in that order (along a Hilbert curve, when the caller
 //    gives one) share most neighbours, so their gathers hit the same L2.
+//  * The exact local metrics (clustering, controllability) keep two bitmaps of
+//    n bits per node in LDS and walk the neighbours' run lists.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
