@@ -124,8 +124,10 @@ def test_prefix_property(hb):
 
 
 # ---------------------------------------------------------------- full-size graphs, sampled
-def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None):
-    """GPU run on the whole graph; the oracle recomputes sampled nodes from exact balls."""
+def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None, reg4=False):
+    """GPU run on the whole graph; the oracle recomputes sampled nodes from exact balls.
+    reg4: also run with 4-bit registers, which must equal min(8-bit registers, 15)
+    at every node after the same number of steps."""
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
     # the oracle reads its own encoding of the graph (the same bytes, checked)
     csr = oracle.from_graph(g)
@@ -137,6 +139,12 @@ def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None):
             results[kernel] = G.run(p, depth, seed, registers=True, kernel=kernel)
             print(f"[parity] {kernel}: passes={results[kernel].passes} "
                   f"iter_ms={results[kernel].iter_ms:.1f}", flush=True)
+        if reg4:
+            r4 = G.run(p, depth, seed, registers=True, register_bits=4)
+            print(f"[parity] 4-bit: passes={r4.passes} iter_ms={r4.iter_ms:.1f}", flush=True)
+            assert depth > 0 and r4.passes == results["runs"].passes == depth
+            assert np.array_equal(hb.unpack_nibbles(r4.registers),
+                                  np.minimum(results["runs"].registers, 15))
     res = results["runs"]
     T = res.passes
     assert depth == 0 or T <= depth
@@ -186,7 +194,7 @@ def test_city_sampled_bench_config(hb):
     Hilbert processing order, default schedule."""
     g = synth.city(0, device="gpu")
     print(f"[parity] city n={g.n} E={g.n_edges} p=10 depth=3", flush=True)
-    res = _sampled_check(hb, g, 10, 3, n_src=64, order=synth.hilbert_order(g))
+    res = _sampled_check(hb, g, 10, 3, n_src=64, order=synth.hilbert_order(g), reg4=True)
     assert res.passes == 3
     # properties at any size: registers never below a node's own insert, values <= 65-p
     assert int(res.registers.max()) <= 55
