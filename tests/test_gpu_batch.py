@@ -1,8 +1,11 @@
-"""Batched runs (hb_run_batch): every job's result equals its hb_run alone, bit for bit."""
+"""Batched runs (hb_run_batch): every job's result equals the oracle's run of the same
+analysis (Alg. 1: registers byte for byte, passes and convergence exactly, reach and
+Eq. 3 sums within 1e-9), and equals its hb_run alone bit for bit."""
 import numpy as np
 import pytest
 
 import synth
+from oracle_ref import assert_matches, ref
 
 pytestmark = pytest.mark.gpu
 
@@ -28,15 +31,17 @@ def test_batch_equals_single_runs(hb, kernel):
               synth.random_graph(200, 0.01, 3), synth.from_edges(1, [], name="single")]
     Gs = [_load(hb, g) for g in graphs]
     ps = [4, 8, 9, 10, 12, 13] if kernel != "runs" else [4, 8, 9, 10, 12, 11]
-    jobs = []
+    jobs, owners = [], []
     for i, G in enumerate(Gs):
         for k, (p, depth) in enumerate([(ps[i], 0), (ps[(i + 2) % 6], 3), (10, 1 + i % 4)]):
             jobs.append((G, p, depth, 1000 * i + k))
+            owners.append(graphs[i])
     print(f"[batch] {len(jobs)} jobs kernel={kernel}", flush=True)
     res = hb.run_batch(jobs, registers=True, kernel=kernel)
-    for (G, p, depth, seed), r in zip(jobs, res):
-        ref = G.run(p, depth, seed, registers=True, kernel=kernel)
-        _same(r, ref, f"p={p} depth={depth} seed={seed}")
+    for (G, p, depth, seed), g, r in zip(jobs, owners, res):
+        what = f"{g.name} p={p} depth={depth} seed={seed}"
+        assert_matches(hb, r, ref(g, p, depth, seed), what)
+        _same(r, G.run(p, depth, seed, registers=True, kernel=kernel), what)
     # a second batch on the same graphs leaves no state behind
     res2 = hb.run_batch(jobs[::-1], registers=True, kernel=kernel)
     for r1, r2 in zip(res, res2[::-1]):
@@ -47,7 +52,7 @@ def test_batch_equals_single_runs(hb, kernel):
 
 def test_batched_workload_sample(hb):
     """A slice of the batched workload (uneven sizes, 1-2 m cells, mixed p and depth)."""
-    Gs, jobs = [], []
+    Gs, jobs, graphs = [], [], []
     for seed in range(8):
         spec = synth.batch_spec(seed)
         g = synth.batch_graph(seed)
@@ -55,9 +60,11 @@ def test_batched_workload_sample(hb):
               flush=True)
         G = _load(hb, g)
         Gs.append(G)
+        graphs.append(g)
         jobs.append((G, spec["p"], spec["depth"], seed))
     res = hb.run_batch(jobs, registers=True)
-    for (G, p, depth, seed), r in zip(jobs, res):
+    for (G, p, depth, seed), g, r in zip(jobs, graphs, res):
+        assert_matches(hb, r, ref(g, p, depth, seed), f"seed={seed} {g.name}")
         _same(r, G.run(p, depth, seed, registers=True), f"seed={seed}")
     for G in Gs:
         G.free()

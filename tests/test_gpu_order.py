@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_ref
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -74,16 +75,20 @@ def test_ordered_graphs_in_batch_and_server(hb):
     graphs = [synth.tiny(0), synth.grid_graph(1, 70, 50), synth.tiny(7)]
     Gs = [_load(hb, g, order=synth.hilbert_order(g)) for g in graphs]
     jobs = [(G, p, d, 11 * i) for i, G in enumerate(Gs) for (p, d) in ((10, 0), (8, 3))]
+    owners = [g for g in graphs for _ in range(2)]
+    refs = [oracle_ref.ref(g, p, d, s) for g, (G, p, d, s) in zip(owners, jobs)]
     single = [G.run(p, d, s, registers=True, tune="off") for (G, p, d, s) in jobs]
     batched = hb.run_batch(jobs, registers=True, tune="off")
-    for a, b in zip(single, batched):
+    for a, b, r, (G, p, d, s) in zip(single, batched, refs, jobs):
+        _check(b, r, f"batched p={p} d={d} seed={s}")
         assert np.array_equal(a.registers, b.registers) and np.array_equal(a.sum_d, b.sum_d)
     hb.server_start()
     try:
         served = [hb.submit(G, p, d, s, registers=True).wait() for (G, p, d, s) in jobs]
     finally:
         hb.server_stop()
-    for a, b in zip(single, served):
+    for a, b, r, (G, p, d, s) in zip(single, served, refs, jobs):
+        _check(b, r, f"served p={p} d={d} seed={s}")
         assert np.array_equal(a.registers, b.registers) and np.array_equal(a.sum_d, b.sum_d)
     for G in Gs:
         G.free()

@@ -187,12 +187,21 @@ def _urban_graph():
     return _URBAN["g"]
 
 
+_CITY = {}
+
+
+def _city_graph():
+    if "g" not in _CITY:
+        _CITY["g"] = synth.city(0, device="gpu")
+    return _CITY["g"]
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
 def test_city_sampled_bench_config(hb):
     """The benchmark's workload and launch configuration: city graph, p = 10, depth 3,
     Hilbert processing order, default schedule."""
-    g = synth.city(0, device="gpu")
+    g = _city_graph()
     print(f"[parity] city n={g.n} E={g.n_edges} p=10 depth=3", flush=True)
     res = _sampled_check(hb, g, 10, 3, n_src=64, order=synth.hilbert_order(g), reg4=True)
     assert res.passes == 3
@@ -201,3 +210,16 @@ def test_city_sampled_bench_config(hb):
     for v in np.random.default_rng(5).choice(g.n, 200, replace=False):
         j, r = oracle.hll_insert(int(v), 0, 10)
         assert res.registers[v, j] >= r
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_city_sampled_unlimited(hb):
+    """The city graph without a depth limit (Hilbert order, p = 10): the run stops by
+    the 0.5 rule of Alg. 1; sampled nodes against the oracle's exact balls after the
+    same number of steps, and both union kernels agree at every node."""
+    g = _city_graph()
+    print(f"[parity] city n={g.n} E={g.n_edges} p=10 unlimited", flush=True)
+    res = _sampled_check(hb, g, 10, 0, n_src=48, order=synth.hilbert_order(g))
+    print(f"[parity] city unlimited: passes={res.passes} converged={res.converged}", flush=True)
+    assert res.converged and res.passes >= 4

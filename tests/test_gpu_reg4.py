@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_ref
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -89,11 +90,14 @@ def test_4bit_batch_and_served(hb):
     graphs = [synth.tiny(0), synth.grid_graph(1, 60, 50), synth.tiny(4)]
     Gs = [_load(hb, g, order=synth.hilbert_order(g)) for g in graphs]
     jobs = [(G, p, d, 5 * i) for i, G in enumerate(Gs) for (p, d) in ((10, 0), (8, 3), (12, 2))]
+    owners = [g for g in graphs for _ in range(3)]
+    refs = [oracle_ref.ref(g, p, d, s, register_bits=4) for g, (G, p, d, s) in zip(owners, jobs)]
     single = [G.run(p, d, s, registers=True, register_bits=4, tune="off")
               for (G, p, d, s) in jobs]
     batched = hb.run_batch(jobs, registers=True, register_bits=4, tune="measure")
-    for a, b in zip(single, batched):
+    for a, b, r, (G, p, d, s) in zip(single, batched, refs, jobs):
         assert b.register_bits == 4
+        oracle_ref.assert_matches(hb, b, r, f"batched p={p} d={d} seed={s}")
         assert np.array_equal(a.registers, b.registers) and np.array_equal(a.sum_d, b.sum_d)
     hb.server_start()
     try:
@@ -101,8 +105,9 @@ def test_4bit_batch_and_served(hb):
                   for (G, p, d, s) in jobs]
     finally:
         hb.server_stop()
-    for a, b in zip(single, served):
+    for a, b, r, (G, p, d, s) in zip(single, served, refs, jobs):
         assert b.register_bits == 4
+        oracle_ref.assert_matches(hb, b, r, f"served p={p} d={d} seed={s}")
         assert np.array_equal(a.registers, b.registers) and np.array_equal(a.sum_d, b.sum_d)
     hb.tune_clear()
     for G in Gs:

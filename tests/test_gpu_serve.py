@@ -1,10 +1,15 @@
-"""Served runs (hb_submit / hb_poll): continuous batching, admission by memory, identical results."""
+"""Served runs (hb_submit / hb_poll): continuous batching, admission by memory, identical results.
+
+Every served result is compared with the oracle's run of the same analysis (Alg. 1)
+and with the same analysis run alone through hb_run: a result is the same alone and
+in the mix."""
 import time
 
 import numpy as np
 import pytest
 
 import synth
+from oracle_ref import assert_matches, ref
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +52,13 @@ def test_served_mix_equals_single_runs(hb, server, slow_lane_bytes):
     for i, G in enumerate(Gs):
         for k, (p, depth) in enumerate([(10, 0), (8, 3), (13, 2), (4 + i, 1)]):
             specs.append((G, p, depth, 77 * i + k))
+    owner = {id(G): g for G, g in zip(Gs, graphs)}
     tickets = [hb.submit(G, p, d, sd, registers=True) for (G, p, d, sd) in specs]
     res = [t.wait() for t in tickets]
     for (G, p, d, sd), r in zip(specs, res):
-        _same(r, G.run(p, d, sd, registers=True), f"p={p} d={d} seed={sd}")
+        what = f"{owner[id(G)].name} p={p} d={d} seed={sd}"
+        assert_matches(hb, r, ref(owner[id(G)], p, d, sd), what)
+        _same(r, G.run(p, d, sd, registers=True), what)
         assert r.t_submit_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_end_ns
     st = hb.server_stats()
     assert st["completed"] >= len(specs) and st["running"] == 0 and st["queued"] == 0
@@ -63,8 +71,9 @@ def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     """A long request keeps running while short ones arrive, join and finish first."""
     # the per-edge kernel keeps the long request long: about 25 GB of gathers a step
     server(slow_lane_bytes=slow_lane_bytes, kernel="edges")
-    big = _load(hb, synth.grid_graph(1, 120, 100))
-    small = _load(hb, synth.tiny(2))
+    gbig, gsmall = synth.grid_graph(1, 120, 100), synth.tiny(2)
+    big = _load(hb, gbig)
+    small = _load(hb, gsmall)
     tb = hb.submit(big, 12, 0, 5)
     for _ in range(200000):  # until the long request has been admitted
         if hb.server_stats()["running"] >= 1:
@@ -75,8 +84,10 @@ def test_requests_join_while_others_run(hb, server, slow_lane_bytes):
     rb = tb.wait()
     assert max(r.t_end_ns for r in rs) <= rb.t_end_ns
     assert any(r.t_admit_ns > rb.t_admit_ns for r in rs)
+    assert_matches(hb, rb, ref(gbig, 12, 0, 5), "big")
     _same(rb, big.run(12, 0, 5, kernel="edges"), "big")
     for s, r in enumerate(rs):
+        assert_matches(hb, r, ref(gsmall, 8, 2, s), f"small {s}")
         _same(r, small.run(8, 2, s, kernel="edges"), f"small {s}")
     big.free()
     small.free()
@@ -94,6 +105,7 @@ def test_admission_respects_the_budget(hb, server):
     assert st["peak_used_bytes"] <= st["budget_bytes"]
     assert st["peak_used_bytes"] >= per
     for s, r in enumerate(rs):
+        assert_matches(hb, r, ref(g, 10, 0, s), f"seed {s}")
         _same(r, G.run(10, 0, s), f"seed {s}")
     with pytest.raises(hb.HBError) as e:
         hb.submit(_load(hb, synth.grid_graph(0, 64, 64)), 12, 0, 0)
@@ -104,7 +116,8 @@ def test_admission_respects_the_budget(hb, server):
 def test_poll_and_ticket_rules(hb, server):
     server(max_running=1, kernel="edges")  # one request at a time: the second one waits
     big = _load(hb, synth.grid_graph(1, 120, 100))
-    G = _load(hb, synth.tiny(5))
+    g = synth.tiny(5)
+    G = _load(hb, g)
     tb = hb.submit(big, 12, 0, 3)
     t = hb.submit(G, 9, 0, 1)
     with pytest.raises(hb.HBError) as e:
@@ -117,6 +130,7 @@ def test_poll_and_ticket_rules(hb, server):
             break
     assert r is not None
     assert tb.poll() is not None or tb.wait() is not None
+    assert_matches(hb, r, ref(g, 9, 0, 1), "polled")
     _same(r, G.run(9, 0, 1, kernel="edges"), "polled")
     with pytest.raises(hb.HBError) as e:
         t.poll()

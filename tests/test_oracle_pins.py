@@ -566,3 +566,51 @@ def test_local_metrics_isolated_nodes_and_subsets():
     part = oracle.local_metrics(csr, nodes=sub)
     for key in ("pairs", "ball2"):
         assert np.array_equal(part[key], full[key][sub])
+
+
+# ------------------------------------------------ the CPU-baseline unit (one union step)
+@pytest.mark.parametrize("which", ["tiny", "raster"])
+def test_union_sample_is_step_one_of_the_iteration(which):
+    """union_sample (one Eq. 2 union + estimate for listed nodes, the unit the CPU
+    baseline times) started from the inserted counters equals step 1 of Alg. 1 at
+    every node, equals the registers of the exact ball B(v, 1), and counts each
+    listed node's directed edges once."""
+    g = synth.tiny(0) if which == "tiny" else synth.grid_graph(3, 40, 30)
+    p = 10 if which == "tiny" else 7
+    csr = oracle.from_graph(g)
+    cur = oracle.initial_registers(g.n, p, seed=0)
+    nxt, est, edges = oracle.union_sample(csr, p, cur, np.arange(g.n))
+    step1 = oracle.hyperball(csr, p, 1, 0)
+    assert edges == g.n_edges
+    assert np.array_equal(nxt, step1.registers)
+    assert np.array_equal(est, step1.reach)
+    dist = oracle.bfs_all(csr)
+    for v in range(0, g.n, 5):
+        assert np.array_equal(nxt[v], oracle.ball_registers(dist[v], 1, p, 0)), v
+    # a shuffled subset comes back in list order, with only its own edges counted
+    sub = np.random.default_rng(4).permutation(g.n)[:57]
+    nxt2, est2, edges2 = oracle.union_sample(csr, p, cur, sub)
+    assert edges2 == int(g.degrees[sub].sum())
+    assert np.array_equal(nxt2, step1.registers[sub])
+    assert np.array_equal(est2, step1.reach[sub])
+
+
+def test_union_sample_keeps_the_own_counter_and_every_neighbour():
+    """From arbitrary counters: the result is the byte-wise max over v and all of its
+    neighbours.  Isolating one register per node shows that neither v's own counter
+    nor any single neighbour is dropped."""
+    g = synth.random_graph(120, 0.05, seed=8)
+    p = 7
+    m = 1 << p
+    csr = oracle.from_graph(g)
+    nodes = np.arange(g.n)
+    # node u holds a single register: index u mod m, value 1 + u // m
+    cur = np.zeros((g.n, m), np.uint8)
+    cur[nodes, nodes % m] = 1 + nodes // m
+    nxt, _, _ = oracle.union_sample(csr, p, cur, nodes)
+    for v in range(g.n):
+        members = [v] + list(g.adj_ids[g.adj_offsets[v]:g.adj_offsets[v + 1]])
+        want = np.zeros(m, np.uint8)
+        for u in members:
+            want[u % m] = max(want[u % m], 1 + u // m)
+        assert np.array_equal(nxt[v], want), v
