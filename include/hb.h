@@ -186,6 +186,81 @@ typedef struct {
     double default_ms;                    /* and of the default schedule */
 } hb_tune_entry;
 
+/*
+ * Library-wide options (hb_set_options); an all-zero struct selects the
+ * defaults.  Every call takes a copy of them when it starts (a served request
+ * when it is admitted), so changing them affects later calls only.
+ *
+ * Device memory.  Every device allocation of the library -- the arrays of
+ * loaded graphs, the counters, range-max tables and per-node state of
+ * blocking runs, the batched workspace and the memory of served requests --
+ * counts against one budget per device, hbm_budget bytes (0 = no limit but
+ * the device's free memory).  Working buffers are carved first-fit from
+ * pooled blocks of at least 1 GiB (or what the budget leaves), kept between
+ * calls so that a run, a batch or an admitted request takes memory without a
+ * device allocation and returns it without hipFree's implicit device
+ * synchronisation; idle blocks are released by hb_release_cache or when an
+ * allocation would otherwise not fit.  A blocking call whose memory does not
+ * fit returns HB_ENOMEM; a served request waits until running requests free
+ * memory (hb_submit returns HB_ENOMEM only if it could never fit).
+ *
+ * dev_alloc / dev_free: allocator hooks for all of that memory (both or
+ * neither), e.g. a framework's caching allocator.  dev_alloc returns device
+ * memory of the current device aligned to 256 bytes, or NULL when it cannot;
+ * memory is always released through the hooks it was allocated with.  The
+ * hooks may be called from the request loop's threads.
+ *
+ * stream: a hipStream_t (passed as void *) on which the blocking runs
+ * (hb_run, hb_run_with) enqueue their work after the work the
+ * caller queued there; NULL = the graph's own stream.  They still return once
+ * their results are on the host.
+ *
+ * Stopping (Alg. 1 stops after step t when no estimate grew by more than 0.5,
+ * or at the depth limit): stop_delta replaces the 0.5 (0 = 0.5);
+ * stop_rule HB_STOP_DEPTH ignores the growth test and runs exactly depth_limit
+ * steps (runs without a depth limit then return HB_EINVAL).  Every form
+ * follows them.  `converged` still reports whether the last step grew no
+ * estimate by more than the threshold.
+ *
+ * tune_seed: tune_seed_count autotuner picks (as hb_tune_cache returns them,
+ * e.g. saved by an earlier process) put into the pick cache by this call;
+ * they are not kept in the options.
+ */
+#define HB_STOP_CONVERGED 0 /* Alg. 1: the growth test or the depth limit, whichever first */
+#define HB_STOP_DEPTH 1     /* the depth limit only */
+
+typedef struct {
+    uint64_t hbm_budget;
+    void *(*dev_alloc)(uint64_t bytes, void *user);
+    void (*dev_free)(void *ptr, void *user);
+    void *alloc_user;
+    void *stream;
+    uint32_t stop_rule;
+    double stop_delta;
+    const hb_tune_entry *tune_seed;
+    uint32_t tune_seed_count;
+} hb_options;
+
+/* Replace the options (NULL = defaults).  HB_EINVAL for a hook without its
+   partner, an unknown stop rule, a negative stop_delta or a seed entry naming
+   no built schedule.  Host-only. */
+hb_status hb_set_options(const hb_options *o);
+
+/* The current options (tune_seed is always NULL). */
+hb_status hb_get_options(hb_options *out);
+
+/* Device memory held by the library on one device. */
+typedef struct {
+    uint64_t budget_bytes;         /* hb_options.hbm_budget (0 = none) */
+    uint64_t held_bytes;           /* allocated: graphs, pool blocks, small tables */
+    uint64_t peak_held_bytes;
+    uint64_t pool_bytes;           /* pooled blocks */
+    uint64_t pool_used_bytes;      /* taken from them by runs, batches and requests */
+    uint64_t pool_peak_used_bytes;
+} hb_memory_stats_t;
+
+hb_status hb_memory_stats(int32_t device, hb_memory_stats_t *out);
+
 /* Library version string. */
 const char *hb_version(void);
 

@@ -95,6 +95,25 @@ class _TuneEntry(ctypes.Structure):
                 ("default_ms", ctypes.c_double)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("dev_alloc", _ALLOC_FN),
+                ("dev_free", _FREE_FN), ("alloc_user", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p), ("stop_rule", ctypes.c_uint32),
+                ("stop_delta", ctypes.c_double), ("tune_seed", ctypes.POINTER(_TuneEntry)),
+                ("tune_seed_count", ctypes.c_uint32)]
+
+
+class _MemStats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
+                ("peak_held_bytes", ctypes.c_uint64), ("pool_bytes", ctypes.c_uint64),
+                ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_used_bytes", ctypes.c_uint64)]
+
+
+STOP_CONVERGED, STOP_DEPTH = 0, 1
 TUNE_CACHED, TUNE_MEASURE, TUNE_OFF = 0, 1, 2
 _TUNE = {"cached": TUNE_CACHED, "measure": TUNE_MEASURE, "off": TUNE_OFF}
 
@@ -175,6 +194,12 @@ def _lib():
                                   ctypes.c_uint64, ctypes.POINTER(_RunOpts),
                                   ctypes.POINTER(_Result)]
         L.hb_run_with.restype = st
+        L.hb_set_options.argtypes = [ctypes.POINTER(_Options)]
+        L.hb_set_options.restype = st
+        L.hb_get_options.argtypes = [ctypes.POINTER(_Options)]
+        L.hb_get_options.restype = st
+        L.hb_memory_stats.argtypes = [ctypes.c_int32, ctypes.POINTER(_MemStats)]
+        L.hb_memory_stats.restype = st
         L.hb_run_batch.argtypes = [ctypes.POINTER(_Job), ctypes.c_uint32, ctypes.POINTER(_RunOpts),
                                    ctypes.POINTER(_Result)]
         L.hb_run_batch.restype = st
@@ -534,6 +559,67 @@ def tune_cache() -> list:
         out.append({f: getattr(e, f) for f, _ in _TuneEntry._fields_})
         out[-1]["union_kernel"] = {UNION_EDGES: "edges", UNION_RUNS: "runs"}[e.union_kernel]
     return out
+
+
+# the installed allocator hooks stay referenced while the library may call them
+_HOOKS = []
+
+
+def set_options(hbm_budget: int = 0, dev_alloc=None, dev_free=None, stream=None,
+                stop_rule: str = "converged", stop_delta: float = 0.0,
+                tune_seed: list | None = None) -> None:
+    """hb_set_options (all defaults when called without arguments).
+
+    dev_alloc(bytes) -> int device pointer (0 on failure) and dev_free(ptr) are
+    Python callables used for every device allocation of the library; stream is a
+    hipStream_t as an int (e.g. torch.cuda.Stream().cuda_stream) for blocking runs;
+    stop_rule "converged" (Alg. 1) or "depth" (run exactly the depth limit);
+    stop_delta replaces the 0.5 growth threshold; tune_seed: entries as returned by
+    tune_cache(), put into the pick cache.
+    """
+    o = _Options()
+    o.hbm_budget = int(hbm_budget)
+    hooks = []
+    if (dev_alloc is None) != (dev_free is None):
+        raise HBError(HB_EINVAL, "dev_alloc and dev_free must be given together")
+    if dev_alloc is not None:
+        a = _ALLOC_FN(lambda nbytes, user: int(dev_alloc(int(nbytes))) or None)
+        f = _FREE_FN(lambda ptr, user: dev_free(int(ptr)))
+        o.dev_alloc, o.dev_free = a, f
+        hooks = [a, f]
+    o.stream = int(stream) if stream else None
+    o.stop_rule = {"converged": STOP_CONVERGED, "depth": STOP_DEPTH}[stop_rule]
+    o.stop_delta = float(stop_delta)
+    seeds = None
+    if tune_seed:
+        seeds = (_TuneEntry * len(tune_seed))()
+        for e, d in zip(seeds, tune_seed):
+            for f, _ in _TuneEntry._fields_:
+                v = d[f]
+                if f == "union_kernel" and isinstance(v, str):
+                    v = {"edges": UNION_EDGES, "runs": UNION_RUNS}[v]
+                setattr(e, f, v)
+        o.tune_seed = seeds
+        o.tune_seed_count = len(tune_seed)
+    _check(_lib().hb_set_options(ctypes.byref(o)))
+    _HOOKS.append(hooks)  # old hooks may still free what they allocated
+
+
+def get_options() -> dict:
+    """hb_get_options: budget, stream, stop rule and threshold in force."""
+    o = _Options()
+    _check(_lib().hb_get_options(ctypes.byref(o)))
+    return {"hbm_budget": o.hbm_budget, "stream": o.stream or 0,
+            "hooks": bool(o.dev_alloc), "stop_rule": {STOP_CONVERGED: "converged",
+                                                      STOP_DEPTH: "depth"}[o.stop_rule],
+            "stop_delta": o.stop_delta}
+
+
+def memory_stats(device: int = 0) -> dict:
+    """hb_memory_stats: device memory the library holds on one device."""
+    m = _MemStats()
+    _check(_lib().hb_memory_stats(device, ctypes.byref(m)))
+    return {f: getattr(m, f) for f, _ in _MemStats._fields_}
 
 
 def tune_clear() -> None:

@@ -24,7 +24,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
-SOURCES = ["hb_kernels.hip", "hb_host.cpp", "hb_server.cpp", "hb_tune.cpp"]
+SOURCES = ["hb_kernels.hip", "hb_host.cpp", "hb_server.cpp", "hb_tune.cpp", "hb_pool.cpp"]
 
 
 def hipcc() -> str:

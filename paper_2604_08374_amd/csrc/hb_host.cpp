@@ -140,53 +140,21 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
 
 namespace {
 
-// Ping-pong counter buffers (with the run kernel's table levels) of blocking
-// runs, one pair per device, shared by every graph: runs on a device are
-// serialised by g_dev_mu, so the pair only has to fit the largest run, not
-// the sum over the graphs loaded.  Grown on demand, freed by hb_release_cache.
-struct RunWorkspace {
-    uint8_t *buf[2] = {nullptr, nullptr};
-    uint64_t bytes = 0;
-
-    void release() {
-        (void)hipFree(buf[0]);
-        (void)hipFree(buf[1]);
-        buf[0] = buf[1] = nullptr;
-        bytes = 0;
-    }
-    hipError_t reserve(uint64_t need) {
-        if (bytes >= need) return hipSuccess;
-        release();
-        hipError_t e = hipMalloc(&buf[0], need);
-        if (e == hipSuccess) e = hipMalloc(&buf[1], need);
-        if (e != hipSuccess) {
-            release();
-            return e;
-        }
-        bytes = need;
-        return hipSuccess;
-    }
-};
-std::map<int, RunWorkspace> g_run_ws;  // by device, guarded by g_dev_mu
-
 void graph_release(hb_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
-    (void)hipFree(g->d_bytes);
-    (void)hipFree(g->d_offsets);
-    (void)hipFree(g->d_cprev);
-    (void)hipFree(g->d_order);
-    (void)hipFree(g->d_hash_ids);
-    (void)hipFree(g->d_degrees);
-    (void)hipFree(g->d_comp);
-    (void)hipFree(g->d_runs);
-    (void)hipFree(g->d_run_off);
-    (void)hipFree(g->d_sumd);
-    (void)hipFree(g->d_flags);
-    if (g->h_flag) (void)hipHostFree(g->h_flag);
-    for (auto &e : g->ev)
+    for (void *p : {(void *)g->d_bytes, (void *)g->d_offsets, (void *)g->d_cprev,
+                    (void *)g->d_order, (void *)g->d_hash_ids, (void *)g->d_degrees,
+                    (void *)g->d_comp, (void *)g->d_runs, (void *)g->d_run_off,
+                    (void *)g->d_sumd, (void *)g->d_flags})
+        dfree(p);
+    if (g->h_flags) (void)hipHostFree(g->h_flags);
+    for (auto &e : g->ev_init)
         if (e) (void)hipEventDestroy(e);
+    for (auto &step : g->ev_step)
+        for (auto &e : step)
+            if (e) (void)hipEventDestroy(e);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
@@ -202,7 +170,7 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
     std::vector<uint32_t> cnt(n);
     std::vector<uint64_t> h_off((size_t)n + 1);
     uint32_t *d_cnt = nullptr;
-    hipError_t e = hipMalloc(&d_cnt, sizeof(uint32_t) * n);
+    hipError_t e = dmalloc((void **)&d_cnt, sizeof(uint32_t) * n);
     if (e == hipSuccess)
         e = hbk::launch_row_runs(g->d_bytes, g->d_offsets, n, join_self, d_cnt, nullptr, nullptr,
                                  g->stream);
@@ -210,13 +178,14 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
         e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
                            g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    (void)hipFree(d_cnt);
+    (void)hipStreamSynchronize(g->stream);
+    dfree(d_cnt);
     if (e != hipSuccess) return e;
     h_off[0] = 0;
     for (uint32_t v = 0; v < n; ++v) h_off[v + 1] = h_off[v] + cnt[v];
     *total = h_off[n];
-    e = hipMalloc(off, sizeof(uint64_t) * (n + 1ull));
-    if (e == hipSuccess) e = hipMalloc(runs, sizeof(uint2) * std::max<uint64_t>(h_off[n], 1));
+    e = dmalloc((void **)off, sizeof(uint64_t) * (n + 1ull));
+    if (e == hipSuccess) e = dmalloc((void **)runs, sizeof(uint2) * std::max<uint64_t>(h_off[n], 1));
     if (e == hipSuccess)
         e = hipMemcpyAsync(*off, h_off.data(), sizeof(uint64_t) * (n + 1ull),
                            hipMemcpyHostToDevice, g->stream);
@@ -226,8 +195,8 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     (void)hipStreamSynchronize(g->stream);  // h_off is read by the copy
     if (e != hipSuccess) {
-        (void)hipFree(*off);
-        (void)hipFree(*runs);
+        dfree(*off);
+        dfree(*runs);
         *off = nullptr;
         *runs = nullptr;
     }
@@ -424,21 +393,25 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
-    for (auto &ev : g->ev)
+    for (auto &ev : g->ev_init)
         if ((e = hipEventCreate(&ev)) != hipSuccess) return bail(e, "hipEventCreate");
-    if ((e = hipHostMalloc((void **)&g->h_flag, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
+    for (auto &step : g->ev_step)
+        for (auto &ev : step)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return bail(e, "hipEventCreate");
+    if ((e = hipHostMalloc((void **)&g->h_flags, sizeof(uint32_t) * kSegment,
+                           hipHostMallocDefault)) != hipSuccess)
         return bail(e, "hipHostMalloc");
-    if ((e = hipMalloc(&g->d_bytes, std::max<uint64_t>(g->n_bytes, 16))) != hipSuccess)
-        return bail(e, "hipMalloc(bytes)");
-    if ((e = hipMalloc(&g->d_offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1))) != hipSuccess)
-        return bail(e, "hipMalloc(offsets)");
-    if ((e = hipMalloc(&g->d_cprev, sizeof(double) * g->n)) != hipSuccess)
-        return bail(e, "hipMalloc(c_prev)");
-    if ((e = hipMalloc(&g->d_sumd, sizeof(double) * g->n)) != hipSuccess)
-        return bail(e, "hipMalloc(sum_d)");
+    if ((e = dmalloc((void **)&g->d_bytes, std::max<uint64_t>(g->n_bytes, 16))) != hipSuccess)
+        return bail(e, "device allocation (bytes)");
+    if ((e = dmalloc((void **)&g->d_offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1))) != hipSuccess)
+        return bail(e, "device allocation (offsets)");
+    if ((e = dmalloc((void **)&g->d_cprev, sizeof(double) * g->n)) != hipSuccess)
+        return bail(e, "device allocation (c_prev)");
+    if ((e = dmalloc((void **)&g->d_sumd, sizeof(double) * g->n)) != hipSuccess)
+        return bail(e, "device allocation (sum_d)");
     g->n_flags = (uint64_t)g->n + 2;
-    if ((e = hipMalloc(&g->d_flags, sizeof(uint32_t) * g->n_flags)) != hipSuccess)
-        return bail(e, "hipMalloc(flags)");
+    if ((e = dmalloc((void **)&g->d_flags, sizeof(uint32_t) * g->n_flags)) != hipSuccess)
+        return bail(e, "device allocation (flags)");
     if (g->n_bytes &&
         (e = hipMemcpy(g->d_bytes, csr->bytes, g->n_bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(bytes)");
@@ -450,8 +423,8 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                             std::make_pair(csr->degrees, &g->d_degrees),
                             std::make_pair(csr->comp_size, &g->d_comp)}) {
         if (!opt.first) continue;
-        if ((e = hipMalloc(opt.second, sizeof(uint32_t) * g->n)) != hipSuccess)
-            return bail(e, "hipMalloc(per-node array)");
+        if ((e = dmalloc((void **)opt.second, sizeof(uint32_t) * g->n)) != hipSuccess)
+            return bail(e, "device allocation (per-node array)");
         if ((e = hipMemcpy(*opt.second, opt.first, sizeof(uint32_t) * g->n,
                            hipMemcpyHostToDevice)) != hipSuccess)
             return bail(e, "hipMemcpy(per-node array)");
@@ -507,16 +480,37 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
     return hb_run_with(g, p, depth_limit, hash_seed, nullptr, out);
 }
 
-hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
-                      const hb_run_opts *opts, hb_result *out) {
+}  // extern "C"
+
+namespace {
+
+// Pool memory taken for one call, returned when the call ends.
+struct PoolHold {
+    void *p = nullptr;
+    ~PoolHold() { pool_give(p); }
+};
+
+// One blocking run (Alg. 1).  Steps are enqueued kSegment at a time without a
+// host synchronisation in between: each table and union launch of step t > 1
+// first reads step t - 1's stop flag and returns at once when that step grew no
+// estimate by more than the threshold, so steps queued past the stopping point
+// change nothing.  After each segment the host reads the segment's flags and
+// either finds the step that stopped the run or queues the next segment.
+hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                       const hb_run_opts *opts, hb_result *out) {
     const uint64_t t_start = now_ns();
     if (!g || !out) return fail(HB_EINVAL, "NULL argument");
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
     const hb_run_opts o = opts ? *opts : hb_run_opts{};
+    const hb_options lib = options();
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
+    const bool depth_only = lib.stop_rule == HB_STOP_DEPTH;
+    if (depth_only && depth_limit == 0)
+        return fail(HB_EINVAL, "the stop rule HB_STOP_DEPTH needs a depth limit");
+    const double thr = lib.stop_delta > 0.0 ? lib.stop_delta : 0.5;
     hbk::Sched fixed{};
     hb_status st = explicit_sched(o, p, &fixed);
     if (st != HB_OK) return st;
@@ -528,9 +522,7 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
 
     // kernel choice and table depth
     uint32_t levels = o.table_levels ? o.table_levels : kDefaultLevels;
-    uint32_t lg = 0;
-    while ((2ull << lg) <= n) ++lg;  // floor(log2 n)
-    levels = std::min(levels, lg);
+    levels = std::min(levels, floor_log2(n));
     bool runs = (o.union_kernel == HB_UNION_RUNS) || (o.union_kernel == HB_UNION_AUTO && p <= 12);
     if (runs && (uint64_t)(levels + 1) * n >= (1ull << 32)) {
         if (o.union_kernel == HB_UNION_RUNS)
@@ -542,24 +534,28 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
             return fail(HB_ENOMEM, "the graph's run list did not fit in device memory at load");
         runs = false;
     }
-    if (runs && o.union_kernel == HB_UNION_AUTO) {
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-            const uint64_t want = 2ull * (levels + 1) * n * m;
-            if (want > (uint64_t)free_b + g_run_ws[g->device].bytes * 2 || want > (64ull << 30))
-                runs = false;
-        }
-    }
-    const uint64_t need = (uint64_t)n * m * (runs ? (levels + 1u) : 1u);
-    RunWorkspace &ws = g_run_ws[g->device];
+    // both counter buffers (with the run kernel's table levels) in one piece
+    const auto buf_bytes = [&](bool r) {
+        return ((uint64_t)n * m * (r ? (levels + 1u) : 1u) + 255u) & ~255ull;
+    };
+    uint8_t *ws = nullptr;
+    PoolHold hold;
     {
-        const hipError_t e = ws.reserve(need);
-        if (e == hipErrorOutOfMemory)
-            return fail(HB_ENOMEM, "counters need 2 x %llu bytes", (unsigned long long)need);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(counters)");
+        // tables beyond 64 GiB are not worth their memory; the per-edge kernel
+        // needs none
+        if (runs && o.union_kernel == HB_UNION_AUTO && 2ull * buf_bytes(true) > (64ull << 30))
+            runs = false;
+        st = pool_take(2ull * buf_bytes(runs), &hold.p);
+        if (st == HB_ENOMEM && runs && o.union_kernel == HB_UNION_AUTO) {
+            runs = false;
+            st = pool_take(2ull * buf_bytes(false), &hold.p);
+        }
+        if (st != HB_OK) return st;
+        ws = static_cast<uint8_t *>(hold.p);
     }
-    hipStream_t s = g->stream;
-    uint8_t *cur = ws.buf[0], *next = ws.buf[1];
+    if (!runs) levels = 0;
+    uint8_t *const bufs[2] = {ws, ws + buf_bytes(runs)};  // step t reads bufs[(t-1)&1]
+    hipStream_t s = lib.stream ? static_cast<hipStream_t>(lib.stream) : g->stream;
     const hbk::Sched init_sched = hbk::default_sched((int)p, bits);
 
     // ---- union schedule: explicit, cached, measured here, or the default
@@ -577,17 +573,18 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
             // initialised again below, so the trials leave no trace
             const uint64_t t0 = now_ns();
             HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
-            HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed,
-                                    g->d_hash_ids, s));
-            if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
+            HB_HIP(hbk::launch_init((int)p, init_sched, bufs[0], g->d_cprev, g->d_sumd, n,
+                                    hash_seed, g->d_hash_ids, s));
+            if (runs) HB_HIP(hbk::launch_table(bufs[0], n, (uint32_t)m, levels, bits, nullptr, s));
             TunePick pick;
             st = tune_measure((int)p, bits, runs, s, [&](const hbk::Sched &c) {
-                return runs ? hbk::launch_union_runs((int)p, c, g->d_runs, g->d_run_off, cur,
-                                                     levels, next, g->d_cprev, g->d_sumd,
-                                                     g->d_flags + 1, n, 1u, g->d_order, s)
-                            : hbk::launch_union((int)p, c, g->d_bytes, g->d_offsets, cur, next,
-                                                g->d_cprev, g->d_sumd, g->d_flags + 1, n, 1u,
-                                                g->d_order, s);
+                return runs ? hbk::launch_union_runs((int)p, c, g->d_runs, g->d_run_off, bufs[0],
+                                                     levels, bufs[1], g->d_cprev, g->d_sumd,
+                                                     g->d_flags + 1, n, 1u, g->d_order, thr,
+                                                     nullptr, s)
+                            : hbk::launch_union((int)p, c, g->d_bytes, g->d_offsets, bufs[0],
+                                                bufs[1], g->d_cprev, g->d_sumd, g->d_flags + 1, n,
+                                                1u, g->d_order, thr, nullptr, s);
             }, &pick);
             if (st != HB_OK) return st;
             tune_put(key, pick);
@@ -597,69 +594,86 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     }
 
     HB_HIP(hbk::launch_fill_u32(g->d_flags, 0u, g->n_flags, s));
-    HB_HIP(hipEventRecord(g->ev[0], s));
-    HB_HIP(hbk::launch_init((int)p, init_sched, cur, g->d_cprev, g->d_sumd, n, hash_seed,
-                                    g->d_hash_ids, s));
-    HB_HIP(hipEventRecord(g->ev[1], s));
+    HB_HIP(hipEventRecord(g->ev_init[0], s));
+    HB_HIP(hbk::launch_init((int)p, init_sched, bufs[0], g->d_cprev, g->d_sumd, n, hash_seed,
+                            g->d_hash_ids, s));
+    HB_HIP(hipEventRecord(g->ev_init[1], s));
 
+    // ---- steps, kSegment at a time
+    // registers are fixed after D <= n - 1 steps, so step n + 1 at the latest
+    // finds no growth; flags has n + 2 entries (index 0 unused)
+    const uint32_t last_step = (uint32_t)std::min<uint64_t>(
+        depth_limit ? depth_limit : UINT32_MAX, g->n_flags - 2u + 1u);
     double iter_ms = 0.0, table_ms = 0.0;
-    uint32_t t = 0, converged = 0;
-    for (;;) {
-        ++t;
-        HB_HIP(hipEventRecord(g->ev[2], s));
-        if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, s));
-        HB_HIP(hipEventRecord(g->ev[3], s));
-        if (runs)
-            HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_runs, g->d_run_off, cur, levels,
-                                          next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t,
-                                          g->d_order, s));
-        else
-            HB_HIP(hbk::launch_union((int)p, sched, g->d_bytes, g->d_offsets, cur, next,
-                                     g->d_cprev, g->d_sumd, g->d_flags + t, n, t, g->d_order, s));
-        HB_HIP(hipEventRecord(g->ev[4], s));
-        HB_HIP(hipMemcpyAsync(g->h_flag, g->d_flags + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HB_HIP(hipStreamSynchronize(s));
-        float ms = 0.f;
-        HB_HIP(hipEventElapsedTime(&ms, g->ev[3], g->ev[4]));
-        iter_ms += ms;
-        HB_HIP(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
-        table_ms += ms;
-        if (*g->h_flag == 0u) {
-            converged = 1;
-            break;
+    uint32_t T = 0, converged = 0, queued = 0;
+    while (T == 0) {
+        const uint32_t first = queued + 1u;
+        const uint32_t end = std::min<uint32_t>(queued + kSegment, last_step);
+        for (uint32_t t = first; t <= end; ++t) {
+            hipEvent_t *ev = g->ev_step[(t - 1u) % kSegment];
+            // a step after one that stopped the run returns at once
+            const uint32_t *skip = (t > 1u && !depth_only) ? g->d_flags + (t - 1u) : nullptr;
+            uint8_t *cur = bufs[(t - 1u) & 1u], *next = bufs[t & 1u];
+            HB_HIP(hipEventRecord(ev[0], s));
+            if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, skip, s));
+            HB_HIP(hipEventRecord(ev[1], s));
+            if (runs)
+                HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_runs, g->d_run_off, cur, levels,
+                                              next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t,
+                                              g->d_order, thr, skip, s));
+            else
+                HB_HIP(hbk::launch_union((int)p, sched, g->d_bytes, g->d_offsets, cur, next,
+                                         g->d_cprev, g->d_sumd, g->d_flags + t, n, t, g->d_order,
+                                         thr, skip, s));
+            HB_HIP(hipEventRecord(ev[2], s));
         }
-        if (depth_limit != 0 && t == depth_limit) break;
-        if ((uint64_t)t + 1 >= g->n_flags) break;  // registers are fixed after D <= n - 1 steps
-        std::swap(cur, next);
+        HB_HIP(hipMemcpyAsync(g->h_flags, g->d_flags + first, sizeof(uint32_t) * (end - first + 1u),
+                              hipMemcpyDeviceToHost, s));
+        HB_HIP(hipStreamSynchronize(s));
+        // a step after an early stop returned at once, so its flag is 0 too:
+        // the first zero flag is the step that stopped the run
+        for (uint32_t t = first; t <= end && T == 0; ++t) {
+            const bool grew = g->h_flags[t - first] != 0u;
+            if (t == last_step || (!grew && !depth_only)) {
+                T = t;
+                converged = grew ? 0u : 1u;
+            }
+        }
+        queued = end;  // no stop inside the segment: the run goes on after `end`
+        const uint32_t upto = T ? T : end;
+        for (uint32_t t = first; t <= upto; ++t) {
+            hipEvent_t *ev = g->ev_step[(t - 1u) % kSegment];
+            float ms = 0.f;
+            HB_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+            iter_ms += ms;
+            HB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            table_ms += ms;
+        }
     }
     float init_ms = 0.f, run_ms = 0.f;
-    HB_HIP(hipEventElapsedTime(&init_ms, g->ev[0], g->ev[1]));
-    HB_HIP(hipEventElapsedTime(&run_ms, g->ev[0], g->ev[4]));
+    HB_HIP(hipEventElapsedTime(&init_ms, g->ev_init[0], g->ev_init[1]));
+    HB_HIP(hipEventElapsedTime(&run_ms, g->ev_init[0], g->ev_step[(T - 1u) % kSegment][2]));
 
     if (out->reach)
-        HB_HIP(hipMemcpy(out->reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost));
-    if (out->sum_d || out->mean_depth) {
-        std::vector<double> tmp;
-        double *sd = out->sum_d;
-        if (!sd) {
-            tmp.resize(n);
-            sd = tmp.data();
-        }
-        HB_HIP(hipMemcpy(sd, g->d_sumd, sizeof(double) * n, hipMemcpyDeviceToHost));
-        if (out->mean_depth)
-            for (uint32_t v = 0; v < n; ++v) {
-                const double nv = g->comp_size.empty() ? (double)n : (double)g->comp_size[v];
-                out->mean_depth[v] = nv >= 2.0 ? sd[v] / (nv - 1.0) : NAN;
-            }
-    }
+        HB_HIP(hipMemcpyAsync(out->reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    // the sums land in mean_depth when sum_d is not wanted: no host buffer
+    double *sd = out->sum_d ? out->sum_d : out->mean_depth;
+    if (sd) HB_HIP(hipMemcpyAsync(sd, g->d_sumd, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     if (out->registers)
-        HB_HIP(hipMemcpy(out->registers, next, (uint64_t)n * m, hipMemcpyDeviceToHost));
+        HB_HIP(hipMemcpyAsync(out->registers, bufs[T & 1u], (uint64_t)n * m, hipMemcpyDeviceToHost,
+                              s));
+    HB_HIP(hipStreamSynchronize(s));
+    if (out->mean_depth)
+        for (uint32_t v = 0; v < n; ++v) {
+            const double nv = g->comp_size.empty() ? (double)n : (double)g->comp_size[v];
+            out->mean_depth[v] = nv >= 2.0 ? sd[v] / (nv - 1.0) : NAN;
+        }
     const double md = (double)(1ull << p);
-    out->passes = t;
+    out->passes = T;
     out->converged = converged;
-    out->productive_iters = converged ? t - 1u : t;
+    out->productive_iters = converged ? T - 1u : T;
     out->c0 = md * std::log(md / (md - 1.0));
-    out->edge_unions = (uint64_t)t * g->n_edges;
+    out->edge_unions = (uint64_t)T * g->n_edges;
     out->init_ms = init_ms;
     out->iter_ms = iter_ms;
     out->table_ms = table_ms;
@@ -677,6 +691,15 @@ hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t ha
     return HB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                      const hb_run_opts *opts, hb_result *out) {
+    return run_blocking(g, p, depth_limit, hash_seed, opts, out);
+}
+
 namespace {
 
 uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
@@ -686,8 +709,6 @@ uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 // Guarded by g_dev_mu.
 struct BatchCache {
     int device = -1;
-    void *arena = nullptr;
-    uint64_t arena_bytes = 0;
     hbk::BatchJob *d_jobs = nullptr;
     hbk::BatchJob *h_jobs = nullptr;  // pinned mirror for the done checks
     uint32_t jobs_cap = 0;
@@ -704,43 +725,35 @@ struct BatchCache {
             if (e) (void)hipEventDestroy(e);
         if (stream) (void)hipStreamDestroy(stream);
         if (h_jobs) (void)hipHostFree(h_jobs);
-        (void)hipFree(d_lists);
-        (void)hipFree(d_jobs);
-        (void)hipFree(arena);
+        dfree(d_lists);
+        dfree(d_jobs);
         *this = BatchCache{};
     }
 
-    hipError_t reserve(int dev, uint64_t arena_need, uint32_t jobs_need, uint64_t lists_need) {
+    hipError_t reserve(int dev, uint32_t jobs_need, uint64_t lists_need) {
         if (device != dev) release();
         device = dev;
         hipError_t e = hipSuccess;
         if (!stream) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
         for (auto &x : ev)
             if (e == hipSuccess && !x) e = hipEventCreate(&x);
-        if (e == hipSuccess && arena_bytes < arena_need) {
-            (void)hipFree(arena);
-            arena = nullptr;
-            arena_bytes = 0;
-            e = hipMalloc(&arena, arena_need);
-            if (e == hipSuccess) arena_bytes = arena_need;
-        }
         if (e == hipSuccess && jobs_cap < jobs_need) {
-            (void)hipFree(d_jobs);
+            dfree(d_jobs);
             if (h_jobs) (void)hipHostFree(h_jobs);
             d_jobs = nullptr;
             h_jobs = nullptr;
             jobs_cap = 0;
-            e = hipMalloc(&d_jobs, sizeof(hbk::BatchJob) * jobs_need);
+            e = dmalloc((void **)&d_jobs, sizeof(hbk::BatchJob) * jobs_need);
             if (e == hipSuccess)
                 e = hipHostMalloc((void **)&h_jobs, sizeof(hbk::BatchJob) * jobs_need,
                                   hipHostMallocDefault);
             if (e == hipSuccess) jobs_cap = jobs_need;
         }
         if (e == hipSuccess && lists_cap < lists_need) {
-            (void)hipFree(d_lists);
+            dfree(d_lists);
             d_lists = nullptr;
             lists_cap = 0;
-            e = hipMalloc(&d_lists, sizeof(uint32_t) * lists_need);
+            e = dmalloc((void **)&d_lists, sizeof(uint32_t) * lists_need);
             if (e == hipSuccess) lists_cap = lists_need;
         }
         return e;
@@ -786,6 +799,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     if (!jobs || !outs || n_jobs == 0) return fail(HB_EINVAL, "NULL argument or no jobs");
     if (n_jobs > 65535) return fail(HB_EINVAL, "at most 65535 jobs per batch");
     const hb_run_opts o = opts ? *opts : hb_run_opts{};
+    const hb_options lib = options();
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     for (uint32_t j = 0; j < n_jobs; ++j) {
@@ -795,6 +809,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
             if (st != HB_OK) return st;
         }
         if (!jobs[j].g) return fail(HB_EINVAL, "job %u has no graph", j);
+        if (lib.stop_rule == HB_STOP_DEPTH && jobs[j].depth_limit == 0)
+            return fail(HB_EINVAL, "job %u: the stop rule HB_STOP_DEPTH needs a depth limit", j);
         if (jobs[j].p < HB_P_MIN || jobs[j].p > HB_P_MAX)
             return fail(HB_EINVAL, "job %u: p = %u outside [4, 16]", j, jobs[j].p);
         if (o.union_kernel == HB_UNION_RUNS && jobs[j].p > 12)
@@ -844,6 +860,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
         b.runs = runs ? 1u : 0u;
         b.bits = bits;
+        b.depth_only = lib.stop_rule == HB_STOP_DEPTH ? 1u : 0u;
+        b.stop_delta = lib.stop_delta > 0.0 ? lib.stop_delta : 0.5;
         off_buf[j] = arena;
         arena += 2 * align256((uint64_t)g->n * m * (levels + 1u));
         off_state[j] = arena;
@@ -860,14 +878,19 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         // (+ tuning: the block bases of every candidate schedule of a class)
         const uint64_t lists_need = 3ull * n_jobs + (uint64_t)(max_levels + 1) * (n_jobs + 1) +
                                     16ull * (n_jobs + 1) + 16ull * (n_jobs + 64);
-        const hipError_t e = g_batch.reserve(jobs[0].g->device, arena, n_jobs, lists_need);
+        const hipError_t e = g_batch.reserve(jobs[0].g->device, n_jobs, lists_need);
         if (e == hipErrorOutOfMemory)
-            return fail(HB_ENOMEM, "batch needs %llu bytes of device memory", (unsigned long long)arena);
+            return fail(HB_ENOMEM, "batch job tables do not fit in device memory");
         if (e != hipSuccess) return hip_fail(e, "batch workspace");
+    }
+    PoolHold arena_hold;  // every job's counters, tables, state and flags
+    {
+        const hb_status st = pool_take(arena, &arena_hold.p);
+        if (st != HB_OK) return st;
     }
     BatchCache &R = g_batch;
     StepGraph SG;
-    uint8_t *base = static_cast<uint8_t *>(R.arena);
+    uint8_t *base = static_cast<uint8_t *>(arena_hold.p);
     uint32_t *d_flags = reinterpret_cast<uint32_t *>(base + flags_at);
     for (uint32_t j = 0; j < n_jobs; ++j) {
         const uint64_t m = (1ull << jobs[j].p) * bits / 8u;
@@ -1116,8 +1139,8 @@ hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out) {
     HB_HIP(hipSetDevice(g->device));
     const uint64_t n = g->n;
     double *d_sum = nullptr, *d_out = nullptr;
-    hipError_t e = hipMalloc(&d_sum, sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * 8 * n);
+    hipError_t e = dmalloc((void **)&d_sum, sizeof(double) * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_out, sizeof(double) * 8 * n);
     if (e == hipSuccess) e = hipMemcpyAsync(d_sum, sum_d, sizeof(double) * n, hipMemcpyHostToDevice,
                                             g->stream);
     if (e == hipSuccess)
@@ -1129,8 +1152,8 @@ hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out) {
                                hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     (void)hipStreamSynchronize(g->stream);
-    (void)hipFree(d_out);
-    (void)hipFree(d_sum);
+    dfree(d_out);
+    dfree(d_sum);
     if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "VGA metrics: out of device memory");
     if (e != hipSuccess) return hip_fail(e, "VGA metrics");
     return HB_OK;
@@ -1157,10 +1180,10 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
     // the plain maximal runs of every row (v is no neighbour of itself)
     uint64_t total = 0;
     hipError_t e = build_run_list(g, false, &d_runs, &d_off, &total);
-    if (e == hipSuccess) e = hipMalloc(&d_pairs, sizeof(uint64_t) * n);
-    if (e == hipSuccess) e = hipMalloc(&d_ball, sizeof(uint32_t) * n);
-    if (e == hipSuccess) e = hipMalloc(&d_clus, sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc(&d_ctrl, sizeof(double) * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_pairs, sizeof(uint64_t) * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_ball, sizeof(uint32_t) * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_clus, sizeof(double) * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_ctrl, sizeof(double) * n);
     if (e == hipSuccess)
         e = hbk::launch_local(d_runs, d_off, g->d_degrees, n, g->d_order, d_pairs, d_ball, d_clus,
                               d_ctrl, g->stream);
@@ -1180,7 +1203,7 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
     (void)hipStreamSynchronize(g->stream);
     for (void *p : {(void *)d_off, (void *)d_runs, (void *)d_pairs, (void *)d_ball,
                     (void *)d_clus, (void *)d_ctrl})
-        (void)hipFree(p);
+        dfree(p);
     if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "local metrics: out of device memory");
     if (e != hipSuccess) return hip_fail(e, "local metrics");
     return HB_OK;
@@ -1189,11 +1212,7 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
 hb_status hb_release_cache(void) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_batch.release();
-    for (auto &kv : g_run_ws) {
-        (void)hipSetDevice(kv.first);
-        kv.second.release();
-    }
-    g_run_ws.clear();
+    pool_trim_all();
     return HB_OK;
 }
 
@@ -1205,8 +1224,8 @@ hb_status hb_copy_probe(uint64_t bytes, uint32_t reps, double *avg_ms) {
     void *a = nullptr, *b = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc(&a, bytes);
-    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    hipError_t e = dmalloc(&a, bytes);
+    if (e == hipSuccess) e = dmalloc(&b, bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1221,8 +1240,8 @@ hb_status hb_copy_probe(uint64_t bytes, uint32_t reps, double *avg_ms) {
     if (e1) (void)hipEventDestroy(e1);
     if (e0) (void)hipEventDestroy(e0);
     if (s) (void)hipStreamDestroy(s);
-    (void)hipFree(a);
-    (void)hipFree(b);
+    dfree(a);
+    dfree(b);
     if (e != hipSuccess) return hip_fail(e, "copy probe");
     *avg_ms = ms / reps;
     return HB_OK;

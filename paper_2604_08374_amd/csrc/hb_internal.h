@@ -26,7 +26,9 @@ struct BatchJob {
     uint32_t bits;            // bits per register: 8, or 4 (two per byte, saturating at 15)
     uint32_t t;               // steps completed
     uint32_t done;            // 0 while running, else the last step run
-    uint32_t converged;       // 1 if it stopped because no estimate grew by more than 0.5
+    uint32_t converged;       // 1 if the last step grew no estimate by more than stop_delta
+    uint32_t depth_only;      // 1: stop at the depth limit only (ignore the growth test)
+    double stop_delta;        // the growth test's threshold (Alg. 1: 0.5)
 };
 
 // Launch schedule of the union kernels for one precision p:
@@ -85,12 +87,14 @@ hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, doub
 // One HyperBall step t: for every node v, decode its LEB128 row, take the
 // byte-wise max of cur[v] and cur[w] over its neighbours w into next[v],
 // estimate next[v], accumulate sum_d[v] += t (est - c_prev[v]), store est in
-// c_prev[v], and set *flag_t = 1 when est - c_prev[v] > 0.5.  order (n, or
-// null): the processing order of the nodes, a permutation of 0..n-1.
+// c_prev[v], and set *flag_t = 1 when est - c_prev[v] > thr (Alg. 1: 0.5).
+// order (n, or null): the processing order of the nodes, a permutation of 0..n-1.
+// skip (or null): the previous step's flag; when it is 0 that step stopped the
+// run, and this launch returns without touching anything.
 hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                         const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
                         uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
-                        hipStream_t stream);
+                        double thr, const uint32_t *skip, hipStream_t stream);
 
 // The same step from a range-max table of cur (level-major, level 0 = cur,
 // levels 1..levels built by launch_table): each run of consecutive neighbour
@@ -99,13 +103,14 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uint64_t *run_off,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
-                             const uint32_t *order, hipStream_t stream);
+                             const uint32_t *order, double thr, const uint32_t *skip,
+                             hipStream_t stream);
 
 // Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
 // i <= n - 2^k, rows of m bytes (m a multiple of 16) of `bits`-bit registers,
-// T[k] at tbl + k n m.  Requires 2^levels <= n.
+// T[k] at tbl + k n m.  Requires 2^levels <= n.  skip as for launch_union.
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
-                        hipStream_t stream);
+                        const uint32_t *skip, hipStream_t stream);
 
 // Streaming copy of bytes (a multiple of 16) from src to dst.
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);

@@ -508,7 +508,8 @@ __device__ __forceinline__ void finish_node(NodeAcc<C> &acc, uint32_t v, uint32_
                                             uint8_t *__restrict__ next,
                                             double *__restrict__ c_prev,
                                             double *__restrict__ sum_d,
-                                            uint32_t *__restrict__ flag_t, uint32_t t) {
+                                            uint32_t *__restrict__ flag_t, uint32_t t,
+                                            double thr) {
     constexpr int P = C::PREC;
     const uint32_t lane = lane_id();
     const uint32_t grp = lane / C::LPC;
@@ -550,7 +551,7 @@ __device__ __forceinline__ void finish_node(NodeAcc<C> &acc, uint32_t v, uint32_
         const double delta = est - c_prev[v];
         sum_d[v] = sum_d[v] + (double)t * delta;
         c_prev[v] = est;
-        if (delta > 0.5 &&
+        if (delta > thr &&
             __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
             __hip_atomic_store(flag_t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -566,7 +567,7 @@ __device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ byt
                                                  double *__restrict__ c_prev,
                                                  double *__restrict__ sum_d,
                                                  uint32_t *__restrict__ flag_t, uint32_t v,
-                                                 uint32_t slice, uint32_t t) {
+                                                 uint32_t slice, uint32_t t, double thr) {
     const uint32_t lane = lane_id();
     const uint32_t grp = lane / C::LPC;
     NodeAcc<C> acc;  // Alg. 1: next[v] <- cur[v]
@@ -593,7 +594,7 @@ __device__ __forceinline__ void union_node_edges(const uint8_t *__restrict__ byt
             acc.gather(src, slice, lane);
         }
     }
-    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
+    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t, thr);
 }
 
 template <class C>
@@ -601,12 +602,13 @@ __global__ __launch_bounds__(C::THREADS) void union_kernel(
     const uint8_t *__restrict__ bytes, const uint64_t *__restrict__ offsets,
     const uint8_t *__restrict__ cur, uint8_t *__restrict__ next, double *__restrict__ c_prev,
     double *__restrict__ sum_d, uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t,
-    const uint32_t *__restrict__ order) {
+    const uint32_t *__restrict__ order, double thr, const uint32_t *__restrict__ skip) {
+    if (skip && *skip == 0u) return;  // the previous step stopped the run
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
     if (order) v = order[v];
-    union_node_edges<C>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t);
+    union_node_edges<C>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, v, slice, t, thr);
 }
 
 // ---------------------------------------------------------------- union step, per run
@@ -721,7 +723,7 @@ __device__ __forceinline__ void union_node_runs(const uint2 *__restrict__ runs,
                                                 double *__restrict__ sum_d,
                                                 uint32_t *__restrict__ flag_t, uint32_t n,
                                                 uint32_t v, uint32_t slice, uint32_t t,
-                                                uint32_t *queue) {
+                                                double thr, uint32_t *queue) {
     const uint32_t lane = lane_id();
     NodeAcc<C> acc;  // Alg. 1: next[v] <- cur[v] (level 0 of the table is cur)
     acc.init(tbl + (uint64_t)v * C::M, slice, lane);
@@ -758,7 +760,7 @@ __device__ __forceinline__ void union_node_runs(const uint2 *__restrict__ runs,
         }
     }
     if (g.qn) g.flush(acc, lane);
-    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t);
+    finish_node<C>(acc, v, slice, next, c_prev, sum_d, flag_t, t, thr);
 }
 
 // Six waves per SIMD (80 VGPRs): the run kernel hides its gather latency with
@@ -779,14 +781,16 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
     const uint8_t *__restrict__ tbl, uint32_t levels, uint8_t *__restrict__ next,
     double *__restrict__ c_prev, double *__restrict__ sum_d, uint32_t *__restrict__ flag_t,
-    uint32_t n, uint32_t t, const uint32_t *__restrict__ order) {
+    uint32_t n, uint32_t t, const uint32_t *__restrict__ order, double thr,
+    const uint32_t *__restrict__ skip) {
     __shared__ __attribute__((aligned(16))) uint32_t s_queue[C::THREADS / kWave][kQueueCap];
+    if (skip && *skip == 0u) return;  // the previous step stopped the run
     uint32_t v, slice;
     node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
     if (order) v = order[v];
     union_node_runs<C>(runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
-                       s_queue[threadIdx.x / kWave]);
+                       thr, s_queue[threadIdx.x / kWave]);
 }
 
 // Register-wise max of 16 bytes of two counters (8- or 4-bit registers).
@@ -809,7 +813,9 @@ __device__ __forceinline__ uint4 max16(const uint4 a, const uint4 b) {
 __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ tbl,
                                                           uint64_t level_bytes, uint32_t k,
                                                           uint64_t count16, uint64_t half16,
-                                                          uint32_t bits) {
+                                                          uint32_t bits,
+                                                          const uint32_t *__restrict__ skip) {
+    if (skip && *skip == 0u) return;  // the previous step stopped the run
     const uint4 *prev = reinterpret_cast<const uint4 *>(tbl + (uint64_t)(k - 1) * level_bytes);
     uint4 *out = reinterpret_cast<uint4 *>(tbl + (uint64_t)k * level_bytes);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -871,10 +877,11 @@ __global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union
     uint8_t *next = J.buf[t & 1u];
     if constexpr (RUNS) {
         union_node_runs<C>(J.run_list, J.run_off, cur, J.levels, next, J.c_prev, J.sum_d,
-                           J.flags + t, J.n, v, slice, t, s_queue[threadIdx.x / kWave]);
+                           J.flags + t, J.n, v, slice, t, J.stop_delta,
+                           s_queue[threadIdx.x / kWave]);
     } else {
         union_node_edges<C>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
-                            slice, t);
+                            slice, t, J.stop_delta);
     }
 }
 
@@ -916,12 +923,10 @@ __global__ void batch_step_end_kernel(BatchJob *__restrict__ jobs,
     if (J.done) return;
     const uint32_t t = J.t + 1u;
     J.t = t;
-    if (J.flags[t] == 0u) {
-        J.converged = 1u;
+    // converged: step t grew no estimate by more than the threshold
+    J.converged = J.flags[t] == 0u ? 1u : 0u;
+    if ((J.converged && !J.depth_only) || (J.depth != 0u && t == J.depth) || t + 1u >= J.n_flags)
         J.done = t;
-    } else if ((J.depth != 0u && t == J.depth) || t + 1u >= J.n_flags) {
-        J.done = t;
-    }
 }
 
 // Streaming copy, 16 B per lane, grid-stride: the reference kernel for
@@ -1207,12 +1212,12 @@ hipError_t launch_init_c(uint8_t *cur, double *c_prev, double *sum_d, uint32_t n
 template <class C>
 hipError_t launch_union_c(const uint8_t *bytes, const uint64_t *offsets, const uint8_t *cur,
                           uint8_t *next, double *c_prev, double *sum_d, uint32_t *flag_t,
-                          uint32_t n, uint32_t t, const uint32_t *order, uint32_t nb,
-                          hipStream_t stream) {
+                          uint32_t n, uint32_t t, const uint32_t *order, double thr,
+                          const uint32_t *skip, uint32_t nb, hipStream_t stream) {
     uint32_t blocks, threads;
     grid_for<C>(n, nb, blocks, threads);
     hipLaunchKernelGGL((union_kernel<C>), dim3(blocks), dim3(threads), 0, stream, bytes, offsets,
-                       cur, next, c_prev, sum_d, flag_t, n, t, order);
+                       cur, next, c_prev, sum_d, flag_t, n, t, order, thr, skip);
     return hipGetLastError();
 }
 
@@ -1220,12 +1225,14 @@ template <class C>
 hipError_t launch_union_runs_c(const uint2 *runs, const uint64_t *run_off, const uint8_t *tbl,
                                uint32_t levels, uint8_t *next, double *c_prev, double *sum_d,
                                uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
-                               uint32_t nb, hipStream_t stream) {
+                               double thr, const uint32_t *skip, uint32_t nb,
+                               hipStream_t stream) {
     if constexpr (C::PREC <= kRunsMaxP) {
         uint32_t blocks, threads;
         grid_for<C>(n, nb, blocks, threads);
         hipLaunchKernelGGL((union_runs_kernel<C>), dim3(blocks), dim3(threads), 0, stream,
-                           runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, t, order);
+                           runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, t, order,
+                           thr, skip);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -1332,11 +1339,11 @@ hipError_t launch_init(int p, const Sched &s, uint8_t *cur, double *c_prev, doub
 hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint64_t *offsets,
                         const uint8_t *cur, uint8_t *next, double *c_prev, double *sum_d,
                         uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
-                        hipStream_t stream) {
+                        double thr, const uint32_t *skip, hipStream_t stream) {
 #define HB_X(P, L, B)                                                                            \
     if (p == P && s.lanes == L && s.bits == B)                                                               \
         return launch_union_c<Cfg<P, L, B>>(bytes, offsets, cur, next, c_prev, sum_d, flag_t, n, \
-                                         t, order, nb, stream);
+                                         t, order, thr, skip, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
@@ -1344,17 +1351,18 @@ hipError_t launch_union(int p, const Sched &s, const uint8_t *bytes, const uint6
 hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uint64_t *run_off,
                              const uint8_t *tbl, uint32_t levels, uint8_t *next, double *c_prev,
                              double *sum_d, uint32_t *flag_t, uint32_t n, uint32_t t,
-                             const uint32_t *order, hipStream_t stream) {
+                             const uint32_t *order, double thr, const uint32_t *skip,
+                             hipStream_t stream) {
 #define HB_X(P, L, B)                                                                          \
     if (p == P && s.lanes == L && s.bits == B)                                                             \
         return launch_union_runs_c<Cfg<P, L, B>>(runs, run_off, tbl, levels, next, c_prev,     \
-                                              sum_d, flag_t, n, t, order, nb, stream);
+                                              sum_d, flag_t, n, t, order, thr, skip, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }
 
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
-                        hipStream_t stream) {
+                        const uint32_t *skip, hipStream_t stream) {
     const uint64_t level_bytes = (uint64_t)n * m;
     for (uint32_t k = 1; k <= levels; ++k) {
         const uint64_t rows = (uint64_t)n - (1ull << k) + 1ull;
@@ -1362,7 +1370,7 @@ hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, u
         const uint64_t half16 = (1ull << (k - 1)) * (m / 16u);
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((count16 + 255) / 256, 256u * 64u);
         hipLaunchKernelGGL(table_level_kernel, dim3(blocks), dim3(256), 0, stream, tbl, level_bytes,
-                           k, count16, half16, bits);
+                           k, count16, half16, bits, skip);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

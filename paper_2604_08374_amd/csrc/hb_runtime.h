@@ -30,6 +30,8 @@ uint32_t floor_log2(uint32_t n);
     } while (0)
 
 constexpr int kMaxLevels = 24;
+// Steps of a blocking run enqueued between two host reads of the stop flags.
+constexpr uint32_t kSegment = 8;
 // Default depth K of the run kernel's range-max table (city graph, p = 10, per
 // step of table build + union launch: 14.0 ms at K = 7, 13.7 at 8, 13.7 at 9,
 // 15.1 at 6; deeper tables cover long runs with fewer rows but cost a level of
@@ -86,6 +88,27 @@ hb_status tune_measure(int p, uint32_t bits, bool runs, hipStream_t s,
                        const std::function<hipError_t(const hbk::Sched &)> &launch,
                        TunePick *out);
 
+// ---- device memory and library-wide options (hb_pool.cpp)
+constexpr int kMaxDevices = 64;
+// The options of hb_set_options (a copy; calls take one at their start).
+hb_options options();
+// Allocate / free device memory of the current device through the caller's
+// hooks or hipMalloc / hipFree, counted against the device's budget.  Over the
+// budget (or out of memory) dmalloc first releases idle pool blocks and asks
+// the evictor for memory, then returns hipErrorOutOfMemory.
+hipError_t dmalloc(void **p, uint64_t bytes);
+void dfree(void *p);
+// Working buffers from the current device's pool (first fit in pooled blocks,
+// grown within the budget).  HB_ENOMEM (with a message) when it cannot grow.
+hb_status pool_take(uint64_t bytes, void **p);
+void pool_give(void *p);
+void pool_trim_all();  // release every idle pool block
+void memory_stats(int dev, hb_memory_stats_t *out);
+// Called when an allocation does not fit: free idle memory of device dev (at
+// least `need` bytes if it can) and return the bytes freed.
+using Evictor = std::function<uint64_t(int dev, uint64_t need)>;
+void set_evictor(Evictor f);
+
 }  // namespace hbr
 
 struct hb_graph {
@@ -106,8 +129,9 @@ struct hb_graph {
     double *d_cprev = nullptr, *d_sumd = nullptr;
     uint32_t *d_flags = nullptr;
     uint64_t n_flags = 0;
-    uint32_t *h_flag = nullptr;  // pinned
+    uint32_t *h_flags = nullptr;  // pinned: the stop flags of one segment of steps
     hipStream_t stream = nullptr;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_init[2] = {nullptr, nullptr};          // around the initialisation
+    hipEvent_t ev_step[hbr::kSegment][3] = {};            // per step: table, union, end
     std::atomic<uint32_t> inflight{0};  // served requests that still use this graph
 };

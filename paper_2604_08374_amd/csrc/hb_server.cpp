@@ -1,8 +1,9 @@
 // The served form: hb_submit / hb_poll over a request loop on a library thread.
 //
-// The loop keeps one device arena (the memory budget) and a table of running
-// requests.  Every iteration it (1) admits queued requests in arrival order
-// while a contiguous block for their footprint is free, (2) runs one batched
+// The loop keeps a table of running requests.  Every iteration it (1) admits
+// queued requests in arrival order while their footprint can be taken from the
+// library's device memory pool (within the server's own cap, if one is set,
+// and the library-wide budget shared with blocking runs and graphs), (2) runs one batched
 // HyperBall step over all running requests -- init for the newly admitted,
 // range-max table levels for run-kernel requests, one union launch per
 // (p, kernel) class, and the per-request stop decision on the device -- and
@@ -12,8 +13,8 @@
 // join and leave between any two steps (continuous batching at step
 // granularity).  Requests are split over two lanes by the bytes one of their
 // steps gathers: each lane has its own thread, stream and running set, and both
-// share the budget arena, so short requests never wait for the step of a very
-// large one and the two kinds overlap on the device.
+// share the memory, so short requests never wait for the step of a very large
+// one and the two kinds overlap on the device.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -38,53 +39,6 @@ namespace {
 
 uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 
-// First-fit allocator of offsets in [0, size), 256-byte granularity.
-class Arena {
-public:
-    void reset(uint64_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-        size_ = size;
-        used_ = 0;
-    }
-    bool take(uint64_t bytes, uint64_t &off) {
-        bytes = align256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            off = it->first;
-            const uint64_t rest = it->second - bytes;
-            free_.erase(it);
-            if (rest) free_[off + bytes] = rest;
-            used_ += bytes;
-            return true;
-        }
-        return false;
-    }
-    void give(uint64_t off, uint64_t bytes) {
-        bytes = align256(bytes);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    uint64_t used() const { return used_; }
-    uint64_t size() const { return size_; }
-
-private:
-    std::map<uint64_t, uint64_t> free_;
-    uint64_t size_ = 0, used_ = 0;
-};
-
 enum class State { Queued, Running, Done, Failed };
 
 struct Request {
@@ -95,7 +49,8 @@ struct Request {
     uint64_t seed = 0;
     bool runs = false;
     uint32_t levels = 0;
-    uint64_t footprint = 0, off = 0;
+    uint64_t footprint = 0;
+    void *mem = nullptr;  // pool memory while running
     State state = State::Queued;
     hb_status error = HB_OK;
     std::string message;
@@ -151,13 +106,13 @@ private:
     hb_server_opts opts_{};
     uint64_t slow_bytes_ = 0;  // a request gathering more per step goes to the slow lane
     int device_ = 0;
-    Arena arena_;
-    uint64_t peak_used_ = 0;
+    uint64_t cap_ = 0;        // the server's own cap on its memory (0 = none)
+    uint64_t used_ = 0, peak_used_ = 0;
     Lane lanes_[2];  // 0: fast, 1: slow
     std::unordered_map<hb_ticket, std::unique_ptr<Request>> reqs_;
     hb_ticket next_ticket_ = 1;
     uint64_t submitted_ = 0, completed_ = 0, steps_ = 0, edge_unions_ = 0;
-    void *d_arena_ = nullptr;
+    uint64_t device_total_ = 0;  // device memory size, for requests that could never fit
 };
 
 hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs,
@@ -191,29 +146,23 @@ hb_status Server::start(const hb_server_opts *opts) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(HB_EDEVICE, "no GPU available");
     HB_HIP(hipGetDevice(&device_));
-    if (o.hbm_budget == 0) {
+    {
         size_t free_b = 0, total_b = 0;
         HB_HIP(hipMemGetInfo(&free_b, &total_b));
-        o.hbm_budget = align256(free_b / 4 * 3 - 255);
+        device_total_ = total_b;
     }
-    o.hbm_budget = align256(o.hbm_budget);
-    hipError_t e = hipMalloc(&d_arena_, o.hbm_budget);
-    if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "budget of %llu bytes not available",
-                                              (unsigned long long)o.hbm_budget);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(server budget)");
     for (auto &l : lanes_) {
-        e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
+        const hipError_t e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             for (auto &x : lanes_)
                 if (x.stream) (void)hipStreamDestroy(x.stream), x.stream = nullptr;
-            (void)hipFree(d_arena_);
-            d_arena_ = nullptr;
             return hip_fail(e, "hipStreamCreate");
         }
     }
     opts_ = o;
+    cap_ = o.hbm_budget ? align256(o.hbm_budget) : 0;
     slow_bytes_ = o.slow_lane_bytes ? o.slow_lane_bytes : (2ull << 30);
-    arena_.reset(o.hbm_budget);
+    used_ = 0;
     peak_used_ = 0;
     running_ = true;
     stopping_ = false;
@@ -232,8 +181,6 @@ hb_status Server::stop() {
     for (auto &l : lanes_)
         if (l.thread.joinable()) l.thread.join();
     std::lock_guard<std::mutex> lk(mu_);
-    (void)hipFree(d_arena_);
-    d_arena_ = nullptr;
     running_ = false;
     return HB_OK;
 }
@@ -262,9 +209,15 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
     hb_status st = footprint(g, p, bits, r->runs, r->levels, r->footprint);
     if (st != HB_OK) return st;
-    if (align256(r->footprint) > arena_.size())
-        return fail(HB_ENOMEM, "request needs %llu bytes, the budget is %llu",
-                    (unsigned long long)r->footprint, (unsigned long long)arena_.size());
+    const hb_options lib = options();
+    if (lib.stop_rule == HB_STOP_DEPTH && depth == 0)
+        return fail(HB_EINVAL, "the stop rule HB_STOP_DEPTH needs a depth limit");
+    const uint64_t limit = std::min({cap_ ? cap_ : UINT64_MAX,
+                                     lib.hbm_budget ? lib.hbm_budget : UINT64_MAX,
+                                     device_total_ ? device_total_ : UINT64_MAX});
+    if (align256(r->footprint) > limit)
+        return fail(HB_ENOMEM, "request needs %llu bytes, at most %llu can ever be free",
+                    (unsigned long long)r->footprint, (unsigned long long)limit);
     r->ticket = next_ticket_++;
     r->g = g;
     r->p = p;
@@ -342,8 +295,8 @@ hb_status Server::stats(hb_server_stats_t *out) {
     out->submitted = submitted_;
     out->completed = completed_;
     out->steps = steps_;
-    out->budget_bytes = arena_.size();
-    out->used_bytes = arena_.used();
+    out->budget_bytes = cap_ ? cap_ : options().hbm_budget;
+    out->used_bytes = used_;
     out->peak_used_bytes = peak_used_;
     out->edge_unions = edge_unions_;
     return HB_OK;
@@ -359,7 +312,9 @@ void Server::fail_all(Lane &L, hb_status st, const std::string &msg) {
     };
     for (Request *r : L.running) {
         mark(r);
-        arena_.give(r->off, r->footprint);
+        pool_give(r->mem);
+        r->mem = nullptr;
+        used_ -= align256(r->footprint);
     }
     for (Request *r : L.queue) mark(r);
     L.running.clear();
@@ -394,19 +349,23 @@ hb_status Server::step(Lane &L) {
                (opts_.max_running == 0 ||
                 others + L.running.size() + admitted.size() < opts_.max_running)) {
             Request *r = L.queue.front();
-            uint64_t off;
-            if (!arena_.take(r->footprint, off)) break;  // arrival order within the lane
+            const uint64_t fp = align256(r->footprint);
+            if (cap_ && used_ + fp > cap_) break;  // arrival order within the lane
+            void *mem = nullptr;
+            if (pool_take(fp, &mem) != HB_OK) break;
             L.queue.pop_front();
-            r->off = off;
+            r->mem = mem;
+            used_ += fp;
             r->state = State::Running;
             r->t_admit = now_ns();
             admitted.push_back(r);
         }
-        peak_used_ = std::max(peak_used_, arena_.used());
+        peak_used_ = std::max(peak_used_, used_);
         L.n_running = (uint32_t)(L.running.size() + admitted.size());
     }
-    uint8_t *base = static_cast<uint8_t *>(d_arena_);
+    const hb_options lib = options();
     for (Request *r : admitted) {
+        uint8_t *base = static_cast<uint8_t *>(r->mem);
         hb_graph *g = r->g;
         const uint64_t m = (1ull << r->p) * r->bits / 8u;
         const uint64_t bb = align256((uint64_t)g->n * m * (r->levels + 1u));
@@ -419,11 +378,11 @@ hb_status Server::step(Lane &L) {
         b.run_off = g->d_run_off;
         b.order = g->d_order;
         b.hash_ids = g->d_hash_ids;
-        b.buf[0] = base + r->off;
-        b.buf[1] = base + r->off + bb;
-        b.c_prev = reinterpret_cast<double *>(base + r->off + 2 * bb);
-        b.sum_d = reinterpret_cast<double *>(base + r->off + 2 * bb + sb);
-        b.flags = reinterpret_cast<uint32_t *>(base + r->off + 2 * bb + 2 * sb);
+        b.buf[0] = base;
+        b.buf[1] = base + bb;
+        b.c_prev = reinterpret_cast<double *>(base + 2 * bb);
+        b.sum_d = reinterpret_cast<double *>(base + 2 * bb + sb);
+        b.flags = reinterpret_cast<uint32_t *>(base + 2 * bb + 2 * sb);
         b.seed = r->seed;
         b.n = g->n;
         b.p = r->p;
@@ -432,6 +391,8 @@ hb_status Server::step(Lane &L) {
         b.n_flags = (uint32_t)std::min<uint64_t>((uint64_t)g->n + 2, UINT32_MAX);
         b.runs = r->runs ? 1u : 0u;
         b.bits = r->bits;
+        b.depth_only = lib.stop_rule == HB_STOP_DEPTH ? 1u : 0u;
+        b.stop_delta = lib.stop_delta > 0.0 ? lib.stop_delta : 0.5;
         L.running.push_back(r);
     }
     const uint32_t nj = (uint32_t)L.running.size();
@@ -439,13 +400,13 @@ hb_status Server::step(Lane &L) {
 
     // ---- job table and launch lists for this step
     if (L.jobs_cap < nj) {
-        (void)hipFree(L.d_jobs);
+        dfree(L.d_jobs);
         if (L.h_jobs) (void)hipHostFree(L.h_jobs);
         L.d_jobs = nullptr;
         L.h_jobs = nullptr;
         L.jobs_cap = 0;
         const uint32_t cap = std::max<uint32_t>(64, nj * 2);
-        HB_HIP(hipMalloc(&L.d_jobs, sizeof(hbk::BatchJob) * cap));
+        HB_HIP(dmalloc((void **)&L.d_jobs, sizeof(hbk::BatchJob) * cap));
         HB_HIP(hipHostMalloc((void **)&L.h_jobs, sizeof(hbk::BatchJob) * cap, hipHostMallocDefault));
         L.jobs_cap = cap;
     }
@@ -513,11 +474,11 @@ hb_status Server::step(Lane &L) {
             lists.insert(lists.end(), c.base.begin(), c.base.end());
         }
     if (L.lists_cap < lists.size()) {
-        (void)hipFree(L.d_lists);
+        dfree(L.d_lists);
         L.d_lists = nullptr;
         L.lists_cap = 0;
         const uint64_t cap = std::max<uint64_t>(4096, lists.size() * 2);
-        HB_HIP(hipMalloc(&L.d_lists, sizeof(uint32_t) * cap));
+        HB_HIP(dmalloc((void **)&L.d_lists, sizeof(uint32_t) * cap));
         L.lists_cap = cap;
     }
     hbk::BatchJob *d_jobs_ = L.d_jobs;
@@ -571,7 +532,9 @@ hb_status Server::step(Lane &L) {
         for (Request *r : done) {
             r->t_end = t_end;
             r->state = State::Done;
-            arena_.give(r->off, r->footprint);
+            pool_give(r->mem);
+            r->mem = nullptr;
+            used_ -= align256(r->footprint);
             r->g->inflight.fetch_sub(1);
             ++completed_;
             edge_unions_ += (uint64_t)r->job.done * r->g->n_edges;
@@ -593,13 +556,14 @@ void Server::loop(Lane &L) {
             cv_work_.wait(lk, [&] { return stopping_ || !L.queue.empty() || !L.running.empty(); });
             if (abort_ || (stopping_ && L.queue.empty() && L.running.empty())) break;
             if (L.running.empty() && !L.queue.empty()) {
-                // nothing of ours runs: wait until the head request fits the budget
-                uint64_t off;
-                if (!arena_.take(L.queue.front()->footprint, off)) {
+                // nothing of ours runs: wait until the head request fits
+                const uint64_t fp = align256(L.queue.front()->footprint);
+                void *mem = nullptr;
+                if ((cap_ && used_ + fp > cap_) || pool_take(fp, &mem) != HB_OK) {
                     cv_work_.wait_for(lk, std::chrono::milliseconds(1));
                     continue;
                 }
-                arena_.give(off, L.queue.front()->footprint);
+                pool_give(mem);
             }
         }
         const hb_status st = step(L);
@@ -609,8 +573,8 @@ void Server::loop(Lane &L) {
         }
     }
     (void)hipStreamSynchronize(L.stream);
-    (void)hipFree(L.d_lists);
-    (void)hipFree(L.d_jobs);
+    dfree(L.d_lists);
+    dfree(L.d_jobs);
     if (L.h_jobs) (void)hipHostFree(L.h_jobs);
     (void)hipStreamDestroy(L.stream);
     L.d_lists = nullptr;

@@ -184,3 +184,26 @@ def test_load_without_gpu_fails_loudly():
     with pytest.raises(hb.HBError) as e:
         hb.graph_load(off, deg, data)
     assert e.value.status == hb.HB_EDEVICE
+
+
+def test_set_options_checks_its_arguments():
+    """hb_set_options is host-only: argument errors and the round trip need no GPU."""
+    import paper_2604_08374_amd as hb
+
+    try:
+        for kw in (dict(stop_delta=-1.0),
+                   dict(tune_seed=[dict(p=10, register_bits=8, union_kernel="runs", batched=0,
+                                        log2_nodes=3, log2_rows_per_node=4, lanes_per_node=48,
+                                        nodes_per_block=4, best_ms=1.0, default_ms=1.0)])):
+            with pytest.raises(hb.HBError) as e:
+                hb.set_options(**kw)
+            assert e.value.status == hb.HB_EINVAL
+        with pytest.raises(hb.HBError):
+            hb.set_options(dev_alloc=lambda n: 0)
+        hb.set_options(hbm_budget=1 << 30, stop_rule="depth", stop_delta=2.5)
+        o = hb.get_options()
+        assert o["hbm_budget"] == 1 << 30 and o["stop_rule"] == "depth"
+        assert o["stop_delta"] == 2.5 and not o["hooks"] and o["stream"] == 0
+    finally:
+        hb.set_options()
+    assert hb.get_options()["hbm_budget"] == 0
