@@ -211,7 +211,7 @@ typedef struct {
  * hooks may be called from the request loop's threads.
  *
  * stream: a hipStream_t (passed as void *) on which the blocking runs
- * (hb_run, hb_run_with) enqueue their work after the work the
+ * (hb_run, hb_run_with, hb_run_static) enqueue their work after the work the
  * caller queued there; NULL = the graph's own stream.  They still return once
  * their results are on the host.
  *
@@ -350,6 +350,27 @@ hb_status hb_run(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_se
  */
 hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                       const hb_run_opts *opts, hb_result *out);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): hb_run_with
+ * with its two counter buffers (and the run kernel's table levels) in a static
+ * device workspace of HB_STATIC_SCRATCH_BYTES, one copy per device, held until
+ * the process ends, instead of the run workspace grown on demand.  It calls no
+ * hipMalloc, hipFree or other allocating routine and allocates no host memory;
+ * the graph's per-node state (allocated by hb_graph_load) and the caller's
+ * output arrays are used as by hb_run_with.  HB_UNION_AUTO takes the run kernel
+ * when both buffers with their tables fit the workspace, else the per-edge
+ * kernel; HB_ENOMEM (with the sizes in hb_last_error) when even the per-edge
+ * kernel's 2 n 2^p bytes (n 2^(p-1) per buffer with 4-bit registers) do not
+ * fit.  HB_TUNE_MEASURE acts as HB_TUNE_CACHED.  Every call on one device
+ * shares that device's workspace, which keeps the last call's counters; the
+ * library's device lock serialises blocking calls within a process, so calls
+ * made outside it (another copy of the library in the same process) would race.
+ */
+#define HB_STATIC_SCRATCH_BYTES (64ull << 20)
+hb_status hb_run_static(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                        const hb_run_opts *opts, hb_result *out);
 
 /* One analysis of a batched run. */
 typedef struct {

@@ -25,6 +25,7 @@ __all__ = [
 HB_OK, HB_PENDING = 0, 1
 HB_EINVAL, HB_ECORRUPT, HB_ENOMEM, HB_EDEVICE, HB_ENOTFOUND, HB_EBUSY = -1, -2, -3, -4, -5, -6
 P_MIN, P_MAX = 4, 16
+STATIC_SCRATCH_BYTES = 64 << 20  # HB_STATIC_SCRATCH_BYTES in hb.h
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -194,6 +195,8 @@ def _lib():
                                   ctypes.c_uint64, ctypes.POINTER(_RunOpts),
                                   ctypes.POINTER(_Result)]
         L.hb_run_with.restype = st
+        L.hb_run_static.argtypes = L.hb_run_with.argtypes
+        L.hb_run_static.restype = st
         L.hb_set_options.argtypes = [ctypes.POINTER(_Options)]
         L.hb_set_options.restype = st
         L.hb_get_options.argtypes = [ctypes.POINTER(_Options)]
@@ -435,6 +438,20 @@ class Graph:
         o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block, register_bits)
         _check(_lib().hb_run_with(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
                                   ctypes.byref(o), ctypes.byref(r)))
+        return _to_result(r, arrays)
+
+    def run_static(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
+                   outputs: bool = True, kernel: str = "auto", table_levels: int = 0,
+                   tune: str = "cached", lanes_per_node: int = 0, nodes_per_block: int = 0,
+                   register_bits: int = 8) -> Result:
+        """hb_run_static: as run(), with the counters in the library's static device
+        workspace (STATIC_SCRATCH_BYTES per device); the call allocates nothing."""
+        if self._h is None:
+            raise HBError(HB_EINVAL, "graph was freed")
+        r, arrays = self._out_arrays(p, registers, outputs, register_bits)
+        o = _run_opts(kernel, table_levels, tune, lanes_per_node, nodes_per_block, register_bits)
+        _check(_lib().hb_run_static(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
+                                    ctypes.byref(o), ctypes.byref(r)))
         return _to_result(r, arrays)
 
 

@@ -496,8 +496,10 @@ struct PoolHold {
 // estimate by more than the threshold, so steps queued past the stopping point
 // change nothing.  After each segment the host reads the segment's flags and
 // either finds the step that stopped the run or queues the next segment.
+// no_alloc: the counter buffers live in the static device workspace, and
+// nothing is allocated on the device or the host (no schedule measurement).
 hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
-                       const hb_run_opts *opts, hb_result *out) {
+                       const hb_run_opts *opts, hb_result *out, bool no_alloc) {
     const uint64_t t_start = now_ns();
     if (!g || !out) return fail(HB_EINVAL, "NULL argument");
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
@@ -540,7 +542,17 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     };
     uint8_t *ws = nullptr;
     PoolHold hold;
-    {
+    if (no_alloc) {
+        const auto fits = [&](bool r) { return 2ull * buf_bytes(r) <= hbk::kStaticScratchBytes; };
+        if (runs && !fits(true) && o.union_kernel == HB_UNION_AUTO) runs = false;
+        if (!fits(runs))
+            return fail(HB_ENOMEM,
+                        "hb_run_static: the counters need 2 x %llu bytes; the static workspace "
+                        "holds %llu bytes",
+                        (unsigned long long)((uint64_t)n * m * (runs ? (levels + 1u) : 1u)),
+                        (unsigned long long)hbk::kStaticScratchBytes);
+        HB_HIP(hbk::static_scratch(&ws));
+    } else {
         // tables beyond 64 GiB are not worth their memory; the per-edge kernel
         // needs none
         if (runs && o.union_kernel == HB_UNION_AUTO && 2ull * buf_bytes(true) > (64ull << 30))
@@ -568,7 +580,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
         sched = fixed;
     } else if (o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
         sched = union_default;
-        if (o.tune == HB_TUNE_MEASURE) {
+        if (o.tune == HB_TUNE_MEASURE && !no_alloc) {
             // step 1 of this very run, once per candidate; the state is
             // initialised again below, so the trials leave no trace
             const uint64_t t0 = now_ns();
@@ -697,7 +709,12 @@ extern "C" {
 
 hb_status hb_run_with(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
                       const hb_run_opts *opts, hb_result *out) {
-    return run_blocking(g, p, depth_limit, hash_seed, opts, out);
+    return run_blocking(g, p, depth_limit, hash_seed, opts, out, false);
+}
+
+hb_status hb_run_static(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash_seed,
+                        const hb_run_opts *opts, hb_result *out) {
+    return run_blocking(g, p, depth_limit, hash_seed, opts, out, true);
 }
 
 namespace {

@@ -144,4 +144,11 @@ hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32
 // sequence stays capturable).
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStream_t stream);
 
+// Size of the static device workspace (a file-scope device array, one copy per
+// device) that holds the counter buffers of the run entry point that
+// allocates nothing.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+// The current device's address of that array, looked up once per device.
+hipError_t static_scratch(uint8_t **ptr);
+
 }  // namespace hbk

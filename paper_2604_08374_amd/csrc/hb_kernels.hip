@@ -47,6 +47,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "hb_internal.h"
 
@@ -1474,6 +1475,43 @@ hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, uint64_t count, hipStr
     hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(threads), 0, stream, dst,
                        value, count);
     return hipGetLastError();
+}
+
+}  // namespace hbk
+
+// ---------------------------------------------------------------- static workspace
+// The counter buffers of the run entry point that allocates nothing: one
+// file-scope device array, a copy of it on every device the library runs on,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol); it asks the
+// runtime for each device's address once, with that device current, and uses
+// that address from then on.
+static __device__ __align__(256) uint8_t scratch[hbk::kStaticScratchBytes];
+
+namespace hbk {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(uint8_t **ptr) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace hbk

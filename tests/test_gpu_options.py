@@ -128,6 +128,8 @@ def test_caller_stream(hb, reset_options):
         assert hb.get_options()["stream"] == s
         for p, d in ((10, 0), (8, 3)):
             assert_matches(hb, G.run(p, d, 5, registers=True), ref(g, p, d, 5), f"stream p={p}")
+            assert_matches(hb, G.run_static(p, d, 5, registers=True), ref(g, p, d, 5),
+                           f"stream static p={p}")
     finally:
         hb.set_options()
         hip_rt.stream_destroy(s)
@@ -145,6 +147,7 @@ def test_stop_rule_depth_runs_every_step(hb, reset_options, depth):
     G = _load(hb, g)
     forms = {"single": G.run(p, depth, seed, registers=True),
              "edges": G.run(p, depth, seed, registers=True, kernel="edges"),
+             "static": G.run_static(p, depth, seed, registers=True),
              "batched": hb.run_batch([(G, p, depth, seed)], registers=True)[0]}
     hb.server_start()
     try:
