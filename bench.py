@@ -25,7 +25,9 @@ import numpy as np  # noqa: E402
 
 METRIC = "HLL edge-unions/s + % HBM roofline (236k cells, p=10); p50/p99 latency, mixed load"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "union_runs_kernel_city_p10_counters.txt")
+# rocprofv3 counter summaries of the city workload (p = 10, depth 3), per union kernel
+COUNTERS_FILES = {"runs": os.path.join(ROOT, "profiles", "union_runs_kernel_city_p10_counters.txt"),
+                  "edges": os.path.join(ROOT, "profiles", "union_kernel_city_p10_counters.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_08374_amd", "csrc", "hb_kernels.hip")
 
 
@@ -80,19 +82,19 @@ def table_bytes(n: int, p: int, levels: int, bits: int = 8) -> int:
     return sum(3 * (n - (1 << k) + 1) * m for k in range(1, levels + 1))
 
 
-def kernel_traffic(config: str, p: int, depth: int, kernel: str, order: str):
-    """HBM bytes per union launch from the committed rocprofv3 counter summary.
+def kernel_traffic(config: str, p: int, depth: int, kind: str, kernel: str, order: str):
+    """Counters per union launch from the committed rocprofv3 summary of that kernel.
 
     The summary was taken on the default workload (city graph, p = 10, depth 3, in
     the processing order it names); for any other workload, or once the kernel
     source has changed, it is None.
     """
-    if (config, p, depth) != ("city", 10, 3):
+    if (config, p, depth) != ("city", 10, 3) or kind not in COUNTERS_FILES:
         return None
     from paper_2604_08374_amd.profiling import kernel_sha256
 
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(COUNTERS_FILES[kind]) as f:
             rec = dict(line.split(None, 1) for line in f if line.strip())
         src_hash = kernel_sha256(KERNEL_SRC)
     except (OSError, ValueError):
@@ -107,8 +109,42 @@ def kernel_traffic(config: str, p: int, depth: int, kernel: str, order: str):
             if k.endswith("_per_launch") or k == "avg_launch_ns"}
 
 
-def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
-    """The oracle's union + estimate on a bounded, seeded sample of nodes."""
+def measure_ceilings(hb, p, n, rows, lanes, nb, bits, kernel):
+    """Ceilings measured in this process on this device: the union loop's gathers in
+    the launch's own shape (hb_gather_probe: the same node count and rows per node,
+    rows from a 2 MiB table that stays in L2, with and without the byte max, and from a
+    1 GiB table that misses L2), and a plain 4 GiB device copy."""
+    out = {}
+    m = (1 << p) * bits // 8
+    if bits == 8 and p <= 12 and kernel == "runs":
+        rpn = max(1, round(rows / n))
+        gathered = n * rpn * m
+        for key, trows, with_max in (("l2_gather_gbs", (2 << 20) // m, True),
+                                     ("l2_loads_only_gbs", (2 << 20) // m, False),
+                                     ("fabric_gather_gbs", (1 << 30) // m, True)):
+            ms = hb.gather_probe(p, n, rpn, trows, with_max, lanes, nb, reps=3)
+            out[key] = gathered / (ms / 1e3) / 1e9
+    nbytes = 4 << 30
+    ms = hb.copy_probe(nbytes, 10)
+    out["copy_gbs"] = 2 * nbytes / (ms / 1e3) / 1e9
+    log("ceilings (GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in out.items()))
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0, one_thread_s=5.0):
+    """The oracle's union + estimate on a bounded, seeded sample of nodes, on every
+    host thread and on one thread."""
     import oracle
 
     csr = oracle.CSR(n=n, offsets=csr_off, degrees=csr_deg, bytes=csr_bytes)
@@ -128,13 +164,29 @@ def cpu_baseline(csr_off, csr_deg, csr_bytes, n, p, seed, target_s=15.0):
     t0 = time.perf_counter()
     _, _, edges = oracle.union_sample(csr, p, cur, sample)
     dt = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    # the same unit on one thread, on the sample's first nodes (~one_thread_s)
+    k1 = int(np.searchsorted(np.cumsum(deg[64:]), rate0 / max(threads, 1) * one_thread_s)) + 1
+    sample1 = order[64:64 + max(min(k1, sample.size), 16)]
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, _, edges1 = oracle.union_sample(csr, p, cur, sample1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
     return {
         "value": edges / dt,
         "unit": "edge-unions/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"one union step (Eq. 2) + estimate for {sample.size} seeded random nodes "
-                   f"({edges} directed edges, {dt:.1f} s) of the same graph, p={p}"),
+                   f"({edges} directed edges, {dt:.1f} s) of the same graph, p={p}, "
+                   f"{threads} threads; the oracle gathers every neighbour's counter"),
+        "cpu_model": cpu_model(),
+        "one_thread": {"value": edges1 / dt1, "unit": "edge-unions/s",
+                       "sample": f"the first {sample1.size} nodes of the same sample "
+                                 f"({edges1} directed edges, {dt1:.1f} s)"},
     }
 
 
@@ -230,8 +282,7 @@ def local_bench(args):
     del g
     G = hb.graph_load(off, deg, data, order=order)
     reads = G.stats()["local_run_reads"]
-    if args.copy_probe:
-        hb.copy_probe(4 << 30, 10)
+    hb.copy_probe(4 << 30, 10)  # the reference kernel for scaling byte counters
     t0 = time.perf_counter()
     lm = G.local_metrics()
     el = time.perf_counter() - t0
@@ -254,10 +305,13 @@ def serve_bench(args):
     the urban generator at 3 m cells); each
     request draws (graph, p in {8, 10, 12}, depth in {3, unlimited}) from a seeded
     stream, and about 10 % name a graph not yet on the device, which is generated
-    beforehand but uploaded on demand inside the request's latency.  The same trace is
-    replayed by a sequential FIFO baseline (one hb_run at a time, arrivals respected).
-    Latency = completion - arrival.  Reports p50/p99 per arrival rate and the
-    edge-unions/s of both, and checks that served results equal the baseline's.
+    beforehand but uploaded on demand inside the request's latency.  Served requests
+    name their graph by key (hb_submit_cached): the library keeps the pool's graphs in
+    its device graph cache and loads a fresh one inside the submitting call.  The same
+    trace is replayed by a sequential FIFO baseline (one hb_run at a time, arrivals
+    respected, fresh graphs loaded on demand).  Latency = completion - arrival.
+    Reports p50/p99 per arrival rate and the edge-unions/s of both, and checks that
+    served results equal the baseline's.
     """
     import threading
 
@@ -281,6 +335,21 @@ def serve_bench(args):
     for k in range(pool_n):
         if k not in fresh:
             resident[k] = hb.graph_load(*graphs[k]["csr"])
+
+    def cache_csr(k):
+        off, deg, data, _, _, order = graphs[k]["csr"]
+        return (off, deg, data, order)
+
+    def warm_cache():
+        """The served side's resident graphs in the device graph cache; fresh ones out."""
+        for k in fresh:
+            try:
+                hb.graph_cache_drop(k)
+            except hb.HBError:
+                pass  # not cached
+        tks = [hb.submit_cached(k, 4, 1, 0, csr=cache_csr(k)) for k in resident]
+        for t in tks:
+            t.wait()
     # request trace
     nreq = args.requests
     req_graph = rng.integers(0, pool_n, nreq)
@@ -344,8 +413,9 @@ def serve_bench(args):
                 wait = (arr_ns[i] - time.monotonic_ns()) / 1e9
                 if wait > 0:
                     time.sleep(wait)
-                G = graph_for(int(req_graph[i]))
-                tk = hb.submit(G, int(req_p[i]), int(req_d[i]), int(req_seed[i]))
+                k = int(req_graph[i])
+                tk = hb.submit_cached(k, int(req_p[i]), int(req_d[i]), int(req_seed[i]),
+                                      csr=cache_csr(k))
                 with lock:
                     pending[i] = tk
             done.set()
@@ -368,6 +438,7 @@ def serve_bench(args):
     for f in args.rates:
         lam = f * lam_seq
         arrivals = np.cumsum(rng.exponential(1.0 / lam, nreq))
+        warm_cache()
         lat_s, res_s, wall_s = run_trace(arrivals, served=True)
         lat_q, res_q, wall_q = run_trace(arrivals, served=False)
         for a, b in zip(res_s, res_q):
@@ -386,7 +457,9 @@ def serve_bench(args):
             f"{rows[-1]['served']['p99_ms']:.1f} ms | sequential p50 "
             f"{rows[-1]['sequential']['p50_ms']:.1f} ms p99 {rows[-1]['sequential']['p99_ms']:.1f} ms")
     stats = hb.server_stats()
+    cache = hb.graph_cache_stats()
     hb.server_stop()
+    hb.graph_cache_clear()
     for G in resident.values():
         G.free()
     top = rows[-1]
@@ -408,6 +481,7 @@ def serve_bench(args):
                    "lambda_seq_per_s": lam_seq, "edge_unions_per_trace": total_unions},
         "rates": rows,
         "server": stats,
+        "graph_cache": cache,
         "identical_results": True,
     }
     return line
@@ -425,7 +499,8 @@ def main():
     ap.add_argument("--pool-max-nodes", type=int, default=120000)
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 1.0, 1.25])
-    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="cap on the request loop's own device memory (0 = the library budget)")
     ap.add_argument("--no-extras", action="store_true",
                     help="single mode: skip the short batched and served runs in the JSON line")
     ap.add_argument("--steps", type=int, default=5)
@@ -446,8 +521,6 @@ def main():
                     help="processing order of the nodes (results are identical either way)")
     ap.add_argument("--tune", default="measure", choices=["measure", "cached", "off"],
                     help="union schedule: measured in the warm-up (default), cached or default")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 4 GiB device copy (measured bandwidth)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -510,20 +583,36 @@ def main():
     avg_launch_s = iter_ms / 1e3 / passes
     kernel = results[-1].union_kernel
     levels = results[-1].table_levels
-    rows = stats["table_rows"][levels] if kernel == "runs" else None
+    rows = stats["table_rows"][levels] if kernel == "runs" else E
     bits = results[-1].register_bits
-    per_launch = algorithmic_bytes(n, E, data.size, p, rows, bits, stats["n_runs"])
+    m = (1 << p) * bits // 8
+    per_launch = algorithmic_bytes(n, E, data.size, p, rows if kernel == "runs" else None, bits,
+                                   stats["n_runs"])
     achieved = per_launch / avg_launch_s / 1e9
-    lanes = results[-1].lanes_per_node
+    lanes, nb = results[-1].lanes_per_node, results[-1].nodes_per_block
     kname = (f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs"
              else f"union_kernel<{p},{lanes},{bits}>")
-    counters = kernel_traffic(args.config, p, depth, kname, args.order)
-    traffic = counters["hbm_bytes_per_launch"] if counters else None
-    edge_equiv = algorithmic_bytes(n, E, data.size, p, None, bits) / avg_launch_s / 1e9
+    counters = kernel_traffic(args.config, p, depth, kernel, kname, args.order)
+    traffic = (counters.get("fabric_bytes_per_launch", counters.get("hbm_bytes_per_launch"))
+               if counters else None)
+    ceil = measure_ceilings(hb, p, n, rows, lanes, nb, bits, kernel)
+    # the ceiling the launch comes closest to: the rate its loop gathers rows at when
+    # they hit in L2, or the fabric bytes its L2 misses need (counters) against the
+    # rate the same loop reaches when every row misses L2
+    l2_frac = achieved / ceil["l2_gather_gbs"] if ceil.get("l2_gather_gbs") else None
+    fab_gbs = traffic / avg_launch_s / 1e9 if traffic else None
+    fab_frac = fab_gbs / ceil["fabric_gather_gbs"] if fab_gbs and ceil.get("fabric_gather_gbs") \
+        else None
+    use_l2 = l2_frac is not None and (fab_frac is None or l2_frac >= fab_frac)
     line = {
         "metric": METRIC,
         "value": value,
         "unit": "edge-unions/s",
+        "value_kind": ("edge-union equivalent: passes x directed edges per second; the run kernel "
+                       "covers each run of consecutive neighbour ids with at most two range-max "
+                       "table rows, so it gathers table_rows_per_s rows, not one per edge"
+                       if kernel == "runs" else "one gathered counter per directed edge and pass"),
+        "table_rows_per_s": rows / avg_launch_s if kernel == "runs" else None,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -546,7 +635,7 @@ def main():
             "node_order": args.order,
             "register_bits": bits,
             "schedule": {"lanes_per_node": lanes,
-                         "nodes_per_block": results[-1].nodes_per_block,
+                         "nodes_per_block": nb,
                          "tune": args.tune, "tune_ms": tune_ms,
                          "measured": [{k: e[k] for k in ("lanes_per_node", "nodes_per_block",
                                                          "best_ms", "default_ms")}
@@ -554,22 +643,41 @@ def main():
                                       if e["batched"] == 0 and e["p"] == p]},
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": f"{kname} (fused decode + gather-max + estimate + accumulate)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
+            # achieved: the launch's algorithmic bytes (its gathered rows x m + its
+            # adjacency + per-node state) per second; peak: the measured ceiling that
+            # binds, both in this run
+            "bound": "l2" if use_l2 else "hbm",
+            "kernel": f"{kname} (gather-max + estimate + accumulate)",
+            "achieved": achieved if use_l2 else fab_gbs,
+            "peak": ceil["l2_gather_gbs"] if use_l2 else ceil["fabric_gather_gbs"],
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": l2_frac if use_l2 else fab_frac,
             "traffic": traffic,
+            "peak_kind": ("measured: the same gather-and-max loop in the same launch shape over "
+                          "rows that stay in L2 (hb_gather_probe, 2 MiB table)" if use_l2 else
+                          "measured: the same gather loop over rows that miss L2 (hb_gather_probe, "
+                          "1 GiB table)"),
             "algorithmic_bytes_per_launch": per_launch,
-            "gathered_rows_per_launch": rows if rows is not None else E,
+            "gathered_rows_per_launch": rows,
             "avg_launch_ms": avg_launch_s * 1e3,
-            "per_edge_equivalent_gbs": edge_equiv,
+            "ceilings_gbs": ceil,
+            "hbm_published_gbs": HBM_PEAK_GBS,
         },
     }
+    if traffic:
+        # L2 misses and write-backs (FETCH_SIZE, WRITE_SIZE) cross the memory fabric, where
+        # the Infinity Cache serves part of the reads: an upper bound on HBM bytes
+        line["roofline"]["fabric"] = {
+            "bytes_per_launch": traffic, "gbs": fab_gbs,
+            "frac_of_hbm_peak": fab_gbs / HBM_PEAK_GBS,
+            "frac_of_miss_gather_ceiling": fab_frac,
+            "counters": os.path.relpath(COUNTERS_FILES[kernel], ROOT)}
+        if counters.get("dram_read_bytes_per_launch"):
+            line["roofline"]["fabric"]["dram_read_bytes_per_launch"] = \
+                counters["dram_read_bytes_per_launch"]
     if counters and "sq_insts_valu_per_launch" in counters:
-        # what the counters say limits the launch: VALU issue (a wave64 VALU
-        # instruction occupies one of the 1,024 SIMDs for 4 cycles at 2.4 GHz)
+        # VALU issue: a wave64 VALU instruction occupies one of the 1,024 SIMDs for 4
+        # cycles at 2.4 GHz
         valu = counters["sq_insts_valu_per_launch"]
         peak_issue = 256 * 4 * 2.4e9 / 4
         line["roofline"]["issue"] = {
@@ -577,20 +685,36 @@ def main():
             "salu_insts_per_launch": counters.get("sq_insts_salu_per_launch"),
             "valu_issue_peak_per_s": peak_issue,
             "valu_issue_frac": valu / peak_issue / avg_launch_s,
-            "hbm_traffic_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS,
         }
+    if kernel == "runs" and not args.no_extras:
+        # the per-edge kernel does the paper's per-edge work (Eq. 2 as written): one
+        # launch of it on the same graph, against the HBM peak on the Eq. 2 bytes
+        log("per-edge kernel: one union launch on the same graph ...")
+        re_ = G.run(p, 1, args.seed, kernel="edges", tune="off", register_bits=bits)
+        e_ms = re_.iter_ms
+        e_bytes = algorithmic_bytes(n, E, data.size, p, None, bits)
+        e_name = f"union_kernel<{p},{re_.lanes_per_node},{bits}>"
+        e_cnt = kernel_traffic(args.config, p, depth, "edges", e_name, args.order)
+        e_traffic = (e_cnt.get("fabric_bytes_per_launch", e_cnt.get("hbm_bytes_per_launch"))
+                     if e_cnt else None)
+        line["roofline"]["per_edge_kernel"] = {
+            "kernel": e_name, "launch_ms": e_ms,
+            "bytes_per_edge_union": m + data.size / E,
+            "algorithmic_bytes_per_launch": e_bytes,
+            "achieved": e_bytes / (e_ms / 1e3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            # above 1 only by the rows its L2 serves (about a fifth on this graph)
+            "algorithmic_over_peak": e_bytes / (e_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": e_traffic,
+            "frac": e_traffic / (e_ms / 1e3) / 1e9 / HBM_PEAK_GBS if e_traffic else None,
+        }
+        log(f"per-edge kernel: {e_ms:.1f} ms, {e_bytes / (e_ms / 1e3) / 1e9:.0f} GB/s of Eq. 2 bytes")
     if kernel == "runs":
         tb = table_bytes(n, p, levels, bits)
         t_s = table_ms / 1e3 / passes
         line["table_build"] = {"bytes_per_step": tb, "avg_ms": t_s * 1e3,
                                "achieved_gbs": tb / t_s / 1e9 if t_s > 0 else None,
                                "runs": stats["n_runs"]}
-    if args.copy_probe:
-        nbytes = 4 << 30
-        ms = hb.copy_probe(nbytes, 10)
-        line["roofline"]["copy_probe_gbs"] = 2 * nbytes / (ms / 1e3) / 1e9
-        line["roofline"]["frac_of_copy"] = achieved / line["roofline"]["copy_probe_gbs"]
-        log(f"copy probe: {nbytes} B in {ms:.3f} ms -> {line['roofline']['copy_probe_gbs']:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(off, deg, data, n, p, args.seed, args.cpu_seconds)
@@ -642,13 +766,11 @@ def main():
                            "workload": b["config"]["workload"], "identical_results": True,
                            "tuned_classes": b["tuned_classes"]}
         log("served form: Poisson mix, served vs sequential FIFO ...")
-        sargs = argparse.Namespace(**vars(args))
-        sargs.pool, sargs.pool_max_nodes, sargs.requests = 40, 60000, 300
-        sargs.rates = [0.5, 1.0, 1.5]
-        sv = serve_bench(sargs)
+        sv = serve_bench(argparse.Namespace(**vars(args)))
         line["serving"] = {"workload": sv["config"]["workload"],
                            "lambda_seq_per_s": sv["config"]["lambda_seq_per_s"],
-                           "rates": sv["rates"], "identical_results": True}
+                           "rates": sv["rates"], "graph_cache": sv["graph_cache"],
+                           "identical_results": True}
     print(json.dumps(line), flush=True)
 
 

@@ -408,21 +408,29 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
  * request that arrives while others run joins at the next step, and finished
  * requests free their memory at once).  Requests whose steps gather more than
  * slow_lane_bytes run on a second lane with its own thread and stream, so
- * short requests do not wait for the steps of very large ones.  Results match
- * hb_run for the same
- * arguments bit for bit.  Graphs stay owned by the caller; hb_graph_free
- * returns HB_EBUSY while a submitted request still uses the graph.
+ * short requests do not wait for the steps of very large ones; that lane runs
+ * slow_lane_running requests at a time (default 1: the large requests in
+ * arrival order, each at the device's full speed).  Memory comes from the
+ * library's pool under the budget of hb_set_options, shared with blocking runs
+ * and graphs.  Results match hb_run for the same arguments bit for bit.
+ * Graphs passed to hb_submit stay owned by the caller; hb_graph_free returns
+ * HB_EBUSY while a submitted request still uses the graph.  hb_submit_cached
+ * names graphs by a key instead and keeps them in the library's device graph
+ * cache (below).
  */
 typedef uint64_t hb_ticket;
 
 typedef struct {
-    uint64_t hbm_budget;      /* device bytes for running requests; 0 = 3/4 of free memory */
+    uint64_t hbm_budget;      /* cap on the device bytes of running requests, within the
+                                 library-wide budget; 0 = no cap of its own */
     uint32_t max_running;     /* cap on admitted requests; 0 = none */
     uint32_t union_kernel;    /* HB_UNION_* for every request */
     uint32_t table_levels;    /* 0 = default */
     uint64_t slow_lane_bytes; /* requests gathering more bytes per step run on a second lane
-                                 (own thread and stream, shared budget); 0 = 2 GiB,
+                                 (own thread and stream, shared memory); 0 = 2 GiB,
                                  UINT64_MAX = one lane */
+    uint32_t slow_lane_running; /* requests the second lane runs at a time; 0 = 1,
+                                   UINT32_MAX = no cap */
 } hb_server_opts;
 
 typedef struct {
@@ -460,6 +468,38 @@ hb_status hb_submit(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t hash
  * status once.
  */
 hb_status hb_poll(hb_ticket t, hb_result *out);
+
+/*
+ * Device graph cache of the served form: graphs named by a caller-chosen key
+ * stay device-resident between requests.  hb_submit_cached queues an analysis
+ * of graph `graph_key`: when the cache holds it, csr is not read (it may be
+ * NULL); otherwise csr is validated and loaded as by hb_graph_load, inside this
+ * call (its time counts in the request's latency), and kept under the key.
+ * HB_ENOTFOUND when the key is not cached and csr is NULL.  A cached graph is
+ * idle while no request of it is queued or running; when a device allocation
+ * of the library does not fit the budget (or the device), idle cached graphs
+ * are released least recently used first.  Other arguments and errors as
+ * hb_submit.
+ */
+hb_status hb_submit_cached(uint64_t graph_key, const hb_csr *csr, uint32_t p,
+                           uint32_t depth_limit, uint64_t hash_seed, uint32_t flags,
+                           hb_ticket *out);
+
+typedef struct {
+    uint32_t graphs;     /* graphs in the cache */
+    uint32_t busy;       /* of those, graphs with queued or running requests */
+    uint64_t bytes;      /* their device bytes */
+    uint64_t hits, misses, evictions;
+} hb_graph_cache_stats_t;
+
+hb_status hb_graph_cache_stats(hb_graph_cache_stats_t *out);
+
+/* Release every idle cached graph (graphs with requests stay; HB_EBUSY then). */
+hb_status hb_graph_cache_clear(void);
+
+/* Release the cached graph `graph_key` (HB_ENOTFOUND if not cached, HB_EBUSY while
+   it has requests). */
+hb_status hb_graph_cache_drop(uint64_t graph_key);
 
 /* hb_poll that blocks until the request has finished. */
 hb_status hb_wait(hb_ticket t, hb_result *out);
@@ -546,6 +586,21 @@ hb_status hb_tune_clear(void);
  * its own buffers.
  */
 hb_status hb_copy_probe(uint64_t bytes, uint32_t reps, double *avg_ms);
+
+/*
+ * Diagnostic: the ceiling of the run kernel's gathers.  n_nodes nodes, in the
+ * run kernel's launch shape for p (lanes_per_node / nodes_per_block; 0 = the
+ * run kernel's default), each gather rows_per_node counter rows of 2^p bytes
+ * picked by a hash from a table of table_rows rows (a power of two; 2048 rows
+ * at p = 10 is 2 MiB, which stays in every L2), and take their byte-wise max
+ * (with_max = 1) or only load them (0).  One warm-up launch, then reps timed
+ * ones; *avg_ms is the device time of one.  n_nodes * rows_per_node * 2^p /
+ * avg_ms is the rate at which that kernel's loop can gather rows that hit in
+ * L2.  Allocates and frees its own buffers.  p in [4, 12].
+ */
+hb_status hb_gather_probe(uint32_t p, uint32_t lanes_per_node, uint32_t nodes_per_block,
+                          uint32_t table_rows, uint32_t n_nodes, uint32_t rows_per_node,
+                          uint32_t with_max, uint32_t reps, double *avg_ms);
 
 #ifdef __cplusplus
 }

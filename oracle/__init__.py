@@ -99,6 +99,8 @@ def _lib():
         L.or_union_sample.restype = i64
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_set_num_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -117,6 +119,11 @@ def _u32(a):
 
 def _u64(a):
     return _p(a, ctypes.c_uint64)
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    _lib().or_set_num_threads(int(k))
 
 
 def num_threads() -> int:

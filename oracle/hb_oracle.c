@@ -596,6 +596,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads used by later parallel loops (timing only; results do not depend on it). */
+void or_set_num_threads(int k) {
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /*
  * VGA metrics (Sec. 3.3, "Metric derivation") for every node, written out one
  * by one: out holds 8 arrays of n doubles -- connectivity k = deg(v); control,

@@ -65,7 +65,13 @@ class _Result(ctypes.Structure):
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_running", ctypes.c_uint32),
                 ("union_kernel", ctypes.c_uint32), ("table_levels", ctypes.c_uint32),
-                ("slow_lane_bytes", ctypes.c_uint64)]
+                ("slow_lane_bytes", ctypes.c_uint64), ("slow_lane_running", ctypes.c_uint32)]
+
+
+class _CacheStats(ctypes.Structure):
+    _fields_ = [("graphs", ctypes.c_uint32), ("busy", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
+                ("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -197,6 +203,8 @@ def _lib():
         L.hb_run_with.restype = st
         L.hb_run_static.argtypes = L.hb_run_with.argtypes
         L.hb_run_static.restype = st
+        L.hb_gather_probe.argtypes = [ctypes.c_uint32] * 8 + [ctypes.POINTER(ctypes.c_double)]
+        L.hb_gather_probe.restype = st
         L.hb_set_options.argtypes = [ctypes.POINTER(_Options)]
         L.hb_set_options.restype = st
         L.hb_get_options.argtypes = [ctypes.POINTER(_Options)]
@@ -219,6 +227,16 @@ def _lib():
         L.hb_wait.restype = st
         L.hb_server_stats.argtypes = [ctypes.POINTER(_ServerStats)]
         L.hb_server_stats.restype = st
+        L.hb_submit_cached.argtypes = [ctypes.c_uint64, ctypes.POINTER(_CSR), ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.hb_submit_cached.restype = st
+        L.hb_graph_cache_stats.argtypes = [ctypes.POINTER(_CacheStats)]
+        L.hb_graph_cache_stats.restype = st
+        L.hb_graph_cache_clear.argtypes = []
+        L.hb_graph_cache_clear.restype = st
+        L.hb_graph_cache_drop.argtypes = [ctypes.c_uint64]
+        L.hb_graph_cache_drop.restype = st
         L.hb_release_cache.argtypes = []
         L.hb_release_cache.restype = st
         L.hb_tune_cache.argtypes = [ctypes.POINTER(_TuneEntry), ctypes.c_uint32, u32p]
@@ -407,19 +425,7 @@ class Graph:
         self.free()
 
     def _out_arrays(self, p: int, registers: bool, outputs: bool, register_bits: int = 8):
-        n = self.n
-        reach = np.empty(n, np.float64) if outputs else None
-        sum_d = np.empty(n, np.float64) if outputs else None
-        md = np.empty(n, np.float64) if outputs else None
-        width = (1 << p) * register_bits // 8 if register_bits in (4, 8) else 0
-        regs = np.empty((n, width), np.uint8) if (registers and P_MIN <= p <= P_MAX and width) \
-            else None
-        r = _Result()
-        r.reach = _ptr(reach, ctypes.c_double)
-        r.sum_d = _ptr(sum_d, ctypes.c_double)
-        r.mean_depth = _ptr(md, ctypes.c_double)
-        r.registers = _ptr(regs, ctypes.c_uint8)
-        return r, (reach, sum_d, md, regs)
+        return _out_arrays(self.n, p, registers, outputs, register_bits)
 
     def run(self, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,
             outputs: bool = True, kernel: str = "auto", table_levels: int = 0,
@@ -453,6 +459,17 @@ class Graph:
         _check(_lib().hb_run_static(self._h, p, depth_limit, seed & 0xFFFFFFFFFFFFFFFF,
                                     ctypes.byref(o), ctypes.byref(r)))
         return _to_result(r, arrays)
+
+
+def gather_probe(p: int = 10, n_nodes: int = 235770, rows_per_node: int = 1024,
+                 table_rows: int = 2048, with_max: bool = True, lanes_per_node: int = 0,
+                 nodes_per_block: int = 0, reps: int = 5) -> float:
+    """hb_gather_probe: device ms of one launch gathering n_nodes * rows_per_node rows
+    of 2^p bytes from an L2-resident table in the run kernel's shape."""
+    ms = ctypes.c_double(0.0)
+    _check(_lib().hb_gather_probe(p, lanes_per_node, nodes_per_block, table_rows, n_nodes,
+                                  rows_per_node, 1 if with_max else 0, reps, ctypes.byref(ms)))
+    return ms.value
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
@@ -503,10 +520,12 @@ _SERVER_STARTED = False
 
 
 def server_start(hbm_budget: int = 0, max_running: int = 0, kernel: str = "auto",
-                 table_levels: int = 0, slow_lane_bytes: int = 0) -> None:
+                 table_levels: int = 0, slow_lane_bytes: int = 0,
+                 slow_lane_running: int = 0) -> None:
     """hb_server_start: start the request loop (continuous batching)."""
     global _SERVER_STARTED
-    o = _ServerOpts(hbm_budget, max_running, _KERNELS[kernel], table_levels, slow_lane_bytes)
+    o = _ServerOpts(hbm_budget, max_running, _KERNELS[kernel], table_levels, slow_lane_bytes,
+                    slow_lane_running)
     _check(_lib().hb_server_start(ctypes.byref(o)))
     _SERVER_STARTED = True
 
@@ -524,16 +543,33 @@ def server_stats() -> dict:
     return {k: int(getattr(st, k)) for k, _ in _ServerStats._fields_}
 
 
+def _out_arrays(n: int, p: int, registers: bool, outputs: bool, register_bits: int = 8):
+    """Host output arrays of one result and the hb_result pointing at them."""
+    reach = np.empty(n, np.float64) if outputs else None
+    sum_d = np.empty(n, np.float64) if outputs else None
+    md = np.empty(n, np.float64) if outputs else None
+    width = (1 << p) * register_bits // 8 if register_bits in (4, 8) else 0
+    regs = np.empty((n, width), np.uint8) if (registers and P_MIN <= p <= P_MAX and width) \
+        else None
+    r = _Result()
+    r.reach = _ptr(reach, ctypes.c_double)
+    r.sum_d = _ptr(sum_d, ctypes.c_double)
+    r.mean_depth = _ptr(md, ctypes.c_double)
+    r.registers = _ptr(regs, ctypes.c_uint8)
+    return r, (reach, sum_d, md, regs)
+
+
 class Ticket:
     """A submitted request: poll() returns None while pending, then the Result once."""
 
-    def __init__(self, graph: "Graph", p: int, registers: bool, ticket: int,
-                 register_bits: int = 8):
+    def __init__(self, graph: "Graph | None", p: int, registers: bool, ticket: int,
+                 register_bits: int = 8, n: int | None = None):
         self.graph, self.p, self.registers, self.id = graph, p, registers, ticket
         self.register_bits = register_bits
+        self.n = graph.n if n is None else n
 
     def _collect(self, fn) -> "Result | None":
-        r, arrays = self.graph._out_arrays(self.p, self.registers, True, self.register_bits)
+        r, arrays = _out_arrays(self.n, self.p, self.registers, True, self.register_bits)
         st = fn(self.id, ctypes.byref(r))
         if st == HB_PENDING:
             return None
@@ -557,6 +593,47 @@ def submit(g: "Graph", p: int, depth_limit: int = 0, seed: int = 0,
                             ctypes.byref(t)))
     _SERVER_STARTED = True
     return Ticket(g, p, registers, int(t.value), register_bits)
+
+
+def submit_cached(key: int, p: int, depth_limit: int = 0, seed: int = 0, csr=None,
+                  registers: bool = False, register_bits: int = 8, n: int | None = None) -> Ticket:
+    """hb_submit_cached: queue an analysis of the cached graph `key`.  csr is None
+    (the graph must be cached) or (offsets, degrees, data[, order]) host arrays, read
+    only when the key is not cached.  n: node count (from csr when given)."""
+    global _SERVER_STARTED
+    t = ctypes.c_uint64(0)
+    flags = (SUBMIT_REGISTERS if registers else 0) | (SUBMIT_REG4 if register_bits == 4 else 0)
+    cptr = None
+    if csr is not None:
+        off, deg, data = csr[0], csr[1], csr[2]
+        order = csr[3] if len(csr) > 3 else None
+        c, keep = _make_csr(off, deg, data, order=order)
+        cptr = ctypes.byref(c)
+        n = c.n
+    if n is None:
+        raise HBError(HB_EINVAL, "n is needed when no CSR is given")
+    _check(_lib().hb_submit_cached(key & 0xFFFFFFFFFFFFFFFF, cptr, p, depth_limit,
+                                   seed & 0xFFFFFFFFFFFFFFFF, flags, ctypes.byref(t)))
+    _SERVER_STARTED = True
+    return Ticket(None, p, registers, int(t.value), register_bits, n=n)
+
+
+def graph_cache_stats() -> dict:
+    """hb_graph_cache_stats: graphs, busy graphs, device bytes, hits, misses, evictions."""
+    c = _CacheStats()
+    _check(_lib().hb_graph_cache_stats(ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in _CacheStats._fields_}
+
+
+def graph_cache_clear() -> None:
+    """hb_graph_cache_clear: release every idle cached graph (HBError HB_EBUSY if some
+    have requests; those stay)."""
+    _check(_lib().hb_graph_cache_clear())
+
+
+def graph_cache_drop(key: int) -> None:
+    """hb_graph_cache_drop: release one idle cached graph."""
+    _check(_lib().hb_graph_cache_drop(key & 0xFFFFFFFFFFFFFFFF))
 
 
 @atexit.register

@@ -140,7 +140,9 @@ bool row_ok(const uint8_t *p, const uint8_t *end, uint32_t v, uint32_t n, uint32
 
 namespace {
 
-void graph_release(hb_graph *g) {
+}  // namespace
+
+void hbr::graph_release(hb_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
@@ -158,6 +160,8 @@ void graph_release(hb_graph *g) {
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
+
+namespace {
 
 // Run lists of g's rows, decoded on the device from the uploaded LEB128 rows:
 // *runs (inclusive first/last pairs) and *off (n + 1 offsets), allocated here;
@@ -441,6 +445,15 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
         graph_release(g);
         return fail(HB_EDEVICE, "run list: %llu runs on the device, %llu on the host",
                     (unsigned long long)total, (unsigned long long)rc.runs);
+    }
+    {
+        const uint64_t n = g->n;
+        uint64_t b = std::max<uint64_t>(g->n_bytes, 16) + 8 * (n + 1) + 16 * n + 4 * g->n_flags;
+        for (const void *a : {(const void *)csr->order, (const void *)csr->hash_ids,
+                              (const void *)csr->degrees, (const void *)csr->comp_size})
+            if (a) b += 4 * n;
+        if (g->d_runs) b += 8 * std::max<uint64_t>(total, 1) + 8 * (n + 1);
+        g->dev_bytes = b;
     }
     *out = g;
     return HB_OK;
@@ -1230,6 +1243,58 @@ hb_status hb_release_cache(void) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_batch.release();
     pool_trim_all();
+    return HB_OK;
+}
+
+hb_status hb_gather_probe(uint32_t p, uint32_t lanes_per_node, uint32_t nodes_per_block,
+                          uint32_t table_rows, uint32_t n_nodes, uint32_t rows_per_node,
+                          uint32_t with_max, uint32_t reps, double *avg_ms) {
+    if (!avg_ms || reps == 0 || n_nodes == 0) return fail(HB_EINVAL, "bad probe arguments");
+    if (p < HB_P_MIN || p > 12) return fail(HB_EINVAL, "the gather probe supports p in [4, 12]");
+    if (table_rows == 0 || (table_rows & (table_rows - 1u)))
+        return fail(HB_EINVAL, "table_rows must be a power of two");
+    hbk::Sched sc = lanes_per_node ? hbk::Sched{lanes_per_node, nodes_per_block, 8u}
+                                   : hbk::default_sched((int)p, 8u, true);
+    if (!sc.nodes_per_block) sc.nodes_per_block = sc.lanes > 64u ? 1u : 4u;
+    if (!hbk::sched_ok((int)p, sc))
+        return fail(HB_EINVAL, "no schedule of %u lanes, %u nodes per workgroup for p = %u",
+                    sc.lanes, sc.nodes_per_block, p);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    hb_status st = have_device();
+    if (st != HB_OK) return st;
+    const uint64_t m = 1ull << p;
+    const uint32_t waves = sc.lanes > 64u ? sc.lanes / 64u : 1u;
+    void *tbl = nullptr, *out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = dmalloc(&tbl, table_rows * m);
+    if (e == hipSuccess) e = dmalloc(&out, sizeof(uint32_t) * 64ull * waves * n_nodes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // registers 1..4: small values like real counters
+    if (e == hipSuccess)
+        e = hbk::launch_fill_u32(static_cast<uint32_t *>(tbl), 0x01020304u, table_rows * m / 4, s);
+    auto launch = [&]() {
+        return hbk::launch_gather_probe((int)p, sc, static_cast<const uint8_t *>(tbl), table_rows,
+                                        rows_per_node, static_cast<uint32_t *>(out), n_nodes,
+                                        with_max ? 1u : 0u, s);
+    };
+    if (e == hipSuccess) e = launch();  // warm-up: the table settles in the caches
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (uint32_t i = 0; e == hipSuccess && i < reps; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (s) (void)hipStreamDestroy(s);
+    dfree(out);
+    dfree(tbl);
+    if (e == hipErrorOutOfMemory) return fail(HB_ENOMEM, "gather probe: out of device memory");
+    if (e != hipSuccess) return hip_fail(e, "gather probe");
+    *avg_ms = ms / reps;
     return HB_OK;
 }
 

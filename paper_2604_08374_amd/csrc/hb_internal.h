@@ -112,6 +112,13 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
                         const uint32_t *skip, hipStream_t stream);
 
+// Gather ceiling of the run kernel's shape: n nodes each gather `rows` rows of
+// a table of table_rows (a power of two) counter rows picked by a hash, with
+// the byte-wise max (with_max) or loads alone; out gets WAVES x 64 words per node.
+hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32_t table_rows,
+                               uint32_t rows, uint32_t *out, uint32_t n, uint32_t with_max,
+                               hipStream_t stream);
+
 // Streaming copy of bytes (a multiple of 16) from src to dst.
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 

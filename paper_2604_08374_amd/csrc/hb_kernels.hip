@@ -794,6 +794,65 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
                        thr, s_queue[threadIdx.x / kWave]);
 }
 
+// ---------------------------------------------------------------- gather ceiling
+// The run kernel's gather loop without its queue or its run list: every node of
+// the launch gathers `rows` counter rows of a small table (table_rows rows, a
+// power of two, sized to stay in the L2 caches), picked by a hash of (node,
+// row), in the run kernel's shape and with as many rows in flight, and either
+// takes the byte-wise max (with_max = 1) or only xors the loaded words (the load
+// path alone).  Rows gathered per second is the rate the run kernel's gathers
+// can reach when every row hits in L2.
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void gather_probe_kernel(
+    const uint8_t *__restrict__ tbl, uint32_t row_mask, uint32_t rows, uint32_t *__restrict__ out,
+    uint32_t n, uint32_t with_max) {
+    uint32_t v, slice;
+    node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
+    if (v >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t grp = lane / C::LPC;
+    constexpr int U = C::RPL >= kRunLoads ? 1 : kRunLoads / C::RPL;
+    const uint32_t seed = probe_hash(v * 0x9e3779b9u + slice);
+    uint32_t sink = 0;
+    NodeAcc<C> acc;
+    acc.init(tbl + (uint64_t)(v & row_mask) * C::M, slice, lane);
+    for (uint32_t k = 0; k < rows; k += U * C::G) {
+        const uint8_t *src[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t r = probe_hash(seed ^ (k + (uint32_t)u * C::G + (C::G == 1 ? 0u : grp)));
+            if (C::G == 1) r = (uint32_t)__builtin_amdgcn_readfirstlane((int)r);
+            src[u] = tbl + (uint64_t)(r & row_mask) * C::M;
+        }
+        if (with_max) {
+            acc.gather(src, slice, lane);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int s2 = 0; s2 < C::RPL; ++s2) {
+                    const uint4 x =
+                        *reinterpret_cast<const uint4 *>(src[u] + slot_offset<C>(slice, lane, s2));
+                    sink ^= x.x ^ x.y ^ x.z ^ x.w;
+                }
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < C::RPL; ++s2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sink ^= acc.m[s2][q].value();
+    out[(uint64_t)v * C::WAVES * kWave + slice * kWave + lane] = sink;
+}
+
 // Register-wise max of 16 bytes of two counters (8- or 4-bit registers).
 template <class A>
 __device__ __forceinline__ uint4 max16(const uint4 a, const uint4 b) {
@@ -1241,6 +1300,21 @@ hipError_t launch_union_runs_c(const uint2 *runs, const uint64_t *run_off, const
 }
 
 template <class C>
+hipError_t launch_gather_probe_c(const uint8_t *tbl, uint32_t row_mask, uint32_t rows,
+                                 uint32_t *out, uint32_t n, uint32_t with_max, uint32_t nb,
+                                 hipStream_t stream) {
+    if constexpr (C::PREC <= kRunsMaxP) {
+        uint32_t blocks, threads;
+        grid_for<C>(n, nb, blocks, threads);
+        hipLaunchKernelGGL((gather_probe_kernel<C>), dim3(blocks), dim3(threads), 0, stream, tbl,
+                           row_mask, rows, out, n, with_max);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class C>
 hipError_t launch_batch_init_c(BatchJob *jobs, const uint32_t *list, const uint32_t *block_base,
                                uint32_t nlist, uint32_t nblocks, uint32_t nb, hipStream_t stream) {
     uint32_t blocks, threads;
@@ -1358,6 +1432,18 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
     if (p == P && s.lanes == L && s.bits == B)                                                             \
         return launch_union_runs_c<Cfg<P, L, B>>(runs, run_off, tbl, levels, next, c_prev,     \
                                               sum_d, flag_t, n, t, order, thr, skip, nb, stream);
+    HB_DISPATCH(HB_X);
+#undef HB_X
+}
+
+hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32_t table_rows,
+                               uint32_t rows, uint32_t *out, uint32_t n, uint32_t with_max,
+                               hipStream_t stream) {
+    if (table_rows == 0 || (table_rows & (table_rows - 1u))) return hipErrorInvalidValue;
+#define HB_X(P, L, B)                                                                          \
+    if (p == P && s.lanes == L && s.bits == B)                                                 \
+        return launch_gather_probe_c<Cfg<P, L, B>>(tbl, table_rows - 1u, rows, out, n,         \
+                                                   with_max, nb, stream);
     HB_DISPATCH(HB_X);
 #undef HB_X
 }

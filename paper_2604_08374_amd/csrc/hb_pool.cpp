@@ -6,7 +6,8 @@
 // (hb_options.hbm_budget), so the blocking runs, the batched workspace, the
 // served requests and the loaded graphs draw on the same memory.  Working
 // buffers (counters, tables, per-node state) are carved first-fit out of
-// pooled blocks of at least kMinBlock bytes, which stay allocated between
+// pooled blocks of at least kMinBlock bytes (under a budget: at most a quarter
+// of the budget left, or the request), which stay allocated between
 // calls: a run, a batch or an admitted request then takes its buffers without
 // a device allocation, and a finished one returns them without the implicit
 // device synchronisation of hipFree.  Idle blocks are released by
@@ -248,8 +249,10 @@ hb_status pool_take(uint64_t bytes, void **p) {
     }
     uint64_t want = std::max(align_up(bytes, 2ull << 20), kMinBlock);
     if (o.hbm_budget) {
+        // under a budget a block takes at most a quarter of what is left, so
+        // that graphs and other blocks still find room
         const uint64_t room = o.hbm_budget > held ? o.hbm_budget - held : 0;
-        want = std::max(bytes, std::min(want, align_up(room, 256)));
+        want = std::max(bytes, std::min(want, align_up(room / 4, 256)));
     }
     void *base = nullptr;
     hipError_t e = dmalloc_impl(&base, want, false);

@@ -109,6 +109,10 @@ void memory_stats(int dev, hb_memory_stats_t *out);
 using Evictor = std::function<uint64_t(int dev, uint64_t need)>;
 void set_evictor(Evictor f);
 
+// Free a loaded graph and its device memory (no lock taken; the caller makes
+// sure nothing uses it).
+void graph_release(hb_graph *g);
+
 }  // namespace hbr
 
 struct hb_graph {
@@ -134,4 +138,5 @@ struct hb_graph {
     hipEvent_t ev_init[2] = {nullptr, nullptr};          // around the initialisation
     hipEvent_t ev_step[hbr::kSegment][3] = {};            // per step: table, union, end
     std::atomic<uint32_t> inflight{0};  // served requests that still use this graph
+    uint64_t dev_bytes = 0;             // device memory of the graph's arrays
 };

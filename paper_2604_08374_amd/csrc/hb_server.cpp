@@ -140,7 +140,7 @@ hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &
 hb_status Server::start(const hb_server_opts *opts) {
     std::lock_guard<std::mutex> lk(mu_);
     if (running_) return fail(HB_EBUSY, "the request loop is already running");
-    hb_server_opts o = opts ? *opts : hb_server_opts{0, 0, 0, 0, 0};
+    hb_server_opts o = opts ? *opts : hb_server_opts{};
     if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels > 24");
     int count = 0;
@@ -345,7 +345,12 @@ hb_status Server::step(Lane &L) {
     {
         std::lock_guard<std::mutex> lk(mu_);
         const uint32_t others = lanes_[0].n_running + lanes_[1].n_running - L.n_running;
-        while (!L.queue.empty() &&
+        // the slow lane runs its large requests a few at a time (default one, in
+        // arrival order), each at the device's full speed
+        const uint64_t lane_cap =
+            &L == &lanes_[1] ? (opts_.slow_lane_running ? opts_.slow_lane_running : 1u)
+                             : UINT64_MAX;
+        while (!L.queue.empty() && L.running.size() + admitted.size() < lane_cap &&
                (opts_.max_running == 0 ||
                 others + L.running.size() + admitted.size() < opts_.max_running)) {
             Request *r = L.queue.front();
@@ -587,6 +592,125 @@ void Server::loop(Lane &L) {
 
 Server g_server;
 
+// ---- device graph cache (hb_submit_cached)
+// Graphs named by a caller's key stay loaded between requests.  A graph is idle
+// while its inflight count is zero; the evictor, called when a device
+// allocation does not fit, releases idle graphs least recently used first.  The
+// lock is recursive because loading a graph may call the evictor on the same
+// thread; the evictor only try-locks it, so a thread blocked elsewhere never
+// waits for it.
+struct CacheEntry {
+    hb_graph *g;
+    uint64_t last_use;
+};
+
+class GraphCache {
+public:
+    hb_status submit(uint64_t key, const hb_csr *csr, uint32_t p, uint32_t depth, uint64_t seed,
+                     uint32_t flags, hb_ticket *out) {
+        if (!out) return fail(HB_EINVAL, "NULL argument");
+        hb_graph *g = nullptr;
+        {
+            std::lock_guard<std::recursive_mutex> lk(mu_);
+            install_evictor();
+            auto it = map_.find(key);
+            if (it != map_.end()) {
+                ++hits_;
+            } else {
+                if (!csr) return fail(HB_ENOTFOUND, "graph %llu is not cached and no CSR was given",
+                                      (unsigned long long)key);
+                hb_graph *ng = nullptr;
+                const hb_status st = hb_graph_load(csr, &ng);
+                if (st != HB_OK) return st;
+                it = map_.emplace(key, CacheEntry{ng, 0}).first;
+                ++misses_;
+            }
+            it->second.last_use = ++clock_;
+            g = it->second.g;
+            g->inflight.fetch_add(1);  // pinned until the request holds it
+        }
+        const hb_status st = g_server.submit(g, p, depth, seed, flags, out);
+        g->inflight.fetch_sub(1);
+        return st;
+    }
+
+    // Release idle graphs of device dev, oldest first, until `need` bytes are free.
+    uint64_t evict(int dev, uint64_t need) {
+        std::unique_lock<std::recursive_mutex> lk(mu_, std::try_to_lock);
+        if (!lk.owns_lock()) return 0;
+        std::vector<std::pair<uint64_t, uint64_t>> idle;  // (last use, key)
+        for (const auto &kv : map_)
+            if (kv.second.g->device == dev && kv.second.g->inflight.load() == 0)
+                idle.emplace_back(kv.second.last_use, kv.first);
+        std::sort(idle.begin(), idle.end());
+        uint64_t freed = 0;
+        for (const auto &e : idle) {
+            if (freed >= need) break;
+            hb_graph *g = map_[e.second].g;
+            freed += g->dev_bytes;
+            map_.erase(e.second);
+            graph_release(g);
+            ++evictions_;
+        }
+        return freed;
+    }
+
+    hb_status clear() {
+        std::lock_guard<std::recursive_mutex> lk(mu_);
+        uint32_t busy = 0;
+        for (auto it = map_.begin(); it != map_.end();) {
+            if (it->second.g->inflight.load() != 0) {
+                ++busy;
+                ++it;
+                continue;
+            }
+            graph_release(it->second.g);
+            it = map_.erase(it);
+        }
+        if (busy) return fail(HB_EBUSY, "%u cached graphs have requests and stay", busy);
+        return HB_OK;
+    }
+
+    hb_status drop(uint64_t key) {
+        std::lock_guard<std::recursive_mutex> lk(mu_);
+        auto it = map_.find(key);
+        if (it == map_.end()) return fail(HB_ENOTFOUND, "graph %llu is not cached",
+                                          (unsigned long long)key);
+        if (it->second.g->inflight.load() != 0)
+            return fail(HB_EBUSY, "graph %llu has requests", (unsigned long long)key);
+        graph_release(it->second.g);
+        map_.erase(it);
+        return HB_OK;
+    }
+
+    void stats(hb_graph_cache_stats_t *out) {
+        std::lock_guard<std::recursive_mutex> lk(mu_);
+        *out = hb_graph_cache_stats_t{};
+        for (const auto &kv : map_) {
+            ++out->graphs;
+            out->busy += kv.second.g->inflight.load() != 0 ? 1u : 0u;
+            out->bytes += kv.second.g->dev_bytes;
+        }
+        out->hits = hits_;
+        out->misses = misses_;
+        out->evictions = evictions_;
+    }
+
+private:
+    void install_evictor() {
+        if (evictor_set_) return;
+        set_evictor([this](int dev, uint64_t need) { return evict(dev, need); });
+        evictor_set_ = true;
+    }
+
+    std::recursive_mutex mu_;
+    std::unordered_map<uint64_t, CacheEntry> map_;
+    uint64_t clock_ = 0, hits_ = 0, misses_ = 0, evictions_ = 0;
+    bool evictor_set_ = false;
+};
+
+GraphCache g_cache;
+
 }  // namespace
 
 extern "C" {
@@ -605,5 +729,21 @@ hb_status hb_poll(hb_ticket t, hb_result *out) { return g_server.poll(t, out, fa
 hb_status hb_wait(hb_ticket t, hb_result *out) { return g_server.poll(t, out, true); }
 
 hb_status hb_server_stats(hb_server_stats_t *out) { return g_server.stats(out); }
+
+hb_status hb_submit_cached(uint64_t graph_key, const hb_csr *csr, uint32_t p,
+                           uint32_t depth_limit, uint64_t hash_seed, uint32_t flags,
+                           hb_ticket *out) {
+    return g_cache.submit(graph_key, csr, p, depth_limit, hash_seed, flags, out);
+}
+
+hb_status hb_graph_cache_stats(hb_graph_cache_stats_t *out) {
+    if (!out) return fail(HB_EINVAL, "out is NULL");
+    g_cache.stats(out);
+    return HB_OK;
+}
+
+hb_status hb_graph_cache_clear(void) { return g_cache.clear(); }
+
+hb_status hb_graph_cache_drop(uint64_t graph_key) { return g_cache.drop(graph_key); }
 
 }  // extern "C"

@@ -4,8 +4,11 @@ Reads the CSV output of three rocprofv3 runs of the same command -- one with
 ``--kernel-trace --stats``, one with ``--pmc FETCH_SIZE``, one with ``--pmc WRITE_SIZE``
 -- and writes a short text summary: per-kernel call counts and average durations,
 the byte counters per dispatch, the counter scale factors measured on the library's
-plain copy kernel (which moves a known number of bytes), and the resulting HBM bytes
-per union launch.  The summary also records the SHA-256 of the kernel source it was
+plain copy kernel (which moves a known number of bytes), and the resulting bytes per
+union launch between L2 and the memory fabric.  FETCH_SIZE and WRITE_SIZE count L2
+misses and write-backs; the 256 MB Infinity Cache on the fabric side serves part of
+those reads, so they are fabric bytes, an upper bound on HBM bytes.  An optional
+run of the TCC_EA0_*_DRAM counters gives the requests L2 sent towards DRAM.  The summary also records the SHA-256 of the kernel source it was
 taken on, so a later benchmark reports the traffic only while the kernel is unchanged.
 
 Usage:
@@ -112,6 +115,9 @@ def main():
     ap.add_argument("--sq", default=None,
                     help="optional --pmc run of SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
                          "SQ_INSTS_VMEM_RD (instruction mix of --kernel)")
+    ap.add_argument("--dram", default=None,
+                    help="optional --pmc run of TCC_EA0_RDREQ_DRAM_sum TCC_EA0_RDREQ_DRAM_32B_sum "
+                         "TCC_EA0_WRREQ_DRAM_sum (requests from L2 towards DRAM)")
     ap.add_argument("--node-order", default="raster",
                     help="processing order of the profiled run (recorded with the counters)")
     args = ap.parse_args()
@@ -163,8 +169,21 @@ def main():
               f"* copy kernel moves {args.copy_bytes} B each way per dispatch: FETCH_SIZE scale "
               f"{f_fetch:.4f}, WRITE_SIZE scale {f_write:.4f}",
               f"* {k}: average duration {avg_ns / 1e6:.3f} ms over {calls} calls",
-              f"* {k}: HBM read {read_b / 1e12:.4f} TB + write {write_b / 1e12:.4f} TB = "
+              f"* {k}: L2-to-fabric read {read_b / 1e12:.4f} TB + write {write_b / 1e12:.4f} TB = "
               f"{traffic / 1e12:.4f} TB per launch -> {traffic / (avg_ns * 1e-9) / 1e9:.0f} GB/s"]
+    dram = {}
+    if args.dram:
+        dc = counter_means(args.dram)
+        for c in ("TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_RDREQ_DRAM_32B_sum", "TCC_EA0_WRREQ_DRAM_sum"):
+            if (k, c) in dc:
+                dram[c] = dc[(k, c)][1]
+        if "TCC_EA0_RDREQ_DRAM_sum" in dram:
+            r32 = dram.get("TCC_EA0_RDREQ_DRAM_32B_sum", 0.0)
+            rd = 64.0 * (dram["TCC_EA0_RDREQ_DRAM_sum"] - r32) + 32.0 * r32
+            dram["dram_read_bytes"] = rd
+            lines.append(f"* {k}: read requests towards DRAM {dram['TCC_EA0_RDREQ_DRAM_sum']:.4g} "
+                         f"({r32:.4g} of 32 B) = {rd / 1e12:.4f} TB per launch "
+                         f"({rd / read_b:.3f} of the FETCH_SIZE bytes)")
     if args.hit:
         hit = counter_means(args.hit)
         h = hit.get((k, "TCC_HIT_sum"), (0, 0.0))[1]
@@ -200,7 +219,9 @@ def main():
         f.write(f"write_kib_per_launch {write_kib:.3f}\n")
         f.write(f"fetch_scale {f_fetch:.6f}\n")
         f.write(f"write_scale {f_write:.6f}\n")
-        f.write(f"hbm_bytes_per_launch {traffic:.0f}\n")
+        f.write(f"fabric_bytes_per_launch {traffic:.0f}\n")
+        if "dram_read_bytes" in dram:
+            f.write(f"dram_read_bytes_per_launch {dram['dram_read_bytes']:.0f}\n")
         for c, v in mix.items():
             f.write(f"{c.lower()}_per_launch {v:.0f}\n")
     print("\n".join(lines))

@@ -145,3 +145,69 @@ def test_poll_and_ticket_rules(hb, server):
     assert t2.wait().passes == 1
     G.free()
     big.free()
+
+
+# ------------------------------------------------------------ device graph cache
+def _csr_of(hb, g):
+    off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
+    return (off, deg, data)
+
+
+@pytest.fixture
+def fresh_cache(hb):
+    hb.graph_cache_clear()
+    yield
+    try:
+        hb.server_stop()
+    except hb.HBError:
+        pass  # not running
+    hb.set_options()
+    hb.graph_cache_clear()
+    hb.release_cache()
+
+
+def test_cached_graphs_load_once_and_match_the_oracle(hb, fresh_cache):
+    graphs = {11: synth.tiny(0), 12: synth.grid_graph(5, 60, 40), 13: synth.star_graph(70)}
+    csrs = {k: _csr_of(hb, g) for k, g in graphs.items()}
+    hb.server_start()
+    jobs = [(k, p, d, 31 * k + i) for i, (p, d) in enumerate([(10, 0), (8, 3), (12, 2)])
+            for k in graphs]
+    tickets = [hb.submit_cached(k, p, d, s, csr=csrs[k], registers=True) for (k, p, d, s) in jobs]
+    for (k, p, d, s), t in zip(jobs, tickets):
+        assert_matches(hb, t.wait(), ref(graphs[k], p, d, s), f"cached key {k} p={p} d={d}")
+    st = hb.graph_cache_stats()
+    assert st["graphs"] == 3 and st["misses"] == 3 and st["hits"] == len(jobs) - 3
+    assert st["busy"] == 0 and st["bytes"] > 0
+    # a cached key needs no CSR; an unknown one does
+    r = hb.submit_cached(12, 9, 1, 5, n=graphs[12].n).wait()
+    assert_matches(hb, r, ref(graphs[12], 9, 1, 5), "cached without csr")
+    with pytest.raises(hb.HBError) as e:
+        hb.submit_cached(99, 9, 1, 5, n=10)
+    assert e.value.status == hb.HB_ENOTFOUND
+
+
+def test_cache_releases_the_least_recently_used_idle_graph(hb, fresh_cache):
+    """Under a budget that holds two of three equal graphs, loading the third releases
+    the graph used least recently; the results stay those of the oracle."""
+    gs = {1: synth.grid_graph(1, 100, 80), 2: synth.grid_graph(2, 100, 80),
+          3: synth.grid_graph(3, 100, 80)}
+    csrs = {k: _csr_of(hb, g) for k, g in gs.items()}
+    hb.server_start()
+    for k in (1, 2):
+        assert_matches(hb, hb.submit_cached(k, 4, 2, k, csr=csrs[k]).wait(), ref(gs[k], 4, 2, k),
+                       f"graph {k}")
+    assert_matches(hb, hb.submit_cached(1, 4, 3, 7, n=gs[1].n).wait(), ref(gs[1], 4, 3, 7),
+                   "graph 1 again")  # graph 2 is now the least recently used
+    hb.release_cache()
+    st = hb.graph_cache_stats()
+    per = st["bytes"] // 2
+    hb.set_options(hbm_budget=hb.memory_stats(0)["held_bytes"] + per // 2 + (4 << 20))
+    assert_matches(hb, hb.submit_cached(3, 4, 2, 3, csr=csrs[3]).wait(), ref(gs[3], 4, 2, 3),
+                   "graph 3 under the budget")
+    st = hb.graph_cache_stats()
+    assert st["evictions"] == 1 and st["graphs"] == 2
+    with pytest.raises(hb.HBError) as e:
+        hb.submit_cached(2, 4, 2, 2, n=gs[2].n)
+    assert e.value.status == hb.HB_ENOTFOUND
+    assert_matches(hb, hb.submit_cached(1, 4, 2, 1, n=gs[1].n).wait(), ref(gs[1], 4, 2, 1),
+                   "graph 1 stayed")
