@@ -82,6 +82,9 @@ def _lib():
         L.or_hyperball.restype = ctypes.c_int
         L.or_vga_metrics.argtypes = [i64, u64p, u32p, u8p, u32p, dp, dp]
         L.or_vga_metrics.restype = ctypes.c_int
+        L.or_point_second_moment.argtypes = [i64, u64p, u32p, u8p, ctypes.POINTER(ctypes.c_int32),
+                                             dp]
+        L.or_point_second_moment.restype = ctypes.c_int
         L.or_local_metrics.argtypes = [i64, u64p, u32p, u8p, u32p, i64, u64p, u32p, dp, dp]
         L.or_local_metrics.restype = ctypes.c_int
         L.or_hyperball_exact.argtypes = [i64, u64p, u32p, u8p, u32, dp, dp, ctypes.POINTER(_Info)]
@@ -387,6 +390,21 @@ def vga_metrics(csr: CSR, sum_d, comp_size=None) -> dict:
     if rc != 0:
         raise RuntimeError("oracle vga_metrics failed (malformed CSR)")
     return {name: out[i] for i, name in enumerate(VGA_METRICS)}
+
+
+def point_second_moment(csr: CSR, xy) -> np.ndarray:
+    """Point second moment of every node (Sec. 3.3): the sum over its neighbours of the
+    squared distance between cell centres, squared cell units; xy: (n, 2) cells."""
+    xy = np.ascontiguousarray(xy, np.int32)
+    if xy.shape != (csr.n, 2):
+        raise ValueError("xy must have shape (n, 2)")
+    out = np.empty(csr.n, np.float64)
+    rc = _lib().or_point_second_moment(csr.n, _u64(csr.offsets), _u32(csr.degrees),
+                                       _bytes_ptr(csr), _p(xy, ctypes.c_int32),
+                                       _p(out, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle point_second_moment failed (malformed CSR)")
+    return out
 
 
 def local_metrics(csr: CSR, nodes=None) -> dict:

@@ -661,6 +661,48 @@ int or_vga_metrics(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
 }
 
 /*
+ * Point second moment (Sec. 3.3, "Metric derivation", a local metric computed
+ * exactly from the 1-hop neighbourhood), read as the second moment of the
+ * visible cells about the cell itself, as Turner et al. (2001) define isovist
+ * moments: PSM(v) = sum over neighbours w of (x_w - x_v)^2 + (y_w - y_v)^2, in
+ * squared cell units, with xy[2v], xy[2v+1] the cell of node v.  The sum is
+ * formed in 64-bit integers and converted to double once.  Returns 0, or -1 on
+ * a malformed row.
+ */
+int or_point_second_moment(int64_t n, const uint64_t *offsets, const uint32_t *degrees,
+                           const uint8_t *bytes, const int32_t *xy, double *out) {
+    int bad = 0;
+#pragma omp parallel
+    {
+        uint32_t *ids = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; ++v) {
+            if ((int64_t)degrees[v] > cap) {
+                free(ids);
+                cap = degrees[v];
+                ids = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+            }
+            const int64_t k = or_decode_row(bytes, offsets, v, ids, cap);
+            if (k != (int64_t)degrees[v]) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            uint64_t sum = 0;
+            for (int64_t e = 0; e < k; ++e) {
+                const int64_t dx = (int64_t)xy[2 * ids[e]] - (int64_t)xy[2 * v];
+                const int64_t dy = (int64_t)xy[2 * ids[e] + 1] - (int64_t)xy[2 * v + 1];
+                sum += (uint64_t)(dx * dx + dy * dy);
+            }
+            out[v] = (double)sum;
+        }
+        free(ids);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * Local VGA metrics from the neighbourhoods (Sec. 3.3, "Metric derivation":
  * computed exactly, without the HLL), for the nodes listed in nodes[0..count)
  * (nodes = NULL: every node, count = n), written out one by one per listed

@@ -614,3 +614,41 @@ def test_union_sample_keeps_the_own_counter_and_every_neighbour():
         for u in members:
             want[u % m] = max(want[u % m], 1 + u // m)
         assert np.array_equal(nxt[v], want), v
+
+
+# ------------------------------------------------ point second moment (Sec. 3.3)
+def _sq_sum(i, L):
+    """sum over cells j != i of a line of L cells of (j - i)^2, in closed form."""
+    a, b = i, L - 1 - i
+    return a * (a + 1) * (2 * a + 1) // 6 + b * (b + 1) * (2 * b + 1) // 6
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 40])
+def test_point_second_moment_corridor(L):
+    """A straight corridor one cell wide: every cell sees every other one, so cell i
+    has sum over j of (j - i)^2."""
+    g = synth.graph_from_raster(np.zeros((1, L), np.uint8), name=f"corridor{L}")
+    assert g.n == L and g.n_edges == L * (L - 1)
+    psm = oracle.point_second_moment(oracle.from_graph(g), g.xy)
+    want = [_sq_sum(int(x), L) for x in g.xy[:, 0]]
+    assert np.array_equal(psm, np.asarray(want, np.float64))
+
+
+@pytest.mark.parametrize("a,b", [(5, 5), (6, 3)])
+def test_point_second_moment_rectangular_room(a, b):
+    """An open a x b room: every cell sees all others; the moment splits into the x and
+    y sums, b S_a(x) + a S_b(y)."""
+    g = synth.graph_from_raster(np.zeros((b, a), np.uint8), name=f"room{a}x{b}")
+    assert g.n == a * b and g.n_edges == a * b * (a * b - 1)
+    psm = oracle.point_second_moment(oracle.from_graph(g), g.xy)
+    want = [b * _sq_sum(int(x), a) + a * _sq_sum(int(y), b) for x, y in g.xy]
+    assert np.array_equal(psm, np.asarray(want, np.float64))
+
+
+def test_point_second_moment_by_brute_force():
+    """Tiny graph with obstacles: each node against its own neighbour list."""
+    g = synth.tiny(2)
+    psm = oracle.point_second_moment(oracle.from_graph(g), g.xy)
+    for v in range(0, g.n, 3):
+        d = g.xy[g.row(v)].astype(np.int64) - g.xy[v].astype(np.int64)
+        assert psm[v] == float((d * d).sum()), v
