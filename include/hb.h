@@ -76,6 +76,8 @@ typedef struct {
     const uint32_t *comp_size; /* n exact component sizes N_v, or NULL = all n */
     const uint32_t *order;     /* n: processing order, a permutation of 0..n-1, or NULL */
     const uint32_t *hash_ids;  /* n: element inserted for node v (Alg. 1), or NULL = v */
+    const int32_t *xy;         /* 2n: cell (x, y) of node v at xy[2v], xy[2v+1], or NULL
+                                  (needed only by the point second moment) */
 } hb_csr;
 
 /*
@@ -527,12 +529,19 @@ hb_status hb_release_cache(void);
  *    (+inf when RA = 0; the paper names RRA but not D_N);
  *  - integration_tekl: log2((MD + 2) / 3), as the paper states it;
  *  - integration_pvalue: max(0, 1 - RA);
- *  - point_first_moment: MD k.
- * The first two are exact; the others inherit the HLL error of sum_d.
+ *  - point_first_moment: MD k;
+ *  - point_second_moment: the sum over neighbours w of (x_w - x_v)^2 + (y_w - y_v)^2,
+ *    the second moment of the visible cells about v (Turner et al. 2001's isovist
+ *    moment; the paper names it among the exact local metrics without a formula), in
+ *    squared cell units, summed exactly in integers; NaN when the graph was loaded
+ *    without hb_csr.xy.
+ * connectivity, control and point_second_moment are exact; the others inherit the
+ * HLL error of sum_d.
  */
 typedef struct {
     double *connectivity, *control, *mean_depth, *relative_asymmetry;
     double *integration_hh, *integration_tekl, *integration_pvalue, *point_first_moment;
+    double *point_second_moment;
 } hb_vga_out;
 
 /* The metrics above for every node of g from the sums of one run (n doubles). */

@@ -45,7 +45,7 @@ class HBError(RuntimeError):
 class _CSR(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("offsets", u64p),
                 ("degrees", u32p), ("bytes", u8p), ("comp_size", u32p), ("order", u32p),
-                ("hash_ids", u32p)]
+                ("hash_ids", u32p), ("xy", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _Result(ctypes.Structure):
@@ -141,7 +141,8 @@ def unpack_nibbles(regs: np.ndarray) -> np.ndarray:
 
 
 VGA_METRICS = ("connectivity", "control", "mean_depth", "relative_asymmetry", "integration_hh",
-               "integration_tekl", "integration_pvalue", "point_first_moment")
+               "integration_tekl", "integration_pvalue", "point_first_moment",
+               "point_second_moment")
 
 
 class _VgaOut(ctypes.Structure):
@@ -295,7 +296,8 @@ def csr_encode(adj_offsets: np.ndarray, adj_ids: np.ndarray):
     return offsets, degrees, data[:int(blen.value)]
 
 
-def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None, order=None, hash_ids=None):
+def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None, order=None, hash_ids=None,
+              xy=None):
     offsets = np.ascontiguousarray(offsets, np.uint64)
     degrees = np.ascontiguousarray(degrees, np.uint32)
     data = np.ascontiguousarray(data, np.uint8)
@@ -318,6 +320,14 @@ def _make_csr(offsets, degrees, data, comp_size=None, n_edges=None, order=None, 
             setattr(c, name, _ptr(arr, ctypes.c_uint32))
         else:
             setattr(c, name, None)
+    if xy is not None:
+        xy = np.ascontiguousarray(xy, np.int32)
+        if xy.shape != (n, 2):
+            raise HBError(HB_EINVAL, "xy must have shape (n, 2)")
+        keep.append(xy)
+        c.xy = _ptr(xy, ctypes.c_int32)
+    else:
+        c.xy = None
     return c, keep
 
 
@@ -363,8 +373,8 @@ class Graph:
     """A compressed CSR resident in device memory (hb_graph)."""
 
     def __init__(self, offsets, degrees, data, comp_size=None, n_edges=None, order=None,
-                 hash_ids=None):
-        c, keep = _make_csr(offsets, degrees, data, comp_size, n_edges, order, hash_ids)
+                 hash_ids=None, xy=None):
+        c, keep = _make_csr(offsets, degrees, data, comp_size, n_edges, order, hash_ids, xy)
         h = ctypes.c_void_p()
         _check(_lib().hb_graph_load(ctypes.byref(c), ctypes.byref(h)))
         del keep
@@ -727,10 +737,11 @@ def release_cache() -> None:
 
 
 def graph_load(offsets, degrees, data, comp_size=None, n_edges=None, order=None,
-               hash_ids=None) -> Graph:
+               hash_ids=None, xy=None) -> Graph:
     """hb_graph_load.  order: processing order of the nodes (a permutation; changes no
-    result); hash_ids: element inserted for each node (its id before a renumbering)."""
-    return Graph(offsets, degrees, data, comp_size, n_edges, order, hash_ids)
+    result); hash_ids: element inserted for each node (its id before a renumbering);
+    xy: (n, 2) cell coordinates, for the point second moment."""
+    return Graph(offsets, degrees, data, comp_size, n_edges, order, hash_ids, xy)
 
 
 def run(g: Graph, p: int, depth_limit: int = 0, seed: int = 0, registers: bool = False,

@@ -149,7 +149,7 @@ void hbr::graph_release(hb_graph *g) {
     for (void *p : {(void *)g->d_bytes, (void *)g->d_offsets, (void *)g->d_cprev,
                     (void *)g->d_order, (void *)g->d_hash_ids, (void *)g->d_degrees,
                     (void *)g->d_comp, (void *)g->d_runs, (void *)g->d_run_off,
-                    (void *)g->d_sumd, (void *)g->d_flags})
+                    (void *)g->d_sumd, (void *)g->d_flags, (void *)g->d_xy})
         dfree(p);
     if (g->h_flags) (void)hipHostFree(g->h_flags);
     for (auto &e : g->ev_init)
@@ -433,6 +433,12 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                            hipMemcpyHostToDevice)) != hipSuccess)
             return bail(e, "hipMemcpy(per-node array)");
     }
+    if (csr->xy) {
+        if ((e = dmalloc((void **)&g->d_xy, 8ull * g->n)) != hipSuccess)
+            return bail(e, "device allocation (xy)");
+        if ((e = hipMemcpy(g->d_xy, csr->xy, 8ull * g->n, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "hipMemcpy(xy)");
+    }
     // the run kernel reads each row as its list of runs, decoded here once; a
     // graph whose run list does not fit loads without it (per-edge kernel only)
     uint64_t total = 0;
@@ -453,6 +459,7 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
                               (const void *)csr->degrees, (const void *)csr->comp_size})
             if (a) b += 4 * n;
         if (g->d_runs) b += 8 * std::max<uint64_t>(total, 1) + 8 * (n + 1);
+        if (csr->xy) b += 8 * n;
         g->dev_bytes = b;
     }
     *out = g;
@@ -1162,21 +1169,21 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
 
 hb_status hb_vga_metrics(hb_graph *g, const double *sum_d, hb_vga_out *out) {
     if (!g || !sum_d || !out) return fail(HB_EINVAL, "NULL argument");
-    double *dst[8] = {out->connectivity, out->control, out->mean_depth, out->relative_asymmetry,
+    double *dst[9] = {out->connectivity, out->control, out->mean_depth, out->relative_asymmetry,
                       out->integration_hh, out->integration_tekl, out->integration_pvalue,
-                      out->point_first_moment};
+                      out->point_first_moment, out->point_second_moment};
     std::lock_guard<std::mutex> lk(g_dev_mu);
     HB_HIP(hipSetDevice(g->device));
     const uint64_t n = g->n;
     double *d_sum = nullptr, *d_out = nullptr;
     hipError_t e = dmalloc((void **)&d_sum, sizeof(double) * n);
-    if (e == hipSuccess) e = dmalloc((void **)&d_out, sizeof(double) * 8 * n);
+    if (e == hipSuccess) e = dmalloc((void **)&d_out, sizeof(double) * 9 * n);
     if (e == hipSuccess) e = hipMemcpyAsync(d_sum, sum_d, sizeof(double) * n, hipMemcpyHostToDevice,
                                             g->stream);
     if (e == hipSuccess)
-        e = hbk::launch_vga(g->d_bytes, g->d_offsets, g->d_degrees, g->d_comp, d_sum, g->n, d_out,
-                            g->stream);
-    for (int i = 0; i < 8 && e == hipSuccess; ++i)
+        e = hbk::launch_vga(g->d_bytes, g->d_offsets, g->d_degrees, g->d_comp, g->d_xy, d_sum,
+                            g->n, d_out, g->stream);
+    for (int i = 0; i < 9 && e == hipSuccess; ++i)
         if (dst[i])
             e = hipMemcpyAsync(dst[i], d_out + (uint64_t)i * n, sizeof(double) * n,
                                hipMemcpyDeviceToHost, g->stream);

@@ -122,13 +122,14 @@ hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32
 // Streaming copy of bytes (a multiple of 16) from src to dst.
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 
-// VGA metrics of every node (Sec. 3.3): out holds 8 arrays of n doubles --
+// VGA metrics of every node (Sec. 3.3): out holds 9 arrays of n doubles --
 // connectivity, control, mean depth, RA, integration [HH], [Tekl], [P-value],
-// point first moment -- from the CSR, the degrees, the exact component sizes
-// (null: all n) and the Eq. 3 sums.
+// point first moment, point second moment -- from the CSR, the degrees, the
+// exact component sizes (null: all n), the cell coordinates (null: the second
+// moment is NaN) and the Eq. 3 sums.
 hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint32_t *degrees,
-                      const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
-                      hipStream_t stream);
+                      const uint32_t *comp_size, const int32_t *xy, const double *sum_d,
+                      uint32_t n, double *out, hipStream_t stream);
 
 // Maximal runs of consecutive ids of every row (join_self: runs through v
 // itself count as one).  runs == null: cnt[v] = the

@@ -1013,6 +1013,7 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
                                                   const uint64_t *__restrict__ offsets,
                                                   const uint32_t *__restrict__ degrees,
                                                   const uint32_t *__restrict__ comp_size,
+                                                  const int32_t *__restrict__ xy,
                                                   const double *__restrict__ sum_d, uint32_t n,
                                                   double *__restrict__ out) {
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -1020,17 +1021,35 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
     const uint32_t v = blockIdx.x * (blockDim.x / kWave) + wave;
     if (v >= n) return;
     double part = 0.0;
+    uint64_t moment2 = 0;  // squared distances to the neighbours, exact
+    int32_t vx = 0, vy = 0;
+    if (xy) {
+        vx = xy[2ull * v];
+        vy = xy[2ull * v + 1];
+    }
     uint32_t k = 0;
     RowDecoder dec;
     const uint64_t row_end = offsets[v + 1];
     for (uint64_t base = offsets[v]; base < row_end; base += kWave) {
         uint32_t cnt;
         const uint32_t ids = dec.chunk(bytes, base, row_end, cnt);
-        if (lane < cnt) part += 1.0 / (double)degrees[ids];
+        if (lane < cnt) {
+            part += 1.0 / (double)degrees[ids];
+            if (xy) {
+                const int64_t dx = (int64_t)xy[2ull * ids] - vx;
+                const int64_t dy = (int64_t)xy[2ull * ids + 1] - vy;
+                moment2 += (uint64_t)(dx * dx + dy * dy);
+            }
+        }
         k += cnt;
     }
 #pragma unroll
-    for (uint32_t mask = 1; mask < kWave; mask <<= 1) part += shfl_xor_f64(part, mask);
+    for (uint32_t mask = 1; mask < kWave; mask <<= 1) {
+        part += shfl_xor_f64(part, mask);
+        const uint32_t lo = shfl_xor((uint32_t)moment2, mask);
+        const uint32_t hi = shfl_xor((uint32_t)(moment2 >> 32), mask);
+        moment2 += ((uint64_t)hi << 32) | lo;
+    }
     if (lane != 0) return;
     const double nan = __builtin_nan("");
     const double N = comp_size ? (double)comp_size[v] : (double)n;  // exact N_v
@@ -1049,6 +1068,7 @@ __global__ __launch_bounds__(256) void vga_kernel(const uint8_t *__restrict__ by
     o[5 * (uint64_t)n] = N >= 2.0 ? log2((md + 2.0) / 3.0) : nan;  // integration [Tekl]
     o[6 * (uint64_t)n] = N >= 3.0 ? fmax(0.0, 1.0 - ra) : nan;     // integration [P-value]
     o[7 * (uint64_t)n] = md * (double)k;                        // point first moment
+    o[8 * (uint64_t)n] = xy ? (double)moment2 : nan;            // point second moment
 }
 
 // ---------------------------------------------------------------- local metrics
@@ -1520,11 +1540,11 @@ hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s
 }
 
 hipError_t launch_vga(const uint8_t *bytes, const uint64_t *offsets, const uint32_t *degrees,
-                      const uint32_t *comp_size, const double *sum_d, uint32_t n, double *out,
-                      hipStream_t stream) {
+                      const uint32_t *comp_size, const int32_t *xy, const double *sum_d,
+                      uint32_t n, double *out, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(vga_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, bytes, offsets,
-                       degrees, comp_size, sum_d, n, out);
+                       degrees, comp_size, xy, sum_d, n, out);
     return hipGetLastError();
 }
 

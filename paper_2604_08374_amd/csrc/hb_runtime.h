@@ -127,6 +127,7 @@ struct hb_graph {
     uint32_t *d_degrees = nullptr;   // n neighbour counts
     uint32_t *d_comp = nullptr;      // exact component sizes, or null (all n)
     uint32_t *d_hash_ids = nullptr;  // inserted ids, or null
+    int32_t *d_xy = nullptr;         // 2n cell coordinates, or null
     uint2 *d_runs = nullptr;         // run list of the rows, v joined in (run kernel)
     uint64_t *d_run_off = nullptr;   // n + 1 offsets into d_runs
     // run state, kept between runs (the counters live in a per-device workspace)

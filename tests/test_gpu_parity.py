@@ -223,3 +223,44 @@ def test_city_sampled_unlimited(hb):
     res = _sampled_check(hb, g, 10, 0, n_src=48, order=synth.hilbert_order(g))
     print(f"[parity] city unlimited: passes={res.passes} converged={res.converged}", flush=True)
     assert res.converged and res.passes >= 4
+
+
+def _has_edges(g, a, b):
+    """Whether b is in row a, for arrays of pairs: a binary search inside each row."""
+    lo = g.adj_offsets[a].astype(np.int64)
+    hi = g.adj_offsets[a + 1].astype(np.int64)
+    b = b.astype(np.uint32)
+    while True:
+        open_ = lo < hi
+        if not open_.any():
+            break
+        mid = (lo + hi) // 2
+        go_right = open_ & (g.adj_ids[np.minimum(mid, g.adj_ids.size - 1)] < b)
+        lo = np.where(go_right, mid + 1, lo)
+        hi = np.where(open_ & ~go_right, mid, hi)
+    found = lo < g.adj_offsets[a + 1].astype(np.int64)
+    found[found] = g.adj_ids[lo[found]] == b[found]
+    return found
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_city_generator_spot_check(hb):
+    """The city graph the GPU generator built against the CPU visibility rule: a million
+    seeded node pairs and the whole rows of sampled nodes."""
+    g = _city_graph()
+    assert abs(g.n - 236000) / 236000 < 0.02
+    rng = np.random.default_rng(2026)
+    a = rng.integers(0, g.n, 1_000_000)
+    b = rng.integers(0, g.n, 1_000_000)
+    keep = a != b
+    a, b = a[keep], b[keep]
+    vis = synth.visible_pairs(g, a, b).astype(bool)
+    got = _has_edges(g, a, b)
+    print(f"[synth] city pairs={a.size} visible={int(vis.sum())}", flush=True)
+    assert np.array_equal(got, vis)
+    for s in rng.integers(0, g.n, 8):
+        t = np.arange(g.n)
+        t = t[t != s]
+        want = t[synth.visible_pairs(g, np.full(t.size, s), t).astype(bool)]
+        assert np.array_equal(g.row(int(s)), want), s

@@ -43,7 +43,10 @@ def test_vga_metrics_match_oracle(hb, gname):
     else:
         g = synth.urban(0, device="gpu")
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
-    G = hb.graph_load(off, deg, data, comp_size=comp, order=synth.hilbert_order(g))
+    raster = gname in ("tiny", "rect90x70", "urban")  # cells with coordinates
+    G = hb.graph_load(off, deg, data, comp_size=comp, order=synth.hilbert_order(g),
+                      xy=g.xy if raster else None)
+    psm = oracle.point_second_moment(oracle.from_graph(g), g.xy) if raster else None
     for p, depth in ((10, 0), (8, 3)):
         r = G.run(p, depth, 1)
         print(f"[vga] {g.name} p={p} d={depth}", flush=True)
@@ -51,6 +54,11 @@ def test_vga_metrics_match_oracle(hb, gname):
         ref = oracle.vga_metrics(oracle.from_graph(g), r.sum_d, comp)
         _compare(got, ref, f"{g.name} p={p} d={depth}")
         np.testing.assert_allclose(got["mean_depth"], r.mean_depth, rtol=1e-15)
+        # the point second moment is an exact integer sum: equal bit for bit
+        if raster:
+            assert np.array_equal(got["point_second_moment"], psm), g.name
+        else:
+            assert np.isnan(got["point_second_moment"]).all(), g.name
     G.free()
 
 
