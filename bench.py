@@ -26,7 +26,9 @@ import numpy as np  # noqa: E402
 METRIC = "HLL edge-unions/s + % HBM roofline (236k cells, p=10); p50/p99 latency, mixed load"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # rocprofv3 counter summaries of the city workload (p = 10, depth 3), per union kernel
-COUNTERS_FILES = {"runs": os.path.join(ROOT, "profiles", "union_runs_kernel_city_p10_counters.txt"),
+COUNTERS_FILES = {"groups": os.path.join(ROOT, "profiles",
+                                         "union_groups_kernel_city_p10_counters.txt"),
+                  "runs": os.path.join(ROOT, "profiles", "union_runs_kernel_city_p10_counters.txt"),
                   "edges": os.path.join(ROOT, "profiles", "union_kernel_city_p10_counters.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_08374_amd", "csrc", "hb_kernels.hip")
 
@@ -60,17 +62,21 @@ def node_order(g, args):
 
 
 def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | None = None,
-                      bits: int = 8, n_runs: int = 0) -> int:
+                      bits: int = 8, n_runs: int = 0, kernel: str = "edges") -> int:
     """Bytes one union launch must move at minimum without reuse.
 
     Per gathered counter row: m bytes (2^p registers of `bits` bits) -- one row per
-    directed edge for the per-edge kernel, or `rows` table rows for the run kernel;
-    the adjacency it reads: the whole LEB128 stream for the per-edge kernel, the run
-    list (8 B per run) for the run kernel; per node: the offsets entry (8 B), its
-    own counter read and next[v] written (2m), and the FP64 state c_prev and sum_d
-    read and written (32 B).
+    directed edge for the per-edge kernel, `rows` table rows for the run kernel, or
+    the groups' distinct table rows for the grouped kernel; the adjacency it reads:
+    the whole LEB128 stream (per edge), the run list (8 B per run) or the group lists
+    (a 4-byte row index and a 1-byte mask per row, 8 B of offsets per group of 8
+    nodes); per node: the offsets entry (8 B; the grouped kernel's own counter is
+    among its rows), its own counter read and next[v] written (2m), and the FP64
+    state c_prev and sum_d read and written (32 B).
     """
     m = (1 << p) * bits // 8
+    if kernel == "groups":
+        return rows * (m + 5) + 8 * ((n + 7) // 8 + 1) + n * (m + 32)
     gathered = n_edges if rows is None else rows
     adjacency = n_bytes if rows is None else 8 * n_runs
     return gathered * m + adjacency + 8 * (n + 1) + n * (2 * m + 32)
@@ -116,7 +122,7 @@ def measure_ceilings(hb, p, n, rows, lanes, nb, bits, kernel):
     1 GiB table that misses L2), and a plain 4 GiB device copy."""
     out = {}
     m = (1 << p) * bits // 8
-    if bits == 8 and p <= 12 and kernel == "runs":
+    if bits == 8 and p <= 12 and kernel in ("runs", "groups"):
         rpn = max(1, round(rows / n))
         gathered = n * rpn * m
         for key, trows, with_max in (("l2_gather_gbs", (2 << 20) // m, True),
@@ -511,7 +517,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "edges", "runs"],
+    ap.add_argument("--kernel", default="auto", choices=["auto", "edges", "runs", "groups"],
                     help="union kernel: per edge, per run from a range-max table, or the "
                          "library's choice")
     ap.add_argument("--table-levels", type=int, default=0)
@@ -583,15 +589,18 @@ def main():
     avg_launch_s = iter_ms / 1e3 / passes
     kernel = results[-1].union_kernel
     levels = results[-1].table_levels
-    rows = stats["table_rows"][levels] if kernel == "runs" else E
+    tabled = kernel in ("runs", "groups")
+    rows = (stats["group_rows"] if kernel == "groups" else
+            stats["table_rows"][levels] if kernel == "runs" else E)
     bits = results[-1].register_bits
     m = (1 << p) * bits // 8
-    per_launch = algorithmic_bytes(n, E, data.size, p, rows if kernel == "runs" else None, bits,
-                                   stats["n_runs"])
+    per_launch = algorithmic_bytes(n, E, data.size, p, rows if tabled else None, bits,
+                                   stats["n_runs"], kernel)
     achieved = per_launch / avg_launch_s / 1e9
     lanes, nb = results[-1].lanes_per_node, results[-1].nodes_per_block
-    kname = (f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs"
-             else f"union_kernel<{p},{lanes},{bits}>")
+    kname = (f"union_groups_kernel<{p},64,{bits}>" if kernel == "groups" else
+             f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs" else
+             f"union_kernel<{p},{lanes},{bits}>")
     counters = kernel_traffic(args.config, p, depth, kernel, kname, args.order)
     traffic = (counters.get("fabric_bytes_per_launch", counters.get("hbm_bytes_per_launch"))
                if counters else None)
@@ -608,11 +617,13 @@ def main():
         "metric": METRIC,
         "value": value,
         "unit": "edge-unions/s",
-        "value_kind": ("edge-union equivalent: passes x directed edges per second; the run kernel "
+        "value_kind": ("edge-union equivalent: passes x directed edges per second; the kernel "
                        "covers each run of consecutive neighbour ids with at most two range-max "
-                       "table rows, so it gathers table_rows_per_s rows, not one per edge"
-                       if kernel == "runs" else "one gathered counter per directed edge and pass"),
-        "table_rows_per_s": rows / avg_launch_s if kernel == "runs" else None,
+                       "table rows" + (", loaded once per group of 8 nodes that share them"
+                                       if kernel == "groups" else "") +
+                       ", so it gathers table_rows_per_s rows, not one per edge"
+                       if tabled else "one gathered counter per directed edge and pass"),
+        "table_rows_per_s": rows / avg_launch_s if tabled else None,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -686,7 +697,7 @@ def main():
             "valu_issue_peak_per_s": peak_issue,
             "valu_issue_frac": valu / peak_issue / avg_launch_s,
         }
-    if kernel == "runs" and not args.no_extras:
+    if tabled and not args.no_extras:
         # the per-edge kernel does the paper's per-edge work (Eq. 2 as written): one
         # launch of it on the same graph, against the HBM peak on the Eq. 2 bytes
         log("per-edge kernel: one union launch on the same graph ...")
@@ -709,7 +720,7 @@ def main():
             "frac": e_traffic / (e_ms / 1e3) / 1e9 / HBM_PEAK_GBS if e_traffic else None,
         }
         log(f"per-edge kernel: {e_ms:.1f} ms, {e_bytes / (e_ms / 1e3) / 1e9:.0f} GB/s of Eq. 2 bytes")
-    if kernel == "runs":
+    if tabled:
         tb = table_bytes(n, p, levels, bits)
         t_s = table_ms / 1e3 / passes
         line["table_build"] = {"bytes_per_step": tb, "avg_ms": t_s * 1e3,

@@ -118,12 +118,17 @@ typedef struct {
 } hb_result;
 
 /* Which union kernel a run uses. */
-#define HB_UNION_AUTO 0  /* the run kernel when p <= 12, its table fits and the graph has
-                            its run list, else per edge */
+#define HB_UNION_AUTO 0  /* the grouped kernel for p = 10 with 8-bit registers when the graph
+                            has its group lists, else the run kernel when p <= 12, its table
+                            fits and the graph has its run list, else per edge (blocking runs;
+                            the batched and served forms use the run or per-edge kernel) */
 #define HB_UNION_EDGES 1 /* gather every neighbour's counter (Eq. 2 as written), decoding the
                             LEB128 row in the kernel */
 #define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table,
                             reading the run list decoded at load */
+#define HB_UNION_GROUPS 3 /* the run kernel's table rows, merged at load over groups of 8
+                             consecutive nodes of the processing order: each distinct row is
+                             loaded once per group (p = 10, 8-bit registers) */
 
 /*
  * Run options; an all-zero struct (or NULL) selects the defaults.
@@ -330,6 +335,9 @@ typedef struct {
     uint64_t local_run_reads;  /* sum over rows w of deg(w) x the maximal runs of w
                                   (v not joined in): the neighbour runs that
                                   hb_local_metrics reads, 8 bytes each */
+    uint64_t group_rows;       /* rows one step of the grouped kernel loads (0 when the
+                                  graph has no group lists) */
+    uint32_t group_levels;     /* table depth the group lists were built for */
 } hb_graph_stats_t;
 
 hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out);

@@ -85,7 +85,8 @@ class _ServerStats(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("n_bytes", ctypes.c_uint64),
                 ("n_runs", ctypes.c_uint64), ("table_rows", ctypes.c_uint64 * 25),
-                ("local_run_reads", ctypes.c_uint64)]
+                ("local_run_reads", ctypes.c_uint64), ("group_rows", ctypes.c_uint64),
+                ("group_levels", ctypes.c_uint32)]
 
 
 class _RunOpts(ctypes.Structure):
@@ -160,8 +161,8 @@ class _Job(ctypes.Structure):
                 ("hash_seed", ctypes.c_uint64)]
 
 
-UNION_AUTO, UNION_EDGES, UNION_RUNS = 0, 1, 2
-_KERNELS = {"auto": UNION_AUTO, "edges": UNION_EDGES, "runs": UNION_RUNS}
+UNION_AUTO, UNION_EDGES, UNION_RUNS, UNION_GROUPS = 0, 1, 2, 3
+_KERNELS = {"auto": UNION_AUTO, "edges": UNION_EDGES, "runs": UNION_RUNS, "groups": UNION_GROUPS}
 
 
 def lib_path() -> str:
@@ -389,7 +390,8 @@ class Graph:
         _check(_lib().hb_graph_stats(self._h, ctypes.byref(st)))
         return {"n": st.n, "n_edges": st.n_edges, "n_bytes": st.n_bytes, "n_runs": st.n_runs,
                 "table_rows": [int(x) for x in st.table_rows],
-                "local_run_reads": int(st.local_run_reads)}
+                "local_run_reads": int(st.local_run_reads), "group_rows": int(st.group_rows),
+                "group_levels": int(st.group_levels)}
 
     def vga_metrics(self, sum_d) -> dict:
         """hb_vga_metrics: the VGA metrics of every node from a run's sum_d (Sec. 3.3)."""
@@ -491,7 +493,8 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20) -> float:
 
 def _to_result(r: _Result, arrays) -> Result:
     reach, sum_d, md, regs = arrays
-    name = {UNION_EDGES: "edges", UNION_RUNS: "runs"}.get(int(r.union_kernel), "?")
+    name = {UNION_EDGES: "edges", UNION_RUNS: "runs", UNION_GROUPS: "groups"}.get(
+        int(r.union_kernel), "?")
     return Result(reach, sum_d, md, regs, int(r.passes), bool(r.converged),
                   int(r.productive_iters), float(r.c0),
                   int(r.edge_unions), float(r.init_ms), float(r.iter_ms), float(r.table_ms),

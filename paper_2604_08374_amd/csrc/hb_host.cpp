@@ -149,7 +149,8 @@ void hbr::graph_release(hb_graph *g) {
     for (void *p : {(void *)g->d_bytes, (void *)g->d_offsets, (void *)g->d_cprev,
                     (void *)g->d_order, (void *)g->d_hash_ids, (void *)g->d_degrees,
                     (void *)g->d_comp, (void *)g->d_runs, (void *)g->d_run_off,
-                    (void *)g->d_sumd, (void *)g->d_flags, (void *)g->d_xy})
+                    (void *)g->d_sumd, (void *)g->d_flags, (void *)g->d_xy,
+                    (void *)g->d_grp_rows, (void *)g->d_grp_mask, (void *)g->d_grp_off})
         dfree(p);
     if (g->h_flags) (void)hipHostFree(g->h_flags);
     for (auto &e : g->ev_init)
@@ -205,6 +206,117 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
         *runs = nullptr;
     }
     return e;
+}
+
+// Row lists of the grouped union kernel: for every group of group_size()
+// consecutive nodes of the processing order, the distinct table rows (k n + i,
+// for tables of depth `levels`) that cover the runs of its nodes, each node's
+// own counter row included, with a mask of the nodes that need each row.
+// Built on the host from the device run list; false when memory is short.
+bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
+    const uint32_t n = g->n;
+    const uint32_t W = hbk::group_size();
+    const uint64_t total = g->runs.runs;
+    if ((uint64_t)(levels + 1) * n >= (1ull << 32)) return false;  // row indices are 32-bit
+    std::vector<uint64_t> roff((size_t)n + 1);
+    std::vector<uint2> runs(std::max<uint64_t>(total, 1));
+    if (hipMemcpy(roff.data(), g->d_run_off, sizeof(uint64_t) * (n + 1ull),
+                  hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(runs.data(), g->d_runs, sizeof(uint2) * total, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return false;
+    const uint32_t n_groups = (n + W - 1) / W;
+    const uint64_t top = 1ull << levels;
+    // per thread: the entries (row << 8 | mask) of a contiguous range of groups
+    const unsigned nt = (unsigned)std::min<uint64_t>(host_threads(), std::max<uint32_t>(n_groups / 64, 1));
+    std::vector<std::vector<uint64_t>> part(nt);
+    std::vector<uint64_t> count(n_groups, 0);
+    std::vector<std::thread> th;
+    for (unsigned ti = 0; ti < nt; ++ti) {
+        th.emplace_back([&, ti] {
+            const uint32_t g0 = (uint32_t)((uint64_t)n_groups * ti / nt);
+            const uint32_t g1 = (uint32_t)((uint64_t)n_groups * (ti + 1) / nt);
+            std::vector<uint64_t> tmp;
+            for (uint32_t gr = g0; gr < g1; ++gr) {
+                tmp.clear();
+                for (uint32_t w = 0; w < W; ++w) {
+                    const uint64_t i = (uint64_t)gr * W + w;
+                    if (i >= n) break;
+                    const uint32_t v = order ? order[i] : (uint32_t)i;
+                    const uint64_t bit = 1ull << w;
+                    tmp.push_back(((uint64_t)v << 8) | bit);  // the node's own counter
+                    for (uint64_t e = roff[v]; e < roff[v + 1]; ++e) {
+                        const uint64_t x = runs[e].x, y = runs[e].y, r = y - x + 1;
+                        if (r <= top) {
+                            const uint32_t k = floor_log2((uint32_t)r);
+                            tmp.push_back(((k * (uint64_t)n + x) << 8) | bit);
+                            if (r != (1ull << k))
+                                tmp.push_back(((k * (uint64_t)n + y - (1ull << k) + 1) << 8) | bit);
+                            continue;
+                        }
+                        for (uint64_t j = x;; j += top) {
+                            const uint64_t at = (j + top - 1 < y) ? j : y - top + 1;
+                            tmp.push_back(((levels * (uint64_t)n + at) << 8) | bit);
+                            if (at != j || j + top - 1 == y) break;
+                        }
+                    }
+                }
+                // position-major (then level): the wave walks the table along the
+                // raster, the way its neighbours' waves do (10.0 against 10.9 ms
+                // per city launch for level-major order)
+                std::sort(tmp.begin(), tmp.end(), [n](uint64_t a, uint64_t b) {
+                    const uint64_t ia = (a >> 8) % n, ib = (b >> 8) % n;
+                    return ia != ib ? ia < ib : a < b;
+                });
+                uint64_t c = 0;
+                for (size_t a = 0; a < tmp.size();) {
+                    uint64_t row = tmp[a] >> 8, mask = 0;
+                    while (a < tmp.size() && (tmp[a] >> 8) == row) mask |= tmp[a++] & 0xFFu;
+                    part[ti].push_back((row << 8) | mask);
+                    ++c;
+                }
+                count[gr] = c;
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    std::vector<uint64_t> goff((size_t)n_groups + 1, 0);
+    for (uint32_t gr = 0; gr < n_groups; ++gr) goff[gr + 1] = goff[gr] + count[gr];
+    const uint64_t entries = goff[n_groups];
+    std::vector<uint32_t> rows(std::max<uint64_t>(entries, 1));
+    std::vector<uint8_t> masks(std::max<uint64_t>(entries, 1));
+    uint64_t at = 0;
+    for (const auto &pv : part)
+        for (uint64_t e : pv) {
+            rows[at] = (uint32_t)(e >> 8);
+            masks[at] = (uint8_t)(e & 0xFFu);
+            ++at;
+        }
+    hipError_t e = dmalloc((void **)&g->d_grp_rows, sizeof(uint32_t) * rows.size());
+    if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_mask, masks.size());
+    if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_off, sizeof(uint64_t) * goff.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(g->d_grp_rows, rows.data(), sizeof(uint32_t) * rows.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(g->d_grp_mask, masks.data(), masks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(g->d_grp_off, goff.data(), sizeof(uint64_t) * goff.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(g->d_grp_rows);
+        dfree(g->d_grp_mask);
+        dfree(g->d_grp_off);
+        g->d_grp_rows = nullptr;
+        g->d_grp_mask = nullptr;
+        g->d_grp_off = nullptr;
+        return false;
+    }
+    g->grp_levels = levels;
+    g->grp_entries = entries;
+    g->dev_bytes += 5 * rows.size() + 8 * goff.size();
+    return true;
 }
 
 hb_status have_device() {
@@ -462,6 +574,8 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
         if (csr->xy) b += 8 * n;
         g->dev_bytes = b;
     }
+    // the grouped kernel's row lists, for tables of the default depth
+    if (g->d_runs) (void)build_group_lists(g, std::min(kDefaultLevels, floor_log2(g->n)), csr->order);
     *out = g;
     return HB_OK;
 }
@@ -492,6 +606,8 @@ hb_status hb_graph_stats(const hb_graph *g, hb_graph_stats_t *out) {
     out->n_runs = g->runs.runs;
     for (int k = 0; k <= kMaxLevels; ++k) out->table_rows[k] = g->runs.lookups[k];
     out->local_run_reads = g->runs.local_reads;
+    out->group_rows = g->grp_entries;
+    out->group_levels = g->grp_levels;
     return HB_OK;
 }
 
@@ -525,9 +641,12 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     if (p < HB_P_MIN || p > HB_P_MAX) return fail(HB_EINVAL, "p = %u outside [4, 16]", p);
     const hb_run_opts o = opts ? *opts : hb_run_opts{};
     const hb_options lib = options();
-    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
+    if (o.union_kernel > HB_UNION_GROUPS)
+        return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
+    if (o.union_kernel == HB_UNION_GROUPS && (p != 10 || (o.register_bits && o.register_bits != 8)))
+        return fail(HB_EINVAL, "the grouped kernel supports p = 10 with 8-bit registers");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     const bool depth_only = lib.stop_rule == HB_STOP_DEPTH;
     if (depth_only && depth_limit == 0)
@@ -545,7 +664,14 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     // kernel choice and table depth
     uint32_t levels = o.table_levels ? o.table_levels : kDefaultLevels;
     levels = std::min(levels, floor_log2(n));
-    bool runs = (o.union_kernel == HB_UNION_RUNS) || (o.union_kernel == HB_UNION_AUTO && p <= 12);
+    const bool have_groups = g->d_grp_rows && levels == g->grp_levels;
+    if (o.union_kernel == HB_UNION_GROUPS && !have_groups)
+        return fail(HB_EINVAL, "the graph has no group lists for table depth %u", levels);
+    // the grouped kernel is the default where it is built (p = 10, 8-bit registers)
+    bool groups = o.union_kernel == HB_UNION_GROUPS ||
+                  (o.union_kernel == HB_UNION_AUTO && p == 10 && bits == 8 && have_groups);
+    bool runs = groups || (o.union_kernel == HB_UNION_RUNS) ||
+                (o.union_kernel == HB_UNION_AUTO && p <= 12);
     if (runs && (uint64_t)(levels + 1) * n >= (1ull << 32)) {
         if (o.union_kernel == HB_UNION_RUNS)
             return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
@@ -585,7 +711,10 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
         if (st != HB_OK) return st;
         ws = static_cast<uint8_t *>(hold.p);
     }
-    if (!runs) levels = 0;
+    if (!runs) {
+        levels = 0;
+        groups = false;  // the tables did not fit: per edge
+    }
     uint8_t *const bufs[2] = {ws, ws + buf_bytes(runs)};  // step t reads bufs[(t-1)&1]
     hipStream_t s = lib.stream ? static_cast<hipStream_t>(lib.stream) : g->stream;
     const hbk::Sched init_sched = hbk::default_sched((int)p, bits);
@@ -598,7 +727,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
         tune_key(p, bits, runs, false, n, runs ? g->runs.lookups[levels] : g->n_edges);
     if (fixed.lanes) {
         sched = fixed;
-    } else if (o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
+    } else if (!groups && o.tune != HB_TUNE_OFF && !tune_get(key, &sched)) {
         sched = union_default;
         if (o.tune == HB_TUNE_MEASURE && !no_alloc) {
             // step 1 of this very run, once per candidate; the state is
@@ -649,7 +778,11 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
             HB_HIP(hipEventRecord(ev[0], s));
             if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, skip, s));
             HB_HIP(hipEventRecord(ev[1], s));
-            if (runs)
+            if (groups)
+                HB_HIP(hbk::launch_union_groups((int)p, g->d_grp_rows, g->d_grp_mask,
+                                                g->d_grp_off, cur, next, g->d_cprev, g->d_sumd,
+                                                g->d_flags + t, n, t, g->d_order, thr, skip, s));
+            else if (runs)
                 HB_HIP(hbk::launch_union_runs((int)p, sched, g->d_runs, g->d_run_off, cur, levels,
                                               next, g->d_cprev, g->d_sumd, g->d_flags + t, n, t,
                                               g->d_order, thr, skip, s));
@@ -710,10 +843,10 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     out->iter_ms = iter_ms;
     out->table_ms = table_ms;
     out->run_ms = run_ms;
-    out->union_kernel = runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+    out->union_kernel = groups ? HB_UNION_GROUPS : (runs ? HB_UNION_RUNS : HB_UNION_EDGES);
     out->table_levels = runs ? levels : 0u;
-    out->lanes_per_node = sched.lanes;
-    out->nodes_per_block = sched.nodes_per_block;
+    out->lanes_per_node = groups ? 64u : sched.lanes;
+    out->nodes_per_block = groups ? hbk::group_size() * 4u : sched.nodes_per_block;
     out->register_bits = bits;
     out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;

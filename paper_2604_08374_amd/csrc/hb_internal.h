@@ -106,6 +106,17 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
                              const uint32_t *order, double thr, const uint32_t *skip,
                              hipStream_t stream);
 
+// The same step from per-group row lists (p = 10, 8-bit registers): group g
+// holds nodes g * group_size() .. of the processing order, and its rows
+// grp_rows[grp_off[g] ..] (table row indices k n + i) with masks of the group's
+// nodes that need them (a node's own row included).
+uint32_t group_size();
+hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint8_t *grp_mask,
+                               const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
+                               double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
+                               uint32_t t, const uint32_t *order, double thr,
+                               const uint32_t *skip, hipStream_t stream);
+
 // Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
 // i <= n - 2^k, rows of m bytes (m a multiple of 16) of `bits`-bit registers,
 // T[k] at tbl + k n m.  Requires 2^levels <= n.  skip as for launch_union.

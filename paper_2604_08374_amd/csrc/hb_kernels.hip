@@ -794,6 +794,83 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
                        thr, s_queue[threadIdx.x / kWave]);
 }
 
+// ---------------------------------------------------------------- union step, per group
+// Nodes that are processed together see almost the same cells, so their run
+// lists hold many identical table rows.  The loader merges the rows of every
+// group of kGroup consecutive nodes of the processing order into one list of
+// distinct rows, each with a bit mask of the group's nodes that need it (their
+// own counters included).  One wave handles a group: it holds the registers of
+// all kGroup nodes, 16 bytes of each per lane, loads every listed row once for
+// the whole wave and takes its max into the accumulators of the nodes in its
+// mask.  The rows loaded per step drop by the rows the nodes share.  p = 10,
+// 8-bit registers: a counter is one wave load.
+constexpr uint32_t kGroup = 8;
+constexpr int kGroupLoads = 8;  // rows in flight per wave
+constexpr uint32_t kGroupLds = 0;  // LDS reserved per workgroup (limits workgroups per CU)
+
+template <class C>
+__global__ __launch_bounds__(256) void union_groups_kernel(
+    const uint32_t *__restrict__ grp_rows, const uint8_t *__restrict__ grp_mask,
+    const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
+    uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
+    uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
+    double thr, const uint32_t *__restrict__ skip) {
+    static_assert(C::G == 1 && C::RPL == 1 && C::WAVES == 1, "one 16-byte slot per lane");
+    if (skip && *skip == 0u) return;  // the previous step stopped the run
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const uint32_t grp = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + wave;
+    const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
+    if (grp >= n_groups) return;
+    const uint32_t lane = lane_id();
+    const uint32_t off = lane * 16u;
+    Max4 acc[kGroup][4];
+#pragma unroll
+    for (uint32_t w = 0; w < kGroup; ++w)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[w][q].init(0u);
+    const uint64_t beg = grp_off[grp], end = grp_off[grp + 1];
+    for (uint64_t base = beg; base < end; base += kWave) {
+        // 64 entries at a time, one per lane, broadcast with readlane
+        const uint32_t cnt = (uint32_t)((end - base < kWave) ? end - base : kWave);
+        const uint32_t e_row = lane < cnt ? grp_rows[base + lane] : 0u;
+        const uint32_t e_mask = lane < cnt ? (uint32_t)grp_mask[base + lane] : 0u;
+        for (uint32_t j = 0; j < cnt; j += kGroupLoads) {
+            uint4 x[kGroupLoads];
+            uint32_t mk[kGroupLoads];
+#pragma unroll
+            for (int u = 0; u < kGroupLoads; ++u) {
+                // past the end: row j again with an empty mask
+                const uint32_t l = j + (uint32_t)u < cnt ? j + (uint32_t)u : j;
+                mk[u] = j + (uint32_t)u < cnt ? readlane(e_mask, l) : 0u;
+                x[u] = *reinterpret_cast<const uint4 *>(tbl + (uint64_t)readlane(e_row, l) * C::M +
+                                                        off);
+            }
+#pragma unroll
+            for (int u = 0; u < kGroupLoads; ++u) {
+                const uint32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                for (uint32_t w = 0; w < kGroup; ++w)
+                    if (mk[u] & (1u << w))
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            acc[w][q].hi = pk_max_u16(acc[w][q].hi, xs[q]);
+                            acc[w][q].lo = pk_max_u16(acc[w][q].lo, xs[q] << 8);
+                        }
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t w = 0; w < kGroup; ++w) {
+        const uint32_t i = grp * kGroup + w;
+        if (i >= n) break;
+        const uint32_t v = order ? order[i] : i;
+        NodeAcc<C> a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.m[0][q] = acc[w][q];
+        finish_node<C>(a, v, 0u, next, c_prev, sum_d, flag_t, t, thr);
+    }
+}
+
 // ---------------------------------------------------------------- gather ceiling
 // The run kernel's gather loop without its queue or its run list: every node of
 // the launch gathers `rows` counter rows of a small table (table_rows rows, a
@@ -882,6 +959,63 @@ __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16; i += stride) {
         const uint4 a = prev[i], b = prev[i + half16];
         out[i] = bits == 4u ? max16<Max8>(a, b) : max16<Max4>(a, b);
+    }
+}
+
+// All levels 1..levels (<= kFusedLevels) of the table in one launch.  A
+// workgroup holds rows i0 .. i0 + kTblRows + 2^levels - 2 of a 64-byte column
+// slice of cur in LDS (the output rows plus the span the largest block reaches
+// past them), builds each level in place from the one before, and writes the
+// level's rows i0 .. i0 + kTblRows - 1 that exist (i <= n - 2^k).  Level 0 is
+// read about 1.5 times instead of twice per level, and no level is read back.
+constexpr uint32_t kFusedLevels = 8;
+constexpr uint32_t kTblRows = 512;                              // output rows per workgroup
+constexpr uint32_t kTblCols = 4;                                // 16-byte columns per workgroup
+constexpr uint32_t kTblSpan = kTblRows + (1u << kFusedLevels) - 1u;
+constexpr uint32_t kTblPer = (kTblSpan * kTblCols + 255u) / 256u;  // LDS chunks per thread
+
+__global__ __launch_bounds__(256) void table_fused_kernel(uint8_t *__restrict__ tbl, uint32_t n,
+                                                          uint32_t m, uint32_t levels,
+                                                          uint32_t bits,
+                                                          const uint32_t *__restrict__ skip) {
+    __shared__ uint4 lds[kTblSpan * kTblCols];
+    if (skip && *skip == 0u) return;  // the previous step stopped the run
+    const uint32_t slices = m / (16u * kTblCols);
+    const uint32_t tile = blockIdx.x / slices, slice = blockIdx.x % slices;
+    const uint64_t i0 = (uint64_t)tile * kTblRows;
+    const uint64_t col = (uint64_t)slice * kTblCols * 16u;
+    const uint64_t level_bytes = (uint64_t)n * m;
+    const uint32_t span = kTblRows + (1u << levels) - 1u;
+    for (uint32_t c = threadIdx.x; c < span * kTblCols; c += blockDim.x) {
+        const uint64_t i = i0 + c / kTblCols;
+        if (i < n)
+            lds[c] = *reinterpret_cast<const uint4 *>(tbl + i * m + col + (c % kTblCols) * 16u);
+    }
+    __syncthreads();
+    for (uint32_t k = 1; k <= levels; ++k) {
+        // level k is exact in LDS rows 0 .. span - 2^k (their blocks end inside the span)
+        const uint32_t len = (span - (1u << k) + 1u) * kTblCols;
+        const uint32_t half = (1u << (k - 1)) * kTblCols;
+        uint4 val[kTblPer];
+#pragma unroll
+        for (uint32_t t = 0; t < kTblPer; ++t) {
+            const uint32_t c = threadIdx.x + t * 256u;
+            if (c < len) val[t] = bits == 4u ? max16<Max8>(lds[c], lds[c + half])
+                                              : max16<Max4>(lds[c], lds[c + half]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t t = 0; t < kTblPer; ++t) {
+            const uint32_t c = threadIdx.x + t * 256u;
+            if (c < len) lds[c] = val[t];
+        }
+        __syncthreads();
+        uint8_t *out = tbl + (uint64_t)k * level_bytes;
+        for (uint32_t c = threadIdx.x; c < kTblRows * kTblCols; c += blockDim.x) {
+            const uint64_t i = i0 + c / kTblCols;
+            if (i + (1ull << k) <= n)
+                *reinterpret_cast<uint4 *>(out + i * m + col + (c % kTblCols) * 16u) = lds[c];
+        }
     }
 }
 
@@ -1456,6 +1590,22 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 #undef HB_X
 }
 
+uint32_t group_size() { return kGroup; }
+
+hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint8_t *grp_mask,
+                               const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
+                               double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
+                               uint32_t t, const uint32_t *order, double thr,
+                               const uint32_t *skip, hipStream_t stream) {
+    if (p != 10) return hipErrorInvalidValue;
+    const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
+    const uint32_t blocks = (n_groups + 3u) / 4u;
+    hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks), dim3(256), kGroupLds, stream,
+                       grp_rows, grp_mask, grp_off, tbl, next, c_prev, sum_d, flag_t, n, t, order,
+                       thr, skip);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32_t table_rows,
                                uint32_t rows, uint32_t *out, uint32_t n, uint32_t with_max,
                                hipStream_t stream) {
@@ -1470,6 +1620,14 @@ hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32
 
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
                         const uint32_t *skip, hipStream_t stream) {
+    if (levels == 0) return hipSuccess;
+    if (levels <= kFusedLevels && m % (16u * kTblCols) == 0) {
+        const uint64_t tiles = ((uint64_t)n + kTblRows - 1) / kTblRows;
+        const uint64_t blocks = tiles * (m / (16u * kTblCols));
+        hipLaunchKernelGGL(table_fused_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, tbl,
+                           n, m, levels, bits, skip);
+        return hipGetLastError();
+    }
     const uint64_t level_bytes = (uint64_t)n * m;
     for (uint32_t k = 1; k <= levels; ++k) {
         const uint64_t rows = (uint64_t)n - (1ull << k) + 1ull;

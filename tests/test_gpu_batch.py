@@ -18,7 +18,8 @@ def _load(hb, g):
 def _same(a, b, what):
     assert a.passes == b.passes, (what, a.passes, b.passes)
     assert a.converged == b.converged, what
-    assert a.union_kernel == b.union_kernel, what
+    # kernels may differ (blocking runs at p = 10 default to the grouped kernel); every
+    # kernel gives the same registers and sums
     assert np.array_equal(a.registers, b.registers), what
     assert np.array_equal(a.reach, b.reach), what
     assert np.array_equal(a.sum_d, b.sum_d), what

@@ -72,7 +72,7 @@ def test_budget_caps_all_device_memory(hb, reset_options):
     hb.set_options(hbm_budget=budget)
     G = _load(hb, g)
     r = G.run(10, 3, 1, registers=True)  # tables 2 x 9 x n KB: about 38 MiB, within it
-    assert r.union_kernel == "runs"
+    assert r.union_kernel == "groups"  # the p = 10 default: tables within the budget
     assert_matches(hb, r, ref(g, 10, 3, 1), "within the budget")
     st = hb.memory_stats(0)
     assert st["budget_bytes"] == budget and st["held_bytes"] <= budget
@@ -197,7 +197,7 @@ def test_tune_seed_sets_the_pick(hb, reset_options):
     g = synth.grid_graph(4, 60, 50)
     G = _load(hb, g)
     hb.tune_clear()
-    r0 = G.run(10, 2, 0, tune="measure")
+    r0 = G.run(10, 2, 0, tune="measure", kernel="runs")
     picks = [e for e in hb.tune_cache() if e["p"] == 10 and e["batched"] == 0]
     assert len(picks) == 1
     other = [(L, nb) for L, nb in ((64, 4), (32, 2), (16, 1))
@@ -205,7 +205,7 @@ def test_tune_seed_sets_the_pick(hb, reset_options):
     seeded = dict(picks[0], lanes_per_node=other[0], nodes_per_block=other[1])
     hb.tune_clear()
     hb.set_options(tune_seed=[seeded])
-    r = G.run(10, 2, 0, registers=True, tune="cached")
+    r = G.run(10, 2, 0, registers=True, tune="cached", kernel="runs")
     assert (r.lanes_per_node, r.nodes_per_block) == other
     assert_matches(hb, r, ref(g, 10, 2, 0), "seeded pick")
     assert r.passes == r0.passes

@@ -32,13 +32,15 @@ def _compare(res, ref, what):
     np.testing.assert_allclose(res.sum_d, ref.sum_d, rtol=RTOL, atol=1e-9, err_msg=what)
 
 
-def _check(hb, g, p, depth, seed=0, kernels=("edges", "runs"), table_levels=0):
+def _check(hb, g, p, depth, seed=0, kernels=("edges", "runs", "groups"), table_levels=0):
     """Every union kernel that supports p against the oracle."""
     ref = oracle.hyperball(oracle.from_graph(g), p, depth, seed)
     with _load(hb, g) as G:
         for kernel in kernels:
             if kernel == "runs" and p > 12:
                 continue
+            if kernel == "groups" and (p != 10 or table_levels not in (0, 8)):
+                continue  # built for p = 10 and the default table depth
             print(f"[parity] {g.name} n={g.n} E={g.n_edges} p={p} depth={depth} seed={seed} "
                   f"kernel={kernel} K={table_levels}", flush=True)
             res = G.run(p, depth, seed, registers=True, kernel=kernel, table_levels=table_levels)
@@ -135,7 +137,7 @@ def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None, reg4=False):
     assert np.array_equal(csr.bytes, data)
     results = {}
     with hb.graph_load(off, deg, data, order=order) as G:
-        for kernel in ("runs", "edges"):
+        for kernel in ("runs", "edges") + (("groups",) if p == 10 else ()):
             results[kernel] = G.run(p, depth, seed, registers=True, kernel=kernel)
             print(f"[parity] {kernel}: passes={results[kernel].passes} "
                   f"iter_ms={results[kernel].iter_ms:.1f}", flush=True)
@@ -148,9 +150,10 @@ def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None, reg4=False):
     res = results["runs"]
     T = res.passes
     assert depth == 0 or T <= depth
-    assert results["edges"].passes == T
-    assert np.array_equal(results["edges"].registers, res.registers)
-    assert np.array_equal(results["edges"].sum_d, res.sum_d)
+    for other in [k for k in results if k != "runs"]:
+        assert results[other].passes == T, other
+        assert np.array_equal(results[other].registers, res.registers), other
+        assert np.array_equal(results[other].sum_d, res.sum_d), other
     src = np.sort(np.random.default_rng(99).choice(g.n, n_src, replace=False))
     src = np.unique(np.concatenate([src, [0, g.n - 1, int(np.argmax(deg)), int(np.argmin(deg))]]))
     regs, reach, sum_d, _ = oracle.sampled_hyperball(csr, src, T, p, seed)
