@@ -83,9 +83,17 @@ def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | No
 
 
 def table_bytes(n: int, p: int, levels: int, bits: int = 8) -> int:
-    """Range-max table build per step: level k reads two rows and writes one per i."""
+    """Range-max table build per step.  Up to 8 levels of rows of a multiple of 64
+    bytes are built in one launch from LDS tiles of 512 rows plus 2^K - 1 rows past
+    them: level 0 is read once per tile (767/512 of it at K = 8) and each level is
+    written once; otherwise each level k reads two rows and writes one per i."""
     m = (1 << p) * bits // 8
-    return sum(3 * (n - (1 << k) + 1) * m for k in range(1, levels + 1))
+    writes = sum((n - (1 << k) + 1) * m for k in range(1, levels + 1))
+    if 1 <= levels <= 8 and m % 64 == 0:
+        span = 512 + (1 << levels) - 1
+        reads = sum(min(i0 + span, n) - i0 for i0 in range(0, n, 512))
+        return writes + reads * m
+    return 3 * writes
 
 
 def kernel_traffic(config: str, p: int, depth: int, kind: str, kernel: str, order: str):
@@ -123,6 +131,8 @@ def measure_ceilings(hb, p, n, rows, lanes, nb, bits, kernel):
     out = {}
     m = (1 << p) * bits // 8
     if bits == 8 and p <= 12 and kernel in ("runs", "groups"):
+        if kernel == "groups":
+            lanes, nb = 64, 4  # a row per wave load, as the grouped kernel loads them
         rpn = max(1, round(rows / n))
         gathered = n * rpn * m
         for key, trows, with_max in (("l2_gather_gbs", (2 << 20) // m, True),
@@ -610,9 +620,13 @@ def main():
     # rate the same loop reaches when every row misses L2
     l2_frac = achieved / ceil["l2_gather_gbs"] if ceil.get("l2_gather_gbs") else None
     fab_gbs = traffic / avg_launch_s / 1e9 if traffic else None
-    fab_frac = fab_gbs / ceil["fabric_gather_gbs"] if fab_gbs and ceil.get("fabric_gather_gbs") \
-        else None
+    # the fabric ceiling: the measured miss-path gather rate, else the published HBM peak
+    fab_peak = ceil.get("fabric_gather_gbs") or HBM_PEAK_GBS
+    fab_frac = fab_gbs / fab_peak if fab_gbs else None
     use_l2 = l2_frac is not None and (fab_frac is None or l2_frac >= fab_frac)
+    if l2_frac is None and fab_frac is None:
+        # no gather probe for this kernel and no counters: its own bytes against HBM
+        fab_gbs, fab_frac = achieved, achieved / HBM_PEAK_GBS
     line = {
         "metric": METRIC,
         "value": value,
@@ -660,14 +674,15 @@ def main():
             "bound": "l2" if use_l2 else "hbm",
             "kernel": f"{kname} (gather-max + estimate + accumulate)",
             "achieved": achieved if use_l2 else fab_gbs,
-            "peak": ceil["l2_gather_gbs"] if use_l2 else ceil["fabric_gather_gbs"],
+            "peak": ceil["l2_gather_gbs"] if use_l2 else fab_peak,
             "unit": "GB/s",
             "frac": l2_frac if use_l2 else fab_frac,
             "traffic": traffic,
             "peak_kind": ("measured: the same gather-and-max loop in the same launch shape over "
                           "rows that stay in L2 (hb_gather_probe, 2 MiB table)" if use_l2 else
                           "measured: the same gather loop over rows that miss L2 (hb_gather_probe, "
-                          "1 GiB table)"),
+                          "1 GiB table)" if ceil.get("fabric_gather_gbs") else
+                          "published MI355X HBM3E peak"),
             "algorithmic_bytes_per_launch": per_launch,
             "gathered_rows_per_launch": rows,
             "avg_launch_ms": avg_launch_s * 1e3,

@@ -30,6 +30,9 @@ uint32_t floor_log2(uint32_t n);
     } while (0)
 
 constexpr int kMaxLevels = 24;
+// Smallest graph on which HB_UNION_AUTO picks the grouped kernel: 4,096 groups
+// of 8 nodes, four waves on every SIMD of the device.
+constexpr uint32_t kGroupsMinNodes = 32768;
 // Steps of a blocking run enqueued between two host reads of the stop flags.
 constexpr uint32_t kSegment = 8;
 // Default depth K of the run kernel's range-max table (city graph, p = 10, per

@@ -72,7 +72,7 @@ def test_budget_caps_all_device_memory(hb, reset_options):
     hb.set_options(hbm_budget=budget)
     G = _load(hb, g)
     r = G.run(10, 3, 1, registers=True)  # tables 2 x 9 x n KB: about 38 MiB, within it
-    assert r.union_kernel == "groups"  # the p = 10 default: tables within the budget
+    assert r.union_kernel == "runs"  # tables within the budget (small graph: run kernel)
     assert_matches(hb, r, ref(g, 10, 3, 1), "within the budget")
     st = hb.memory_stats(0)
     assert st["budget_bytes"] == budget and st["held_bytes"] <= budget

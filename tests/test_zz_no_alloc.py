@@ -53,7 +53,7 @@ def test_static_runs_equal_allocating_runs(hb):
     assert hb.memory_stats(0)["held_bytes"] == held0
     for (G, g, p, depth, seed), r in zip(cases, static):
         what = f"{g.name} p={p} d={depth}"
-        assert r.union_kernel == "groups", what  # the p = 10 default, with its tables
+        assert r.union_kernel == "runs", what  # small graphs: the run kernel, with its tables
         _same(r, G.run(p, depth, seed, registers=True), what)
         assert_matches(hb, r, ref(g, p, depth, seed), what)
     Gb.free()
