@@ -69,14 +69,14 @@ def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | No
     directed edge for the per-edge kernel, `rows` table rows for the run kernel, or
     the groups' distinct table rows for the grouped kernel; the adjacency it reads:
     the whole LEB128 stream (per edge), the run list (8 B per run) or the group lists
-    (a 4-byte row index and a 1-byte mask per row, 8 B of offsets per group of 8
+    (a 4-byte row index and a 2-byte mask per row, 8 B of offsets per group of 16
     nodes); per node: the offsets entry (8 B; the grouped kernel's own counter is
     among its rows), its own counter read and next[v] written (2m), and the FP64
     state c_prev and sum_d read and written (32 B).
     """
     m = (1 << p) * bits // 8
     if kernel == "groups":
-        return rows * (m + 5) + 8 * ((n + 7) // 8 + 1) + n * (m + 32)
+        return rows * (m + 6) + 8 * ((n + 15) // 16 + 1) + n * (m + 32)
     gathered = n_edges if rows is None else rows
     adjacency = n_bytes if rows is None else 8 * n_runs
     return gathered * m + adjacency + 8 * (n + 1) + n * (2 * m + 32)
@@ -633,7 +633,7 @@ def main():
         "unit": "edge-unions/s",
         "value_kind": ("edge-union equivalent: passes x directed edges per second; the kernel "
                        "covers each run of consecutive neighbour ids with at most two range-max "
-                       "table rows" + (", loaded once per group of 8 nodes that share them"
+                       "table rows" + (", loaded once per group of 16 nodes that share them"
                                        if kernel == "groups" else "") +
                        ", so it gathers table_rows_per_s rows, not one per edge"
                        if tabled else "one gathered counter per directed edge and pass"),

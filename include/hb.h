@@ -127,7 +127,7 @@ typedef struct {
                             LEB128 row in the kernel */
 #define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table,
                             reading the run list decoded at load */
-#define HB_UNION_GROUPS 3 /* the run kernel's table rows, merged at load over groups of 8
+#define HB_UNION_GROUPS 3 /* the run kernel's table rows, merged at load over groups of 16
                              consecutive nodes of the processing order: each distinct row is
                              loaded once per group (p = 10, 8-bit registers) */
 

@@ -211,11 +211,12 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
 // Row lists of the grouped union kernel: for every group of group_size()
 // consecutive nodes of the processing order, the distinct table rows (k n + i,
 // for tables of depth `levels`) that cover the runs of its nodes, each node's
-// own counter row included, with a mask of the nodes that need each row.
-// Built on the host from the device run list; false when memory is short.
+// own counter row included, with a mask of the nodes that need each row; rows
+// of one mask are listed together, in table position order.  Built on the host
+// from the device run list; false when memory is short.
 bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     const uint32_t n = g->n;
-    const uint32_t W = hbk::group_size();
+    const uint32_t W = hbk::group_size();  // <= 16: a mask is 16 bits
     const uint64_t total = g->runs.runs;
     if ((uint64_t)(levels + 1) * n >= (1ull << 32)) return false;  // row indices are 32-bit
     std::vector<uint64_t> roff((size_t)n + 1);
@@ -227,7 +228,7 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
         return false;
     const uint32_t n_groups = (n + W - 1) / W;
     const uint64_t top = 1ull << levels;
-    // per thread: the entries (row << 8 | mask) of a contiguous range of groups
+    // per thread: the entries (row << 16 | mask) of a contiguous range of groups
     const unsigned nt = (unsigned)std::min<uint64_t>(host_threads(), std::max<uint32_t>(n_groups / 64, 1));
     std::vector<std::vector<uint64_t>> part(nt);
     std::vector<uint64_t> count(n_groups, 0);
@@ -236,7 +237,7 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
         th.emplace_back([&, ti] {
             const uint32_t g0 = (uint32_t)((uint64_t)n_groups * ti / nt);
             const uint32_t g1 = (uint32_t)((uint64_t)n_groups * (ti + 1) / nt);
-            std::vector<uint64_t> tmp;
+            std::vector<uint64_t> tmp, merged;
             for (uint32_t gr = g0; gr < g1; ++gr) {
                 tmp.clear();
                 for (uint32_t w = 0; w < W; ++w) {
@@ -244,38 +245,39 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
                     if (i >= n) break;
                     const uint32_t v = order ? order[i] : (uint32_t)i;
                     const uint64_t bit = 1ull << w;
-                    tmp.push_back(((uint64_t)v << 8) | bit);  // the node's own counter
+                    tmp.push_back(((uint64_t)v << 16) | bit);  // the node's own counter
                     for (uint64_t e = roff[v]; e < roff[v + 1]; ++e) {
                         const uint64_t x = runs[e].x, y = runs[e].y, r = y - x + 1;
                         if (r <= top) {
                             const uint32_t k = floor_log2((uint32_t)r);
-                            tmp.push_back(((k * (uint64_t)n + x) << 8) | bit);
+                            tmp.push_back(((k * (uint64_t)n + x) << 16) | bit);
                             if (r != (1ull << k))
-                                tmp.push_back(((k * (uint64_t)n + y - (1ull << k) + 1) << 8) | bit);
+                                tmp.push_back(((k * (uint64_t)n + y - (1ull << k) + 1) << 16) | bit);
                             continue;
                         }
                         for (uint64_t j = x;; j += top) {
                             const uint64_t at = (j + top - 1 < y) ? j : y - top + 1;
-                            tmp.push_back(((levels * (uint64_t)n + at) << 8) | bit);
+                            tmp.push_back(((levels * (uint64_t)n + at) << 16) | bit);
                             if (at != j || j + top - 1 == y) break;
                         }
                     }
                 }
-                // position-major (then level): the wave walks the table along the
-                // raster, the way its neighbours' waves do (10.0 against 10.9 ms
-                // per city launch for level-major order)
-                std::sort(tmp.begin(), tmp.end(), [n](uint64_t a, uint64_t b) {
-                    const uint64_t ia = (a >> 8) % n, ib = (b >> 8) % n;
+                std::sort(tmp.begin(), tmp.end());
+                merged.clear();
+                for (size_t a = 0; a < tmp.size();) {
+                    uint64_t row = tmp[a] >> 16, mask = 0;
+                    while (a < tmp.size() && (tmp[a] >> 16) == row) mask |= tmp[a++] & 0xFFFFu;
+                    merged.push_back((row << 16) | mask);
+                }
+                // by mask, then table position, then level
+                std::sort(merged.begin(), merged.end(), [n](uint64_t a, uint64_t b) {
+                    const uint64_t ma = a & 0xFFFFu, mb = b & 0xFFFFu;
+                    if (ma != mb) return ma < mb;
+                    const uint64_t ia = (a >> 16) % n, ib = (b >> 16) % n;
                     return ia != ib ? ia < ib : a < b;
                 });
-                uint64_t c = 0;
-                for (size_t a = 0; a < tmp.size();) {
-                    uint64_t row = tmp[a] >> 8, mask = 0;
-                    while (a < tmp.size() && (tmp[a] >> 8) == row) mask |= tmp[a++] & 0xFFu;
-                    part[ti].push_back((row << 8) | mask);
-                    ++c;
-                }
-                count[gr] = c;
+                part[ti].insert(part[ti].end(), merged.begin(), merged.end());
+                count[gr] = merged.size();
             }
         });
     }
@@ -284,22 +286,23 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     for (uint32_t gr = 0; gr < n_groups; ++gr) goff[gr + 1] = goff[gr] + count[gr];
     const uint64_t entries = goff[n_groups];
     std::vector<uint32_t> rows(std::max<uint64_t>(entries, 1));
-    std::vector<uint8_t> masks(std::max<uint64_t>(entries, 1));
+    std::vector<uint16_t> masks(std::max<uint64_t>(entries, 1));
     uint64_t at = 0;
     for (const auto &pv : part)
         for (uint64_t e : pv) {
-            rows[at] = (uint32_t)(e >> 8);
-            masks[at] = (uint8_t)(e & 0xFFu);
+            rows[at] = (uint32_t)(e >> 16);
+            masks[at] = (uint16_t)(e & 0xFFFFu);
             ++at;
         }
     hipError_t e = dmalloc((void **)&g->d_grp_rows, sizeof(uint32_t) * rows.size());
-    if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_mask, masks.size());
+    if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_mask, sizeof(uint16_t) * masks.size());
     if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_off, sizeof(uint64_t) * goff.size());
     if (e == hipSuccess)
         e = hipMemcpy(g->d_grp_rows, rows.data(), sizeof(uint32_t) * rows.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(g->d_grp_mask, masks.data(), masks.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(g->d_grp_mask, masks.data(), sizeof(uint16_t) * masks.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(g->d_grp_off, goff.data(), sizeof(uint64_t) * goff.size(),
                       hipMemcpyHostToDevice);
@@ -315,7 +318,7 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     }
     g->grp_levels = levels;
     g->grp_entries = entries;
-    g->dev_bytes += 5 * rows.size() + 8 * goff.size();
+    g->dev_bytes += 6 * rows.size() + 8 * goff.size();
     return true;
 }
 
@@ -849,7 +852,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     out->union_kernel = groups ? HB_UNION_GROUPS : (runs ? HB_UNION_RUNS : HB_UNION_EDGES);
     out->table_levels = runs ? levels : 0u;
     out->lanes_per_node = groups ? 64u : sched.lanes;
-    out->nodes_per_block = groups ? hbk::group_size() * 4u : sched.nodes_per_block;
+    out->nodes_per_block = groups ? hbk::group_nodes_per_block() : sched.nodes_per_block;
     out->register_bits = bits;
     out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;

@@ -799,75 +799,141 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 // lists hold many identical table rows.  The loader merges the rows of every
 // group of kGroup consecutive nodes of the processing order into one list of
 // distinct rows, each with a bit mask of the group's nodes that need it (their
-// own counters included).  One wave handles a group: it holds the registers of
-// all kGroup nodes, 16 bytes of each per lane, loads every listed row once for
-// the whole wave and takes its max into the accumulators of the nodes in its
-// mask.  The rows loaded per step drop by the rows the nodes share.  p = 10,
-// 8-bit registers: a counter is one wave load.
-constexpr uint32_t kGroup = 8;
-constexpr int kGroupLoads = 8;  // rows in flight per wave
-constexpr uint32_t kGroupLds = 0;  // LDS reserved per workgroup (limits workgroups per CU)
+// own counters included), rows of one mask next to each other.  kGroupWaves
+// waves handle a group, each on its own slice of the counters (p = 10, 8-bit
+// registers: 512 bytes, 8 per lane).  A wave loads every listed row's slice
+// once and takes the max of the rows of one mask into a running value; when
+// the mask changes, that value goes into the accumulators of the nodes in the
+// mask, which sit in LDS (kGroup x 512 bytes per wave), so that the per-node
+// work is paid once per distinct mask, not once per row.
+constexpr uint32_t kGroup = 16;
+constexpr uint32_t kGroupWaves = 2;
+constexpr int kGroupLoads = 16;  // rows in flight per wave
+constexpr uint32_t kGroupBlock = 256;
 
 template <class C>
-__global__ __launch_bounds__(256) void union_groups_kernel(
-    const uint32_t *__restrict__ grp_rows, const uint8_t *__restrict__ grp_mask,
+__global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
+    const uint32_t *__restrict__ grp_rows, const uint16_t *__restrict__ grp_mask,
     const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
     uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
     uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
     double thr, const uint32_t *__restrict__ skip) {
-    static_assert(C::G == 1 && C::RPL == 1 && C::WAVES == 1, "one 16-byte slot per lane");
-    if (skip && *skip == 0u) return;  // the previous step stopped the run
+    static_assert(C::BITS == 8, "8-bit registers");
+    constexpr uint32_t kSlice = (uint32_t)C::M / kGroupWaves;  // counter bytes per wave
+    static_assert(kSlice == kWave * 8u, "one 8-byte slot per lane");
+    constexpr uint32_t kWavesPerBlock = kGroupBlock / kWave;
+    constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / kGroupWaves;
+    __shared__ uint2 s_acc[kWavesPerBlock][kGroup][kWave];
+    __shared__ uint64_t s_lo[kWavesPerBlock][kGroup];
+    __shared__ uint64_t s_hi[kWavesPerBlock][kGroup];
+    __shared__ uint32_t s_z[kWavesPerBlock][kGroup];
+    if (skip && *skip == 0u) return;  // the previous step stopped the run (whole launch)
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const uint32_t grp = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + wave;
+    const uint32_t grp = xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + wave / kGroupWaves;
+    const uint32_t half = wave % kGroupWaves;
     const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
-    if (grp >= n_groups) return;
+    const bool active = grp < n_groups;  // every wave reaches the barrier below
     const uint32_t lane = lane_id();
-    const uint32_t off = lane * 16u;
-    Max4 acc[kGroup][4];
+    const uint32_t off = half * kSlice + lane * 8u;
+    uint2(*acc)[kWave] = s_acc[wave];  // this wave's accumulators, read and written by its lanes
 #pragma unroll
-    for (uint32_t w = 0; w < kGroup; ++w)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[w][q].init(0u);
-    const uint64_t beg = grp_off[grp], end = grp_off[grp + 1];
-    for (uint64_t base = beg; base < end; base += kWave) {
-        // 64 entries at a time, one per lane, broadcast with readlane
-        const uint32_t cnt = (uint32_t)((end - base < kWave) ? end - base : kWave);
-        const uint32_t e_row = lane < cnt ? grp_rows[base + lane] : 0u;
-        const uint32_t e_mask = lane < cnt ? (uint32_t)grp_mask[base + lane] : 0u;
-        for (uint32_t j = 0; j < cnt; j += kGroupLoads) {
-            uint4 x[kGroupLoads];
-            uint32_t mk[kGroupLoads];
-#pragma unroll
-            for (int u = 0; u < kGroupLoads; ++u) {
-                // past the end: row j again with an empty mask
-                const uint32_t l = j + (uint32_t)u < cnt ? j + (uint32_t)u : j;
-                mk[u] = j + (uint32_t)u < cnt ? readlane(e_mask, l) : 0u;
-                x[u] = *reinterpret_cast<const uint4 *>(tbl + (uint64_t)readlane(e_row, l) * C::M +
-                                                        off);
+    for (uint32_t w = 0; w < kGroup; ++w) acc[w][lane] = make_uint2(0u, 0u);
+    if (active) {
+        const uint64_t beg = grp_off[grp], end = grp_off[grp + 1];
+        Max4 run[2];
+        run[0].init(0u);
+        run[1].init(0u);
+        uint32_t run_mask = 0u;
+        // the running value into the accumulators of the nodes in its mask
+        const auto merge = [&](uint32_t mask) {
+#pragma unroll 1
+            while (mask) {
+                const uint32_t w = (uint32_t)__builtin_ctz(mask);
+                mask &= mask - 1u;
+                const uint2 a = acc[w][lane];
+                Max4 b0, b1;
+                b0.init(a.x);
+                b1.init(a.y);
+                b0.hi = pk_max_u16(b0.hi, run[0].hi);
+                b0.lo = pk_max_u16(b0.lo, run[0].lo);
+                b1.hi = pk_max_u16(b1.hi, run[1].hi);
+                b1.lo = pk_max_u16(b1.lo, run[1].lo);
+                acc[w][lane] = make_uint2(b0.value(), b1.value());
             }
+        };
+        for (uint64_t base = beg; base < end; base += kWave) {
+            // 64 entries at a time, one per lane, broadcast with readlane
+            const uint32_t cnt = (uint32_t)((end - base < kWave) ? end - base : kWave);
+            const uint32_t e_row = lane < cnt ? grp_rows[base + lane] : 0u;
+            const uint32_t e_mask = lane < cnt ? (uint32_t)grp_mask[base + lane] : 0u;
+            for (uint32_t j = 0; j < cnt; j += kGroupLoads) {
+                uint2 x[kGroupLoads];
 #pragma unroll
-            for (int u = 0; u < kGroupLoads; ++u) {
-                const uint32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+                for (int u = 0; u < kGroupLoads; ++u) {
+                    // past the end: row j again (not used)
+                    const uint32_t l = j + (uint32_t)u < cnt ? j + (uint32_t)u : j;
+                    x[u] = *reinterpret_cast<const uint2 *>(
+                        tbl + (uint64_t)readlane(e_row, l) * C::M + off);
+                }
 #pragma unroll
-                for (uint32_t w = 0; w < kGroup; ++w)
-                    if (mk[u] & (1u << w))
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            acc[w][q].hi = pk_max_u16(acc[w][q].hi, xs[q]);
-                            acc[w][q].lo = pk_max_u16(acc[w][q].lo, xs[q] << 8);
-                        }
+                for (int u = 0; u < kGroupLoads; ++u) {
+                    if (j + (uint32_t)u >= cnt) break;
+                    const uint32_t mk = readlane(e_mask, j + (uint32_t)u);
+                    if (mk != run_mask) {
+                        merge(run_mask);
+                        run_mask = mk;
+                        run[0].init(x[u].x);
+                        run[1].init(x[u].y);
+                    } else {
+                        run[0].add(x[u].x);
+                        run[1].add(x[u].y);
+                    }
+                }
             }
         }
+        merge(run_mask);
     }
-#pragma unroll
+    // registers of every node: store this wave's slice, estimator partials to LDS
+#pragma unroll 1
     for (uint32_t w = 0; w < kGroup; ++w) {
         const uint32_t i = grp * kGroup + w;
-        if (i >= n) break;
+        if (!active || i >= n) break;
         const uint32_t v = order ? order[i] : i;
-        NodeAcc<C> a;
+        const uint2 r = acc[w][lane];
+        *reinterpret_cast<uint2 *>(next + (uint64_t)v * C::M + off) = r;
+        EstPart e;
+        e.clear();
+        e.template add_dword<8>(r.x, C::TOP);
+        e.template add_dword<8>(r.y, C::TOP);
+        e.wave_reduce();
+        if (lane == 0) {
+            s_lo[wave][w] = e.lo;
+            s_hi[wave][w] = e.hi;
+            s_z[wave][w] = e.zeros;
+        }
+    }
+    __syncthreads();
+    // lane w of the group's first wave: node w's estimate, Eq. 3 and the stop test
+    const uint32_t i = grp * kGroup + lane;
+    if (active && half == 0u && lane < kGroup && i < n) {
+        EstPart tot;
+        tot.clear();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a.m[0][q] = acc[w][q];
-        finish_node<C>(a, v, 0u, next, c_prev, sum_d, flag_t, t, thr);
+        for (uint32_t h = 0; h < kGroupWaves; ++h) {
+            EstPart o;
+            o.lo = s_lo[wave + h][lane];
+            o.hi = s_hi[wave + h][lane];
+            o.zeros = s_z[wave + h][lane];
+            tot.add(o);
+        }
+        const uint32_t v = order ? order[i] : i;
+        const double est = estimate<C::PREC>(tot);
+        const double delta = est - c_prev[v];
+        sum_d[v] = sum_d[v] + (double)t * delta;
+        c_prev[v] = est;
+        if (delta > thr &&
+            __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+            __hip_atomic_store(flag_t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1591,16 +1657,19 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 }
 
 uint32_t group_size() { return kGroup; }
+uint32_t group_nodes_per_block() { return kGroupBlock / kWave / kGroupWaves * kGroup; }
 
-hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint8_t *grp_mask,
+hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint16_t *grp_mask,
                                const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
                                double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
                                uint32_t t, const uint32_t *order, double thr,
                                const uint32_t *skip, hipStream_t stream) {
     if (p != 10) return hipErrorInvalidValue;
+    constexpr uint32_t per_block = kGroupBlock / kWave / kGroupWaves;
     const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
-    const uint32_t blocks = (n_groups + 3u) / 4u;
-    hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks), dim3(256), kGroupLds, stream,
+    const uint32_t blocks = (n_groups + per_block - 1u) / per_block;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks), dim3(kGroupBlock), 0, stream,
                        grp_rows, grp_mask, grp_off, tbl, next, c_prev, sum_d, flag_t, n, t, order,
                        thr, skip);
     return hipGetLastError();
