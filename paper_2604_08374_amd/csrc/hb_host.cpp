@@ -216,7 +216,7 @@ hipError_t build_run_list(hb_graph *g, bool join_self, uint2 **runs, uint64_t **
 // from the device run list; false when memory is short.
 bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     const uint32_t n = g->n;
-    const uint32_t W = hbk::group_size();  // <= 16: a mask is 16 bits
+    const uint32_t W = hbk::kGroupNodes;
     const uint64_t total = g->runs.runs;
     if ((uint64_t)(levels + 1) * n >= (1ull << 32)) return false;  // row indices are 32-bit
     std::vector<uint64_t> roff((size_t)n + 1);
@@ -228,7 +228,7 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
         return false;
     const uint32_t n_groups = (n + W - 1) / W;
     const uint64_t top = 1ull << levels;
-    // per thread: the entries (row << 16 | mask) of a contiguous range of groups
+    // per thread: the entries (row << 32 | mask) of a contiguous range of groups
     const unsigned nt = (unsigned)std::min<uint64_t>(host_threads(), std::max<uint32_t>(n_groups / 64, 1));
     std::vector<std::vector<uint64_t>> part(nt);
     std::vector<uint64_t> count(n_groups, 0);
@@ -245,19 +245,19 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
                     if (i >= n) break;
                     const uint32_t v = order ? order[i] : (uint32_t)i;
                     const uint64_t bit = 1ull << w;
-                    tmp.push_back(((uint64_t)v << 16) | bit);  // the node's own counter
+                    tmp.push_back(((uint64_t)v << 32) | bit);  // the node's own counter
                     for (uint64_t e = roff[v]; e < roff[v + 1]; ++e) {
                         const uint64_t x = runs[e].x, y = runs[e].y, r = y - x + 1;
                         if (r <= top) {
                             const uint32_t k = floor_log2((uint32_t)r);
-                            tmp.push_back(((k * (uint64_t)n + x) << 16) | bit);
+                            tmp.push_back(((k * (uint64_t)n + x) << 32) | bit);
                             if (r != (1ull << k))
-                                tmp.push_back(((k * (uint64_t)n + y - (1ull << k) + 1) << 16) | bit);
+                                tmp.push_back(((k * (uint64_t)n + y - (1ull << k) + 1) << 32) | bit);
                             continue;
                         }
                         for (uint64_t j = x;; j += top) {
                             const uint64_t at = (j + top - 1 < y) ? j : y - top + 1;
-                            tmp.push_back(((levels * (uint64_t)n + at) << 16) | bit);
+                            tmp.push_back(((levels * (uint64_t)n + at) << 32) | bit);
                             if (at != j || j + top - 1 == y) break;
                         }
                     }
@@ -265,15 +265,15 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
                 std::sort(tmp.begin(), tmp.end());
                 merged.clear();
                 for (size_t a = 0; a < tmp.size();) {
-                    uint64_t row = tmp[a] >> 16, mask = 0;
-                    while (a < tmp.size() && (tmp[a] >> 16) == row) mask |= tmp[a++] & 0xFFFFu;
-                    merged.push_back((row << 16) | mask);
+                    uint64_t row = tmp[a] >> 32, mask = 0;
+                    while (a < tmp.size() && (tmp[a] >> 32) == row) mask |= tmp[a++] & 0xFFFFFFFFu;
+                    merged.push_back((row << 32) | mask);
                 }
                 // by mask, then table position, then level
                 std::sort(merged.begin(), merged.end(), [n](uint64_t a, uint64_t b) {
-                    const uint64_t ma = a & 0xFFFFu, mb = b & 0xFFFFu;
+                    const uint64_t ma = a & 0xFFFFFFFFu, mb = b & 0xFFFFFFFFu;
                     if (ma != mb) return ma < mb;
-                    const uint64_t ia = (a >> 16) % n, ib = (b >> 16) % n;
+                    const uint64_t ia = (a >> 32) % n, ib = (b >> 32) % n;
                     return ia != ib ? ia < ib : a < b;
                 });
                 part[ti].insert(part[ti].end(), merged.begin(), merged.end());
@@ -286,22 +286,23 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     for (uint32_t gr = 0; gr < n_groups; ++gr) goff[gr + 1] = goff[gr] + count[gr];
     const uint64_t entries = goff[n_groups];
     std::vector<uint32_t> rows(std::max<uint64_t>(entries, 1));
-    std::vector<uint16_t> masks(std::max<uint64_t>(entries, 1));
+    std::vector<hbk::GroupMask> masks(std::max<uint64_t>(entries, 1));
     uint64_t at = 0;
     for (const auto &pv : part)
         for (uint64_t e : pv) {
-            rows[at] = (uint32_t)(e >> 16);
-            masks[at] = (uint16_t)(e & 0xFFFFu);
+            rows[at] = (uint32_t)(e >> 32);
+            masks[at] = (hbk::GroupMask)(e & 0xFFFFFFFFu);
             ++at;
         }
     hipError_t e = dmalloc((void **)&g->d_grp_rows, sizeof(uint32_t) * rows.size());
-    if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_mask, sizeof(uint16_t) * masks.size());
+    if (e == hipSuccess)
+        e = dmalloc((void **)&g->d_grp_mask, sizeof(hbk::GroupMask) * masks.size());
     if (e == hipSuccess) e = dmalloc((void **)&g->d_grp_off, sizeof(uint64_t) * goff.size());
     if (e == hipSuccess)
         e = hipMemcpy(g->d_grp_rows, rows.data(), sizeof(uint32_t) * rows.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(g->d_grp_mask, masks.data(), sizeof(uint16_t) * masks.size(),
+        e = hipMemcpy(g->d_grp_mask, masks.data(), sizeof(hbk::GroupMask) * masks.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(g->d_grp_off, goff.data(), sizeof(uint64_t) * goff.size(),
@@ -318,7 +319,7 @@ bool build_group_lists(hb_graph *g, uint32_t levels, const uint32_t *order) {
     }
     g->grp_levels = levels;
     g->grp_entries = entries;
-    g->dev_bytes += 6 * rows.size() + 8 * goff.size();
+    g->dev_bytes += (4 + sizeof(hbk::GroupMask)) * rows.size() + 8 * goff.size();
     return true;
 }
 

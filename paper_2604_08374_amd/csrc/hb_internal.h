@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hbk {
 
 // One job of a batched run, in device memory.  The host fills every field
@@ -107,13 +109,18 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
                              hipStream_t stream);
 
 // The same step from per-group row lists (p = 10, 8-bit registers): group g
-// holds nodes g * group_size() .. of the processing order (at most 16), and its
-// rows grp_rows[grp_off[g] ..] (table row indices k n + i) with masks of the
-// group's nodes that need them (bit w: node g * group_size() + w; a node's own
-// row included), rows of equal masks next to each other.
+// holds nodes g * kGroupNodes .. of the processing order, and its rows
+// grp_rows[grp_off[g] ..] (table row indices k n + i) with masks of the group's
+// nodes that need them (bit w: node g * kGroupNodes + w; a node's own row
+// included), rows of equal masks next to each other.  kGroupWaves waves share a
+// group, each on 1 / kGroupWaves of every counter.
+constexpr uint32_t kGroupNodes = 16;
+constexpr uint32_t kGroupWaves = 2;
+using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
+static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
 uint32_t group_size();
 uint32_t group_nodes_per_block();  // nodes of one workgroup of the grouped kernel
-hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint16_t *grp_mask,
+hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const GroupMask *grp_mask,
                                const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
                                double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
                                uint32_t t, const uint32_t *order, double thr,

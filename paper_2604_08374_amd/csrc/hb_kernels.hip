@@ -36,10 +36,14 @@
 //  * The estimator sums 2^(65-p-M) over the registers as an exact 128-bit
 //    integer (wave butterfly with carries) and converts it to double with a
 //    single rounding, so the estimate is independent of the reduction order.
-//  * Workgroups are remapped so that each of the 8 XCDs (which take
-//    workgroups round-robin) works on one contiguous range of the processing
-//    order: nodes close in that order (along a Hilbert curve, when the caller
-//    gives one) share most neighbours, so their gathers hit the same L2.
+//  * Workgroups are remapped across the 8 XCDs (which take workgroups
+//    round-robin).  The per-edge kernel gives each XCD one contiguous range of
+//    the processing order: nodes close in that order (along a Hilbert curve,
+//    when the caller gives one) share most neighbours, so their gathers hit the
+//    same L2.  The table kernels keep all XCDs on one stretch of the order at a
+//    time, 64 workgroups each, so that the rows they share meet in the memory-
+//    side cache that all XCDs share (city graph, p = 10: 7.9 against 9.0 ms
+//    per grouped launch, 11.0 against 13.0 ms per run-kernel launch).
 //  * The exact local metrics (clustering, controllability) keep two bitmaps of
 //    n bits per node in LDS and walk the neighbours' run lists.
 #include <hip/hip_runtime.h>
@@ -292,6 +296,19 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t i, uint32_t nblocks) {
     const uint32_t q = nblocks / kXcds, r = nblocks % kXcds;
     const uint32_t x = i % kXcds, k = i / kXcds;
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Workgroup index -> logical block so that the XCDs work side by side: in every
+// span of kXcds * chunk workgroups, XCD x (taking workgroups i with i % 8 == x)
+// processes logical blocks x * chunk .. x * chunk + chunk - 1 of the span, so
+// that at any time all XCDs work on one stretch of the processing order; a
+// last, partial span keeps the identity.
+constexpr uint32_t kXcdSpanChunk = 64;  // 16 to 256 measured on the city graph: 64 best
+__device__ __forceinline__ uint32_t xcd_span_block(uint32_t i, uint32_t nblocks,
+                                                   uint32_t chunk) {
+    const uint32_t span = chunk * kXcds, s = i / span;
+    if ((s + 1u) * span > nblocks) return i;
+    return s * span + (i % kXcds) * chunk + (i - s * span) / kXcds;
 }
 
 // Byte offset, within a counter, of lane-slot s (s < RPL) of this lane.
@@ -774,9 +791,10 @@ __device__ __forceinline__ void union_node_runs(const uint2 *__restrict__ runs,
 // table rows, then gathers its own slice of each.
 //
 // order (optional) is the processing order: logical node i is node order[i].
-// Nodes that are processed together (one XCD walks a contiguous stretch of the
-// order) gather overlapping table rows, so an order along a space-filling
-// curve over the raster raises cache reuse; the results do not depend on it.
+// Nodes that are processed together (the XCDs walk one stretch of the order
+// side by side) gather overlapping table rows, so an order along a
+// space-filling curve over the raster raises cache reuse; the results do not
+// depend on it.
 template <class C>
 __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
@@ -787,7 +805,7 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
     __shared__ __attribute__((aligned(16))) uint32_t s_queue[C::THREADS / kWave][kQueueCap];
     if (skip && *skip == 0u) return;  // the previous step stopped the run
     uint32_t v, slice;
-    node_of<C>(xcd_block(blockIdx.x, gridDim.x), v, slice);
+    node_of<C>(xcd_span_block(blockIdx.x, gridDim.x, kXcdSpanChunk), v, slice);
     if (v >= n) return;  // uniform per workgroup when WAVES > 1
     if (order) v = order[v];
     union_node_runs<C>(runs, run_off, tbl, levels, next, c_prev, sum_d, flag_t, n, v, slice, t,
@@ -797,52 +815,93 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 // ---------------------------------------------------------------- union step, per group
 // Nodes that are processed together see almost the same cells, so their run
 // lists hold many identical table rows.  The loader merges the rows of every
-// group of kGroup consecutive nodes of the processing order into one list of
-// distinct rows, each with a bit mask of the group's nodes that need it (their
-// own counters included), rows of one mask next to each other.  kGroupWaves
-// waves handle a group, each on its own slice of the counters (p = 10, 8-bit
-// registers: 512 bytes, 8 per lane).  A wave loads every listed row's slice
-// once and takes the max of the rows of one mask into a running value; when
-// the mask changes, that value goes into the accumulators of the nodes in the
-// mask, which sit in LDS (kGroup x 512 bytes per wave), so that the per-node
-// work is paid once per distinct mask, not once per row.
-constexpr uint32_t kGroup = 16;
-constexpr uint32_t kGroupWaves = 2;
-constexpr int kGroupLoads = 16;  // rows in flight per wave
+// group of kGroupNodes consecutive nodes of the processing order into one list
+// of distinct rows, each with a bit mask of the group's nodes that need it
+// (their own counters included), rows of one mask next to each other.
+// kGroupWaves waves handle a group, each on its own slice of the counters
+// (p = 10, 8-bit registers: 1024 / kGroupWaves bytes).  A wave loads every
+// listed row's slice once and takes the max of the rows of one mask into a
+// running value; when the mask changes, that value goes into the accumulators
+// of the nodes in the mask, which sit in LDS, so that the per-node work is paid
+// once per distinct mask, not once per row.
 constexpr uint32_t kGroupBlock = 256;
+constexpr int kGroupLoads = 16;  // rows in flight per wave (one batch)
+
+// This lane's part of one counter slice: kDw dwords.
+template <uint32_t kDw> struct LaneSlice;
+template <> struct LaneSlice<1> {
+    uint32_t d[1];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        d[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+    __device__ __forceinline__ void store(uint8_t *p) const {
+        *reinterpret_cast<uint32_t *>(p) = d[0];
+    }
+};
+template <> struct LaneSlice<2> {
+    uint32_t d[2];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        d[0] = x.x;
+        d[1] = x.y;
+    }
+    __device__ __forceinline__ void store(uint8_t *p) const {
+        *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
+    }
+};
+
+// Byte-wise max of the raw registers a and the running value r: the high bytes
+// of both 16-bit halves from one packed max, the low bytes (shifted up) from
+// another, and a byte permute puts them back in place.
+__device__ __forceinline__ uint32_t byte_max_raw(uint32_t a, const Max4 &r) {
+    const uint32_t hi = pk_max_u16(a, r.hi);
+    const uint32_t lo = pk_max_u16(a << 8, r.lo);
+    // bytes 0..3 of the result: lo.1, hi.1, lo.3, hi.3 (selector bytes 0-3 pick
+    // from the second operand, 4-7 from the first)
+    return __builtin_amdgcn_perm(hi, lo, 0x07030501u);
+}
 
 template <class C>
 __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
-    const uint32_t *__restrict__ grp_rows, const uint16_t *__restrict__ grp_mask,
+    const uint32_t *__restrict__ grp_rows, const GroupMask *__restrict__ grp_mask,
     const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
     uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
     uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
     double thr, const uint32_t *__restrict__ skip) {
     static_assert(C::BITS == 8, "8-bit registers");
-    constexpr uint32_t kSlice = (uint32_t)C::M / kGroupWaves;  // counter bytes per wave
-    static_assert(kSlice == kWave * 8u, "one 8-byte slot per lane");
+    constexpr uint32_t W = kGroupNodes, H = kGroupWaves;
+    constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
+    constexpr uint32_t kDw = kSlice / kWave / 4u;    // dwords per lane
+    static_assert(kDw == 1 || kDw == 2, "4 or 8 bytes per lane");
+    constexpr int U = kGroupLoads;  // rows per batch
+    static_assert(U * kDw <= 32, "at most 32 VGPRs of loads per batch");
+    static_assert(kWave % U == 0, "a batch lies in one chunk of 64 entries");
     constexpr uint32_t kWavesPerBlock = kGroupBlock / kWave;
-    constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / kGroupWaves;
-    __shared__ uint2 s_acc[kWavesPerBlock][kGroup][kWave];
-    __shared__ uint64_t s_lo[kWavesPerBlock][kGroup];
-    __shared__ uint64_t s_hi[kWavesPerBlock][kGroup];
-    __shared__ uint32_t s_z[kWavesPerBlock][kGroup];
+    constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / H;
+    using Slice = LaneSlice<kDw>;
+    __shared__ Slice s_acc[kWavesPerBlock][W][kWave];
+    __shared__ uint64_t s_lo[kWavesPerBlock][W];
+    __shared__ uint64_t s_hi[kWavesPerBlock][W];
+    __shared__ uint32_t s_z[kWavesPerBlock][W];
     if (skip && *skip == 0u) return;  // the previous step stopped the run (whole launch)
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const uint32_t grp = xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + wave / kGroupWaves;
-    const uint32_t half = wave % kGroupWaves;
-    const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
+    const uint32_t grp =
+        xcd_span_block(blockIdx.x, gridDim.x, kXcdSpanChunk) * kGroupsPerBlock + wave / H;
+    const uint32_t part = wave % H;
+    const uint32_t n_groups = (n + W - 1u) / W;
     const bool active = grp < n_groups;  // every wave reaches the barrier below
     const uint32_t lane = lane_id();
-    const uint32_t off = half * kSlice + lane * 8u;
-    uint2(*acc)[kWave] = s_acc[wave];  // this wave's accumulators, read and written by its lanes
+    const uint32_t off = part * kSlice + lane * (kDw * 4u);
+    Slice(*acc)[kWave] = s_acc[wave];  // this wave's accumulators, each lane its own
 #pragma unroll
-    for (uint32_t w = 0; w < kGroup; ++w) acc[w][lane] = make_uint2(0u, 0u);
+    for (uint32_t w = 0; w < W; ++w)
+#pragma unroll
+        for (uint32_t k = 0; k < kDw; ++k) acc[w][lane].d[k] = 0u;
     if (active) {
-        const uint64_t beg = grp_off[grp], end = grp_off[grp + 1];
-        Max4 run[2];
-        run[0].init(0u);
-        run[1].init(0u);
+        const uint64_t end = grp_off[grp + 1];
+        Max4 run[kDw];
+#pragma unroll
+        for (uint32_t k = 0; k < kDw; ++k) run[k].init(0u);
         uint32_t run_mask = 0u;
         // the running value into the accumulators of the nodes in its mask
         const auto merge = [&](uint32_t mask) {
@@ -850,61 +909,63 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
             while (mask) {
                 const uint32_t w = (uint32_t)__builtin_ctz(mask);
                 mask &= mask - 1u;
-                const uint2 a = acc[w][lane];
-                Max4 b0, b1;
-                b0.init(a.x);
-                b1.init(a.y);
-                b0.hi = pk_max_u16(b0.hi, run[0].hi);
-                b0.lo = pk_max_u16(b0.lo, run[0].lo);
-                b1.hi = pk_max_u16(b1.hi, run[1].hi);
-                b1.lo = pk_max_u16(b1.lo, run[1].lo);
-                acc[w][lane] = make_uint2(b0.value(), b1.value());
+                Slice a = acc[w][lane];
+#pragma unroll
+                for (uint32_t k = 0; k < kDw; ++k) a.d[k] = byte_max_raw(a.d[k], run[k]);
+                acc[w][lane] = a;
             }
         };
-        for (uint64_t base = beg; base < end; base += kWave) {
-            // 64 entries at a time, one per lane, broadcast with readlane
+        const auto process = [&](const Slice(&x)[U], const uint32_t(&mk)[U]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (mk[u] == 0u) break;
+                if (mk[u] != run_mask) {
+                    merge(run_mask);
+                    run_mask = mk[u];
+#pragma unroll
+                    for (uint32_t k = 0; k < kDw; ++k) run[k].init(x[u].d[k]);
+                } else {
+#pragma unroll
+                    for (uint32_t k = 0; k < kDw; ++k) run[k].add(x[u].d[k]);
+                }
+            }
+        };
+        // list entries 64 at a time, one per lane, broadcast with readlane; a
+        // batch of U rows in flight at a time (issuing the next batch before
+        // processing this one was slower: 10.0 against 9.0 ms per city launch)
+#pragma unroll 1
+        for (uint64_t base = grp_off[grp]; base < end; base += kWave) {
             const uint32_t cnt = (uint32_t)((end - base < kWave) ? end - base : kWave);
             const uint32_t e_row = lane < cnt ? grp_rows[base + lane] : 0u;
             const uint32_t e_mask = lane < cnt ? (uint32_t)grp_mask[base + lane] : 0u;
-            for (uint32_t j = 0; j < cnt; j += kGroupLoads) {
-                uint2 x[kGroupLoads];
+#pragma unroll 1
+            for (uint32_t j = 0; j < cnt; j += (uint32_t)U) {
+                Slice x[U];
+                uint32_t mk[U];  // the batch's masks; 0 past the list's end
 #pragma unroll
-                for (int u = 0; u < kGroupLoads; ++u) {
+                for (int u = 0; u < U; ++u) {
                     // past the end: row j again (not used)
                     const uint32_t l = j + (uint32_t)u < cnt ? j + (uint32_t)u : j;
-                    x[u] = *reinterpret_cast<const uint2 *>(
-                        tbl + (uint64_t)readlane(e_row, l) * C::M + off);
+                    x[u].load(tbl + (uint64_t)readlane(e_row, l) * C::M + off);
+                    mk[u] = j + (uint32_t)u < cnt ? readlane(e_mask, l) : 0u;
                 }
-#pragma unroll
-                for (int u = 0; u < kGroupLoads; ++u) {
-                    if (j + (uint32_t)u >= cnt) break;
-                    const uint32_t mk = readlane(e_mask, j + (uint32_t)u);
-                    if (mk != run_mask) {
-                        merge(run_mask);
-                        run_mask = mk;
-                        run[0].init(x[u].x);
-                        run[1].init(x[u].y);
-                    } else {
-                        run[0].add(x[u].x);
-                        run[1].add(x[u].y);
-                    }
-                }
+                process(x, mk);
             }
         }
         merge(run_mask);
     }
     // registers of every node: store this wave's slice, estimator partials to LDS
 #pragma unroll 1
-    for (uint32_t w = 0; w < kGroup; ++w) {
-        const uint32_t i = grp * kGroup + w;
+    for (uint32_t w = 0; w < W; ++w) {
+        const uint32_t i = grp * W + w;
         if (!active || i >= n) break;
         const uint32_t v = order ? order[i] : i;
-        const uint2 r = acc[w][lane];
-        *reinterpret_cast<uint2 *>(next + (uint64_t)v * C::M + off) = r;
+        const Slice r = acc[w][lane];
+        r.store(next + (uint64_t)v * C::M + off);
         EstPart e;
         e.clear();
-        e.template add_dword<8>(r.x, C::TOP);
-        e.template add_dword<8>(r.y, C::TOP);
+#pragma unroll
+        for (uint32_t k = 0; k < kDw; ++k) e.template add_dword<8>(r.d[k], C::TOP);
         e.wave_reduce();
         if (lane == 0) {
             s_lo[wave][w] = e.lo;
@@ -914,12 +975,12 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
     }
     __syncthreads();
     // lane w of the group's first wave: node w's estimate, Eq. 3 and the stop test
-    const uint32_t i = grp * kGroup + lane;
-    if (active && half == 0u && lane < kGroup && i < n) {
+    const uint32_t i = grp * W + lane;
+    if (active && part == 0u && lane < W && i < n) {
         EstPart tot;
         tot.clear();
 #pragma unroll
-        for (uint32_t h = 0; h < kGroupWaves; ++h) {
+        for (uint32_t h = 0; h < H; ++h) {
             EstPart o;
             o.lo = s_lo[wave + h][lane];
             o.hi = s_hi[wave + h][lane];
@@ -1656,17 +1717,17 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 #undef HB_X
 }
 
-uint32_t group_size() { return kGroup; }
-uint32_t group_nodes_per_block() { return kGroupBlock / kWave / kGroupWaves * kGroup; }
+uint32_t group_size() { return kGroupNodes; }
+uint32_t group_nodes_per_block() { return kGroupBlock / kWave / kGroupWaves * kGroupNodes; }
 
-hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const uint16_t *grp_mask,
+hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const GroupMask *grp_mask,
                                const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
                                double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
                                uint32_t t, const uint32_t *order, double thr,
                                const uint32_t *skip, hipStream_t stream) {
     if (p != 10) return hipErrorInvalidValue;
     constexpr uint32_t per_block = kGroupBlock / kWave / kGroupWaves;
-    const uint32_t n_groups = (n + kGroup - 1u) / kGroup;
+    const uint32_t n_groups = (n + kGroupNodes - 1u) / kGroupNodes;
     const uint32_t blocks = (n_groups + per_block - 1u) / per_block;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks), dim3(kGroupBlock), 0, stream,

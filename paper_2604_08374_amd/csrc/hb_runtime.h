@@ -132,7 +132,7 @@ struct hb_graph {
     uint32_t *d_hash_ids = nullptr;  // inserted ids, or null
     int32_t *d_xy = nullptr;         // 2n cell coordinates, or null
     uint32_t *d_grp_rows = nullptr;  // grouped kernel: distinct table rows per node group
-    uint16_t *d_grp_mask = nullptr;  // and the group's nodes that need each
+    hbk::GroupMask *d_grp_mask = nullptr;  // and the group's nodes that need each
     uint64_t *d_grp_off = nullptr;   // n_groups + 1 offsets
     uint32_t grp_levels = 0;         // table depth the group lists were built for
     uint64_t grp_entries = 0;
