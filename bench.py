@@ -382,8 +382,12 @@ def serve_bench(args):
     t0 = time.perf_counter()
     probe = list(range(min(nreq, 40)))
     for i in probe:
-        G = resident.get(int(req_graph[i])) or hb.graph_load(*graphs[int(req_graph[i])]["csr"])
-        service(i, G)
+        G = resident.get(int(req_graph[i]))
+        if G is None:
+            with hb.graph_load(*graphs[int(req_graph[i])]["csr"]) as G:
+                service(i, G)
+        else:
+            service(i, G)
     mean_s = (time.perf_counter() - t0) / len(probe)
     lam_seq = 1.0 / mean_s
     log(f"mean sequential service {mean_s * 1e3:.2f} ms -> lambda_seq {lam_seq:.1f}/s")
@@ -516,7 +520,8 @@ def main():
     ap.add_argument("--pool", type=int, default=200)
     ap.add_argument("--pool-max-nodes", type=int, default=120000)
     ap.add_argument("--requests", type=int, default=1000)
-    ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 1.0, 1.25])
+    ap.add_argument("--rates", type=float, nargs="+",
+                    default=[0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0])
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="cap on the request loop's own device memory (0 = the library budget)")
     ap.add_argument("--no-extras", action="store_true",
