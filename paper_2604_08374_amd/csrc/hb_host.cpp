@@ -649,8 +649,8 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
         return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
-    if (o.union_kernel == HB_UNION_GROUPS && (p != 10 || (o.register_bits && o.register_bits != 8)))
-        return fail(HB_EINVAL, "the grouped kernel supports p = 10 with 8-bit registers");
+    if (o.union_kernel == HB_UNION_GROUPS && p != 10)
+        return fail(HB_EINVAL, "the grouped kernel supports p = 10");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     const bool depth_only = lib.stop_rule == HB_STOP_DEPTH;
     if (depth_only && depth_limit == 0)
@@ -671,11 +671,11 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     const bool have_groups = g->d_grp_rows && levels == g->grp_levels;
     if (o.union_kernel == HB_UNION_GROUPS && !have_groups)
         return fail(HB_EINVAL, "the graph has no group lists for table depth %u", levels);
-    // the grouped kernel is the default where it is built (p = 10, 8-bit registers)
-    // and the graph has enough groups to fill the device (a wave per group: on a
-    // 709-node graph a grouped launch takes 43 us against 12 us for the run kernel)
+    // the grouped kernel is the default where it is built (p = 10) and the graph
+    // has enough groups to fill the device (on a 709-node graph a grouped launch
+    // takes 43 us against 12 us for the run kernel)
     bool groups = o.union_kernel == HB_UNION_GROUPS ||
-                  (o.union_kernel == HB_UNION_AUTO && p == 10 && bits == 8 && have_groups &&
+                  (o.union_kernel == HB_UNION_AUTO && p == 10 && have_groups &&
                    n >= kGroupsMinNodes);
     bool runs = groups || (o.union_kernel == HB_UNION_RUNS) ||
                 (o.union_kernel == HB_UNION_AUTO && p <= 12);
@@ -786,7 +786,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
             if (runs) HB_HIP(hbk::launch_table(cur, n, (uint32_t)m, levels, bits, skip, s));
             HB_HIP(hipEventRecord(ev[1], s));
             if (groups)
-                HB_HIP(hbk::launch_union_groups((int)p, g->d_grp_rows, g->d_grp_mask,
+                HB_HIP(hbk::launch_union_groups((int)p, bits, g->d_grp_rows, g->d_grp_mask,
                                                 g->d_grp_off, cur, next, g->d_cprev, g->d_sumd,
                                                 g->d_flags + t, n, t, g->d_order, thr, skip, s));
             else if (runs)
@@ -853,7 +853,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     out->union_kernel = groups ? HB_UNION_GROUPS : (runs ? HB_UNION_RUNS : HB_UNION_EDGES);
     out->table_levels = runs ? levels : 0u;
     out->lanes_per_node = groups ? 64u : sched.lanes;
-    out->nodes_per_block = groups ? hbk::group_nodes_per_block() : sched.nodes_per_block;
+    out->nodes_per_block = groups ? hbk::group_nodes_per_block(bits) : sched.nodes_per_block;
     out->register_bits = bits;
     out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;

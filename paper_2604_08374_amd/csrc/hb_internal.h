@@ -108,23 +108,23 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
                              const uint32_t *order, double thr, const uint32_t *skip,
                              hipStream_t stream);
 
-// The same step from per-group row lists (p = 10, 8-bit registers): group g
-// holds nodes g * kGroupNodes .. of the processing order, and its rows
+// The same step from per-group row lists (p = 10, 8- or 4-bit registers):
+// group g holds nodes g * kGroupNodes .. of the processing order, and its rows
 // grp_rows[grp_off[g] ..] (table row indices k n + i) with masks of the group's
 // nodes that need them (bit w: node g * kGroupNodes + w; a node's own row
-// included), rows of equal masks next to each other.  kGroupWaves waves share a
-// group, each on 1 / kGroupWaves of every counter.
+// included), rows of equal masks next to each other.  group_waves(bits) waves
+// share a group, each on a 512-byte slice of every counter.
 constexpr uint32_t kGroupNodes = 16;
-constexpr uint32_t kGroupWaves = 2;
+constexpr uint32_t group_waves(uint32_t bits) { return bits == 8 ? 2u : 1u; }
 using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
 static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
 uint32_t group_size();
-uint32_t group_nodes_per_block();  // nodes of one workgroup of the grouped kernel
-hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const GroupMask *grp_mask,
-                               const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
-                               double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
-                               uint32_t t, const uint32_t *order, double thr,
-                               const uint32_t *skip, hipStream_t stream);
+uint32_t group_nodes_per_block(uint32_t bits);  // nodes of one workgroup of the grouped kernel
+hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
+                               const GroupMask *grp_mask, const uint64_t *grp_off,
+                               const uint8_t *tbl, uint8_t *next, double *c_prev, double *sum_d,
+                               uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
+                               double thr, const uint32_t *skip, hipStream_t stream);
 
 // Build table levels 1..levels: T[k][i] = max(T[k-1][i], T[k-1][i + 2^(k-1)]),
 // i <= n - 2^k, rows of m bytes (m a multiple of 16) of `bits`-bit registers,

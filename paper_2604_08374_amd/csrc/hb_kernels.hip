@@ -818,8 +818,8 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 // group of kGroupNodes consecutive nodes of the processing order into one list
 // of distinct rows, each with a bit mask of the group's nodes that need it
 // (their own counters included), rows of one mask next to each other.
-// kGroupWaves waves handle a group, each on its own slice of the counters
-// (p = 10, 8-bit registers: 1024 / kGroupWaves bytes).  A wave loads every
+// group_waves(bits) waves handle a group, each on its own 512-byte slice of the
+// counters (p = 10: two waves for 8-bit registers, one for 4-bit).  A wave loads every
 // listed row's slice once and takes the max of the rows of one mask into a
 // running value; when the mask changes, that value goes into the accumulators
 // of the nodes in the mask, which sit in LDS, so that the per-node work is paid
@@ -850,15 +850,24 @@ template <> struct LaneSlice<2> {
     }
 };
 
-// Byte-wise max of the raw registers a and the running value r: the high bytes
-// of both 16-bit halves from one packed max, the low bytes (shifted up) from
-// another, and a byte permute puts them back in place.
-__device__ __forceinline__ uint32_t byte_max_raw(uint32_t a, const Max4 &r) {
+// Register-wise max of the raw registers a (one dword) and the running value r.
+// 8-bit: the high bytes of both 16-bit halves from one packed max, the low
+// bytes (shifted up) from another, and a byte permute puts them back in place.
+__device__ __forceinline__ uint32_t max_into_raw(uint32_t a, const Max4 &r) {
     const uint32_t hi = pk_max_u16(a, r.hi);
     const uint32_t lo = pk_max_u16(a << 8, r.lo);
     // bytes 0..3 of the result: lo.1, hi.1, lo.3, hi.3 (selector bytes 0-3 pick
     // from the second operand, 4-7 from the first)
     return __builtin_amdgcn_perm(hi, lo, 0x07030501u);
+}
+// 4-bit: the four nibble positions of each half through the accumulator's
+// four shifted copies.
+__device__ __forceinline__ uint32_t max_into_raw(uint32_t a, const Max8 &r) {
+    Max8 b;
+    b.init(a);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b.a[i] = pk_max_u16(b.a[i], r.a[i]);
+    return b.value();
 }
 
 template <class C>
@@ -868,8 +877,7 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
     uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
     uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
     double thr, const uint32_t *__restrict__ skip) {
-    static_assert(C::BITS == 8, "8-bit registers");
-    constexpr uint32_t W = kGroupNodes, H = kGroupWaves;
+    constexpr uint32_t W = kGroupNodes, H = group_waves(C::BITS);
     constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
     constexpr uint32_t kDw = kSlice / kWave / 4u;    // dwords per lane
     static_assert(kDw == 1 || kDw == 2, "4 or 8 bytes per lane");
@@ -899,7 +907,7 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
         for (uint32_t k = 0; k < kDw; ++k) acc[w][lane].d[k] = 0u;
     if (active) {
         const uint64_t end = grp_off[grp + 1];
-        Max4 run[kDw];
+        typename AccOf<C::BITS>::T run[kDw];
 #pragma unroll
         for (uint32_t k = 0; k < kDw; ++k) run[k].init(0u);
         uint32_t run_mask = 0u;
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
                 mask &= mask - 1u;
                 Slice a = acc[w][lane];
 #pragma unroll
-                for (uint32_t k = 0; k < kDw; ++k) a.d[k] = byte_max_raw(a.d[k], run[k]);
+                for (uint32_t k = 0; k < kDw; ++k) a.d[k] = max_into_raw(a.d[k], run[k]);
                 acc[w][lane] = a;
             }
         };
@@ -965,7 +973,7 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
         EstPart e;
         e.clear();
 #pragma unroll
-        for (uint32_t k = 0; k < kDw; ++k) e.template add_dword<8>(r.d[k], C::TOP);
+        for (uint32_t k = 0; k < kDw; ++k) e.template add_dword<C::BITS>(r.d[k], C::TOP);
         e.wave_reduce();
         if (lane == 0) {
             s_lo[wave][w] = e.lo;
@@ -1718,21 +1726,30 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 }
 
 uint32_t group_size() { return kGroupNodes; }
-uint32_t group_nodes_per_block() { return kGroupBlock / kWave / kGroupWaves * kGroupNodes; }
+uint32_t group_nodes_per_block(uint32_t bits) {
+    return kGroupBlock / kWave / group_waves(bits) * kGroupNodes;
+}
 
-hipError_t launch_union_groups(int p, const uint32_t *grp_rows, const GroupMask *grp_mask,
-                               const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
-                               double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
-                               uint32_t t, const uint32_t *order, double thr,
-                               const uint32_t *skip, hipStream_t stream) {
-    if (p != 10) return hipErrorInvalidValue;
-    constexpr uint32_t per_block = kGroupBlock / kWave / kGroupWaves;
+hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
+                               const GroupMask *grp_mask, const uint64_t *grp_off,
+                               const uint8_t *tbl, uint8_t *next, double *c_prev, double *sum_d,
+                               uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
+                               double thr, const uint32_t *skip, hipStream_t stream) {
+    if (p != 10 || (bits != 8 && bits != 4)) return hipErrorInvalidValue;
+    const uint32_t per_block = kGroupBlock / kWave / group_waves(bits);
     const uint32_t n_groups = (n + kGroupNodes - 1u) / kGroupNodes;
     const uint32_t blocks = (n_groups + per_block - 1u) / per_block;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks), dim3(kGroupBlock), 0, stream,
-                       grp_rows, grp_mask, grp_off, tbl, next, c_prev, sum_d, flag_t, n, t, order,
-                       thr, skip);
+    // Cfg fixes the counter size, the register width and the estimator's
+    // constants; the lanes-per-node field is not used by this kernel
+    if (bits == 8)
+        hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks),
+                           dim3(kGroupBlock), 0, stream, grp_rows, grp_mask, grp_off, tbl, next,
+                           c_prev, sum_d, flag_t, n, t, order, thr, skip);
+    else
+        hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 32, 4>>), dim3(blocks),
+                           dim3(kGroupBlock), 0, stream, grp_rows, grp_mask, grp_off, tbl, next,
+                           c_prev, sum_d, flag_t, n, t, order, thr, skip);
     return hipGetLastError();
 }
 

@@ -62,8 +62,10 @@ def test_4bit_matches_oracle(hb, p):
                                register_bits=4)
         assert ref.registers.max() == 15
         G = _load(hb, g, hash_ids=hid)
-        for kernel in (("runs", "edges") if p <= 12 else ("edges",)):
-            for nb in ((4, 1) if p <= 11 else (0,)):
+        kernels = (("runs", "edges") if p <= 12 else ("edges",)) + \
+            (("groups",) if p == 10 else ())
+        for kernel in kernels:
+            for nb in ((4, 1) if p <= 11 and kernel != "groups" else (0,)):
                 what = f"{g.name} p={p} d={depth} {kernel} nb={nb}"
                 print(f"[reg4] {what}", flush=True)
                 kw = {} if nb == 0 else dict(lanes_per_node=LANES4[p], nodes_per_block=nb)
@@ -83,6 +85,11 @@ def test_4bit_clamps_the_8bit_registers(hb):
     r8 = G.run(p, r4.passes, seed, registers=True)
     assert r8.registers.max() >= 16
     assert np.array_equal(hb.unpack_nibbles(r4.registers), np.minimum(r8.registers, 15))
+    # the grouped kernel at both widths
+    g4 = G.run(p, 0, seed, registers=True, register_bits=4, kernel="groups")
+    g8 = G.run(p, g4.passes, seed, registers=True, kernel="groups")
+    assert g4.union_kernel == "groups" and g8.union_kernel == "groups"
+    assert np.array_equal(g4.registers, r4.registers) and np.array_equal(g8.registers, r8.registers)
     G.free()
 
 
