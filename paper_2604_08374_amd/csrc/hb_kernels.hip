@@ -827,18 +827,8 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 constexpr uint32_t kGroupBlock = 256;
 constexpr int kGroupLoads = 16;  // rows in flight per wave (one batch)
 
-// This lane's part of one counter slice: kDw dwords.
-template <uint32_t kDw> struct LaneSlice;
-template <> struct LaneSlice<1> {
-    uint32_t d[1];
-    __device__ __forceinline__ void load(const uint8_t *p) {
-        d[0] = *reinterpret_cast<const uint32_t *>(p);
-    }
-    __device__ __forceinline__ void store(uint8_t *p) const {
-        *reinterpret_cast<uint32_t *>(p) = d[0];
-    }
-};
-template <> struct LaneSlice<2> {
+// This lane's part of one 512-byte counter slice: two dwords.
+struct LaneSlice {
     uint32_t d[2];
     __device__ __forceinline__ void load(const uint8_t *p) {
         const uint2 x = *reinterpret_cast<const uint2 *>(p);
@@ -880,13 +870,13 @@ __global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
     constexpr uint32_t W = kGroupNodes, H = group_waves(C::BITS);
     constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
     constexpr uint32_t kDw = kSlice / kWave / 4u;    // dwords per lane
-    static_assert(kDw == 1 || kDw == 2, "4 or 8 bytes per lane");
+    static_assert(kDw == 2, "8 bytes per lane");
     constexpr int U = kGroupLoads;  // rows per batch
     static_assert(U * kDw <= 32, "at most 32 VGPRs of loads per batch");
     static_assert(kWave % U == 0, "a batch lies in one chunk of 64 entries");
     constexpr uint32_t kWavesPerBlock = kGroupBlock / kWave;
     constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / H;
-    using Slice = LaneSlice<kDw>;
+    using Slice = LaneSlice;
     __shared__ Slice s_acc[kWavesPerBlock][W][kWave];
     __shared__ uint64_t s_lo[kWavesPerBlock][W];
     __shared__ uint64_t s_hi[kWavesPerBlock][W];
@@ -1169,8 +1159,8 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t *__restrict__ block_
 
 // Workgroups are dispatched in index order, so a job's contiguous block range
 // runs on all XCDs together (its working set is shared, not eight jobs'); the
-// XCD of block base + l depends only on l mod 8, so remapping the local index
-// gives each XCD one contiguous node range of the job.
+// XCD of block base + l is (base + l) mod 8, a fixed rotation of l mod 8, so
+// remapping the local index gives each XCD one contiguous node range of the job.
 __device__ __forceinline__ uint32_t job_block(uint32_t blk, const uint32_t *__restrict__ block_base,
                                               uint32_t i) {
     return xcd_block(blk - block_base[i], block_base[i + 1] - block_base[i]);
