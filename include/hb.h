@@ -102,13 +102,15 @@ typedef struct {
     uint64_t edge_unions;  /* passes * n_edges */
     double init_ms;        /* device time of the initialisation kernel */
     double iter_ms;        /* device time summed over the passes union kernels */
-    double table_ms;       /* device time summed over range-max table builds (run kernel) */
+    double table_ms;       /* device time summed over range-max table builds (run and
+                              grouped kernels) */
     double run_ms;         /* device time from init start to the last union end */
-    uint32_t union_kernel; /* kernel that ran: HB_UNION_EDGES or HB_UNION_RUNS */
-    uint32_t table_levels; /* table levels K used by the run kernel (0 otherwise) */
+    uint32_t union_kernel; /* kernel that ran: HB_UNION_EDGES, HB_UNION_RUNS or HB_UNION_GROUPS */
+    uint32_t table_levels; /* table levels K used by the run or grouped kernel (0 otherwise) */
     uint32_t lanes_per_node;  /* union schedule that ran (see hb_run_opts); for a batch,
-                                 that of the job's (p, kernel) class */
-    uint32_t nodes_per_block;
+                                 that of the job's (p, kernel) class; for the grouped
+                                 kernel 64 (a wavefront on each counter slice) */
+    uint32_t nodes_per_block; /* for the grouped kernel: nodes per workgroup (16 per group) */
     uint32_t register_bits;   /* register width of the run: 8 or 4 */
     double tune_ms;        /* host time spent measuring schedules in this call (0 if none) */
     uint64_t t_submit_ns;  /* host CLOCK_MONOTONIC: hb_submit accepted it (else = t_start_ns) */
