@@ -649,7 +649,7 @@ def main():
                                    stats["n_runs"], kernel)
     achieved = per_launch / avg_launch_s / 1e9
     lanes, nb = results[-1].lanes_per_node, results[-1].nodes_per_block
-    kname = (f"union_groups_kernel<{p},{64 if bits == 8 else 32},{bits}>" if kernel == "groups" else
+    kname = (f"union_groups_kernel<{p},{m // 16},{bits}>" if kernel == "groups" else
              f"union_runs_kernel<{p},{lanes},{bits}>" if kernel == "runs" else
              f"union_kernel<{p},{lanes},{bits}>")
     counters = kernel_traffic(args.config, p, depth, kernel, kname, args.order)

@@ -120,8 +120,8 @@ typedef struct {
 } hb_result;
 
 /* Which union kernel a run uses. */
-#define HB_UNION_AUTO 0  /* the grouped kernel for p = 10 (8- or 4-bit registers) when the graph
-                            has its group lists and at least 32,768 nodes, else the run kernel
+#define HB_UNION_AUTO 0  /* the grouped kernel where it is built (below) when the graph has
+                            its group lists and at least 32,768 nodes, else the run kernel
                             when p <= 12, its table fits and the graph has its run list, else
                             per edge (blocking runs; the batched and served forms use the run
                             or per-edge kernel) */
@@ -131,7 +131,8 @@ typedef struct {
                             reading the run list decoded at load */
 #define HB_UNION_GROUPS 3 /* the run kernel's table rows, merged at load over groups of 16
                              consecutive nodes of the processing order: each distinct row is
-                             loaded once per group (p = 10, 8- or 4-bit registers) */
+                             loaded once per group (counters of 512 to 4096 bytes: p = 9..12
+                             with 8-bit registers, p = 10..12 with 4-bit) */
 
 /*
  * Run options; an all-zero struct (or NULL) selects the defaults.

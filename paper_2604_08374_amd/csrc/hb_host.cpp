@@ -649,8 +649,10 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
         return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
-    if (o.union_kernel == HB_UNION_GROUPS && p != 10)
-        return fail(HB_EINVAL, "the grouped kernel supports p = 10");
+    if (o.union_kernel == HB_UNION_GROUPS &&
+        !hbk::group_ok((int)p, o.register_bits ? o.register_bits : 8u))
+        return fail(HB_EINVAL,
+                    "the grouped kernel supports p = 9..12 (8-bit registers) or 10..12 (4-bit)");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     const bool depth_only = lib.stop_rule == HB_STOP_DEPTH;
     if (depth_only && depth_limit == 0)
@@ -671,12 +673,12 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     const bool have_groups = g->d_grp_rows && levels == g->grp_levels;
     if (o.union_kernel == HB_UNION_GROUPS && !have_groups)
         return fail(HB_EINVAL, "the graph has no group lists for table depth %u", levels);
-    // the grouped kernel is the default where it is built (p = 10) and the graph
-    // has enough groups to fill the device (on a 709-node graph a grouped launch
-    // takes 43 us against 12 us for the run kernel)
+    // the grouped kernel is the default where it is built (counters of 512 to
+    // 4096 bytes) and the graph has enough groups to fill the device (on a
+    // 709-node graph a grouped launch takes 43 us against 12 us for the run kernel)
     bool groups = o.union_kernel == HB_UNION_GROUPS ||
-                  (o.union_kernel == HB_UNION_AUTO && p == 10 && have_groups &&
-                   n >= kGroupsMinNodes);
+                  (o.union_kernel == HB_UNION_AUTO && hbk::group_ok((int)p, bits) &&
+                   have_groups && n >= kGroupsMinNodes);
     bool runs = groups || (o.union_kernel == HB_UNION_RUNS) ||
                 (o.union_kernel == HB_UNION_AUTO && p <= 12);
     if (runs && (uint64_t)(levels + 1) * n >= (1ull << 32)) {
@@ -853,7 +855,8 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     out->union_kernel = groups ? HB_UNION_GROUPS : (runs ? HB_UNION_RUNS : HB_UNION_EDGES);
     out->table_levels = runs ? levels : 0u;
     out->lanes_per_node = groups ? 64u : sched.lanes;
-    out->nodes_per_block = groups ? hbk::group_nodes_per_block(bits) : sched.nodes_per_block;
+    out->nodes_per_block = groups ? hbk::group_nodes_per_block((int)p, bits)
+                                  : sched.nodes_per_block;
     out->register_bits = bits;
     out->tune_ms = tune_ms;
     out->t_submit_ns = t_start;

@@ -108,18 +108,30 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
                              const uint32_t *order, double thr, const uint32_t *skip,
                              hipStream_t stream);
 
-// The same step from per-group row lists (p = 10, 8- or 4-bit registers):
-// group g holds nodes g * kGroupNodes .. of the processing order, and its rows
-// grp_rows[grp_off[g] ..] (table row indices k n + i) with masks of the group's
-// nodes that need them (bit w: node g * kGroupNodes + w; a node's own row
-// included), rows of equal masks next to each other.  group_waves(bits) waves
-// share a group, each on a 512-byte slice of every counter.
+// The same step from per-group row lists: group g holds nodes g * kGroupNodes
+// .. of the processing order, and its rows grp_rows[grp_off[g] ..] (table row
+// indices k n + i) with masks of the group's nodes that need them (bit w: node
+// g * kGroupNodes + w; a node's own row included), rows of equal masks next to
+// each other.  group_waves(p, bits) waves share a group, each on a 512-byte
+// slice of every counter: built where a counter is 512 to 4096 bytes
+// (group_ok), p = 9..12 with 8-bit registers and p = 10..12 with 4-bit.
 constexpr uint32_t kGroupNodes = 16;
-constexpr uint32_t group_waves(uint32_t bits) { return bits == 8 ? 2u : 1u; }
+constexpr uint32_t kGroupSlice = 512;
+constexpr uint32_t group_counter_bytes(int p, uint32_t bits) {
+    return p < 1 || p > 16 ? 0u : (1u << p) * bits / 8u;
+}
+constexpr bool group_ok(int p, uint32_t bits) {
+    return (bits == 8u || bits == 4u) && p <= 12 &&
+           group_counter_bytes(p, bits) >= kGroupSlice;
+}
+constexpr uint32_t group_waves(int p, uint32_t bits) {
+    return group_counter_bytes(p, bits) / kGroupSlice;
+}
 using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
 static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
 uint32_t group_size();
-uint32_t group_nodes_per_block(uint32_t bits);  // nodes of one workgroup of the grouped kernel
+// nodes of one workgroup of the grouped kernel (group_ok(p, bits))
+uint32_t group_nodes_per_block(int p, uint32_t bits);
 hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
                                const GroupMask *grp_mask, const uint64_t *grp_off,
                                const uint8_t *tbl, uint8_t *next, double *c_prev, double *sum_d,

@@ -818,13 +818,18 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 // group of kGroupNodes consecutive nodes of the processing order into one list
 // of distinct rows, each with a bit mask of the group's nodes that need it
 // (their own counters included), rows of one mask next to each other.
-// group_waves(bits) waves handle a group, each on its own 512-byte slice of the
-// counters (p = 10: two waves for 8-bit registers, one for 4-bit).  A wave loads every
+// group_waves(p, bits) waves handle a group, each on its own 512-byte slice of
+// the counters (p = 10: two waves for 8-bit registers, one for 4-bit; p = 12,
+// 8-bit: eight, in a workgroup of their own).  A wave loads every
 // listed row's slice once and takes the max of the rows of one mask into a
 // running value; when the mask changes, that value goes into the accumulators
 // of the nodes in the mask, which sit in LDS, so that the per-node work is paid
 // once per distinct mask, not once per row.
-constexpr uint32_t kGroupBlock = 256;
+// Workgroup size for a counter of M bytes: four waves, or one group's waves
+// when a group has more.
+constexpr uint32_t group_block(uint32_t m) {
+    return (m / kGroupSlice) * kWave > 256u ? (m / kGroupSlice) * kWave : 256u;
+}
 constexpr int kGroupLoads = 16;  // rows in flight per wave (one batch)
 
 // This lane's part of one 512-byte counter slice: two dwords.
@@ -861,20 +866,21 @@ __device__ __forceinline__ uint32_t max_into_raw(uint32_t a, const Max8 &r) {
 }
 
 template <class C>
-__global__ __launch_bounds__(kGroupBlock) void union_groups_kernel(
+__global__ __launch_bounds__(group_block(C::M)) void union_groups_kernel(
     const uint32_t *__restrict__ grp_rows, const GroupMask *__restrict__ grp_mask,
     const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
     uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
     uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
     double thr, const uint32_t *__restrict__ skip) {
-    constexpr uint32_t W = kGroupNodes, H = group_waves(C::BITS);
+    constexpr uint32_t W = kGroupNodes, H = group_waves(C::PREC, C::BITS);
     constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
+    static_assert(kSlice == kGroupSlice && H >= 1, "512-byte slices");
     constexpr uint32_t kDw = kSlice / kWave / 4u;    // dwords per lane
     static_assert(kDw == 2, "8 bytes per lane");
     constexpr int U = kGroupLoads;  // rows per batch
     static_assert(U * kDw <= 32, "at most 32 VGPRs of loads per batch");
     static_assert(kWave % U == 0, "a batch lies in one chunk of 64 entries");
-    constexpr uint32_t kWavesPerBlock = kGroupBlock / kWave;
+    constexpr uint32_t kWavesPerBlock = group_block(C::M) / kWave;
     constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / H;
     using Slice = LaneSlice;
     __shared__ Slice s_acc[kWavesPerBlock][W][kWave];
@@ -1716,31 +1722,51 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 }
 
 uint32_t group_size() { return kGroupNodes; }
-uint32_t group_nodes_per_block(uint32_t bits) {
-    return kGroupBlock / kWave / group_waves(bits) * kGroupNodes;
+uint32_t group_nodes_per_block(int p, uint32_t bits) {
+    const uint32_t m = group_counter_bytes(p, bits);
+    return group_block(m) / kWave / group_waves(p, bits) * kGroupNodes;
 }
+
+namespace {
+template <class C>
+hipError_t launch_union_groups_c(const uint32_t *grp_rows, const GroupMask *grp_mask,
+                                 const uint64_t *grp_off, const uint8_t *tbl, uint8_t *next,
+                                 double *c_prev, double *sum_d, uint32_t *flag_t, uint32_t n,
+                                 uint32_t t, const uint32_t *order, double thr,
+                                 const uint32_t *skip, hipStream_t stream) {
+    constexpr uint32_t block = group_block(C::M);
+    constexpr uint32_t per_block = block / kWave / group_waves(C::PREC, C::BITS);
+    const uint32_t n_groups = (n + kGroupNodes - 1u) / kGroupNodes;
+    const uint32_t blocks = (n_groups + per_block - 1u) / per_block;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((union_groups_kernel<C>), dim3(blocks), dim3(block), 0, stream, grp_rows,
+                       grp_mask, grp_off, tbl, next, c_prev, sum_d, flag_t, n, t, order, thr,
+                       skip);
+    return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
                                const GroupMask *grp_mask, const uint64_t *grp_off,
                                const uint8_t *tbl, uint8_t *next, double *c_prev, double *sum_d,
                                uint32_t *flag_t, uint32_t n, uint32_t t, const uint32_t *order,
                                double thr, const uint32_t *skip, hipStream_t stream) {
-    if (p != 10 || (bits != 8 && bits != 4)) return hipErrorInvalidValue;
-    const uint32_t per_block = kGroupBlock / kWave / group_waves(bits);
-    const uint32_t n_groups = (n + kGroupNodes - 1u) / kGroupNodes;
-    const uint32_t blocks = (n_groups + per_block - 1u) / per_block;
-    if (blocks == 0) return hipSuccess;
     // Cfg fixes the counter size, the register width and the estimator's
-    // constants; the lanes-per-node field is not used by this kernel
-    if (bits == 8)
-        hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 64, 8>>), dim3(blocks),
-                           dim3(kGroupBlock), 0, stream, grp_rows, grp_mask, grp_off, tbl, next,
-                           c_prev, sum_d, flag_t, n, t, order, thr, skip);
-    else
-        hipLaunchKernelGGL((union_groups_kernel<Cfg<10, 32, 4>>), dim3(blocks),
-                           dim3(kGroupBlock), 0, stream, grp_rows, grp_mask, grp_off, tbl, next,
-                           c_prev, sum_d, flag_t, n, t, order, thr, skip);
-    return hipGetLastError();
+    // constants; its lanes-per-node field is not used by this kernel
+#define HB_G(P, L, B)                                                                         \
+    if (p == P && bits == B)                                                                  \
+        return launch_union_groups_c<Cfg<P, L, B>>(grp_rows, grp_mask, grp_off, tbl, next,    \
+                                                   c_prev, sum_d, flag_t, n, t, order, thr,   \
+                                                   skip, stream);
+    HB_G(9, 32, 8)
+    HB_G(10, 64, 8)
+    HB_G(11, 128, 8)
+    HB_G(12, 256, 8)
+    HB_G(10, 32, 4)
+    HB_G(11, 64, 4)
+    HB_G(12, 128, 4)
+#undef HB_G
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32_t table_rows,
