@@ -123,8 +123,7 @@ typedef struct {
 #define HB_UNION_AUTO 0  /* the grouped kernel where it is built (below) when the graph has
                             its group lists and at least 32,768 nodes, else the run kernel
                             when p <= 12, its table fits and the graph has its run list, else
-                            per edge (blocking runs; the batched and served forms use the run
-                            or per-edge kernel) */
+                            per edge (in every form: blocking, batched, served) */
 #define HB_UNION_EDGES 1 /* gather every neighbour's counter (Eq. 2 as written), decoding the
                             LEB128 row in the kernel */
 #define HB_UNION_RUNS 2  /* cover runs of consecutive neighbour ids from a range-max table,

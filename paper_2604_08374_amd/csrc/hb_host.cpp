@@ -957,6 +957,7 @@ struct BatchClass {
     uint32_t p;
     bool runs;
     std::vector<uint32_t> list;
+    bool groups = false;                    // grouped kernel (its tables as for runs)
     uint64_t nodes = 0, rows = 0;           // tuner shape class
     hbk::Sched sched{};                     // union schedule
     bool measure = false;                   // pick it by measurement in this call
@@ -967,6 +968,14 @@ struct BatchClass {
         const uint32_t npb = hbk::shape_for((int)p, s).nodes_per_block;
         std::vector<uint32_t> b(1, 0u);
         for (uint32_t j : list) b.push_back(b.back() + (hj[j].n + npb - 1) / npb);
+        return b;
+    }
+    // Block bases of the union step: the grouped kernel's, else those of s.
+    std::vector<uint32_t> union_bases(const std::vector<hbk::BatchJob> &hj, const hbk::Sched &s,
+                                      uint32_t bits) const {
+        if (!groups) return bases(hj, s);
+        std::vector<uint32_t> b(1, 0u);
+        for (uint32_t j : list) b.push_back(b.back() + hbk::group_blocks((int)p, bits, hj[j].n));
         return b;
     }
 };
@@ -980,7 +989,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     if (n_jobs > 65535) return fail(HB_EINVAL, "at most 65535 jobs per batch");
     const hb_run_opts o = opts ? *opts : hb_run_opts{};
     const hb_options lib = options();
-    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
+    if (o.union_kernel > HB_UNION_GROUPS)
+        return fail(HB_EINVAL, "unknown union kernel %u", o.union_kernel);
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     for (uint32_t j = 0; j < n_jobs; ++j) {
         hbk::Sched fixed{};
@@ -995,6 +1005,9 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
             return fail(HB_EINVAL, "job %u: p = %u outside [4, 16]", j, jobs[j].p);
         if (o.union_kernel == HB_UNION_RUNS && jobs[j].p > 12)
             return fail(HB_EINVAL, "job %u: the run kernel supports p <= 12", j);
+        if (o.union_kernel == HB_UNION_GROUPS &&
+            !hbk::group_ok((int)jobs[j].p, o.register_bits ? o.register_bits : 8u))
+            return fail(HB_EINVAL, "job %u: no grouped kernel for p = %u", j, jobs[j].p);
         if (jobs[j].g->device != jobs[0].g->device)
             return fail(HB_EINVAL, "all graphs of a batch must live on one device");
     }
@@ -1012,7 +1025,8 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         const uint32_t p = jobs[j].p;
         const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
         uint32_t levels = std::min(o.table_levels ? o.table_levels : kDefaultLevels, floor_log2(g->n));
-        bool runs = o.union_kernel == HB_UNION_RUNS || (o.union_kernel == HB_UNION_AUTO && p <= 12);
+        bool runs = o.union_kernel == HB_UNION_RUNS || o.union_kernel == HB_UNION_GROUPS ||
+                    (o.union_kernel == HB_UNION_AUTO && p <= 12);
         if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
             if (o.union_kernel == HB_UNION_RUNS)
                 return fail(HB_EINVAL, "job %u: table rows (levels + 1) * n must stay below 2^32", j);
@@ -1024,6 +1038,16 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
             runs = false;
         }
         if (!runs) levels = 0;
+        // the grouped kernel where it is built and the graph has its lists for this
+        // table depth, as in a blocking run
+        const bool can_groups = runs && hbk::group_ok((int)p, bits) && g->d_grp_rows &&
+                                levels == g->grp_levels;
+        if (o.union_kernel == HB_UNION_GROUPS && !can_groups)
+            return fail(HB_EINVAL, "job %u: the graph has no group lists for table depth %u", j,
+                        levels);
+        const bool groups = o.union_kernel == HB_UNION_GROUPS ||
+                            (o.union_kernel == HB_UNION_AUTO && can_groups &&
+                             g->n >= kGroupsMinNodes);
         hbk::BatchJob &b = hj[j];
         b = hbk::BatchJob{};
         b.bytes = g->d_bytes;
@@ -1042,6 +1066,12 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         b.bits = bits;
         b.depth_only = lib.stop_rule == HB_STOP_DEPTH ? 1u : 0u;
         b.stop_delta = lib.stop_delta > 0.0 ? lib.stop_delta : 0.5;
+        if (groups) {
+            b.groups = 1u;
+            b.grp_rows = g->d_grp_rows;
+            b.grp_mask = g->d_grp_mask;
+            b.grp_off = g->d_grp_off;
+        }
         off_buf[j] = arena;
         arena += 2 * align256((uint64_t)g->n * m * (levels + 1u));
         off_state[j] = arena;
@@ -1090,10 +1120,12 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         if (hj[j].runs) runs_list.push_back(j);
         BatchClass *c = nullptr;
         for (auto &x : classes)
-            if (x.p == hj[j].p && x.runs == (hj[j].runs != 0)) c = &x;
+            if (x.p == hj[j].p && x.runs == (hj[j].runs != 0) && x.groups == (hj[j].groups != 0))
+                c = &x;
         if (!c) {
             classes.push_back(BatchClass{hj[j].p, hj[j].runs != 0, {}});
             c = &classes.back();
+            c->groups = hj[j].groups != 0;
         }
         c->list.push_back(j);
         c->nodes += hj[j].n;
@@ -1104,7 +1136,9 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         hbk::Sched fixed{};
         (void)explicit_sched(o, c.p, &fixed);
         c.sched = hbk::default_sched((int)c.p, bits, c.runs);
-        if (fixed.lanes) {
+        if (c.groups) {
+            // one launch shape: nothing to tune
+        } else if (fixed.lanes) {
             c.sched = fixed;
         } else if (o.tune != HB_TUNE_OFF &&
                    !tune_get(tune_key(c.p, bits, c.runs, true, c.nodes, c.rows), &c.sched)) {
@@ -1203,7 +1237,7 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
     }
     // ---- the union bases of the chosen schedules
     for (auto &c : classes) {
-        const std::vector<uint32_t> b = c.bases(hj, c.sched);
+        const std::vector<uint32_t> b = c.union_bases(hj, c.sched, bits);
         c.base_off = (uint32_t)lists.size();
         lists.insert(lists.end(), b.begin(), b.end());
         c.nblocks = b.back();
@@ -1228,9 +1262,14 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
                                         (uint32_t)runs_list.size(), table_blocks[k], k, s);
         for (auto &c : classes) {
             if (e != hipSuccess) break;
-            e = hbk::launch_batch_union((int)c.p, c.sched, c.runs, R.d_jobs,
-                                        R.d_lists + c.list_off, R.d_lists + c.base_off,
-                                        (uint32_t)c.list.size(), c.nblocks, s);
+            e = c.groups ? hbk::launch_batch_groups((int)c.p, bits, R.d_jobs,
+                                                    R.d_lists + c.list_off,
+                                                    R.d_lists + c.base_off,
+                                                    (uint32_t)c.list.size(), c.nblocks, s)
+                         : hbk::launch_batch_union((int)c.p, c.sched, c.runs, R.d_jobs,
+                                                   R.d_lists + c.list_off,
+                                                   R.d_lists + c.base_off,
+                                                   (uint32_t)c.list.size(), c.nblocks, s);
         }
         if (e == hipSuccess) e = hbk::launch_batch_step_end(R.d_jobs, R.d_lists, n_jobs, s);
         const hipError_t e2 = hipStreamEndCapture(s, &SG.graph);
@@ -1293,12 +1332,13 @@ hb_status hb_run_batch(const hb_job *jobs, uint32_t n_jobs, const hb_run_opts *o
         out->iter_ms = 0.0;
         out->table_ms = 0.0;
         out->run_ms = run_ms;
-        out->union_kernel = b.runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+        out->union_kernel = b.groups ? HB_UNION_GROUPS : (b.runs ? HB_UNION_RUNS : HB_UNION_EDGES);
         out->table_levels = b.levels;
         for (const auto &c : classes)
-            if (c.p == b.p && c.runs == (b.runs != 0)) {
-                out->lanes_per_node = c.sched.lanes;
-                out->nodes_per_block = c.sched.nodes_per_block;
+            if (c.p == b.p && c.runs == (b.runs != 0) && c.groups == (b.groups != 0)) {
+                out->lanes_per_node = c.groups ? 64u : c.sched.lanes;
+                out->nodes_per_block = c.groups ? hbk::group_nodes_per_block((int)b.p, bits)
+                                                : c.sched.nodes_per_block;
             }
         out->register_bits = bits;
         out->tune_ms = tune_ms;

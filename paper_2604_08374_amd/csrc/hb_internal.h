@@ -9,6 +9,25 @@
 
 namespace hbk {
 
+// Grouped union kernel: nodes are taken in groups of kGroupNodes consecutive
+// nodes of the processing order; group_waves(p, bits) waves share a group, each
+// on a 512-byte slice of every counter.  Built where a counter is 512 to 4096
+// bytes (group_ok): p = 9..12 with 8-bit registers, p = 10..12 with 4-bit.
+constexpr uint32_t kGroupNodes = 16;
+constexpr uint32_t kGroupSlice = 512;
+constexpr uint32_t group_counter_bytes(int p, uint32_t bits) {
+    return p < 1 || p > 16 ? 0u : (1u << p) * bits / 8u;
+}
+constexpr bool group_ok(int p, uint32_t bits) {
+    return (bits == 8u || bits == 4u) && p <= 12 &&
+           group_counter_bytes(p, bits) >= kGroupSlice;
+}
+constexpr uint32_t group_waves(int p, uint32_t bits) {
+    return group_counter_bytes(p, bits) / kGroupSlice;
+}
+using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
+static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
+
 // One job of a batched run, in device memory.  The host fills every field
 // before the first step; the step-end kernel advances t, done and converged.
 struct BatchJob {
@@ -31,6 +50,10 @@ struct BatchJob {
     uint32_t converged;       // 1 if the last step grew no estimate by more than stop_delta
     uint32_t depth_only;      // 1: stop at the depth limit only (ignore the growth test)
     double stop_delta;        // the growth test's threshold (Alg. 1: 0.5)
+    const uint32_t *grp_rows; // grouped kernel's row lists (groups == 1), as for
+    const GroupMask *grp_mask;//   launch_union_groups
+    const uint64_t *grp_off;
+    uint32_t groups;          // 1: grouped kernel (runs is 1 as well: its tables are built)
 };
 
 // Launch schedule of the union kernels for one precision p:
@@ -71,6 +94,13 @@ hipError_t launch_batch_init(int p, const Sched &s, BatchJob *jobs, const uint32
 hipError_t launch_batch_union(int p, const Sched &s, bool runs, BatchJob *jobs,
                               const uint32_t *list, const uint32_t *block_base, uint32_t nlist,
                               uint32_t nblocks, hipStream_t stream);
+// The grouped kernel over listed jobs of one (p, bits) with group lists: job
+// list[i] owns workgroups [block_base[i], block_base[i+1]),
+// group_blocks(p, bits, n) of them.
+uint32_t group_blocks(int p, uint32_t bits, uint32_t n);
+hipError_t launch_batch_groups(int p, uint32_t bits, BatchJob *jobs, const uint32_t *list,
+                               const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                               hipStream_t stream);
 // Table level k for listed run-kernel jobs with levels >= k; job list[i] owns
 // workgroups [block_base[i], block_base[i+1]), batch_table_blocks(n, p, k) of them.
 uint32_t batch_table_blocks(uint32_t n, uint32_t row_bytes, uint32_t k);
@@ -115,20 +145,6 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 // each other.  group_waves(p, bits) waves share a group, each on a 512-byte
 // slice of every counter: built where a counter is 512 to 4096 bytes
 // (group_ok), p = 9..12 with 8-bit registers and p = 10..12 with 4-bit.
-constexpr uint32_t kGroupNodes = 16;
-constexpr uint32_t kGroupSlice = 512;
-constexpr uint32_t group_counter_bytes(int p, uint32_t bits) {
-    return p < 1 || p > 16 ? 0u : (1u << p) * bits / 8u;
-}
-constexpr bool group_ok(int p, uint32_t bits) {
-    return (bits == 8u || bits == 4u) && p <= 12 &&
-           group_counter_bytes(p, bits) >= kGroupSlice;
-}
-constexpr uint32_t group_waves(int p, uint32_t bits) {
-    return group_counter_bytes(p, bits) / kGroupSlice;
-}
-using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
-static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
 uint32_t group_size();
 // nodes of one workgroup of the grouped kernel (group_ok(p, bits))
 uint32_t group_nodes_per_block(int p, uint32_t bits);

@@ -865,13 +865,15 @@ __device__ __forceinline__ uint32_t max_into_raw(uint32_t a, const Max8 &r) {
     return b.value();
 }
 
+// One workgroup of the grouped step: logical block lb holds groups
+// lb * (groups per workgroup) ..; every wave of the workgroup calls it.
 template <class C>
-__global__ __launch_bounds__(group_block(C::M)) void union_groups_kernel(
+__device__ __forceinline__ void groups_step(
     const uint32_t *__restrict__ grp_rows, const GroupMask *__restrict__ grp_mask,
     const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
     uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
     uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
-    double thr, const uint32_t *__restrict__ skip) {
+    double thr, uint32_t lb) {
     constexpr uint32_t W = kGroupNodes, H = group_waves(C::PREC, C::BITS);
     constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
     static_assert(kSlice == kGroupSlice && H >= 1, "512-byte slices");
@@ -887,10 +889,8 @@ __global__ __launch_bounds__(group_block(C::M)) void union_groups_kernel(
     __shared__ uint64_t s_lo[kWavesPerBlock][W];
     __shared__ uint64_t s_hi[kWavesPerBlock][W];
     __shared__ uint32_t s_z[kWavesPerBlock][W];
-    if (skip && *skip == 0u) return;  // the previous step stopped the run (whole launch)
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const uint32_t grp =
-        xcd_span_block(blockIdx.x, gridDim.x, kXcdSpanChunk) * kGroupsPerBlock + wave / H;
+    const uint32_t grp = lb * kGroupsPerBlock + wave / H;
     const uint32_t part = wave % H;
     const uint32_t n_groups = (n + W - 1u) / W;
     const bool active = grp < n_groups;  // every wave reaches the barrier below
@@ -1000,6 +1000,18 @@ __global__ __launch_bounds__(group_block(C::M)) void union_groups_kernel(
             __hip_atomic_load(flag_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
             __hip_atomic_store(flag_t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+template <class C>
+__global__ __launch_bounds__(group_block(C::M)) void union_groups_kernel(
+    const uint32_t *__restrict__ grp_rows, const GroupMask *__restrict__ grp_mask,
+    const uint64_t *__restrict__ grp_off, const uint8_t *__restrict__ tbl,
+    uint8_t *__restrict__ next, double *__restrict__ c_prev, double *__restrict__ sum_d,
+    uint32_t *__restrict__ flag_t, uint32_t n, uint32_t t, const uint32_t *__restrict__ order,
+    double thr, const uint32_t *__restrict__ skip) {
+    if (skip && *skip == 0u) return;  // the previous step stopped the run (whole launch)
+    groups_step<C>(grp_rows, grp_mask, grp_off, tbl, next, c_prev, sum_d, flag_t, n, t, order,
+                   thr, xcd_span_block(blockIdx.x, gridDim.x, kXcdSpanChunk));
 }
 
 // ---------------------------------------------------------------- gather ceiling
@@ -1208,6 +1220,22 @@ __global__ __launch_bounds__(C::THREADS, RUNS ? C::RUN_OCC : 1) void batch_union
         union_node_edges<C>(J.bytes, J.offsets, cur, next, J.c_prev, J.sum_d, J.flags + t, v,
                             slice, t, J.stop_delta);
     }
+}
+
+// The grouped step for listed jobs: job list[i]'s workgroups hold its groups,
+// all XCDs on one stretch of its processing order as in a single run.
+template <class C>
+__global__ __launch_bounds__(group_block(C::M)) void batch_groups_kernel(
+    BatchJob *__restrict__ jobs, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ block_base, uint32_t nlist) {
+    const uint32_t i = find_job(block_base, nlist, blockIdx.x);
+    const BatchJob &J = jobs[list[i]];
+    if (J.done) return;  // uniform per workgroup
+    const uint32_t t = J.t + 1u;
+    const uint32_t lb = xcd_span_block(blockIdx.x - block_base[i],
+                                       block_base[i + 1] - block_base[i], kXcdSpanChunk);
+    groups_step<C>(J.grp_rows, J.grp_mask, J.grp_off, J.buf[(t - 1u) & 1u], J.buf[t & 1u],
+                   J.c_prev, J.sum_d, J.flags + t, J.n, t, J.order, J.stop_delta, lb);
 }
 
 // Table level k for a list of jobs: workgroup blk handles 16-byte chunks
@@ -1758,6 +1786,35 @@ hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
         return launch_union_groups_c<Cfg<P, L, B>>(grp_rows, grp_mask, grp_off, tbl, next,    \
                                                    c_prev, sum_d, flag_t, n, t, order, thr,   \
                                                    skip, stream);
+    HB_G(9, 32, 8)
+    HB_G(10, 64, 8)
+    HB_G(11, 128, 8)
+    HB_G(12, 256, 8)
+    HB_G(10, 32, 4)
+    HB_G(11, 64, 4)
+    HB_G(12, 128, 4)
+#undef HB_G
+    return hipErrorInvalidValue;
+}
+
+uint32_t group_blocks(int p, uint32_t bits, uint32_t n) {
+    const uint32_t per_block =
+        group_block(group_counter_bytes(p, bits)) / kWave / group_waves(p, bits);
+    const uint32_t n_groups = (n + kGroupNodes - 1u) / kGroupNodes;
+    return (n_groups + per_block - 1u) / per_block;
+}
+
+hipError_t launch_batch_groups(int p, uint32_t bits, BatchJob *jobs, const uint32_t *list,
+                               const uint32_t *block_base, uint32_t nlist, uint32_t nblocks,
+                               hipStream_t stream) {
+    if (nblocks == 0) return hipSuccess;
+#define HB_G(P, L, B)                                                                        \
+    if (p == P && bits == B) {                                                               \
+        hipLaunchKernelGGL((batch_groups_kernel<Cfg<P, L, B>>), dim3(nblocks),              \
+                           dim3(group_block(Cfg<P, L, B>::M)), 0, stream, jobs, list,       \
+                           block_base, nlist);                                               \
+        return hipGetLastError();                                                            \
+    }
     HB_G(9, 32, 8)
     HB_G(10, 64, 8)
     HB_G(11, 128, 8)

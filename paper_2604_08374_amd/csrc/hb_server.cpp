@@ -48,6 +48,7 @@ struct Request {
     uint32_t bits = 8;  // register width
     uint64_t seed = 0;
     bool runs = false;
+    bool groups = false;  // grouped kernel (its tables as for runs)
     uint32_t levels = 0;
     uint64_t footprint = 0;
     void *mem = nullptr;  // pool memory while running
@@ -97,7 +98,8 @@ private:
     hb_status step(Lane &L);
     void fail_all(Lane &L, hb_status st, const std::string &msg);
     void retire(Lane &L, Request *r);
-    hb_status footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs, uint32_t &levels,
+    hb_status footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs, bool &groups,
+                        uint32_t &levels,
                         uint64_t &bytes) const;
 
     std::mutex mu_;  // guards everything below that client threads touch
@@ -116,21 +118,31 @@ private:
 };
 
 hb_status Server::footprint(const hb_graph *g, uint32_t p, uint32_t bits, bool &runs,
-                            uint32_t &levels, uint64_t &bytes) const {
+                            bool &groups, uint32_t &levels, uint64_t &bytes) const {
     const uint64_t m = (1ull << p) * bits / 8u;  // bytes per counter
     levels = std::min(opts_.table_levels ? opts_.table_levels : kDefaultLevels, floor_log2(g->n));
-    runs = opts_.union_kernel == HB_UNION_RUNS || (opts_.union_kernel == HB_UNION_AUTO && p <= 12);
+    runs = opts_.union_kernel == HB_UNION_RUNS || opts_.union_kernel == HB_UNION_GROUPS ||
+           (opts_.union_kernel == HB_UNION_AUTO && p <= 12);
+    const bool forced = opts_.union_kernel == HB_UNION_RUNS || opts_.union_kernel == HB_UNION_GROUPS;
     if (runs && (uint64_t)(levels + 1) * g->n >= (1ull << 32)) {
-        if (opts_.union_kernel == HB_UNION_RUNS)
+        if (forced)
             return fail(HB_EINVAL, "table rows (levels + 1) * n must stay below 2^32");
         runs = false;
     }
     if (runs && !g->d_runs) {
-        if (opts_.union_kernel == HB_UNION_RUNS)
+        if (forced)
             return fail(HB_ENOMEM, "the graph's run list did not fit in device memory at load");
         runs = false;
     }
     if (!runs) levels = 0;
+    // the grouped kernel where it is built, as in a blocking run
+    const bool can_groups = runs && hbk::group_ok((int)p, bits) && g->d_grp_rows &&
+                            levels == g->grp_levels;
+    if (opts_.union_kernel == HB_UNION_GROUPS && !can_groups)
+        return fail(HB_EINVAL, "no grouped kernel for p = %u or no group lists for depth %u", p,
+                    levels);
+    groups = opts_.union_kernel == HB_UNION_GROUPS ||
+             (opts_.union_kernel == HB_UNION_AUTO && can_groups && g->n >= kGroupsMinNodes);
     const uint64_t n_flags = (uint64_t)g->n + 2;
     bytes = 2 * align256((uint64_t)g->n * m * (levels + 1u)) + 2 * align256(8ull * g->n) +
             align256(4ull * n_flags);
@@ -141,7 +153,7 @@ hb_status Server::start(const hb_server_opts *opts) {
     std::lock_guard<std::mutex> lk(mu_);
     if (running_) return fail(HB_EBUSY, "the request loop is already running");
     hb_server_opts o = opts ? *opts : hb_server_opts{};
-    if (o.union_kernel > HB_UNION_RUNS) return fail(HB_EINVAL, "unknown union kernel");
+    if (o.union_kernel > HB_UNION_GROUPS) return fail(HB_EINVAL, "unknown union kernel");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels > 24");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(HB_EDEVICE, "no GPU available");
@@ -207,7 +219,7 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
     auto r = std::make_unique<Request>();
     if (opts_.union_kernel == HB_UNION_RUNS && p > 12)
         return fail(HB_EINVAL, "the run kernel supports p <= 12");
-    hb_status st = footprint(g, p, bits, r->runs, r->levels, r->footprint);
+    hb_status st = footprint(g, p, bits, r->runs, r->groups, r->levels, r->footprint);
     if (st != HB_OK) return st;
     const hb_options lib = options();
     if (lib.stop_rule == HB_STOP_DEPTH && depth == 0)
@@ -226,8 +238,10 @@ hb_status Server::submit(hb_graph *g, uint32_t p, uint32_t depth, uint64_t seed,
     r->flags = flags;
     r->bits = bits;
     r->t_submit = now_ns();
-    // bytes one step gathers: counter rows (table rows for the run kernel) x counter bytes
-    const uint64_t rows = r->runs ? g->runs.lookups[r->levels] : g->n_edges;
+    // bytes one step gathers: counter rows (table rows for the run kernel, the group
+    // lists' rows for the grouped one) x counter bytes
+    const uint64_t rows = r->groups ? g->grp_entries
+                          : r->runs ? g->runs.lookups[r->levels] : g->n_edges;
     const int lane = rows * ((1ull << p) * bits / 8u) > slow_bytes_ ? 1 : 0;
     g->inflight.fetch_add(1);
     *out = r->ticket;
@@ -273,10 +287,12 @@ hb_status Server::poll(hb_ticket t, hb_result *out, bool block) {
     out->edge_unions = (uint64_t)r->job.done * r->g->n_edges;
     out->init_ms = out->iter_ms = out->table_ms = 0.0;
     out->run_ms = (double)(r->t_end - r->t_admit) / 1e6;
-    out->union_kernel = r->runs ? HB_UNION_RUNS : HB_UNION_EDGES;
+    out->union_kernel = r->groups ? HB_UNION_GROUPS : (r->runs ? HB_UNION_RUNS : HB_UNION_EDGES);
     out->table_levels = r->levels;
-    out->lanes_per_node = hbk::default_sched((int)r->p, r->bits, r->runs).lanes;
-    out->nodes_per_block = hbk::default_sched((int)r->p, r->bits, r->runs).nodes_per_block;
+    out->lanes_per_node = r->groups ? 64u : hbk::default_sched((int)r->p, r->bits, r->runs).lanes;
+    out->nodes_per_block = r->groups ? hbk::group_nodes_per_block((int)r->p, r->bits)
+                                     : hbk::default_sched((int)r->p, r->bits, r->runs)
+                                           .nodes_per_block;
     out->register_bits = r->bits;
     out->tune_ms = 0.0;
     out->t_submit_ns = r->t_submit;
@@ -398,6 +414,12 @@ hb_status Server::step(Lane &L) {
         b.bits = r->bits;
         b.depth_only = lib.stop_rule == HB_STOP_DEPTH ? 1u : 0u;
         b.stop_delta = lib.stop_delta > 0.0 ? lib.stop_delta : 0.5;
+        if (r->groups) {
+            b.groups = 1u;
+            b.grp_rows = g->d_grp_rows;
+            b.grp_mask = g->d_grp_mask;
+            b.grp_off = g->d_grp_off;
+        }
         L.running.push_back(r);
     }
     const uint32_t nj = (uint32_t)L.running.size();
@@ -419,7 +441,7 @@ hb_status Server::step(Lane &L) {
     for (uint32_t j = 0; j < nj; ++j) h_jobs_[j] = L.running[j]->job;
     struct Cls {
         uint32_t p;
-        bool runs;
+        bool runs, groups;
         uint32_t bits;
         std::vector<uint32_t> list, base;
         uint32_t list_off, base_off;
@@ -427,33 +449,40 @@ hb_status Server::step(Lane &L) {
     std::vector<Cls> classes, inits;
     std::vector<uint32_t> all(nj), runs_list, new_list;
     uint32_t max_levels = 0;
-    auto add_to = [&](std::vector<Cls> &cs, uint32_t j, bool runs) {
+    auto add_to = [&](std::vector<Cls> &cs, uint32_t j, bool runs, bool groups) {
         Cls *c = nullptr;
         for (auto &x : cs)
-            if (x.p == h_jobs_[j].p && x.runs == runs && x.bits == h_jobs_[j].bits) c = &x;
+            if (x.p == h_jobs_[j].p && x.runs == runs && x.groups == groups &&
+                x.bits == h_jobs_[j].bits)
+                c = &x;
         if (!c) {
-            cs.push_back(Cls{h_jobs_[j].p, runs, h_jobs_[j].bits, {}, {0u}, 0, 0});
+            cs.push_back(Cls{h_jobs_[j].p, runs, groups, h_jobs_[j].bits, {}, {0u}, 0, 0});
             c = &cs.back();
         }
         // the default schedule: a served step's class mix changes from step to step
         const int p = (int)h_jobs_[j].p;
-        const uint32_t npb =
-            hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits, runs)).nodes_per_block;
+        const uint32_t blocks =
+            groups ? hbk::group_blocks(p, h_jobs_[j].bits, h_jobs_[j].n)
+                   : (h_jobs_[j].n +
+                      hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits, runs))
+                          .nodes_per_block - 1) /
+                         hbk::shape_for(p, hbk::default_sched(p, h_jobs_[j].bits, runs))
+                             .nodes_per_block;
         c->list.push_back(j);
-        c->base.push_back(c->base.back() + (h_jobs_[j].n + npb - 1) / npb);
+        c->base.push_back(c->base.back() + blocks);
     };
     for (uint32_t j = 0; j < nj; ++j) {
         all[j] = j;
         const bool is_new = j >= nj - admitted.size();
         if (is_new) {
             new_list.push_back(j);
-            add_to(inits, j, false);
+            add_to(inits, j, false, false);
         }
         if (h_jobs_[j].runs) {
             runs_list.push_back(j);
             max_levels = std::max(max_levels, h_jobs_[j].levels);
         }
-        add_to(classes, j, h_jobs_[j].runs != 0);
+        add_to(classes, j, h_jobs_[j].runs != 0, h_jobs_[j].groups != 0);
     }
     std::vector<uint32_t> lists(all);
     const uint32_t runs_off = (uint32_t)lists.size();
@@ -506,12 +535,17 @@ hb_status Server::step(Lane &L) {
     for (uint32_t k = 1; k <= max_levels; ++k)
         HB_HIP(hbk::launch_batch_table(d_jobs_, d_lists_ + runs_off, d_lists_ + table_off[k],
                                        (uint32_t)runs_list.size(), table_blocks[k], k, s));
-    for (auto &c : classes)
-        HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p, c.bits, c.runs),
-                                       c.runs, d_jobs_,
-                                       d_lists_ + c.list_off,
-                                       d_lists_ + c.base_off, (uint32_t)c.list.size(),
-                                       c.base.back(), s));
+    for (auto &c : classes) {
+        if (c.groups)
+            HB_HIP(hbk::launch_batch_groups((int)c.p, c.bits, d_jobs_, d_lists_ + c.list_off,
+                                            d_lists_ + c.base_off, (uint32_t)c.list.size(),
+                                            c.base.back(), s));
+        else
+            HB_HIP(hbk::launch_batch_union((int)c.p, hbk::default_sched((int)c.p, c.bits, c.runs),
+                                           c.runs, d_jobs_, d_lists_ + c.list_off,
+                                           d_lists_ + c.base_off, (uint32_t)c.list.size(),
+                                           c.base.back(), s));
+    }
     HB_HIP(hbk::launch_batch_step_end(d_jobs_, d_lists_, nj, s));
     HB_HIP(hipMemcpyAsync(h_jobs_, d_jobs_, sizeof(hbk::BatchJob) * nj, hipMemcpyDeviceToHost, s));
     HB_HIP(hipStreamSynchronize(s));

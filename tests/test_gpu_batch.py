@@ -81,3 +81,29 @@ def test_batch_argument_errors(hb):
         hb.run_batch([(G, 13, 0, 0)], kernel="runs")
     assert e.value.status == hb.HB_EINVAL
     G.free()
+
+
+def _sparse_large(n=34000, n_edges=200000, seed=23):
+    """Above the grouped kernel's size threshold, cheap for the oracle."""
+    rng = np.random.default_rng(seed)
+    a, b = rng.integers(0, n, n_edges), rng.integers(0, n, n_edges)
+    return synth.from_edges(n, list(zip(a.tolist(), b.tolist())), name=f"sparse{n}")
+
+
+@pytest.mark.parametrize("bits", [8, 4])
+def test_batch_grouped_jobs(hb, bits):
+    """Jobs on a graph of more than 32,768 nodes take the grouped kernel where it is
+    built (p = 9..12 with 8-bit registers, 10..12 with 4-bit), beside run-kernel jobs."""
+    g = _sparse_large()
+    G = _load(hb, g)
+    ps = [8, 9, 10, 11, 12] if bits == 8 else [9, 10, 11, 12]
+    jobs = [(G, p, (0, 3, 2)[i % 3], 100 + i) for i, p in enumerate(ps)]
+    print(f"[batch] grouped jobs n={g.n} E={g.n_edges} bits={bits}", flush=True)
+    res = hb.run_batch(jobs, registers=True, register_bits=bits)
+    for (_, p, d, seed), r in zip(jobs, res):
+        what = f"{g.name} p={p} d={d} seed={seed} bits={bits}"
+        grouped = (9 if bits == 8 else 10) <= p <= 12
+        assert r.union_kernel == ("groups" if grouped else "runs"), (what, r.union_kernel)
+        assert_matches(hb, r, ref(g, p, d, seed, register_bits=bits), what)
+        _same(r, G.run(p, d, seed, registers=True, register_bits=bits, kernel="runs"), what)
+    G.free()

@@ -211,3 +211,26 @@ def test_cache_releases_the_least_recently_used_idle_graph(hb, fresh_cache):
     assert e.value.status == hb.HB_ENOTFOUND
     assert_matches(hb, hb.submit_cached(1, 4, 2, 1, n=gs[1].n).wait(), ref(gs[1], 4, 2, 1),
                    "graph 1 stayed")
+
+
+def test_served_grouped_requests(hb, server):
+    """Requests on a graph of more than 32,768 nodes take the grouped kernel where it is
+    built, in both lanes, and match the oracle and the run kernel alone."""
+    server(slow_lane_bytes=1 << 30)
+    rng = np.random.default_rng(29)
+    n = 34000
+    a, b = rng.integers(0, n, 200000), rng.integers(0, n, 200000)
+    g = synth.from_edges(n, list(zip(a.tolist(), b.tolist())), name=f"sparse{n}")
+    G = _load(hb, g)
+    specs = [(9, 0, 1, 8), (10, 3, 2, 8), (12, 2, 3, 8), (8, 0, 4, 8), (10, 0, 5, 4),
+             (12, 3, 6, 4)]
+    tickets = [hb.submit(G, p, d, sd, registers=True, register_bits=bits)
+               for (p, d, sd, bits) in specs]
+    for (p, d, sd, bits), t in zip(specs, tickets):
+        r = t.wait()
+        what = f"{g.name} p={p} d={d} seed={sd} bits={bits}"
+        grouped = (9 if bits == 8 else 10) <= p <= 12
+        assert r.union_kernel == ("groups" if grouped else "runs"), (what, r.union_kernel)
+        assert_matches(hb, r, ref(g, p, d, sd, register_bits=bits), what)
+        _same(r, G.run(p, d, sd, registers=True, register_bits=bits, kernel="runs"), what)
+    G.free()
