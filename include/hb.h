@@ -130,8 +130,8 @@ typedef struct {
                             reading the run list decoded at load */
 #define HB_UNION_GROUPS 3 /* the run kernel's table rows, merged at load over groups of 16
                              consecutive nodes of the processing order: each distinct row is
-                             loaded once per group (counters of 512 to 4096 bytes: p = 9..12
-                             with 8-bit registers, p = 10..12 with 4-bit) */
+                             loaded once per group (counters of 256 to 4096 bytes: p = 8..12
+                             with 8-bit registers, p = 9..12 with 4-bit) */
 
 /*
  * Run options; an all-zero struct (or NULL) selects the defaults.

@@ -652,7 +652,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     if (o.union_kernel == HB_UNION_GROUPS &&
         !hbk::group_ok((int)p, o.register_bits ? o.register_bits : 8u))
         return fail(HB_EINVAL,
-                    "the grouped kernel supports p = 9..12 (8-bit registers) or 10..12 (4-bit)");
+                    "the grouped kernel supports p = 8..12 (8-bit registers) or 9..12 (4-bit)");
     if (o.table_levels > 24) return fail(HB_EINVAL, "table_levels %u > 24", o.table_levels);
     const bool depth_only = lib.stop_rule == HB_STOP_DEPTH;
     if (depth_only && depth_limit == 0)
@@ -673,7 +673,7 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     const bool have_groups = g->d_grp_rows && levels == g->grp_levels;
     if (o.union_kernel == HB_UNION_GROUPS && !have_groups)
         return fail(HB_EINVAL, "the graph has no group lists for table depth %u", levels);
-    // the grouped kernel is the default where it is built (counters of 512 to
+    // the grouped kernel is the default where it is built (counters of 256 to
     // 4096 bytes) and the graph has enough groups to fill the device (on a
     // 709-node graph a grouped launch takes 43 us against 12 us for the run kernel)
     bool groups = o.union_kernel == HB_UNION_GROUPS ||

@@ -11,8 +11,9 @@ namespace hbk {
 
 // Grouped union kernel: nodes are taken in groups of kGroupNodes consecutive
 // nodes of the processing order; group_waves(p, bits) waves share a group, each
-// on a 512-byte slice of every counter.  Built where a counter is 512 to 4096
-// bytes (group_ok): p = 9..12 with 8-bit registers, p = 10..12 with 4-bit.
+// on a 512-byte slice of every counter (one wave on a 256-byte counter).  Built
+// where a counter is 256 to 4096 bytes (group_ok): p = 8..12 with 8-bit
+// registers, p = 9..12 with 4-bit.
 constexpr uint32_t kGroupNodes = 16;
 constexpr uint32_t kGroupSlice = 512;
 constexpr uint32_t group_counter_bytes(int p, uint32_t bits) {
@@ -20,10 +21,12 @@ constexpr uint32_t group_counter_bytes(int p, uint32_t bits) {
 }
 constexpr bool group_ok(int p, uint32_t bits) {
     return (bits == 8u || bits == 4u) && p <= 12 &&
-           group_counter_bytes(p, bits) >= kGroupSlice;
+           group_counter_bytes(p, bits) >= kGroupSlice / 2u;
 }
+// waves per group: one per 512-byte slice (a 256-byte counter takes one wave)
 constexpr uint32_t group_waves(int p, uint32_t bits) {
-    return group_counter_bytes(p, bits) / kGroupSlice;
+    return group_counter_bytes(p, bits) > kGroupSlice ? group_counter_bytes(p, bits) / kGroupSlice
+                                                      : 1u;
 }
 using GroupMask = std::conditional<(kGroupNodes <= 16), uint16_t, uint32_t>::type;
 static_assert(kGroupNodes <= 32, "a mask is at most 32 bits");
@@ -142,9 +145,7 @@ hipError_t launch_union_runs(int p, const Sched &s, const uint2 *runs, const uin
 // .. of the processing order, and its rows grp_rows[grp_off[g] ..] (table row
 // indices k n + i) with masks of the group's nodes that need them (bit w: node
 // g * kGroupNodes + w; a node's own row included), rows of equal masks next to
-// each other.  group_waves(p, bits) waves share a group, each on a 512-byte
-// slice of every counter: built where a counter is 512 to 4096 bytes
-// (group_ok), p = 9..12 with 8-bit registers and p = 10..12 with 4-bit.
+// each other.  group_waves(p, bits) waves share a group (group_ok(p, bits)).
 uint32_t group_size();
 // nodes of one workgroup of the grouped kernel (group_ok(p, bits))
 uint32_t group_nodes_per_block(int p, uint32_t bits);

@@ -820,7 +820,8 @@ __global__ __launch_bounds__(C::THREADS, C::RUN_OCC) void union_runs_kernel(
 // (their own counters included), rows of one mask next to each other.
 // group_waves(p, bits) waves handle a group, each on its own 512-byte slice of
 // the counters (p = 10: two waves for 8-bit registers, one for 4-bit; p = 12,
-// 8-bit: eight, in a workgroup of their own).  A wave loads every
+// 8-bit: eight, in a workgroup of their own; a 256-byte counter: one wave, 4
+// bytes per lane).  A wave loads every
 // listed row's slice once and takes the max of the rows of one mask into a
 // running value; when the mask changes, that value goes into the accumulators
 // of the nodes in the mask, which sit in LDS, so that the per-node work is paid
@@ -832,8 +833,10 @@ constexpr uint32_t group_block(uint32_t m) {
 }
 constexpr int kGroupLoads = 16;  // rows in flight per wave (one batch)
 
-// This lane's part of one 512-byte counter slice: two dwords.
-struct LaneSlice {
+// This lane's part of one counter slice: kDw dwords (two of a 512-byte slice,
+// one of a 256-byte counter).
+template <uint32_t kDw> struct LaneSlice;
+template <> struct LaneSlice<2> {
     uint32_t d[2];
     __device__ __forceinline__ void load(const uint8_t *p) {
         const uint2 x = *reinterpret_cast<const uint2 *>(p);
@@ -842,6 +845,15 @@ struct LaneSlice {
     }
     __device__ __forceinline__ void store(uint8_t *p) const {
         *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
+    }
+};
+template <> struct LaneSlice<1> {
+    uint32_t d[1];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        d[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+    __device__ __forceinline__ void store(uint8_t *p) const {
+        *reinterpret_cast<uint32_t *>(p) = d[0];
     }
 };
 
@@ -876,15 +888,16 @@ __device__ __forceinline__ void groups_step(
     double thr, uint32_t lb) {
     constexpr uint32_t W = kGroupNodes, H = group_waves(C::PREC, C::BITS);
     constexpr uint32_t kSlice = (uint32_t)C::M / H;  // counter bytes per wave
-    static_assert(kSlice == kGroupSlice && H >= 1, "512-byte slices");
+    static_assert((kSlice == kGroupSlice || (H == 1 && kSlice == kGroupSlice / 2)) && H >= 1,
+                  "512-byte slices, or one 256-byte counter");
     constexpr uint32_t kDw = kSlice / kWave / 4u;    // dwords per lane
-    static_assert(kDw == 2, "8 bytes per lane");
+    static_assert(kDw == 1 || kDw == 2, "4 or 8 bytes per lane");
     constexpr int U = kGroupLoads;  // rows per batch
     static_assert(U * kDw <= 32, "at most 32 VGPRs of loads per batch");
     static_assert(kWave % U == 0, "a batch lies in one chunk of 64 entries");
     constexpr uint32_t kWavesPerBlock = group_block(C::M) / kWave;
     constexpr uint32_t kGroupsPerBlock = kWavesPerBlock / H;
-    using Slice = LaneSlice;
+    using Slice = LaneSlice<kDw>;
     __shared__ Slice s_acc[kWavesPerBlock][W][kWave];
     __shared__ uint64_t s_lo[kWavesPerBlock][W];
     __shared__ uint64_t s_hi[kWavesPerBlock][W];
@@ -1786,10 +1799,12 @@ hipError_t launch_union_groups(int p, uint32_t bits, const uint32_t *grp_rows,
         return launch_union_groups_c<Cfg<P, L, B>>(grp_rows, grp_mask, grp_off, tbl, next,    \
                                                    c_prev, sum_d, flag_t, n, t, order, thr,   \
                                                    skip, stream);
+    HB_G(8, 16, 8)
     HB_G(9, 32, 8)
     HB_G(10, 64, 8)
     HB_G(11, 128, 8)
     HB_G(12, 256, 8)
+    HB_G(9, 16, 4)
     HB_G(10, 32, 4)
     HB_G(11, 64, 4)
     HB_G(12, 128, 4)
@@ -1815,10 +1830,12 @@ hipError_t launch_batch_groups(int p, uint32_t bits, BatchJob *jobs, const uint3
                            block_base, nlist);                                               \
         return hipGetLastError();                                                            \
     }
+    HB_G(8, 16, 8)
     HB_G(9, 32, 8)
     HB_G(10, 64, 8)
     HB_G(11, 128, 8)
     HB_G(12, 256, 8)
+    HB_G(9, 16, 4)
     HB_G(10, 32, 4)
     HB_G(11, 64, 4)
     HB_G(12, 128, 4)

@@ -93,17 +93,19 @@ def _sparse_large(n=34000, n_edges=200000, seed=23):
 @pytest.mark.parametrize("bits", [8, 4])
 def test_batch_grouped_jobs(hb, bits):
     """Jobs on a graph of more than 32,768 nodes take the grouped kernel where it is
-    built (p = 9..12 with 8-bit registers, 10..12 with 4-bit), beside run-kernel jobs."""
+    built (p = 8..12 with 8-bit registers, 9..12 with 4-bit), beside run-kernel and
+    per-edge jobs."""
     g = _sparse_large()
     G = _load(hb, g)
-    ps = [8, 9, 10, 11, 12] if bits == 8 else [9, 10, 11, 12]
+    ps = [8, 9, 10, 11, 12, 13] if bits == 8 else [8, 9, 10, 11, 12]
     jobs = [(G, p, (0, 3, 2)[i % 3], 100 + i) for i, p in enumerate(ps)]
     print(f"[batch] grouped jobs n={g.n} E={g.n_edges} bits={bits}", flush=True)
     res = hb.run_batch(jobs, registers=True, register_bits=bits)
     for (_, p, d, seed), r in zip(jobs, res):
         what = f"{g.name} p={p} d={d} seed={seed} bits={bits}"
-        grouped = (9 if bits == 8 else 10) <= p <= 12
-        assert r.union_kernel == ("groups" if grouped else "runs"), (what, r.union_kernel)
+        grouped = (8 if bits == 8 else 9) <= p <= 12
+        other = "runs" if p <= 12 else "edges"
+        assert r.union_kernel == ("groups" if grouped else other), (what, r.union_kernel)
         assert_matches(hb, r, ref(g, p, d, seed, register_bits=bits), what)
-        _same(r, G.run(p, d, seed, registers=True, register_bits=bits, kernel="runs"), what)
+        _same(r, G.run(p, d, seed, registers=True, register_bits=bits, kernel=other), what)
     G.free()

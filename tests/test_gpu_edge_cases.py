@@ -1,7 +1,7 @@
 """Decoder edge cases on the GPU: multi-byte varints, varints cut by chunk ends, long runs.
 
 Every union kernel is checked against the oracle, byte for byte (the grouped one
-where it is built: p = 9..12 at the default table depth).  Rows are built so
+where it is built: p = 8..12 at the default table depth).  Rows are built so
 that the wave-cooperative decoder meets every case: 2- and 3-byte deltas, a varint
 split across two 64-byte chunks, chunks that are all deltas of one, runs longer than
 any table block, and a row whose only run passes over the node itself.
@@ -21,7 +21,7 @@ def _check(hb, g, p, depth, seed=0, levels=0):
     ref = oracle.hyperball(oracle.from_graph(g), p, depth, seed)
     off, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
     with hb.graph_load(off, deg, data) as G:
-        for kernel in ("runs", "edges") + (("groups",) if 9 <= p <= 12 and levels == 0 else ()):
+        for kernel in ("runs", "edges") + (("groups",) if 8 <= p <= 12 and levels == 0 else ()):
             print(f"[edge] {g.name} n={g.n} E={g.n_edges} p={p} d={depth} {kernel} K={levels}",
                   flush=True)
             r = G.run(p, depth, seed, registers=True, kernel=kernel, table_levels=levels)
@@ -95,7 +95,7 @@ def test_very_long_row(hb):
         off_b, deg, data = hb.csr_encode(g.adj_offsets, g.adj_ids)
         assert int(off_b[1]) >= 99_000  # the centre row spans ~1,560 chunks
         with hb.graph_load(off_b, deg, data) as G:
-            for kernel in ("runs", "edges") + (("groups",) if 9 <= p <= 12 else ()):
+            for kernel in ("runs", "edges") + (("groups",) if 8 <= p <= 12 else ()):
                 print(f"[edge] star100k p={p} d={depth} {kernel}", flush=True)
                 r = G.run(p, depth, 3, registers=True, kernel=kernel, tune="off")
                 assert r.passes == ref.passes and r.converged == ref.converged

@@ -45,7 +45,7 @@ def test_processing_order_changes_nothing(hb, gname):
         for oname, order in orders.items():
             G = _load(hb, g, order=order)
             kernels = (("runs", "edges") if p <= 12 else ("edges",)) + \
-                (("groups",) if 9 <= p <= 12 else ())
+                (("groups",) if 8 <= p <= 12 else ())
             for kernel in kernels:
                 what = f"{g.name} order={oname} p={p} d={depth} {kernel}"
                 print(f"[order] {what}", flush=True)
@@ -63,7 +63,7 @@ def test_renumbered_graph_with_hash_ids(hb):
         a = oracle.hyperball(oracle.from_graph(g), p, depth, 7)
         b = oracle.hyperball(oracle.from_graph(h), p, depth, 7, hash_ids=orig)
         G = _load(hb, h, hash_ids=orig)
-        for kernel in ("runs", "edges") + (("groups",) if 9 <= p <= 12 else ()):
+        for kernel in ("runs", "edges") + (("groups",) if 8 <= p <= 12 else ()):
             r = G.run(p, depth, 7, registers=True, kernel=kernel, tune="off")
             what = f"renumbered p={p} d={depth} {kernel}"
             print(f"[order] {what}", flush=True)

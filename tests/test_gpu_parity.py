@@ -39,8 +39,8 @@ def _check(hb, g, p, depth, seed=0, kernels=("edges", "runs", "groups"), table_l
         for kernel in kernels:
             if kernel == "runs" and p > 12:
                 continue
-            if kernel == "groups" and (not 9 <= p <= 12 or table_levels not in (0, 8)):
-                continue  # built for p = 9..12 and the default table depth
+            if kernel == "groups" and (not 8 <= p <= 12 or table_levels not in (0, 8)):
+                continue  # built for p = 8..12 and the default table depth
             print(f"[parity] {g.name} n={g.n} E={g.n_edges} p={p} depth={depth} seed={seed} "
                   f"kernel={kernel} K={table_levels}", flush=True)
             res = G.run(p, depth, seed, registers=True, kernel=kernel, table_levels=table_levels)
@@ -137,7 +137,7 @@ def _sampled_check(hb, g, p, depth, n_src=64, seed=0, order=None, reg4=False):
     assert np.array_equal(csr.bytes, data)
     results = {}
     with hb.graph_load(off, deg, data, order=order) as G:
-        for kernel in ("runs", "edges") + (("groups",) if 9 <= p <= 12 else ()):
+        for kernel in ("runs", "edges") + (("groups",) if 8 <= p <= 12 else ()):
             results[kernel] = G.run(p, depth, seed, registers=True, kernel=kernel)
             print(f"[parity] {kernel}: passes={results[kernel].passes} "
                   f"iter_ms={results[kernel].iter_ms:.1f}", flush=True)

@@ -63,7 +63,7 @@ def test_4bit_matches_oracle(hb, p):
         assert ref.registers.max() == 15
         G = _load(hb, g, hash_ids=hid)
         kernels = (("runs", "edges") if p <= 12 else ("edges",)) + \
-            (("groups",) if 10 <= p <= 12 else ())
+            (("groups",) if 9 <= p <= 12 else ())
         for kernel in kernels:
             for nb in ((4, 1) if p <= 11 and kernel != "groups" else (0,)):
                 what = f"{g.name} p={p} d={depth} {kernel} nb={nb}"

@@ -223,14 +223,15 @@ def test_served_grouped_requests(hb, server):
     g = synth.from_edges(n, list(zip(a.tolist(), b.tolist())), name=f"sparse{n}")
     G = _load(hb, g)
     specs = [(9, 0, 1, 8), (10, 3, 2, 8), (12, 2, 3, 8), (8, 0, 4, 8), (10, 0, 5, 4),
-             (12, 3, 6, 4)]
+             (12, 3, 6, 4), (13, 2, 7, 8), (8, 3, 8, 4)]
     tickets = [hb.submit(G, p, d, sd, registers=True, register_bits=bits)
                for (p, d, sd, bits) in specs]
     for (p, d, sd, bits), t in zip(specs, tickets):
         r = t.wait()
         what = f"{g.name} p={p} d={d} seed={sd} bits={bits}"
-        grouped = (9 if bits == 8 else 10) <= p <= 12
-        assert r.union_kernel == ("groups" if grouped else "runs"), (what, r.union_kernel)
+        grouped = (8 if bits == 8 else 9) <= p <= 12
+        other = "runs" if p <= 12 else "edges"
+        assert r.union_kernel == ("groups" if grouped else other), (what, r.union_kernel)
         assert_matches(hb, r, ref(g, p, d, sd, register_bits=bits), what)
-        _same(r, G.run(p, d, sd, registers=True, register_bits=bits, kernel="runs"), what)
+        _same(r, G.run(p, d, sd, registers=True, register_bits=bits, kernel=other), what)
     G.free()
