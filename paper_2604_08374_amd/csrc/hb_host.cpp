@@ -1406,7 +1406,7 @@ hb_status hb_local_metrics(hb_graph *g, hb_local_out *out) {
     if (e == hipSuccess) e = dmalloc((void **)&d_ctrl, sizeof(double) * n);
     if (e == hipSuccess)
         e = hbk::launch_local(d_runs, d_off, g->d_degrees, n, g->d_order, d_pairs, d_ball, d_clus,
-                              d_ctrl, g->stream);
+                              d_ctrl, (uint32_t)lim, g->stream);
     if (e == hipSuccess && out->pairs)
         e = hipMemcpyAsync(out->pairs, d_pairs, sizeof(uint64_t) * n, hipMemcpyDeviceToHost,
                            g->stream);

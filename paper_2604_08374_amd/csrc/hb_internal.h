@@ -193,9 +193,13 @@ hipError_t launch_row_runs(const uint8_t *bytes, const uint64_t *offsets, uint32
 // Needs 8 (n + 31) / 32 bytes of LDS, plus 12 per wave, per workgroup of
 // local_threads() threads.
 uint32_t local_threads();
+// lds_limit: LDS bytes per workgroup on the device; n up to about lds_limit * 2
+// nodes takes the kernel with constant work per neighbour run (four arrays of
+// n / 32 words), larger n the one with two bitmaps.
 hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32_t *degrees,
                         uint32_t n, const uint32_t *order, uint64_t *pairs, uint32_t *ball2,
-                        double *clustering, double *controllability, hipStream_t stream);
+                        double *clustering, double *controllability, uint32_t lds_limit,
+                        hipStream_t stream);
 
 // Fill count u32 words with value (used instead of hipMemsetAsync so the
 // sequence stays capturable).

@@ -1560,6 +1560,151 @@ __global__ __launch_bounds__(kLocalWaves * kWave) void local_kernel(
         controllability[v] = ball >= 1u ? (double)k / (double)ball : nan;
 }
 
+// The same metrics with constant work per neighbour run, for n up to a quarter
+// of the LDS in 32-bit words.  LDS holds, over words+1 32-bit words each: N(v);
+// P, the popcount of N(v) before each word; D, a difference array of the words
+// that neighbours' runs cover whole; and U, the union of their runs' partial end
+// words.  A run [a, b] then adds rank(b + 1) - rank(a) to the pairs count, with
+// rank(x) = P[x / 32] + popcount(N(v) word x / 32 below bit x % 32), ORs its end
+// words into U and marks its whole words in D (+1 at the first, -1 after the
+// last).  At the end the prefix sums of D give the words some run covers whole,
+// and B(v, 2) \ {v} is the popcount of N(v) | U | (covered words) without v.
+// Every count is an exact integer, so the results equal the bitmap kernel's.
+__device__ __forceinline__ uint32_t rank_bits(const uint32_t *nv, const uint32_t *pre, uint32_t x) {
+    const uint32_t w = x >> 5, below = (1u << (x & 31u)) - 1u;
+    return pre[w] + (uint32_t)__builtin_popcount(nv[w] & below);
+}
+
+// In-place exclusive (inclusive when `inclusive`) prefix sum of a[0 .. count)
+// by the whole workgroup (T threads of kLocalWaves waves); tmp holds
+// kLocalWaves words.  Every thread of the workgroup calls it.
+template <uint32_t T>
+__device__ void block_scan(uint32_t *a, uint32_t count, uint32_t *tmp, bool inclusive) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t per = (count + T - 1u) / T;
+    const uint32_t b0 = tid * per < count ? tid * per : count;
+    const uint32_t b1 = b0 + per < count ? b0 + per : count;
+    uint32_t sum = 0;
+    for (uint32_t i = b0; i < b1; ++i) sum += a[i];
+    const uint32_t incl = wave_scan(sum);
+    if (lane == kWave - 1) tmp[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < wave; ++k) before += tmp[k];
+    uint32_t run = before + incl - sum;  // exclusive prefix of this thread's chunk
+    __syncthreads();                     // tmp is read before anyone reuses it
+    for (uint32_t i = b0; i < b1; ++i) {
+        const uint32_t x = a[i];
+        a[i] = inclusive ? run + x : run;
+        run += x;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kLocalWaves * kWave) void local_rank_kernel(
+    const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_off,
+    const uint32_t *__restrict__ degrees, uint32_t n, uint32_t words,
+    const uint32_t *__restrict__ order, uint64_t *__restrict__ pairs_out,
+    uint32_t *__restrict__ ball2_out, double *__restrict__ clustering,
+    double *__restrict__ controllability) {
+    extern __shared__ uint32_t s_bits[];
+    __shared__ uint64_t s_pairs[kLocalWaves];
+    __shared__ uint32_t s_reach[kLocalWaves];
+    __shared__ uint32_t s_scan[kLocalWaves];
+    constexpr uint32_t T = kLocalWaves * kWave;
+    const uint32_t W1 = words + 1u;  // one word past the last, for rank(n) and D
+    uint32_t *nv = s_bits, *pre = s_bits + W1, *cov = s_bits + 2u * W1, *un = s_bits + 3u * W1;
+    // all XCDs on one stretch of the order, as the table kernels (4.5 against
+    // 5.9 s on the city graph with one node range per XCD)
+    uint32_t v = xcd_span_block(blockIdx.x, gridDim.x, kXcdSpanChunk);
+    if (v >= n) return;  // uniform per workgroup
+    if (order) v = order[v];
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid / kWave));
+    for (uint32_t i = tid; i < 4u * W1; i += T) s_bits[i] = 0u;
+    __syncthreads();
+    const uint64_t rs = run_off[v], re = run_off[v + 1];
+    // a run outside [0, n) or reversed is skipped (the loader validated the
+    // rows, so none occurs; the check keeps every LDS index in bounds)
+    for (uint64_t r = rs + tid; r < re; r += T) {
+        const uint2 x = runs[r];
+        if (x.x <= x.y && x.y < n) range_set(nv, x.x, x.y);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < W1; i += T) pre[i] = (uint32_t)__builtin_popcount(nv[i]);
+    __syncthreads();
+    block_scan<T>(pre, W1, s_scan, false);
+    uint64_t pairs = 0;
+    // wave i takes the neighbours w = i mod kLocalWaves; its lanes take the
+    // neighbour's runs, kLocalLoads per lane in flight
+    for (uint64_t r = rs; r < re; ++r) {
+        const uint2 x = runs[r];
+        if (!(x.x <= x.y && x.y < n)) continue;
+        const uint32_t w0 = x.x + (wave + kLocalWaves - x.x % kLocalWaves) % kLocalWaves;
+        for (uint64_t w = w0; w <= x.y; w += kLocalWaves) {
+            const uint2 *row = runs + run_off[w];
+            const uint32_t cnt = (uint32_t)(run_off[w + 1] - run_off[w]);  // < 2^32 per row
+            for (uint32_t q = lane; q < cnt; q += kLocalLoads * kWave) {
+                uint2 y[kLocalLoads];
+#pragma unroll
+                for (uint32_t u = 0; u < kLocalLoads; ++u)
+                    y[u] = q + u * kWave < cnt ? row[q + u * kWave] : make_uint2(1u, 0u);
+#pragma unroll
+                for (uint32_t u = 0; u < kLocalLoads; ++u) {
+                    const uint32_t a = y[u].x, b = y[u].y;
+                    if (!(a <= b && b < n)) continue;
+                    pairs += rank_bits(nv, pre, b + 1u) - rank_bits(nv, pre, a);
+                    const uint32_t wa = a >> 5, wb = b >> 5;
+                    const uint32_t lo = ~0u << (a & 31u), hi = ~0u >> (31u - (b & 31u));
+                    if (wa == wb) {
+                        atomicOr(&un[wa], lo & hi);
+                    } else {
+                        atomicOr(&un[wa], lo);
+                        atomicOr(&un[wb], hi);
+                        if (wb > wa + 1u) {
+                            atomicAdd(&cov[wa + 1u], 1u);
+                            atomicSub(&cov[wb], 1u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    block_scan<T>(cov, W1, s_scan, true);
+    uint32_t reach = 0;
+    for (uint32_t i = tid; i < words; i += T)
+        reach += (uint32_t)__builtin_popcount(nv[i] | un[i] | (cov[i] ? ~0u : 0u));
+#pragma unroll
+    for (uint32_t mask = 1; mask < kWave; mask <<= 1) {
+        reach += shfl_xor(reach, mask);
+        const uint32_t lo = shfl_xor((uint32_t)pairs, mask), hi = shfl_xor((uint32_t)(pairs >> 32), mask);
+        pairs += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0) {
+        s_pairs[wave] = pairs;
+        s_reach[wave] = reach;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    uint64_t links = 0;
+    uint32_t ball = 0;
+    for (uint32_t i = 0; i < kLocalWaves; ++i) {
+        links += s_pairs[i];
+        ball += s_reach[i];
+    }
+    const uint32_t wv = nv[v >> 5] | un[v >> 5] | (cov[v >> 5] ? ~0u : 0u);
+    ball -= (wv >> (v & 31u)) & 1u;  // v itself
+    const uint32_t k = degrees[v];
+    const double nan = __builtin_nan("");
+    if (pairs_out) pairs_out[v] = links;
+    if (ball2_out) ball2_out[v] = ball;
+    if (clustering)  // Watts & Strogatz: links among neighbours over k (k - 1)
+        clustering[v] = k >= 2u ? (double)links / ((double)k * (double)(k - 1u)) : nan;
+    if (controllability)  // first-step neighbourhood over the two-step one
+        controllability[v] = ball >= 1u ? (double)k / (double)ball : nan;
+}
+
 __global__ void fill_u32_kernel(uint32_t *dst, uint32_t value, uint64_t count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = value;
@@ -1956,9 +2101,22 @@ uint32_t local_threads() { return kLocalWaves * kWave; }
 
 hipError_t launch_local(const uint2 *runs, const uint64_t *run_off, const uint32_t *degrees,
                         uint32_t n, const uint32_t *order, uint64_t *pairs, uint32_t *ball2,
-                        double *clustering, double *controllability, hipStream_t stream) {
+                        double *clustering, double *controllability, uint32_t lds_limit,
+                        hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint32_t words = (n + 31u) / 32u;
+    // constant work per run when its four arrays fit, else the two bitmaps
+    const size_t lds_rank = sizeof(uint32_t) * 4u * (words + 1u);
+    if (lds_rank + 16u * kLocalWaves <= lds_limit) {
+        hipError_t e = hipFuncSetAttribute((const void *)local_rank_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_rank);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(local_rank_kernel, dim3(n), dim3(kLocalWaves * kWave), lds_rank,
+                           stream, runs, run_off, degrees, n, words, order, pairs, ball2,
+                           clustering, controllability);
+        return hipGetLastError();
+    }
     const size_t lds = sizeof(uint32_t) * 2u * words;
     hipError_t e = hipFuncSetAttribute((const void *)local_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
