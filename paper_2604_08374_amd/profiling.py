@@ -46,11 +46,12 @@ def _short(name: str) -> str:
     The union kernels are templates over Cfg<p, lanes per node> (and, batched,
     the kernel kind), shown as <p,lanes> or <p,lanes,true|false>.
     """
-    for key in ("batch_union_kernel", "batch_table_kernel", "batch_init_kernel",
-                "batch_step_end_kernel", "union_groups_kernel", "union_runs_kernel",
-                "union_kernel", "table_fused_kernel", "table_level_kernel", "gather_probe_kernel",
-                "init_kernel", "copy_kernel", "fill_u32_kernel", "vis_rows_kernel",
-                "local_kernel", "row_runs_kernel", "vga_kernel"):
+    for key in ("batch_union_kernel", "batch_groups_kernel", "batch_table_kernel",
+                "batch_init_kernel", "batch_step_end_kernel", "union_groups_kernel",
+                "union_runs_kernel", "union_kernel", "table_fused_kernel", "table_level_kernel",
+                "gather_probe_kernel", "init_kernel", "copy_kernel", "fill_u32_kernel",
+                "vis_rows_kernel", "local_rank_kernel", "local_kernel", "row_runs_kernel",
+                "vga_kernel"):
         at = name.find(key)
         if at < 0 or (at > 0 and (name[at - 1].isalnum() or name[at - 1] == "_")):
             continue
