@@ -396,8 +396,11 @@ typedef struct {
 /*
  * Run n_jobs analyses together (blocking).  All jobs advance one HyperBall
  * step per batched step: one launch per (p, union kernel) class covers the
- * nodes of every running job of that class, one launch per table level builds
- * the range-max tables of all run-kernel jobs, and a step-end kernel applies
+ * nodes of every running job of that class (the union kernel of each job
+ * chosen by opts->union_kernel as for hb_run_with: HB_UNION_AUTO takes the
+ * grouped kernel for graphs of at least 32,768 nodes where it is built), one
+ * launch per table level builds the range-max tables of all run-kernel and
+ * grouped jobs, and a step-end kernel applies
  * each job's own stop rule on the device, so jobs of different sizes, p and
  * depth limits finish independently.  Each step is a captured HIP graph,
  * replayed a few steps at a time between host checks.  outs[j] is filled as
