@@ -153,6 +153,7 @@ void hbr::graph_release(hb_graph *g) {
                     (void *)g->d_grp_rows, (void *)g->d_grp_mask, (void *)g->d_grp_off})
         dfree(p);
     if (g->h_flags) (void)hipHostFree(g->h_flags);
+    if (g->h_out) (void)hipHostFree(g->h_out);
     for (auto &e : g->ev_init)
         if (e) (void)hipEventDestroy(e);
     for (auto &step : g->ev_step)
@@ -521,6 +522,9 @@ hb_status hb_graph_load(const hb_csr *csr, hb_graph **out) {
     if ((e = hipHostMalloc((void **)&g->h_flags, sizeof(uint32_t) * kSegment,
                            hipHostMallocDefault)) != hipSuccess)
         return bail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc((void **)&g->h_out, sizeof(double) * 2ull * std::max<uint32_t>(g->n, 1u),
+                           hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
     if ((e = dmalloc((void **)&g->d_bytes, std::max<uint64_t>(g->n_bytes, 16))) != hipSuccess)
         return bail(e, "device allocation (bytes)");
     if ((e = dmalloc((void **)&g->d_offsets, sizeof(uint64_t) * ((uint64_t)g->n + 1))) != hipSuccess)
@@ -828,19 +832,22 @@ hb_status run_blocking(hb_graph *g, uint32_t p, uint32_t depth_limit, uint64_t h
     HB_HIP(hipEventElapsedTime(&init_ms, g->ev_init[0], g->ev_init[1]));
     HB_HIP(hipEventElapsedTime(&run_ms, g->ev_init[0], g->ev_step[(T - 1u) % kSegment][2]));
 
+    // reach and sums through the graph's pinned staging buffer, then to the caller
+    double *h_reach = g->h_out, *h_sum = g->h_out + n;
     if (out->reach)
-        HB_HIP(hipMemcpyAsync(out->reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    // the sums land in mean_depth when sum_d is not wanted: no host buffer
-    double *sd = out->sum_d ? out->sum_d : out->mean_depth;
-    if (sd) HB_HIP(hipMemcpyAsync(sd, g->d_sumd, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        HB_HIP(hipMemcpyAsync(h_reach, g->d_cprev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    if (out->sum_d || out->mean_depth)
+        HB_HIP(hipMemcpyAsync(h_sum, g->d_sumd, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     if (out->registers)
         HB_HIP(hipMemcpyAsync(out->registers, bufs[T & 1u], (uint64_t)n * m, hipMemcpyDeviceToHost,
                               s));
     HB_HIP(hipStreamSynchronize(s));
+    if (out->reach) memcpy(out->reach, h_reach, sizeof(double) * n);
+    if (out->sum_d) memcpy(out->sum_d, h_sum, sizeof(double) * n);
     if (out->mean_depth)
         for (uint32_t v = 0; v < n; ++v) {
             const double nv = g->comp_size.empty() ? (double)n : (double)g->comp_size[v];
-            out->mean_depth[v] = nv >= 2.0 ? sd[v] / (nv - 1.0) : NAN;
+            out->mean_depth[v] = nv >= 2.0 ? h_sum[v] / (nv - 1.0) : NAN;
         }
     const double md = (double)(1ull << p);
     out->passes = T;

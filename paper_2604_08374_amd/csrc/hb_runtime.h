@@ -143,6 +143,8 @@ struct hb_graph {
     uint32_t *d_flags = nullptr;
     uint64_t n_flags = 0;
     uint32_t *h_flags = nullptr;  // pinned: the stop flags of one segment of steps
+    double *h_out = nullptr;      // pinned: reach and sum_d of a blocking run (2 n), staged
+                                  // here so the device copies need no pageable bounce
     hipStream_t stream = nullptr;
     hipEvent_t ev_init[2] = {nullptr, nullptr};          // around the initialisation
     hipEvent_t ev_step[hbr::kSegment][3] = {};            // per step: table, union, end
