@@ -90,14 +90,16 @@ def algorithmic_bytes(n: int, n_edges: int, n_bytes: int, p: int, rows: int | No
 
 def table_bytes(n: int, p: int, levels: int, bits: int = 8) -> int:
     """Range-max table build per step.  Up to 8 levels of rows of a multiple of 64
-    bytes are built in one launch from LDS tiles of 512 rows plus 2^K - 1 rows past
-    them: level 0 is read once per tile (767/512 of it at K = 8) and each level is
-    written once; otherwise each level k reads two rows and writes one per i."""
+    bytes are built in one launch from LDS tiles of T rows plus 2^K - 1 rows past
+    them (T = 256 for 8-bit rows of at least 1 KB, else 512): level 0 is read once
+    per tile and each level is written once; otherwise each level k reads two rows
+    and writes one per i."""
     m = (1 << p) * bits // 8
     writes = sum((n - (1 << k) + 1) * m for k in range(1, levels + 1))
     if 1 <= levels <= 8 and m % 64 == 0:
-        span = 512 + (1 << levels) - 1
-        reads = sum(min(i0 + span, n) - i0 for i0 in range(0, n, 512))
+        tile = 256 if bits == 8 and m >= 1024 and m % 128 == 0 else 512
+        span = tile + (1 << levels) - 1
+        reads = sum(min(i0 + span, n) - i0 for i0 in range(0, n, tile))
         return writes + reads * m
     return 3 * writes
 

@@ -1119,21 +1119,24 @@ __global__ __launch_bounds__(256) void table_level_kernel(uint8_t *__restrict__ 
 }
 
 // All levels 1..levels (<= kFusedLevels) of the table in one launch.  A
-// workgroup holds rows i0 .. i0 + kTblRows + 2^levels - 2 of a 64-byte column
-// slice of cur in LDS (the output rows plus the span the largest block reaches
-// past them), builds each level in place from the one before, and writes the
-// level's rows i0 .. i0 + kTblRows - 1 that exist (i <= n - 2^k).  Level 0 is
-// read about 1.5 times instead of twice per level, and no level is read back.
+// workgroup holds rows i0 .. i0 + kTblRows + 2^levels - 2 of a column slice of
+// kTblCols x 16 bytes of cur in LDS (the output rows plus the span the largest
+// block reaches past them), builds each level in place from the one before,
+// and writes the level's rows i0 .. i0 + kTblRows - 1 that exist
+// (i <= n - 2^k).  Level 0 is read about 1.5 times instead of twice per level,
+// and no level is read back.  Two tile shapes: 512 rows of 64 bytes, or, for
+// 8-bit counters of at least 1 KB, 256 rows of 128 bytes (whole 128-byte lines
+// written; city graph, p = 10: 0.60 against 0.66 ms per step, while 4-bit
+// counters of 512 bytes were slower with it).
 constexpr uint32_t kFusedLevels = 8;
-constexpr uint32_t kTblRows = 512;                              // output rows per workgroup
-constexpr uint32_t kTblCols = 4;                                // 16-byte columns per workgroup
-constexpr uint32_t kTblSpan = kTblRows + (1u << kFusedLevels) - 1u;
-constexpr uint32_t kTblPer = (kTblSpan * kTblCols + 255u) / 256u;  // LDS chunks per thread
 
+template <uint32_t kTblRows, uint32_t kTblCols>
 __global__ __launch_bounds__(256) void table_fused_kernel(uint8_t *__restrict__ tbl, uint32_t n,
                                                           uint32_t m, uint32_t levels,
                                                           uint32_t bits,
                                                           const uint32_t *__restrict__ skip) {
+    constexpr uint32_t kTblSpan = kTblRows + (1u << kFusedLevels) - 1u;
+    constexpr uint32_t kTblPer = (kTblSpan * kTblCols + 255u) / 256u;  // LDS chunks per thread
     __shared__ uint4 lds[kTblSpan * kTblCols];
     if (skip && *skip == 0u) return;  // the previous step stopped the run
     const uint32_t slices = m / (16u * kTblCols);
@@ -2003,11 +2006,18 @@ hipError_t launch_gather_probe(int p, const Sched &s, const uint8_t *tbl, uint32
 hipError_t launch_table(uint8_t *tbl, uint32_t n, uint32_t m, uint32_t levels, uint32_t bits,
                         const uint32_t *skip, hipStream_t stream) {
     if (levels == 0) return hipSuccess;
-    if (levels <= kFusedLevels && m % (16u * kTblCols) == 0) {
-        const uint64_t tiles = ((uint64_t)n + kTblRows - 1) / kTblRows;
-        const uint64_t blocks = tiles * (m / (16u * kTblCols));
-        hipLaunchKernelGGL(table_fused_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, tbl,
-                           n, m, levels, bits, skip);
+    if (levels <= kFusedLevels && bits == 8u && m >= 1024u && m % 128u == 0) {
+        const uint64_t tiles = ((uint64_t)n + 255u) / 256u;
+        const uint64_t blocks = tiles * (m / 128u);
+        hipLaunchKernelGGL((table_fused_kernel<256, 8>), dim3((uint32_t)blocks), dim3(256), 0,
+                           stream, tbl, n, m, levels, bits, skip);
+        return hipGetLastError();
+    }
+    if (levels <= kFusedLevels && m % 64u == 0) {
+        const uint64_t tiles = ((uint64_t)n + 511u) / 512u;
+        const uint64_t blocks = tiles * (m / 64u);
+        hipLaunchKernelGGL((table_fused_kernel<512, 4>), dim3((uint32_t)blocks), dim3(256), 0,
+                           stream, tbl, n, m, levels, bits, skip);
         return hipGetLastError();
     }
     const uint64_t level_bytes = (uint64_t)n * m;

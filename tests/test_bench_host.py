@@ -46,6 +46,12 @@ def test_fused_table_bytes_read_each_tile_with_its_halo():
     span = 512 + (1 << levels) - 1
     reads = sum(min(i0 + span, n) - i0 for i0 in range(0, n, 512)) * m
     assert bench.table_bytes(n, p, levels) == writes + reads
+    # 8-bit rows of 1 KB: tiles of 256 rows
+    m, levels = 1024, 8
+    writes = sum((n - (1 << k) + 1) * m for k in range(1, levels + 1))
+    span = 256 + (1 << levels) - 1
+    reads = sum(min(i0 + span, n) - i0 for i0 in range(0, n, 256)) * m
+    assert bench.table_bytes(n, 10, levels) == writes + reads
     # rows narrower than 64 bytes take the per-level kernel: two reads, one write
     assert bench.table_bytes(n, 5, levels, bits=4) == 3 * sum(
         (n - (1 << k) + 1) * 16 for k in range(1, levels + 1))
