@@ -2,14 +2,18 @@
 //
 // One launch is one whole HyperBall step: the register-wise max of Eq. 2 for
 // every node, with the estimator and the Eq. 3 accumulation fused into its
-// epilogue.  Two union kernels give the same registers:
+// epilogue.  Three union kernels give the same registers:
 //
 //  * the per-edge kernel is the paper's fused decode-union step (Sec. 3.4): it
 //    decodes the node's LEB128 row and gathers every neighbour's counter;
-//  * the run kernel (default, p <= 12) covers each run of consecutive
-//    neighbour ids with one or two rows of a range-max table of the counters,
-//    built every step, and reads the runs from a run list that the loader
-//    decodes once from the LEB128 rows.
+//  * the run kernel (p <= 12) covers each run of consecutive neighbour ids
+//    with one or two rows of a range-max table of the counters, built every
+//    step, and reads the runs from a run list that the loader decodes once
+//    from the LEB128 rows;
+//  * the grouped kernel (the default for counters of 256 to 4096 bytes on
+//    graphs of at least 32,768 nodes) reads the same table rows, merged by the
+//    loader over groups of 16 nodes of the processing order, so that a row
+//    that several nodes of a group need is loaded once for all of them.
 //
 // Design on gfx950:
 //
@@ -44,8 +48,10 @@
 //    time, 64 workgroups each, so that the rows they share meet in the memory-
 //    side cache that all XCDs share (city graph, p = 10: 7.9 against 9.0 ms
 //    per grouped launch, 11.0 against 13.0 ms per run-kernel launch).
-//  * The exact local metrics (clustering, controllability) keep two bitmaps of
-//    n bits per node in LDS and walk the neighbours' run lists.
+//  * The exact local metrics (clustering, controllability) walk the
+//    neighbours' run lists against LDS arrays of n bits per node: a prefix
+//    popcount of N(v) answers each run's intersection count in constant time,
+//    and a difference array marks the words a run covers whole.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
