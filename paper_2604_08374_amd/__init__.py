@@ -445,7 +445,9 @@ class Graph:
             register_bits: int = 8) -> Result:
         """hb_run_with: HyperBall with precision p; depth_limit 0 = until convergence.
 
-        kernel: "auto", "edges" (gather every neighbour) or "runs" (range-max table).
+        kernel: "auto", "edges" (gather every neighbour), "runs" (range-max table) or
+        "groups" (the table's rows merged over groups of 16 nodes; counters of 256 to
+        4096 bytes).
         tune: "cached" (a cached schedule pick, else the default), "measure" (measure
         the schedules first when nothing is cached) or "off"; lanes_per_node and
         nodes_per_block name a schedule explicitly.
